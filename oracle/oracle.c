@@ -1,0 +1,903 @@
+/*
+ * oracle.c - plain FP64 history-based Monte Carlo k-eigenvalue transport.
+ *
+ * TEST INFRASTRUCTURE: the reference the HIP event-based path is checked
+ * against.  Loaded only by the tests, the smoke check and the benchmark's
+ * CPU-baseline leg.  Nothing here is shared with the HIP path.
+ *
+ * The paper (Sec. 1) names the capabilities: multigroup energy physics,
+ * constructive solid geometry with surface tracking, k-eigenvalue power
+ * iteration and replicable random numbers; Sec. 2 describes the
+ * to-be-processed / processed particle banks and the fission bank; Sec. 5
+ * fixes FP64 arithmetic.  It gives no transport equations, so each history
+ * here is textbook analog Monte Carlo, one particle at a time, in the order:
+ *
+ *   birth -> { cross-section lookup, distance to collision, distance to
+ *   boundary, move + track-length tally, collide | cross } until death
+ *
+ * and each generation ends with a canonical fission bank, the k estimators,
+ * the Shannon entropy of the bank and systematic combing back to N sites.
+ *
+ * Build: gcc -O2 -std=gnu11 -ffp-contract=off -fno-fast-math (no FMA
+ * contraction; every product and sum is rounded on its own), -lquadmath.
+ *
+ * The two transcendental functions of the path, ln(xi) for the flight
+ * distance and cos/sin(2 pi xi) for the azimuth, are taken correctly rounded
+ * (the binary64 value nearest the exact result), so that the result of every
+ * operation of a history has a single definition independent of any libm.
+ */
+#define _GNU_SOURCE
+#include "oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <quadmath.h>
+#include <stdatomic.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as  */
+/* easy as 1, 2, 3", SC'11).  Round: multiply words 0 and 2 by the two     */
+/* round multipliers, swap and xor the high halves with the other words    */
+/* and the key; the key is bumped by the two Weyl constants between rounds. */
+/* ------------------------------------------------------------------------ */
+
+#define PHILOX_M0 0xD2E7470EE14C6C93ULL
+#define PHILOX_M1 0xCA5A826395121157ULL
+#define PHILOX_W0 0x9E3779B97F4A7C15ULL
+#define PHILOX_W1 0xBB67AE8584CAA73BULL
+
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint64_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += PHILOX_W0;
+      k1 += PHILOX_W1;
+    }
+    unsigned __int128 p0 = (unsigned __int128)PHILOX_M0 * c0;
+    unsigned __int128 p1 = (unsigned __int128)PHILOX_M1 * c2;
+    uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+    uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    uint64_t n0 = hi1 ^ c1 ^ k0;
+    uint64_t n1 = lo1;
+    uint64_t n2 = hi0 ^ c3 ^ k1;
+    uint64_t n3 = lo0;
+    c0 = n0;
+    c1 = n1;
+    c2 = n2;
+    c3 = n3;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+/* 64-bit word -> uniform in the open interval (0, 1): the top 52 bits plus
+   one half, times 2^-52.  Every value is exact in binary64 and lies in
+   [2^-53, 1 - 2^-53]. */
+double orc_uniform(uint64_t word) { return ((double)(word >> 12) + 0.5) * 0x1p-52; }
+
+/* A stream is keyed by (seed, tag) and counts draws; draw d reads word d % 4
+   of the block at counter (d / 4, particle id, generation, problem). */
+typedef struct {
+  uint64_t key[2];
+  uint64_t id, gen, prob;
+  uint32_t draw;
+  int64_t blk_idx;
+  uint64_t blk[4];
+} stream_t;
+
+static void stream_init(stream_t* s, uint64_t seed, uint64_t tag, uint64_t id, uint64_t gen,
+                        uint64_t prob) {
+  s->key[0] = seed;
+  s->key[1] = tag;
+  s->id = id;
+  s->gen = gen;
+  s->prob = prob;
+  s->draw = 0;
+  s->blk_idx = -1;
+}
+
+static double next_uniform(stream_t* s) {
+  int64_t b = (int64_t)(s->draw >> 2);
+  if (b != s->blk_idx) {
+    uint64_t ctr[4] = {(uint64_t)b, s->id, s->gen, s->prob};
+    orc_philox4x64_10(ctr, s->key, s->blk);
+    s->blk_idx = b;
+  }
+  uint64_t w = s->blk[s->draw & 3u];
+  s->draw += 1u;
+  return orc_uniform(w);
+}
+
+double orc_stream_uniform(uint64_t seed, uint64_t tag, uint64_t id, uint64_t gen,
+                          uint64_t prob, uint32_t draw) {
+  stream_t s;
+  stream_init(&s, seed, tag, id, gen, prob);
+  s.draw = draw;
+  return next_uniform(&s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* geometry                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Distance along the flight direction to the plane ahead of a particle in
+   the slab lo <= x <= hi: the upper plane when moving up, the lower when
+   moving down, infinity for a direction parallel to both; a negative
+   distance (position a rounding error past the plane) counts as zero. */
+double orc_dist_plane(double x, double lo, double hi, double u) {
+  double t;
+  if (u > 0.0) {
+    t = (hi - x) / u;
+  } else if (u < 0.0) {
+    t = (lo - x) / u;
+  } else {
+    return INFINITY;
+  }
+  return t < 0.0 ? 0.0 : t;
+}
+
+/* Distance to a z-aligned cylinder of radius R centred at the local origin,
+   for a particle at (dx, dy) with direction (u, v, w): the smallest positive
+   root of a t^2 + 2 k t + c = 0, a = u^2 + v^2, k = dx u + dy v,
+   c = dx^2 + dy^2 - R^2.  The side the particle is on is known logically
+   (surface tracking), so c is clamped to that side, and each root is taken
+   in the cancellation-free form. */
+double orc_dist_cylinder(double dx, double dy, double u, double v, double radius, int inside) {
+  double a = u * u + v * v;
+  if (a == 0.0) return INFINITY;
+  double k = dx * u + dy * v;
+  double c = dx * dx + dy * dy - radius * radius;
+  if (inside) {
+    if (c > 0.0) c = 0.0;
+  } else {
+    if (c < 0.0) c = 0.0;
+  }
+  double disc = k * k - a * c;
+  if (inside) {
+    if (k >= 0.0) {
+      double q = -(k + sqrt(disc));
+      return q == 0.0 ? 0.0 : c / q;
+    }
+    return (-k + sqrt(disc)) / a;
+  }
+  if (k >= 0.0 || disc < 0.0) return INFINITY;
+  return c / (-k + sqrt(disc));
+}
+
+/* ------------------------------------------------------------------------ */
+/* correctly rounded transcendental functions                               */
+/* ------------------------------------------------------------------------ */
+
+/* ln(x), correctly rounded.  The 64-bit-significand (x87 extended) logarithm
+   is accurate to about 2^-63 relative, so rounding it to binary64 gives the
+   nearest double unless it falls within 2^-8 of a binary64 ulp of a rounding
+   boundary; there the 113-bit quad-precision logarithm decides. */
+double orc_cr_log(double x) {
+  long double yl = logl((long double)x);
+  double y = (double)yl;
+  double nb = (long double)y < yl ? nextafter(y, INFINITY) : nextafter(y, -INFINITY);
+  long double mid = ((long double)y + (long double)nb) * 0.5L;
+  long double ulp = fabsl((long double)nb - (long double)y);
+  if (fabsl(yl - mid) < ulp * 0x1p-8L) return (double)logq((__float128)x);
+  return y;
+}
+
+/* cos(2 pi t) and sin(2 pi t) for the exact real 2 pi t, 0 <= t < 1,
+   correctly rounded.  The angle pi x, x = 2t, is folded exactly (every
+   subtraction below is exact by Sterbenz's lemma) into pi y with
+   0 <= y <= 1/4, where the quad-precision sine and cosine have a relative
+   error near 2^-112, and the result is rounded once to binary64. */
+void orc_cr_cossin_2pi(double t, double* c, double* s) {
+  double x = 2.0 * t;
+  int neg_s = 0, neg_c = 0, swap = 0;
+  if (x >= 1.0) { /* sin(pi (x + 1)) = -sin(pi x), cos likewise */
+    x = x - 1.0;
+    neg_s = !neg_s;
+    neg_c = !neg_c;
+  }
+  if (x > 0.5) { /* sin(pi (1 - x)) = sin(pi x), cos(pi (1 - x)) = -cos(pi x) */
+    x = 1.0 - x;
+    neg_c = !neg_c;
+  }
+  if (x > 0.25) { /* sin(pi x) = cos(pi (1/2 - x)) and the reverse */
+    x = 0.5 - x;
+    swap = 1;
+  }
+  __float128 a = M_PIq * (__float128)x;
+  double sv = (double)sinq(a);
+  double cv = (double)cosq(a);
+  if (swap) {
+    double tmp = sv;
+    sv = cv;
+    cv = tmp;
+  }
+  *s = neg_s ? -sv : sv;
+  *c = neg_c ? -cv : cv;
+}
+
+/* Isotropic direction: polar cosine w = 2 xi_mu - 1 about z, azimuth
+   2 pi xi_phi. */
+void orc_isotropic(double xi_mu, double xi_phi, double out[3]) {
+  double w = 2.0 * xi_mu - 1.0;
+  double s2 = 1.0 - w * w;
+  double s = sqrt(s2 > 0.0 ? s2 : 0.0);
+  double c, sn;
+  orc_cr_cossin_2pi(xi_phi, &c, &sn);
+  out[0] = s * c;
+  out[1] = s * sn;
+  out[2] = w;
+}
+
+/* Discrete sampling: cumulate the weights in index order; the sample is the
+   first index j with xi * total < cum_j; if rounding leaves none, the last
+   index with a nonzero weight. */
+int orc_sample_cdf(double xi, const double* weights, int n) {
+  double total = 0.0;
+  for (int j = 0; j < n; ++j) total += weights[j];
+  double target = xi * total;
+  double cum = 0.0;
+  for (int j = 0; j < n; ++j) {
+    cum += weights[j];
+    if (target < cum) return j;
+  }
+  for (int j = n - 1; j >= 0; --j)
+    if (weights[j] > 0.0) return j;
+  return n - 1;
+}
+
+/* Systematic combing of M banked sites down (or up) to N: site i of the new
+   source is bank entry floor((i + xi0) M / N), capped at M - 1. */
+void orc_comb(int64_t n, int64_t m, double xi0, int64_t* idx) {
+  for (int64_t i = 0; i < n; ++i) {
+    double t = ((double)i + xi0) * (double)m / (double)n;
+    int64_t k = (int64_t)floor(t);
+    if (k > m - 1) k = m - 1;
+    idx[i] = k;
+  }
+}
+
+/* Shannon entropy (base 2) of the bank over the mesh bins. */
+double orc_entropy(const int64_t* counts, int64_t n_bins, int64_t m) {
+  double h = 0.0;
+  if (m <= 0) return 0.0;
+  for (int64_t b = 0; b < n_bins; ++b) {
+    if (counts[b] > 0) {
+      double p = (double)counts[b] / (double)m;
+      h -= p * log2(p);
+    }
+  }
+  return h;
+}
+
+/* Neumaier's compensated summation. */
+typedef struct {
+  double s, c;
+} nsum_t;
+
+static void nadd(nsum_t* a, double x) {
+  double t = a->s + x;
+  if (fabs(a->s) >= fabs(x))
+    a->c += (a->s - t) + x;
+  else
+    a->c += (x - t) + a->s;
+  a->s = t;
+}
+
+static double nval(const nsum_t* a) { return a->s + a->c; }
+
+double orc_neumaier(const double* v, int64_t n) {
+  nsum_t a = {0.0, 0.0};
+  for (int64_t i = 0; i < n; ++i) nadd(&a, v[i]);
+  return nval(&a);
+}
+
+/* ------------------------------------------------------------------------ */
+/* the run                                                                  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  double* x;
+  double* y;
+  int32_t* g;
+  int64_t n, cap;
+} sites_t;
+
+static int sites_push(sites_t* s, double x, double y, int32_t g) {
+  if (s->n == s->cap) {
+    int64_t nc = s->cap ? 2 * s->cap : 1024;
+    double* nx = realloc(s->x, (size_t)nc * sizeof(double));
+    if (!nx) return -1;
+    s->x = nx;
+    double* ny = realloc(s->y, (size_t)nc * sizeof(double));
+    if (!ny) return -1;
+    s->y = ny;
+    int32_t* ng = realloc(s->g, (size_t)nc * sizeof(int32_t));
+    if (!ng) return -1;
+    s->g = ng;
+    s->cap = nc;
+  }
+  s->x[s->n] = x;
+  s->y[s->n] = y;
+  s->g[s->n] = g;
+  s->n += 1;
+  return 0;
+}
+
+static void sites_free(sites_t* s) {
+  free(s->x);
+  free(s->y);
+  free(s->g);
+  memset(s, 0, sizeof(*s));
+}
+
+/* Accumulators of one fixed chunk of histories.  Chunks are summed in chunk
+   order, so results do not depend on the number of threads. */
+typedef struct {
+  nsum_t k[3];
+  nsum_t* flux;
+  nsum_t* prod;
+  int64_t counts[ORC_NCOUNT];
+  sites_t sites;
+  int err;
+} chunk_t;
+
+typedef struct {
+  const orc_problem* p;
+  int64_t n_bins;
+  int32_t mr1;                 /* max_rings + 1 */
+  int32_t* fissile;            /* [n_mat] */
+  double* sig_s_tot;           /* [n_mat][n_grp], summed in index order */
+  /* current generation */
+  int gen;
+  double k_used;
+  const double* src_x;
+  const double* src_y;
+  const int32_t* src_g;
+  const double* src_dir;       /* [N][3] or NULL */
+  chunk_t* chunks;
+  int64_t n_chunks, chunk_size;
+  atomic_long next_chunk;
+  orc_record* records;         /* this generation's records or NULL */
+} ctx_t;
+
+static void locate(const orc_problem* p, double x, double y, int* ci, int* cj, int* cr) {
+  int i = (int)floor((x - p->x0) / p->pitch);
+  int j = (int)floor((y - p->y0) / p->pitch);
+  if (i < 0) i = 0;
+  if (i > p->nx - 1) i = p->nx - 1;
+  if (j < 0) j = 0;
+  if (j > p->ny - 1) j = p->ny - 1;
+  int un = p->pin_map[j * p->nx + i];
+  double dx = x - (p->x0 + ((double)i + 0.5) * p->pitch);
+  double dy = y - (p->y0 + ((double)j + 0.5) * p->pitch);
+  double rr = dx * dx + dy * dy;
+  int nr = p->n_rings[un];
+  int r = nr;
+  for (int k = 0; k < nr; ++k) {
+    double rad = p->radii[un * p->max_rings + k];
+    if (rr < rad * rad) {
+      r = k;
+      break;
+    }
+  }
+  *ci = i;
+  *cj = j;
+  *cr = r;
+}
+
+static int material_at(const ctx_t* C, int i, int j, int r) {
+  const orc_problem* p = C->p;
+  int un = p->pin_map[j * p->nx + i];
+  return p->mats[un * C->mr1 + r];
+}
+
+/* Source site of particle id in batch gen: rejection in the lattice's
+   bounding box until the point lies in a fissile material, then a group
+   from that material's fission spectrum. */
+static int sample_source(const ctx_t* C, int64_t id, int gen, double* sx, double* sy,
+                         int32_t* sg) {
+  const orc_problem* p = C->p;
+  stream_t s;
+  stream_init(&s, p->seed, ORC_TAG_SRC, (uint64_t)id, (uint64_t)gen, p->problem_id);
+  double width = (double)p->nx * p->pitch;
+  double height = (double)p->ny * p->pitch;
+  for (int t = 0; t < 10000; ++t) {
+    double xa = next_uniform(&s);
+    double ya = next_uniform(&s);
+    double x = p->x0 + xa * width;
+    double y = p->y0 + ya * height;
+    int i, j, r;
+    locate(p, x, y, &i, &j, &r);
+    int m = material_at(C, i, j, r);
+    if (C->fissile[m]) {
+      double xi = next_uniform(&s);
+      *sx = x;
+      *sy = y;
+      *sg = orc_sample_cdf(xi, p->chi + (int64_t)m * p->n_grp, p->n_grp);
+      return 0;
+    }
+  }
+  return -1;
+}
+
+static void run_history(ctx_t* C, int64_t id, chunk_t* ch) {
+  const orc_problem* p = C->p;
+  const int G = p->n_grp;
+  stream_t rs;
+  stream_init(&rs, p->seed, ORC_TAG_TRANSPORT, (uint64_t)id, (uint64_t)C->gen, p->problem_id);
+
+  double x = C->src_x[id], y = C->src_y[id];
+  int g = C->src_g[id];
+  int i, j, r;
+  locate(p, x, y, &i, &j, &r);
+  double dir[3];
+  if (C->src_dir) {
+    dir[0] = C->src_dir[3 * id + 0];
+    dir[1] = C->src_dir[3 * id + 1];
+    dir[2] = C->src_dir[3 * id + 2];
+  } else {
+    double xm = next_uniform(&rs);
+    double xp = next_uniform(&rs);
+    orc_isotropic(xm, xp, dir);
+  }
+  double u = dir[0], v = dir[1], w = dir[2];
+  (void)w; /* z-invariant geometry: w only fixes the in-plane speed sqrt(1-w^2) */
+
+  int32_t n_seg = 0, n_col = 0, n_cross = 0, n_refl = 0, n_sites = 0;
+  int fate = ORC_ALIVE;
+  double tl_sum = 0.0, kcol_sum = 0.0;
+
+  for (;;) {
+    if (n_seg >= p->max_events) {
+      fate = ORC_KILLED;
+      break;
+    }
+    int c = j * p->nx + i;
+    int un = p->pin_map[c];
+    int nr = p->n_rings[un];
+    int m = p->mats[un * C->mr1 + r];
+    double st = p->sig_t[m * G + g];
+    double nusf = p->nu_sig_f[m * G + g];
+
+    /* distance to collision: exponential with mean 1 / sig_t */
+    double xi = next_uniform(&rs);
+    double d_col = -orc_cr_log(xi) / st;
+
+    /* distance to boundary: the lattice cell's planes ahead and the rings
+       bounding the current region */
+    double xlo = p->x0 + (double)i * p->pitch, xhi = p->x0 + (double)(i + 1) * p->pitch;
+    double ylo = p->y0 + (double)j * p->pitch, yhi = p->y0 + (double)(j + 1) * p->pitch;
+    double tx = orc_dist_plane(x, xlo, xhi, u);
+    double ty = orc_dist_plane(y, ylo, yhi, v);
+    double cx = p->x0 + ((double)i + 0.5) * p->pitch;
+    double cy = p->y0 + ((double)j + 0.5) * p->pitch;
+    double dx = x - cx, dy = y - cy;
+    double t_out = INFINITY, t_in = INFINITY;
+    if (r < nr) t_out = orc_dist_cylinder(dx, dy, u, v, p->radii[un * p->max_rings + r], 1);
+    if (r > 0) t_in = orc_dist_cylinder(dx, dy, u, v, p->radii[un * p->max_rings + r - 1], 0);
+    double d_bnd = tx;
+    if (ty < d_bnd) d_bnd = ty;
+    if (t_out < d_bnd) d_bnd = t_out;
+    if (t_in < d_bnd) d_bnd = t_in;
+
+    n_seg += 1;
+    int collide = d_col < d_bnd;
+    double d = collide ? d_col : d_bnd;
+    x = x + d * u;
+    y = y + d * v;
+
+    /* track-length tallies: flux and nu-fission production per bin */
+    int64_t bin = ((int64_t)c * C->mr1 + r) * G + g;
+    nadd(&ch->flux[bin], d);
+    nadd(&ch->prod[bin], d * nusf);
+    nadd(&ch->k[1], d * nusf);
+    tl_sum += d;
+
+    if (collide) {
+      n_col += 1;
+      double kc = nusf / st;
+      kcol_sum += kc;
+      nadd(&ch->k[0], kc);
+      /* fission: bank floor(nu_sig_f / (sig_t k) + xi) sites at the
+         collision point, each with a group from the fission spectrum */
+      if (!p->fixed_source && nusf > 0.0) {
+        double xf = next_uniform(&rs);
+        int nf = (int)floor(nusf / (st * C->k_used) + xf);
+        for (int s = 0; s < nf; ++s) {
+          double xs = next_uniform(&rs);
+          int gs = orc_sample_cdf(xs, p->chi + (int64_t)m * G, G);
+          if (sites_push(&ch->sites, x, y, gs)) ch->err = ORC_ENOMEM;
+          n_sites += 1;
+        }
+      }
+      /* scatter with probability sig_s / sig_t, else absorption */
+      double xr = next_uniform(&rs);
+      double sst = C->sig_s_tot[m * G + g];
+      if (xr * st < sst) {
+        double xg = next_uniform(&rs);
+        g = orc_sample_cdf(xg, p->sig_s + ((int64_t)m * G + g) * G, G);
+        double xm = next_uniform(&rs);
+        double xp = next_uniform(&rs);
+        orc_isotropic(xm, xp, dir);
+        u = dir[0];
+        v = dir[1];
+        w = dir[2];
+        ch->counts[ORC_C_SCAT] += 1;
+      } else {
+        nadd(&ch->k[2], nusf > 0.0 ? nusf / (st - sst) : 0.0);
+        fate = ORC_ABSORBED;
+        break;
+      }
+    } else {
+      n_cross += 1;
+      int hit_x = tx == d_bnd;
+      int hit_y = ty == d_bnd;
+      if (hit_x || hit_y) {
+        /* lattice boundary: neighbour cell, or an outer side of the lattice */
+        int out_x = hit_x && (u > 0.0 ? i == p->nx - 1 : i == 0);
+        int out_y = hit_y && (v > 0.0 ? j == p->ny - 1 : j == 0);
+        int side_x = u > 0.0 ? 1 : 0;
+        int side_y = v > 0.0 ? 3 : 2;
+        if ((out_x && p->bc[side_x] == ORC_VACUUM) || (out_y && p->bc[side_y] == ORC_VACUUM)) {
+          fate = ORC_LEAKED;
+          break;
+        }
+        int refl = 0;
+        if (hit_x) {
+          if (out_x) {
+            u = -u;
+            refl = 1;
+          } else {
+            i += u > 0.0 ? 1 : -1;
+          }
+        }
+        if (hit_y) {
+          if (out_y) {
+            v = -v;
+            refl = 1;
+          } else {
+            j += v > 0.0 ? 1 : -1;
+          }
+        }
+        if (refl) n_refl += 1;
+        /* a lattice face lies outside every ring */
+        r = p->n_rings[p->pin_map[j * p->nx + i]];
+      } else if (t_out == d_bnd) {
+        r += 1;
+      } else {
+        r -= 1;
+      }
+    }
+  }
+
+  ch->counts[ORC_C_SEG] += n_seg;
+  ch->counts[ORC_C_COL] += n_col;
+  ch->counts[ORC_C_CROSS] += n_cross;
+  ch->counts[ORC_C_REFL] += n_refl;
+  ch->counts[ORC_C_SITES] += n_sites;
+  if (fate == ORC_LEAKED) ch->counts[ORC_C_LEAK] += 1;
+  if (fate == ORC_ABSORBED) ch->counts[ORC_C_ABS] += 1;
+  if (fate == ORC_KILLED) ch->counts[ORC_C_KILLED] += 1;
+  if (C->records) {
+    orc_record* rec = &C->records[id];
+    rec->n_seg = n_seg;
+    rec->n_col = n_col;
+    rec->n_cross = n_cross;
+    rec->n_refl = n_refl;
+    rec->fate = fate;
+    rec->n_sites = n_sites;
+    rec->g_final = g;
+    rec->ctr_final = rs.draw;
+    rec->tl_sum = tl_sum;
+    rec->kcol_sum = kcol_sum;
+    rec->x_final = x;
+    rec->y_final = y;
+  }
+}
+
+static void* worker(void* arg) {
+  ctx_t* C = (ctx_t*)arg;
+  const int64_t n = C->p->n_per_gen;
+  for (;;) {
+    int64_t k = atomic_fetch_add(&C->next_chunk, 1);
+    if (k >= C->n_chunks) break;
+    chunk_t* ch = &C->chunks[k];
+    int64_t lo = k * C->chunk_size;
+    int64_t hi = lo + C->chunk_size;
+    if (hi > n) hi = n;
+    for (int64_t id = lo; id < hi; ++id) run_history(C, id, ch);
+  }
+  return NULL;
+}
+
+static void chunk_reset(chunk_t* ch, int64_t n_bins) {
+  memset(ch->k, 0, sizeof(ch->k));
+  memset(ch->flux, 0, (size_t)n_bins * sizeof(nsum_t));
+  memset(ch->prod, 0, (size_t)n_bins * sizeof(nsum_t));
+  memset(ch->counts, 0, sizeof(ch->counts));
+  ch->sites.n = 0;
+  ch->err = 0;
+}
+
+int64_t orc_n_bins(const orc_problem* p) {
+  return (int64_t)p->nx * p->ny * (p->max_rings + 1) * p->n_grp;
+}
+
+static int fail(orc_output* out, int code, const char* msg) {
+  snprintf(out->errmsg, sizeof(out->errmsg), "%s", msg);
+  return code;
+}
+
+static int validate(const orc_problem* p, orc_output* out) {
+  if (p->nx < 1 || p->ny < 1 || !(p->pitch > 0.0)) return fail(out, ORC_EINVAL, "bad lattice");
+  if (p->n_univ < 1 || p->max_rings < 1 || p->n_mat < 1 || p->n_grp < 1)
+    return fail(out, ORC_EINVAL, "bad sizes");
+  if (p->n_per_gen < 1 || p->n_gen < 1 || p->n_inactive < 0 || p->n_inactive >= p->n_gen)
+    return fail(out, ORC_EINVAL, "bad run sizes");
+  for (int k = 0; k < p->nx * p->ny; ++k)
+    if (p->pin_map[k] < 0 || p->pin_map[k] >= p->n_univ) return fail(out, ORC_EINVAL, "pin map");
+  for (int u = 0; u < p->n_univ; ++u) {
+    int nr = p->n_rings[u];
+    if (nr < 0 || nr > p->max_rings) return fail(out, ORC_EINVAL, "ring count");
+    for (int k = 0; k <= nr; ++k) {
+      int m = p->mats[u * (p->max_rings + 1) + k];
+      if (m < 0 || m >= p->n_mat) return fail(out, ORC_EINVAL, "ring material");
+    }
+    double prev = 0.0;
+    for (int k = 0; k < nr; ++k) {
+      double rad = p->radii[u * p->max_rings + k];
+      if (!(rad > prev) || !(rad < 0.5 * p->pitch)) return fail(out, ORC_EINVAL, "ring radius");
+      prev = rad;
+    }
+  }
+  for (int64_t k = 0; k < (int64_t)p->n_mat * p->n_grp; ++k) {
+    if (!(p->sig_t[k] > 0.0) || !(p->nu_sig_f[k] >= 0.0) || !(p->chi[k] >= 0.0))
+      return fail(out, ORC_EINVAL, "cross section sign");
+  }
+  for (int64_t k = 0; k < (int64_t)p->n_mat * p->n_grp * p->n_grp; ++k)
+    if (!(p->sig_s[k] >= 0.0)) return fail(out, ORC_EINVAL, "scatter sign");
+  return ORC_OK;
+}
+
+int orc_run(const orc_problem* p, orc_output* out) {
+  out->errmsg[0] = 0;
+  int rc = validate(p, out);
+  if (rc) return rc;
+  const int G = p->n_grp;
+  const int64_t N = p->n_per_gen;
+
+  ctx_t C;
+  memset(&C, 0, sizeof(C));
+  C.p = p;
+  C.n_bins = orc_n_bins(p);
+  C.mr1 = p->max_rings + 1;
+  C.fissile = calloc((size_t)p->n_mat, sizeof(int32_t));
+  C.sig_s_tot = calloc((size_t)p->n_mat * G, sizeof(double));
+  for (int m = 0; m < p->n_mat; ++m) {
+    for (int g = 0; g < G; ++g) {
+      if (p->nu_sig_f[m * G + g] > 0.0) C.fissile[m] = 1;
+      double s = 0.0;
+      for (int h = 0; h < G; ++h) s += p->sig_s[((int64_t)m * G + g) * G + h];
+      C.sig_s_tot[m * G + g] = s;
+      if (s > p->sig_t[m * G + g]) {
+        free(C.fissile);
+        free(C.sig_s_tot);
+        return fail(out, ORC_EINVAL, "sig_s exceeds sig_t");
+      }
+    }
+  }
+
+  /* fixed chunking: at most 256 chunks of at least 512 histories */
+  C.chunk_size = 512;
+  if ((N + C.chunk_size - 1) / C.chunk_size > 256) C.chunk_size = (N + 255) / 256;
+  C.n_chunks = (N + C.chunk_size - 1) / C.chunk_size;
+  C.chunks = calloc((size_t)C.n_chunks, sizeof(chunk_t));
+  for (int64_t k = 0; k < C.n_chunks; ++k) {
+    C.chunks[k].flux = calloc((size_t)C.n_bins, sizeof(nsum_t));
+    C.chunks[k].prod = calloc((size_t)C.n_bins, sizeof(nsum_t));
+  }
+
+  double* src_x = malloc((size_t)N * sizeof(double));
+  double* src_y = malloc((size_t)N * sizeof(double));
+  int32_t* src_g = malloc((size_t)N * sizeof(int32_t));
+  double* src_dir = NULL;
+  double* gflux = malloc((size_t)p->n_gen * C.n_bins * sizeof(double));
+  double* gprod = malloc((size_t)p->n_gen * C.n_bins * sizeof(double));
+  sites_t bank = {0};
+  int64_t* ent_counts = calloc((size_t)p->ent_nx * p->ent_ny, sizeof(int64_t));
+  int64_t* comb_idx = malloc((size_t)N * sizeof(int64_t));
+  if (!src_x || !src_y || !src_g || !gflux || !gprod || !ent_counts || !comb_idx) {
+    rc = fail(out, ORC_ENOMEM, "out of host memory");
+    goto done;
+  }
+
+  double k_used = 1.0;
+  int n_threads = p->n_threads > 0 ? p->n_threads : 1;
+  for (int gen = 0; gen < p->n_gen; ++gen) {
+    /* source of this generation */
+    if (gen == 0 || p->fixed_source) {
+      free(src_dir);
+      src_dir = NULL;
+      if (gen == 0 && p->ext_state) {
+        src_dir = malloc((size_t)N * 3 * sizeof(double));
+        for (int64_t id = 0; id < N; ++id) {
+          src_x[id] = p->ext_state[6 * id + 0];
+          src_y[id] = p->ext_state[6 * id + 1];
+          src_dir[3 * id + 0] = p->ext_state[6 * id + 2];
+          src_dir[3 * id + 1] = p->ext_state[6 * id + 3];
+          src_dir[3 * id + 2] = p->ext_state[6 * id + 4];
+          src_g[id] = (int32_t)p->ext_state[6 * id + 5];
+        }
+      } else {
+        for (int64_t id = 0; id < N; ++id) {
+          if (sample_source(&C, id, gen, &src_x[id], &src_y[id], &src_g[id])) {
+            rc = fail(out, ORC_EINVAL, "source rejection sampling found no fissile point");
+            goto done;
+          }
+        }
+      }
+    }
+
+    C.gen = gen;
+    C.k_used = k_used;
+    C.src_x = src_x;
+    C.src_y = src_y;
+    C.src_g = src_g;
+    C.src_dir = src_dir;
+    C.records = out->records ? out->records + (int64_t)gen * N : NULL;
+    for (int64_t k = 0; k < C.n_chunks; ++k) chunk_reset(&C.chunks[k], C.n_bins);
+    atomic_store(&C.next_chunk, 0);
+    if (n_threads == 1) {
+      worker(&C);
+    } else {
+      pthread_t th[256];
+      int nt = n_threads > 256 ? 256 : n_threads;
+      for (int t = 0; t < nt; ++t) pthread_create(&th[t], NULL, worker, &C);
+      for (int t = 0; t < nt; ++t) pthread_join(th[t], NULL);
+    }
+
+    /* combine chunks in chunk order */
+    nsum_t ks[3] = {{0, 0}, {0, 0}, {0, 0}};
+    int64_t counts[ORC_NCOUNT] = {0};
+    bank.n = 0;
+    for (int64_t k = 0; k < C.n_chunks; ++k) {
+      chunk_t* ch = &C.chunks[k];
+      if (ch->err) {
+        rc = fail(out, ch->err, "out of host memory in the fission bank");
+        goto done;
+      }
+      for (int e = 0; e < 3; ++e) {
+        nadd(&ks[e], ch->k[e].s);
+        nadd(&ks[e], ch->k[e].c);
+      }
+      for (int e = 0; e < ORC_NCOUNT; ++e) counts[e] += ch->counts[e];
+      for (int64_t s = 0; s < ch->sites.n; ++s)
+        if (sites_push(&bank, ch->sites.x[s], ch->sites.y[s], ch->sites.g[s])) {
+          rc = fail(out, ORC_ENOMEM, "out of host memory in the bank");
+          goto done;
+        }
+    }
+    for (int64_t b = 0; b < C.n_bins; ++b) {
+      nsum_t fs = {0, 0}, ps = {0, 0};
+      for (int64_t k = 0; k < C.n_chunks; ++k) {
+        nadd(&fs, C.chunks[k].flux[b].s);
+        nadd(&fs, C.chunks[k].flux[b].c);
+        nadd(&ps, C.chunks[k].prod[b].s);
+        nadd(&ps, C.chunks[k].prod[b].c);
+      }
+      gflux[(int64_t)gen * C.n_bins + b] = nval(&fs) / (double)N;
+      gprod[(int64_t)gen * C.n_bins + b] = nval(&ps) / (double)N;
+    }
+    for (int e = 0; e < 3; ++e) out->gen_k[gen * 3 + e] = nval(&ks[e]) / (double)N;
+    for (int e = 0; e < ORC_NCOUNT; ++e) out->gen_counts[(int64_t)gen * ORC_NCOUNT + e] = counts[e];
+
+    /* the canonical bank is the chunk concatenation: histories in id order,
+       each history's sites in the order they were banked */
+    const int64_t M = bank.n;
+    const int64_t n_ent = (int64_t)p->ent_nx * p->ent_ny;
+    memset(ent_counts, 0, (size_t)n_ent * sizeof(int64_t));
+    double width = (double)p->nx * p->pitch;
+    double height = (double)p->ny * p->pitch;
+    for (int64_t s = 0; s < M; ++s) {
+      int bx = (int)floor((bank.x[s] - p->x0) / width * (double)p->ent_nx);
+      int by = (int)floor((bank.y[s] - p->y0) / height * (double)p->ent_ny);
+      if (bx < 0) bx = 0;
+      if (bx > p->ent_nx - 1) bx = p->ent_nx - 1;
+      if (by < 0) by = 0;
+      if (by > p->ent_ny - 1) by = p->ent_ny - 1;
+      ent_counts[(int64_t)by * p->ent_nx + bx] += 1;
+    }
+    out->gen_entropy[gen] = orc_entropy(ent_counts, n_ent, M);
+
+    if (!p->fixed_source) {
+      if (M == 0) {
+        rc = fail(out, ORC_EEXTINCT, "fission bank is empty");
+        goto done;
+      }
+      stream_t rs;
+      stream_init(&rs, p->seed, ORC_TAG_RESAMPLE, 0, (uint64_t)gen, p->problem_id);
+      double xi0 = next_uniform(&rs);
+      orc_comb(N, M, xi0, comb_idx);
+      for (int64_t id = 0; id < N; ++id) {
+        src_x[id] = bank.x[comb_idx[id]];
+        src_y[id] = bank.y[comb_idx[id]];
+        src_g[id] = bank.g[comb_idx[id]];
+      }
+      free(src_dir);
+      src_dir = NULL;
+      k_used = out->gen_k[gen * 3 + 0];
+    }
+  }
+
+  /* active-generation mean and standard deviation of the mean */
+  {
+    const int A = p->n_gen - p->n_inactive;
+    for (int e = 0; e < 3; ++e) {
+      double s = 0.0;
+      for (int g = p->n_inactive; g < p->n_gen; ++g) s += out->gen_k[g * 3 + e];
+      double mean = s / (double)A;
+      double v = 0.0;
+      for (int g = p->n_inactive; g < p->n_gen; ++g) {
+        double d = out->gen_k[g * 3 + e] - mean;
+        v += d * d;
+      }
+      out->k_mean[e] = mean;
+      out->k_sigma[e] = A > 1 ? sqrt(v / ((double)A * (double)(A - 1))) : 0.0;
+    }
+    for (int t = 0; t < 2; ++t) {
+      const double* gv = t == 0 ? gflux : gprod;
+      double* mo = t == 0 ? out->flux_mean : out->prod_mean;
+      double* so = t == 0 ? out->flux_sigma : out->prod_sigma;
+      if (!mo) continue;
+      for (int64_t b = 0; b < C.n_bins; ++b) {
+        double s = 0.0;
+        for (int g = p->n_inactive; g < p->n_gen; ++g) s += gv[(int64_t)g * C.n_bins + b];
+        double mean = s / (double)A;
+        double v = 0.0;
+        for (int g = p->n_inactive; g < p->n_gen; ++g) {
+          double d = gv[(int64_t)g * C.n_bins + b] - mean;
+          v += d * d;
+        }
+        mo[b] = mean;
+        if (so) so[b] = A > 1 ? sqrt(v / ((double)A * (double)(A - 1))) : 0.0;
+      }
+    }
+    if (out->gen_flux) memcpy(out->gen_flux, gflux, (size_t)p->n_gen * C.n_bins * sizeof(double));
+    if (out->gen_prod) memcpy(out->gen_prod, gprod, (size_t)p->n_gen * C.n_bins * sizeof(double));
+    out->bank_len = bank.n;
+    if (out->bank) {
+      int64_t nb = bank.n < out->bank_cap ? bank.n : out->bank_cap;
+      for (int64_t s = 0; s < nb; ++s) {
+        out->bank[3 * s + 0] = bank.x[s];
+        out->bank[3 * s + 1] = bank.y[s];
+        out->bank[3 * s + 2] = (double)bank.g[s];
+      }
+    }
+  }
+
+done:
+  for (int64_t k = 0; k < C.n_chunks; ++k) {
+    free(C.chunks[k].flux);
+    free(C.chunks[k].prod);
+    sites_free(&C.chunks[k].sites);
+  }
+  free(C.chunks);
+  free(C.fissile);
+  free(C.sig_s_tot);
+  free(src_x);
+  free(src_y);
+  free(src_g);
+  free(src_dir);
+  free(gflux);
+  free(gprod);
+  free(ent_counts);
+  free(comb_idx);
+  sites_free(&bank);
+  return rc;
+}

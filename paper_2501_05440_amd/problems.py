@@ -1,0 +1,257 @@
+"""Seeded synthetic problem generators.
+
+This module builds the inputs that both the HIP transport path and the CPU
+oracle consume: lattice geometry, multigroup cross sections and run
+parameters.  It holds none of the transport arithmetic (no sampling, no
+tracking, no estimators); it only draws problem data from numpy generators
+with fixed seeds.
+
+The paper's workloads (a 3D C5G7 multigroup k-eigenvalue benchmark and an
+OpenMC-data continuous-energy pin cell; Sec. 4) need data that is not
+available here.  The problems below are synthetic stand-ins with the same
+shapes: a 7-group pin cell, a 17x17 lattice of such pins, a batch of small
+fixed-source pin cells, plus closed-form test problems (homogeneous media,
+a pure-absorber slab).
+
+A problem is a plain dict:
+
+    geometry:  nx, ny, pitch, x0, y0, bc[4] (xmin, xmax, ymin, ymax;
+               0 = vacuum, 1 = reflective), n_rings[n_univ],
+               radii[n_univ, max_rings], mats[n_univ, max_rings + 1],
+               pin_map[ny, nx]
+    xs:        sig_t[M, G], sig_s[M, G, G] (row g = scatter out of group g),
+               nu_sig_f[M, G], chi[M, G]
+    run:       seed, n_per_gen, n_gen, n_inactive, fixed_source, problem_id,
+               ent_nx, ent_ny, max_events
+"""
+from __future__ import annotations
+
+import hashlib
+import math
+
+import numpy as np
+
+VACUUM = 0
+REFLECT = 1
+
+PIN_PITCH = 1.26
+PIN_RADIUS = 0.54
+N_GROUPS = 7
+
+
+# ---------------------------------------------------------------------------
+# cross sections
+# ---------------------------------------------------------------------------
+
+def _removal_matrix(sig_t, sig_s):
+    """diag(sig_t) - sig_s^T: the infinite-medium group balance operator."""
+    return np.diag(sig_t) - sig_s.T
+
+
+def mg_kinf(sig_t, sig_s, nu_sig_f, chi):
+    """Infinite-medium multiplication of one material, nu_sig_f^T A^-1 chi.
+
+    Used here only to scale generated fuels to a target k_inf; it is the
+    dominant (and only nonzero) eigenvalue of the rank-one fission operator.
+    """
+    a = _removal_matrix(np.asarray(sig_t, float), np.asarray(sig_s, float))
+    return float(np.asarray(nu_sig_f, float) @ np.linalg.solve(a, np.asarray(chi, float)))
+
+
+def mg_material(rng, n_groups=N_GROUPS, fissile=True, k_target=1.2):
+    """One synthetic multigroup material.
+
+    total XS ~ U[0.2, 1.5]/cm per group; scattering ratio ~ U[0.5, 0.95];
+    the out-scatter of group g is spread over groups g' >= g with U[0,1]
+    weights (last group: self-scatter only).  Fissile materials get a fission
+    spectrum in the first three groups and nu_sig_f = r_g * sig_a_g with
+    r_g ~ U[0.5, 1.5], rescaled so that the material's own k_inf equals
+    k_target; draws are repeated while any nu_sig_f_g exceeds 2.5 sig_a_g.
+    """
+    g_n = n_groups
+    sig_t = rng.uniform(0.2, 1.5, g_n)
+    ratio = rng.uniform(0.5, 0.95, g_n)
+    sig_s = np.zeros((g_n, g_n))
+    for g in range(g_n):
+        if g == g_n - 1:
+            w = np.ones(1)
+        else:
+            w = rng.uniform(0.0, 1.0, g_n - g)
+        sig_s[g, g:] = ratio[g] * sig_t[g] * w / w.sum()
+    sig_a = sig_t - sig_s.sum(axis=1)
+    chi = np.zeros(g_n)
+    nu_sig_f = np.zeros(g_n)
+    if fissile:
+        n_chi = min(3, g_n)
+        chi[:n_chi] = rng.uniform(0.0, 1.0, n_chi)
+        chi /= chi.sum()
+        for _ in range(1000):
+            r = rng.uniform(0.5, 1.5, g_n)
+            nu_sig_f = r * sig_a
+            nu_sig_f *= k_target / mg_kinf(sig_t, sig_s, nu_sig_f, chi)
+            if np.all(nu_sig_f <= 2.5 * sig_a):
+                break
+        else:  # pragma: no cover - the bound is loose enough in practice
+            raise RuntimeError("could not draw a fissile material within bounds")
+    return dict(sig_t=sig_t, sig_s=sig_s, nu_sig_f=nu_sig_f, chi=chi)
+
+
+def stack_materials(mats):
+    return dict(
+        sig_t=np.ascontiguousarray(np.stack([m["sig_t"] for m in mats]), dtype=np.float64),
+        sig_s=np.ascontiguousarray(np.stack([m["sig_s"] for m in mats]), dtype=np.float64),
+        nu_sig_f=np.ascontiguousarray(np.stack([m["nu_sig_f"] for m in mats]), dtype=np.float64),
+        chi=np.ascontiguousarray(np.stack([m["chi"] for m in mats]), dtype=np.float64),
+    )
+
+
+# ---------------------------------------------------------------------------
+# geometry
+# ---------------------------------------------------------------------------
+
+def lattice_geometry(nx, ny, pitch, universes, pin_map, bc, x0=None, y0=None):
+    """Rectangular lattice of pin universes.
+
+    universes: list of (radii, mats) with len(mats) == len(radii) + 1; region
+    r of a pin is inside ring r (r < len(radii)) or outside every ring.
+    The lattice is centred on the origin unless x0/y0 are given.
+    """
+    max_rings = max(1, max(len(r) for r, _ in universes))
+    n_univ = len(universes)
+    n_rings = np.zeros(n_univ, np.int32)
+    radii = np.zeros((n_univ, max_rings), np.float64)
+    mats = np.full((n_univ, max_rings + 1), -1, np.int32)
+    for u, (rr, mm) in enumerate(universes):
+        assert len(mm) == len(rr) + 1
+        n_rings[u] = len(rr)
+        radii[u, : len(rr)] = rr
+        mats[u, : len(mm)] = mm
+        mats[u, len(mm):] = mm[-1]
+    pin_map = np.ascontiguousarray(np.asarray(pin_map, np.int32).reshape(ny, nx))
+    if x0 is None:
+        x0 = -0.5 * nx * pitch
+    if y0 is None:
+        y0 = -0.5 * ny * pitch
+    return dict(nx=int(nx), ny=int(ny), pitch=float(pitch), x0=float(x0), y0=float(y0),
+                bc=[int(b) for b in bc], n_rings=n_rings, radii=radii, mats=mats,
+                pin_map=pin_map)
+
+
+def run_params(seed, n_per_gen, n_gen, n_inactive, fixed_source=False, problem_id=0,
+               ent=(8, 8), max_events=100000):
+    return dict(seed=int(seed), n_per_gen=int(n_per_gen), n_gen=int(n_gen),
+                n_inactive=int(n_inactive), fixed_source=bool(fixed_source),
+                problem_id=int(problem_id), ent_nx=int(ent[0]), ent_ny=int(ent[1]),
+                max_events=int(max_events))
+
+
+def make_problem(name, geometry, xs, run):
+    return dict(name=name, geometry=geometry, xs=xs, run=run)
+
+
+# ---------------------------------------------------------------------------
+# the workloads
+# ---------------------------------------------------------------------------
+
+def pin_cell(n_per_gen=10_000, n_gen=30, n_inactive=10, seed=1, xs_seed=1000):
+    """7-group pin cell: r = 0.54 cm fuel pin in a 1.26 cm reflective square."""
+    rng = np.random.default_rng(xs_seed)
+    fuel = mg_material(rng, fissile=True)
+    mod = mg_material(rng, fissile=False)
+    geo = lattice_geometry(1, 1, PIN_PITCH, [([PIN_RADIUS], [0, 1])], [[0]],
+                           [REFLECT] * 4)
+    return make_problem("pin_cell_7g", geo, stack_materials([fuel, mod]),
+                        run_params(seed, n_per_gen, n_gen, n_inactive, ent=(8, 8)))
+
+
+def lattice_17x17(n_per_gen=1_000_000, n_gen=60, n_inactive=20, seed=2):
+    """17x17 lattice of the pin cell: 3 fuels + moderator, seeded pin map, vacuum."""
+    fuels = [mg_material(np.random.default_rng(1001 + f), fissile=True) for f in range(3)]
+    mod = mg_material(np.random.default_rng(1004), fissile=False)
+    pin_map = np.random.default_rng(2001).integers(0, 3, size=(17, 17))
+    univ = [([PIN_RADIUS], [f, 3]) for f in range(3)]
+    geo = lattice_geometry(17, 17, PIN_PITCH, univ, pin_map, [VACUUM] * 4)
+    return make_problem("lattice_17x17_7g", geo, stack_materials(fuels + [mod]),
+                        run_params(seed, n_per_gen, n_gen, n_inactive, ent=(17, 17)))
+
+
+def batch_pin_cells(n_problems=512, batch_seed=3001, n_min=1_000, n_max=1_000_000):
+    """Independent fixed-source pin cells with their own XS, radius and size."""
+    rng = np.random.default_rng(batch_seed)
+    radii = rng.uniform(0.3, 0.6, n_problems)
+    sizes = np.rint(np.exp(rng.uniform(math.log(n_min), math.log(n_max), n_problems)))
+    probs = []
+    for p in range(n_problems):
+        r = np.random.default_rng(10000 + p)
+        fuel = mg_material(r, fissile=True)
+        mod = mg_material(r, fissile=False)
+        geo = lattice_geometry(1, 1, PIN_PITCH, [([float(radii[p])], [0, 1])], [[0]],
+                               [REFLECT] * 4)
+        run = run_params(100000 + p, int(sizes[p]), 1, 0, fixed_source=True,
+                         problem_id=p, ent=(8, 8))
+        probs.append(make_problem(f"batch_pin_{p}", geo, stack_materials([fuel, mod]), run))
+    return probs
+
+
+# ---------------------------------------------------------------------------
+# closed-form test problems
+# ---------------------------------------------------------------------------
+
+def homogeneous(xs_material, n_per_gen, n_gen, n_inactive, seed, fixed_source=False,
+                pitch=2.0):
+    """Infinite medium: one reflective cell of a single material, no rings."""
+    geo = lattice_geometry(1, 1, pitch, [([], [0])], [[0]], [REFLECT] * 4)
+    return make_problem("homogeneous", geo, stack_materials([xs_material]),
+                        run_params(seed, n_per_gen, n_gen, n_inactive,
+                                   fixed_source=fixed_source, ent=(4, 4)))
+
+
+def one_group(sig_t, sig_s, nu_sig_f):
+    return dict(sig_t=np.array([sig_t], float), sig_s=np.array([[sig_s]], float),
+                nu_sig_f=np.array([nu_sig_f], float),
+                chi=np.array([1.0 if nu_sig_f > 0 else 0.0]))
+
+
+def pin_cell_same_material(xs_material, n_per_gen, n_gen, n_inactive, seed, radius=PIN_RADIUS,
+                           fixed_source=False):
+    """Pin cell whose fuel and moderator are the same material (two copies)."""
+    geo = lattice_geometry(1, 1, PIN_PITCH, [([radius], [0, 1])], [[0]], [REFLECT] * 4)
+    return make_problem("pin_same", geo, stack_materials([xs_material, xs_material]),
+                        run_params(seed, n_per_gen, n_gen, n_inactive,
+                                   fixed_source=fixed_source, ent=(8, 8)))
+
+
+def slab(thickness, sig_t, n_per_gen, seed):
+    """Pure absorber slab: one cell of width `thickness`, vacuum in x,
+    reflective in y.  Used with explicitly supplied start states."""
+    geo = lattice_geometry(1, 1, thickness, [([], [0])], [[0]],
+                           [VACUUM, VACUUM, REFLECT, REFLECT], x0=0.0,
+                           y0=-0.5 * thickness)
+    xs = stack_materials([one_group(sig_t, 0.0, 0.0)])
+    return make_problem("slab", geo, xs,
+                        run_params(seed, n_per_gen, 1, 0, fixed_source=True, ent=(1, 1)))
+
+
+def with_run(problem, **kw):
+    """Copy of a problem with some run parameters replaced."""
+    p = dict(problem)
+    p["run"] = dict(problem["run"])
+    p["run"].update(kw)
+    return p
+
+
+def n_bins(problem):
+    geo, xs = problem["geometry"], problem["xs"]
+    return geo["nx"] * geo["ny"] * (geo["radii"].shape[1] + 1) * xs["sig_t"].shape[1]
+
+
+def digest(problem):
+    """sha256 over every array and scalar of a problem (records the inputs)."""
+    h = hashlib.sha256()
+    for part in ("geometry", "xs", "run"):
+        d = problem[part]
+        for k in sorted(d):
+            v = d[k]
+            h.update(k.encode())
+            h.update(np.ascontiguousarray(np.asarray(v)).tobytes())
+    return h.hexdigest()
