@@ -1,0 +1,155 @@
+#!/usr/bin/env python3
+"""Throughput of the event-based Monte Carlo k-eigenvalue path on one MI355X.
+
+One step is one full power iteration of the 17x17-pin, 7-group lattice
+(1e6 histories per generation, 60 generations, 20 inactive) in FP64, with the
+problem data and workspace resident on the GPU.  Prints one JSON line with
+histories/s (value), events/s, the roofline of the dominant event kernel
+(timed with HIP events on the run's stream) and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per processed particle (FP64 bank entry: x, y, u, v as f64,
+# cell, group|sites, draw counter, id as u32 = 48 B)
+STATE_BYTES = 48
+SITE_BYTES = 28  # banked fission site: x, y (f64), group, parent, sequence (u32)
+TALLY_BYTES_ADV = 32  # two fixed-point tally bins, two 64-bit atomic halves each
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-per-gen", type=int, default=1_000_000)
+    ap.add_argument("--n-gen", type=int, default=60)
+    ap.add_argument("--n-inactive", type=int, default=20)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--tail", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-gens", type=int, default=2)
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU design is "
+              "described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2501_05440_amd import mcx
+    from paper_2501_05440_amd import problems as P
+
+    if not os.path.exists(mcx.LIB_PATH):
+        from paper_2501_05440_amd import build as B
+        B.build()
+    prob = P.lattice_17x17(n_per_gen=a.n_per_gen, n_gen=a.n_gen, n_inactive=a.n_inactive)
+    N, G = a.n_per_gen, a.n_gen
+    print(f"[bench] lattice 17x17, {N} histories x {G} generations, steps={a.steps} "
+          f"warmup={a.warmup}", file=sys.stderr, flush=True)
+    ctx = mcx.Context(prob, device=0, block_size=a.block, tail_threshold=a.tail,
+                      time_kernels=True)
+    for w in range(a.warmup):
+        ctx.run()
+        print(f"[bench] warmup {w + 1}/{a.warmup} done", file=sys.stderr, flush=True)
+    tot = dict(advance_ms=0.0, collide_ms=0.0, tail_ms=0.0, n_advance=0, n_collide=0,
+               advance_items=0, collide_items=0, n_iterations=0, run_ms=0.0)
+    segs = cols = scats = sites = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        ctx.run()
+        t = ctx.timing()
+        for key in tot:
+            tot[key] += t[key]
+        _, c = ctx.generation_stats()
+        segs += int(c[:, 0].sum())
+        cols += int(c[:, 1].sum())
+        sites += int(c[:, 7].sum())
+        scats += int(c[:, 8].sum())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    km, ks, _ = ctx.keff()
+    ctx.close()
+    histories = a.steps * N * G
+    value = histories / elapsed
+
+    # roofline of the dominant event kernel
+    adv_avg_ms = tot["advance_ms"] / max(1, tot["n_advance"])
+    col_avg_ms = tot["collide_ms"] / max(1, tot["n_collide"])
+    adv_items = tot["advance_items"] / max(1, tot["n_advance"])
+    col_items = tot["collide_items"] / max(1, tot["n_collide"])
+    adv_bytes = 2 * STATE_BYTES + TALLY_BYTES_ADV
+    col_bytes = STATE_BYTES + STATE_BYTES * (scats / max(1, cols)) + SITE_BYTES * (sites / max(1, cols))
+    if tot["advance_ms"] >= tot["collide_ms"]:
+        name, avg_ms, per_launch = "k_advance", adv_avg_ms, adv_items * adv_bytes
+        per_item = adv_bytes
+    else:
+        name, avg_ms, per_launch = "k_collide", col_avg_ms, col_items * col_bytes
+        per_item = col_bytes
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "bytes_per_item": round(per_item, 2),
+                "items_per_launch": round(adv_items if name == "k_advance" else col_items, 1),
+                "avg_launch_us": round(avg_ms * 1e3, 2),
+                "kernel_ms_per_step": {"advance": round(tot["advance_ms"] / a.steps, 2),
+                                       "collide": round(tot["collide_ms"] / a.steps, 2),
+                                       "tail": round(tot["tail_ms"] / a.steps, 2)}}
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        from oracle import oracle as O
+        cores = os.cpu_count() or 1
+        sample = P.with_run(prob, n_gen=a.cpu_gens, n_inactive=a.cpu_gens - 1)
+        print(f"[bench] cpu oracle: {a.cpu_gens} generations of {N} histories on {cores} threads",
+              file=sys.stderr, flush=True)
+        c0 = time.perf_counter()
+        O.run(sample, n_threads=cores)
+        c1 = time.perf_counter()
+        cpu = {"value": round(a.cpu_gens * N / (c1 - c0), 1), "unit": "histories/s",
+               "cores": cores, "kind": "oracle",
+               "sample": f"first {a.cpu_gens} generations of the same lattice problem "
+                         f"({a.cpu_gens * N} histories, {c1 - c0:.1f} s)"}
+
+    out = {
+        "metric": "histories/s per MI355X (FP64 event-based, k-eigenvalue power iteration)",
+        "value": round(value, 1),
+        "unit": "histories/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(elapsed / a.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"lattice_17x17_7g: 17x17 pin cells, 3 fuels + moderator, 7 groups, "
+                               f"vacuum boundary, {N} histories/gen x {G} gens ({a.n_inactive} "
+                               f"inactive), FP64 event-based",
+                   "histories_per_step": N * G, "block_size": a.block or 256,
+                   "tail_threshold": a.tail or 4096},
+        "events_per_s": round(segs / elapsed, 1),
+        "segments_per_history": round(segs / histories, 4),
+        "k_eff": {"collision": round(float(km[0]), 6), "sigma": round(float(ks[0]), 6)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

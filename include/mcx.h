@@ -1,0 +1,224 @@
+/*
+ * mcx.h - C ABI of libmcx: event-based Monte Carlo neutron transport for
+ * k-eigenvalue power iteration on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one the paper studies (Morgan, Cuneo, Variansyah,
+ * Niemeyer, M&C 2025, arXiv 2501.05440): Sec. 1 names the physics
+ * (multigroup energy, constructive solid geometry with surface tracking,
+ * k-eigenvalue power iteration, replicable CPU/GPU random numbers); Sec. 2
+ * names the event-based GPU structure (particles taken from a
+ * to-be-processed bank, written to a processed bank, events launched as
+ * separate kernels); Sec. 5 fixes FP64 arithmetic.  Each generation runs
+ * birth, then repeated {advance: cross-section lookup, distance to
+ * collision, distance to boundary, move, track-length tallies, surface
+ * crossing} and {collide: fission-bank append, absorption or scatter}
+ * kernels over compacted particle banks, then builds the canonical fission
+ * bank, the k estimators, the Shannon entropy and the next source.
+ *
+ * Conventions
+ *  - Every call returns MCX_OK (0) or a negative MCX_E* code and never
+ *    aborts; mcx_last_error() gives a message for the context.
+ *  - Host arrays passed to mcx_load_* / mcx_seed_source are copied before
+ *    the call returns; the caller may free them afterwards.
+ *  - The device workspace and the stream belong to the caller.  The library
+ *    never allocates or frees device memory; it carves the bound workspace.
+ *  - Output arrays of mcx_get_* are caller-allocated host memory.
+ *  - Call order: create -> load_geometry, load_mg_xs, seed_source (any
+ *    order) -> workspace_size -> bind_workspace -> run_generations ->
+ *    get_* -> destroy.  Loading or seeding again requires binding again.
+ *  - Not thread-safe per context; distinct contexts are independent.
+ */
+#ifndef MCX_H
+#define MCX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mcx_ctx mcx_ctx;
+
+enum mcx_status {
+  MCX_OK = 0,
+  MCX_EINVAL = -1,     /* invalid argument or problem data */
+  MCX_ESTATE = -2,     /* call out of order */
+  MCX_ENOMEM = -3,     /* workspace too small, or host allocation failed */
+  MCX_EDEVICE = -4,    /* HIP runtime error */
+  MCX_ELOST = -5,      /* source sampling found no fissile point */
+  MCX_EGUARD = -6,     /* histories stopped by the per-history event guard */
+  MCX_EEXTINCT = -7,   /* empty fission bank in a k-eigenvalue generation */
+  MCX_EOVERFLOW = -8   /* fission bank or per-history site count overflow */
+};
+
+enum { MCX_FP64 = 0, MCX_FP32_MIXED = 1 };
+enum { MCX_VACUUM = 0, MCX_REFLECT = 1 };
+enum { MCX_FATE_ABSORBED = 1, MCX_FATE_LEAKED = 2, MCX_FATE_KILLED = 3 };
+
+/* Per-generation counters, in this order (mcx_get_generation_stats). */
+enum {
+  MCX_CNT_SEG = 0,    /* flight segments = collisions + crossings */
+  MCX_CNT_COL = 1,    /* collisions */
+  MCX_CNT_CROSS = 2,  /* surface crossings (reflections and leaks included) */
+  MCX_CNT_REFL = 3,   /* crossings with a reflection */
+  MCX_CNT_LEAK = 4,   /* histories ended by leakage */
+  MCX_CNT_ABS = 5,    /* histories ended by absorption */
+  MCX_CNT_KILLED = 6, /* histories ended by the event guard */
+  MCX_CNT_SITES = 7,  /* fission sites banked */
+  MCX_CNT_SCAT = 8,   /* scatters */
+  MCX_N_CNT = 9
+};
+
+typedef struct {
+  int32_t precision;        /* MCX_FP64 (the paper's precision, Sec. 5) */
+  int32_t device;           /* HIP device ordinal the workspace lives on */
+  void* stream;             /* hipStream_t for every launch and copy; NULL = null stream */
+  int32_t block_size;       /* threads per block of the event kernels, multiple of 64; 0 = 256 */
+  int32_t tail_threshold;   /* live-particle count at or below which one history-based
+                               kernel finishes the generation; 0 = default (4096);
+                               negative = event kernels until every history ends */
+  int32_t lookahead;        /* event iterations enqueued ahead of the last live count
+                               read back; 0 = default (4) */
+  int64_t max_events;       /* per-history segment guard; 0 = 100000 */
+  int32_t record_histories; /* 1: keep one mcx_record per history per generation */
+  int32_t time_kernels;     /* 1: time every event kernel with HIP events (mcx_get_timing) */
+} mcx_options;
+
+/* Lattice of pin universes (paper Sec. 1: CSG geometry).  Cell (i, j),
+   0 <= i < nx, 0 <= j < ny, spans [x0 + i pitch, x0 + (i+1) pitch] x
+   [y0 + j pitch, y0 + (j+1) pitch]; universe u has n_rings[u] concentric
+   z-cylinders about the cell centre with strictly increasing radii below
+   pitch / 2; region r < n_rings[u] is inside ring r (and outside ring r-1),
+   region n_rings[u] is outside every ring; its material is
+   mats[u * (max_rings + 1) + r].  bc = {xmin, xmax, ymin, ymax} sides, each
+   MCX_VACUUM or MCX_REFLECT.  Limits: nx, ny <= 4095, max_rings <= 254. */
+typedef struct {
+  int32_t nx, ny;
+  double pitch, x0, y0;
+  int32_t bc[4];
+  int32_t n_univ, max_rings;
+  const int32_t* n_rings;   /* [n_univ] */
+  const double* radii;      /* [n_univ][max_rings] */
+  const int32_t* mats;      /* [n_univ][max_rings + 1] */
+  const int32_t* pin_map;   /* [ny][nx] universe of each cell */
+} mcx_geometry;
+
+/* Source and run description.  The generation-0 source (and every batch of
+   a fixed-source run) is uniform over the fissile volume with a group drawn
+   from the fission spectrum.  fixed_source = 1 treats fission as capture
+   (production is tallied, no sites are banked) and samples a fresh source
+   every batch.  problem_id enters every random-number counter, so a problem
+   run alone or inside a batch sees the same streams.  The entropy mesh
+   (ent_nx x ent_ny) covers the lattice's bounding box. */
+typedef struct {
+  uint64_t seed;
+  int64_t n_per_gen;        /* 1 <= n_per_gen <= 2^30 */
+  int32_t fixed_source;
+  uint64_t problem_id;
+  int32_t ent_nx, ent_ny;
+} mcx_source;
+
+/* Per-history record (record_histories = 1). */
+typedef struct {
+  int32_t n_seg, n_col, n_cross, n_refl;
+  int32_t fate, n_sites, g_final;
+  uint32_t ctr_final;       /* transport-stream draws consumed */
+  double tl_sum;            /* total track length */
+  double kcol_sum;          /* sum of nu_sig_f / sig_t over collisions */
+  double x_final, y_final;
+} mcx_record;
+
+/* Timing of the last mcx_run_generations.  The *_ms kernel sums are filled
+   when time_kernels = 1 (events recorded on the stream around each launch);
+   *_items count the particles each kernel class processed. */
+typedef struct {
+  double run_ms;            /* stream time of the whole run, generation ends included */
+  int64_t n_iterations;     /* advance + collide iterations launched */
+  int64_t n_tail_launches;
+  double advance_ms, collide_ms, tail_ms;
+  int64_t n_advance, n_collide;
+  int64_t advance_items;    /* particles processed by advance kernels (= their segments + kills) */
+  int64_t collide_items;    /* collisions processed by collide kernels */
+} mcx_timing;
+
+/* Create a context on opt->device (NULL opt = defaults). */
+int mcx_create(mcx_ctx** out, const mcx_options* opt);
+
+/* Copy and validate the geometry (MCX_EINVAL on bad sizes, radii, pin map). */
+int mcx_load_geometry(mcx_ctx* ctx, const mcx_geometry* geo);
+
+/* Copy and validate multigroup data (paper Sec. 1: multigroup physics):
+   sig_t[m][g] > 0; sig_s[m][g][g'] >= 0 is the transfer g -> g' with
+   sum_g' sig_s <= sig_t; nu_sig_f[m][g] >= 0; chi[m][g] >= 0 summing to
+   about 1 for every fissile material.  1 <= n_grp <= 65535. */
+int mcx_load_mg_xs(mcx_ctx* ctx, int32_t n_mat, int32_t n_grp, const double* sig_t,
+                   const double* sig_s, const double* nu_sig_f, const double* chi);
+
+int mcx_seed_source(mcx_ctx* ctx, const mcx_source* src);
+
+/* Bytes of device workspace needed to run up to n_gen_max generations. */
+int mcx_workspace_size(mcx_ctx* ctx, int32_t n_gen_max, size_t* bytes);
+
+/* Bind a caller-owned device buffer (256-byte aligned, on opt->device) of at
+   least mcx_workspace_size bytes and upload the tables; MCX_ENOMEM if small. */
+int mcx_bind_workspace(mcx_ctx* ctx, void* device_ptr, size_t bytes, int32_t n_gen_max);
+
+/* Power iteration (paper Sec. 4: inactive then active cycles): n_gen
+   generations, statistics over the last n_gen - n_inactive.  Blocks until
+   the stream has finished.  Returns MCX_EEXTINCT, MCX_EOVERFLOW, MCX_ELOST,
+   MCX_EGUARD (results are still readable) or MCX_EDEVICE on failure. */
+int mcx_run_generations(mcx_ctx* ctx, int32_t n_gen, int32_t n_inactive);
+
+/* Active-generation mean and standard deviation of the mean of the
+   collision, track-length and absorption k estimators (mean3, sigma3), and
+   optionally the per-generation values per_gen[n_gen][3] (may be NULL). */
+int mcx_get_keff(mcx_ctx* ctx, double* mean3, double* sigma3, double* per_gen);
+
+/* Per-generation Shannon entropy of the fission bank entropy[n_gen] and
+   counters counts[n_gen][MCX_N_CNT]; either may be NULL. */
+int mcx_get_generation_stats(mcx_ctx* ctx, double* entropy, int64_t* counts);
+
+/* Active-generation mean and standard deviation of the mean of the
+   track-length flux and nu-fission production per source particle, bin
+   ((cell j * nx + i) * (max_rings + 1) + region) * n_grp + group; n_bins must
+   equal nx * ny * (max_rings + 1) * n_grp.  Any pointer may be NULL. */
+int mcx_get_tallies(mcx_ctx* ctx, double* flux_mean, double* flux_sigma, double* prod_mean,
+                    double* prod_sigma, int64_t n_bins);
+
+/* One generation's flux and production tallies per source particle. */
+int mcx_get_generation_tallies(mcx_ctx* ctx, int32_t gen, double* flux, double* prod,
+                               int64_t n_bins);
+
+/* Per-history records of generation gen (record_histories = 1), n_per_gen
+   entries indexed by history id. */
+int mcx_get_records(mcx_ctx* ctx, int32_t gen, mcx_record* out, int64_t n);
+
+/* Canonical fission bank of the last k-eigenvalue generation, ordered by
+   (parent history, banking order): xyg[k][3] = x, y, group; *len receives
+   the bank size (entries beyond cap are not written). */
+int mcx_get_bank(mcx_ctx* ctx, double* xyg, int64_t cap, int64_t* len);
+
+int mcx_get_timing(mcx_ctx* ctx, mcx_timing* out);
+
+/* Diagnostics of the device arithmetic (device pointers, on ctx's stream):
+   which = 0: out[i] = ln(in[i]); 1: out[2i], out[2i+1] = cos, sin(2 pi in[i]);
+   2: out[i] = sqrt(in[i]); 3: out[i] = uniform(bits of in[i]) mapping of a
+   64-bit word to (0, 1).  Same functions the kernels call. */
+int mcx_diag_math(mcx_ctx* ctx, int32_t which, const double* d_in, double* d_out, int64_t n);
+
+/* The same functions evaluated on the host (no device needed). */
+int mcx_host_math(int32_t which, const double* in, double* out, int64_t n);
+
+/* Philox4x64-10 blocks on the device: in[i] = {c0, c1, c2, c3, k0, k1},
+   out[i] = 4 output words (device pointers). */
+int mcx_diag_philox(mcx_ctx* ctx, const uint64_t* d_in, uint64_t* d_out, int64_t n);
+
+const char* mcx_last_error(const mcx_ctx* ctx);
+
+void mcx_destroy(mcx_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

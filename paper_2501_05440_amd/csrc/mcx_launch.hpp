@@ -1,0 +1,55 @@
+// mcx_launch.hpp - host-side launchers of the transport kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "mcx_device.hpp"
+
+namespace mcx {
+
+hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_source(const Tables& T, uint32_t gen, uint32_t n, double* sx, double* sy,
+                         int32_t* sg, uint32_t* status, hipStream_t s);
+hipError_t launch_birth(const Tables& T, uint32_t gen, uint32_t n, const double* sx,
+                        const double* sy, const int32_t* sg, const Bank& out, uint32_t* cnt_live,
+                        uint32_t* cnt_col, hipStream_t s);
+hipError_t launch_advance(bool rec, const Tables& T, uint32_t gen, uint32_t it, const Bank& in,
+                          const uint32_t* n_in, const Bank& live, uint32_t* n_live,
+                          const Bank& col, uint32_t* n_col, const Accum& A, const Records& R,
+                          uint32_t* clr_live, uint32_t* clr_col, uint32_t bound, int block,
+                          hipStream_t s);
+hipError_t launch_collide(bool rec, const Tables& T, uint32_t gen, const Bank& in,
+                          const uint32_t* n_in, const Bank& live, uint32_t* n_live,
+                          const Accum& A, const Records& R, uint32_t bound, int block,
+                          hipStream_t s);
+hipError_t launch_tail(bool rec, const Tables& T, uint32_t gen, uint32_t it0, const Bank& in,
+                       const uint32_t* n_in, const Accum& A, const Records& R, uint32_t bound,
+                       hipStream_t s);
+uint32_t scan_chunks(uint32_t n);
+hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* chunk_sum, uint32_t* out,
+                       uint32_t* total, hipStream_t s);
+hipError_t launch_canon(const Sites& fis, const uint32_t* n_fis, const uint32_t* offs,
+                        const uint32_t* nsite_id, uint32_t cap, double* cx, double* cy,
+                        int32_t* cg, uint32_t* status, uint32_t bound, hipStream_t s);
+hipError_t launch_gen_totals(const Tables& T, uint32_t gen, uint32_t n, const Accum& A,
+                             double* gen_k, unsigned long long* gen_cnt, uint32_t* gen_m,
+                             double* k_used, double* xi0, hipStream_t s);
+hipError_t launch_gen_tallies(const Tables& T, uint32_t gen, uint32_t n, const Accum& A,
+                              double* gen_tal, hipStream_t s);
+hipError_t launch_entropy(const Tables& T, uint32_t gen, const double* cx, const double* cy,
+                          const uint32_t* n_p, uint32_t cap, uint32_t* hist, double* gen_h,
+                          uint32_t bound, hipStream_t s);
+hipError_t launch_comb(uint32_t n, const uint32_t* m_p, uint32_t cap, const double* xi0,
+                       const double* cx, const double* cy, const int32_t* cg, double* sx,
+                       double* sy, int32_t* sg, hipStream_t s);
+hipError_t launch_stats(int n_bins2, int n_gen, int n_inactive, const double* gen_tal,
+                        double* tal_mean, double* tal_sigma, const double* gen_k, double* k_stat,
+                        hipStream_t s);
+hipError_t launch_diag_math(int which, const double* in, double* out, int64_t n, hipStream_t s);
+hipError_t launch_diag_philox(const uint64_t* in, uint64_t* out, int64_t n, hipStream_t s);
+void host_math(int which, const double* in, double* out, int64_t n);
+
+}  // namespace mcx

@@ -1,0 +1,55 @@
+"""CPU checks of the HIP library: it loads, exports every declared symbol, and
+its arithmetic (compiled for the host from the same source as the kernels)
+gives the oracle's correctly rounded values."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2501_05440_amd import mcx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    text = open(os.path.join(ROOT, "include", "mcx.h")).read()
+    return sorted(set(re.findall(r"^(?:int|void|const char\*)\s+(mcx_\w+)\(", text, re.M)))
+
+
+def test_header_declarations_are_bound():
+    assert declared() == sorted(mcx.EXPORTS)
+
+
+def test_library_exports_every_symbol():
+    L = mcx.lib()
+    for name in declared():
+        assert hasattr(L, name), name
+
+
+def test_host_math_matches_oracle(oracle):
+    rng = np.random.default_rng(31)
+    words = rng.integers(0, 2**63, 200000, dtype=np.int64).astype(np.uint64) * np.uint64(2) + np.uint64(1)
+    xi = ((words >> np.uint64(12)).astype(np.float64) + 0.5) * 2.0**-52
+    got = mcx.host_math(0, xi)
+    want = np.array([oracle.cr_log(x) for x in xi])
+    assert np.array_equal(got, want)
+    cs = mcx.host_math(1, xi)
+    want_cs = np.array([oracle.cr_cossin_2pi(x) for x in xi])
+    assert np.array_equal(cs, want_cs)
+    # the uniform mapping of a 64-bit word
+    u = mcx.host_math(3, words.view(np.float64))
+    assert np.array_equal(u, np.array([oracle.uniform(int(w)) for w in words[:2000]] +
+                                      list(xi[2000:])))
+
+
+def test_host_math_edges(oracle):
+    x = np.array([2.0**-53, 1 - 2.0**-53, 0.5, 0.25, 1e-300, 3.0, 1e300, 5e-324])
+    assert np.array_equal(mcx.host_math(0, x), [oracle.cr_log(v) for v in x])
+    t = np.array([0.0, 0.25, 0.5, 0.75, 0.125, 2.0**-53, 1 - 2.0**-53, 0.25 + 2.0**-54])
+    assert np.array_equal(mcx.host_math(1, t), [oracle.cr_cossin_2pi(v) for v in t])
+
+
+def test_host_math_rejects_bad_selector():
+    with pytest.raises(mcx.MCXError):
+        mcx.host_math(9, np.ones(3))
