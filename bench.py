@@ -22,7 +22,29 @@ HBM_PEAK_GBS = 8000.0
 # cell, group|sites, draw counter, id as u32 = 48 B)
 STATE_BYTES = 48
 SITE_BYTES = 28  # banked fission site: x, y (f64), group, parent, sequence (u32)
-TALLY_BYTES_ADV = 32  # two fixed-point tally bins, two 64-bit atomic halves each
+TALLY_BYTES_ADV = 16  # one 64-bit fixed-point flux atomic (read-modify-write)
+COUNTERS = os.path.join(ROOT, "profiles", "k_advance_lattice17x17_counters.md")
+KERNEL_SOURCES = ["paper_2501_05440_amd/csrc/mcx_kernels.hip",
+                  "paper_2501_05440_amd/csrc/mcx_device.hpp",
+                  "paper_2501_05440_amd/csrc/mcx_math.hpp"]
+
+
+def measured_traffic_per_item():
+    """HBM bytes per advanced particle from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line)
+    h = hashlib.sha256()
+    for src in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if fields.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return float(fields["traffic_bytes_per_item"])
 
 
 def parse():
@@ -100,9 +122,13 @@ def main():
         name, avg_ms, per_launch = "k_collide", col_avg_ms, col_items * col_bytes
         per_item = col_bytes
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = None
+    tpi = measured_traffic_per_item() if name == "k_advance" else None
+    if tpi is not None:
+        traffic = round(tpi * adv_items)  # HBM bytes per launch
     roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_item": round(per_item, 2),
+                "traffic": traffic, "bytes_per_item": round(per_item, 2),
                 "items_per_launch": round(adv_items if name == "k_advance" else col_items, 1),
                 "avg_launch_us": round(avg_ms * 1e3, 2),
                 "kernel_ms_per_step": {"advance": round(tot["advance_ms"] / a.steps, 2),
@@ -141,7 +167,7 @@ def main():
                                f"vacuum boundary, {N} histories/gen x {G} gens ({a.n_inactive} "
                                f"inactive), FP64 event-based",
                    "histories_per_step": N * G, "block_size": a.block or 256,
-                   "tail_threshold": a.tail or 4096},
+                   "tail_threshold": a.tail or max(4096, N // 8)},
         "events_per_s": round(segs / elapsed, 1),
         "segments_per_history": round(segs / histories, 4),
         "k_eff": {"collision": round(float(km[0]), 6), "sigma": round(float(ks[0]), 6)},

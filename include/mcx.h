@@ -76,8 +76,9 @@ typedef struct {
   void* stream;             /* hipStream_t for every launch and copy; NULL = null stream */
   int32_t block_size;       /* threads per block of the event kernels, multiple of 64; 0 = 256 */
   int32_t tail_threshold;   /* live-particle count at or below which one history-based
-                               kernel finishes the generation; 0 = default (4096);
-                               negative = event kernels until every history ends */
+                               kernel finishes the generation; 0 = default
+                               (max(4096, n_per_gen / 8)); negative = event kernels
+                               until every history ends */
   int32_t lookahead;        /* event iterations enqueued ahead of the last live count
                                read back; 0 = default (4) */
   int64_t max_events;       /* per-history segment guard; 0 = 100000 */

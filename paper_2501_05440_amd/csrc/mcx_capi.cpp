@@ -72,6 +72,7 @@ struct Dev {
   double *k_used = nullptr, *xi0 = nullptr, *k_stat = nullptr;
   double *tal_stat = nullptr;  // [mean flux | mean prod | sigma flux | sigma prod]
   uint32_t* ent_hist = nullptr;
+  double* ent_term = nullptr;
   unsigned long long* acc_base = nullptr;
   size_t acc_words = 0;
   unsigned long long* rec_base = nullptr;
@@ -149,7 +150,7 @@ int mcx_create(mcx_ctx** out, const mcx_options* opt) {
     delete c;
     return MCX_EINVAL;
   }
-  if (c->opt.tail_threshold == 0) c->opt.tail_threshold = DEFAULT_TAIL;
+  // tail_threshold == 0: N / 8, at least DEFAULT_TAIL (resolved per run)
   if (c->opt.lookahead <= 0) c->opt.lookahead = DEFAULT_LOOKAHEAD;
   if (c->opt.lookahead > RING - 2) c->opt.lookahead = RING - 2;
   if (c->opt.max_events <= 0) c->opt.max_events = DEFAULT_MAX_EVENTS;
@@ -319,7 +320,7 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   const int mr1 = c->max_rings + 1;
   const size_t MG = (size_t)c->n_mat * c->G;
   const int nb = c->nx * c->ny * mr1 * c->G;
-  const int stripes = std::max(1, std::min(STRIPES, 65536 / std::max(1, 4 * nb)));
+  const int stripes = std::max(1, std::min(STRIPES, 65536 / std::max(1, 2 * nb)));
   const uint32_t fis_cap = (uint32_t)std::min<size_t>(2 * N + 4096, 0xFFFFFFF0u);
   const size_t n_ent = (size_t)c->src.ent_nx * c->src.ent_ny;
   const size_t n_cnt_slots = (size_t)c->opt.max_events + 4;
@@ -369,7 +370,7 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   d.cnt_live = cv.take<uint32_t>(n_cnt_slots);
   d.cnt_col = cv.take<uint32_t>(n_cnt_slots);
   // per-generation accumulators, zeroed together
-  const size_t w_tally = (size_t)stripes * 4 * nb;
+  const size_t w_tally = (size_t)stripes * 2 * nb;
   const size_t w_k = 3 * STRIPES * 2;
   const size_t w_cnt = (size_t)N_CNT_ALL * STRIPES;
   const size_t w_misc = 1 + (n_ent + 1) / 2;
@@ -389,6 +390,7 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   d.gen_m = cv.take<uint32_t>(n_gen_max);
   d.gen_tal = cv.take<double>((size_t)2 * nb * n_gen_max);
   d.tal_stat = cv.take<double>((size_t)4 * nb);
+  d.ent_term = cv.take<double>(n_ent);
   d.k_stat = cv.take<double>(6);
   d.k_used = cv.take<double>(1);
   d.xi0 = cv.take<double>(1);
@@ -459,11 +461,10 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
 
   // fixed-point scales of the exact accumulators
   const double ln_max = 36.8;  // -ln of the smallest uniform draw, 2^-53
-  double d_max = 0, p_max = 0, kc_max = 0, ka_max = 0;
+  double d_max = 0, kc_max = 0, ka_max = 0;
   for (size_t mg = 0; mg < c->sig_t.size(); ++mg) {
     const double d = ln_max / c->sig_t[mg];
     d_max = std::max(d_max, d);
-    p_max = std::max(p_max, d * c->nusf[mg]);
     kc_max = std::max(kc_max, c->nusf[mg] / c->sig_t[mg]);
     if (c->nusf[mg] > 0.0) ka_max = std::max(ka_max, c->nusf[mg] / (c->sig_t[mg] - c->sst[mg]));
   }
@@ -489,7 +490,6 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
   T.n_bins = c->d.n_bins;
   T.tally_stripes = c->d.stripes;
   T.q_flux = fixed_point_scale(d_max);
-  T.q_prod = fixed_point_scale(p_max);
   T.q_kcol = fixed_point_scale(kc_max);
   T.q_kabs = fixed_point_scale(ka_max);
   T.max_events = c->opt.max_events;
@@ -567,12 +567,15 @@ static int run_generation(mcx_ctx* c, int gen) {
   // upper bound for every later iteration
   uint32_t bound = N;
   int64_t known = 0, it = 0;
+  const int64_t tail = c->opt.tail_threshold != 0
+                           ? (int64_t)c->opt.tail_threshold
+                           : std::max<int64_t>(DEFAULT_TAIL, (int64_t)N / 8);
   int cur = 0;
   const int block = c->opt.block_size;
   for (;;) {
     if (bound == 0) break;
     if ((size_t)it + 3 >= c->d.n_cnt_slots) return fail(c, MCX_EDEVICE, "iteration slots exhausted");
-    if (c->opt.tail_threshold > 0 && bound <= (uint32_t)c->opt.tail_threshold) {
+    if (tail > 0 && bound <= (uint32_t)tail) {
       HIP_TRY(c, time_mark(c, 2, true));
       HIP_TRY(c, launch_tail(rec, T, gen, (uint32_t)it, c->d.bank[cur], c->d.cnt_live + it, A, c->d.R,
                              bound, s));
@@ -612,13 +615,13 @@ static int run_generation(mcx_ctx* c, int gen) {
 
   // generation end
   HIP_TRY(c, launch_gen_totals(T, gen, N, A, c->d.gen_k, c->d.gen_cnt, c->d.gen_m, c->d.k_used, c->d.xi0, s));
-  HIP_TRY(c, launch_gen_tallies(T, gen, N, A, c->d.gen_tal, s));
+  HIP_TRY(c, launch_gen_tallies(T, gen, N, A, c->d.gen_tal, c->d.gen_k, s));
   if (!T.fixed_source) {
     HIP_TRY(c, launch_scan(A.nsite_id, N, c->d.chunk_sum, c->d.offs, c->d.scan_total, s));
     HIP_TRY(c, launch_canon(A.fis, A.n_fis, c->d.offs, A.nsite_id, c->d.fis_cap, c->d.can_x, c->d.can_y,
                             c->d.can_g, A.status, c->d.fis_cap, s));
     HIP_TRY(c, launch_entropy(T, gen, c->d.can_x, c->d.can_y, A.n_fis, c->d.fis_cap, c->d.ent_hist,
-                              c->d.gen_h, c->d.fis_cap, s));
+                              c->d.ent_term, c->d.gen_h, c->d.fis_cap, s));
     HIP_TRY(c, launch_comb(N, A.n_fis, c->d.fis_cap, c->d.xi0, c->d.can_x, c->d.can_y, c->d.can_g, c->d.src_x, c->d.src_y,
                            c->d.src_g, s));
   } else {

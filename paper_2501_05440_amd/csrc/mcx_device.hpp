@@ -72,7 +72,7 @@ struct Tables {
   int ent_nx, ent_ny;
   int n_bins;          // bins per tally: nx * ny * mr1 * G
   int tally_stripes;   // copies of the tally accumulators
-  double q_flux, q_prod, q_kcol, q_kabs;  // fixed-point scales 2^s
+  double q_flux, q_kcol, q_kabs;  // fixed-point scales 2^s
   int64_t max_events;
 };
 
@@ -114,7 +114,7 @@ struct Records {
 
 // Per-generation accumulators (zeroed at the start of every generation).
 struct Accum {
-  unsigned long long* tally;  // [stripe][2 tallies][bin][2 halves]
+  unsigned long long* tally;  // flux: [stripe][bin][2 halves]
   unsigned long long* k;      // [3][STRIPES][2 halves]
   unsigned long long* cnt;    // [N_CNT_ALL][STRIPES]
   uint32_t* n_fis;            // fission sites appended
@@ -219,8 +219,10 @@ MCX_HD void isotropic_uv(double xi_mu, double xi_phi, double* u, double* v) {
 
 // ---------------------------------------------------------------------------
 // exact fixed-point accumulation: a nonnegative term t becomes the integer
-// q = round(t * 2^s) < 2^62, added as two 32-bit halves into 64-bit counters,
-// so that sums are exact and independent of the order of the atomics.
+// q = round(t * 2^s) < 2^61; an accumulator is a pair of 64-bit words
+// (lo, hi) holding hi * 2^64 + lo.  Adding q is one returning atomic on lo
+// plus, when that add wraps around, one increment of hi, so every sum is
+// exact and independent of the order of the atomics.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ uint64_t quantize(double t, double scale) {
@@ -229,9 +231,18 @@ __device__ __forceinline__ uint64_t quantize(double t, double scale) {
 
 __device__ __forceinline__ void acc_add(unsigned long long* pair, uint64_t q) {
   if (q == 0) return;
-  atomicAdd(pair + 0, (unsigned long long)(q & 0xFFFFFFFFull));
-  const uint64_t hi = q >> 32;
-  if (hi) atomicAdd(pair + 1, (unsigned long long)hi);
+  const unsigned long long old = atomicAdd(pair, (unsigned long long)q);
+  if (old + q < old) atomicAdd(pair + 1, 1ull);
+}
+
+// Add the 128-bit value w1 * 2^64 + w0.
+__device__ __forceinline__ void acc_add128(unsigned long long* pair, unsigned long long w0,
+                                           unsigned long long w1) {
+  if (w0) {
+    const unsigned long long old = atomicAdd(pair, w0);
+    if (old + w0 < old) w1 += 1ull;
+  }
+  if (w1) atomicAdd(pair + 1, w1);
 }
 
 // ---------------------------------------------------------------------------
@@ -273,6 +284,73 @@ __device__ __forceinline__ uint32_t wave_reserve(uint32_t n, uint32_t* counter) 
   return base + incl - n;
 }
 
+// Block-level reservation: every thread of the block calls it with its own
+// count; one atomic per block on the counter; the slots of a block are
+// contiguous, in thread order.  lds: MAX_WAVES + 2 words, reusable after the
+// call returns.
+constexpr int MAX_WAVES = 16;
+
+__device__ __forceinline__ uint32_t block_reserve(uint32_t n, uint32_t* counter, uint32_t* lds) {
+  const uint32_t lane = lane_id();
+  const uint32_t wid = threadIdx.x >> 6;
+  const uint32_t nw = (blockDim.x + 63) >> 6;
+  uint32_t incl = n;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(incl, off);
+    if ((int)lane >= off) incl += t;
+  }
+  if (lane == 63) lds[wid] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (uint32_t w = 0; w < nw; ++w) {
+      const uint32_t t = lds[w];
+      lds[w] = run;
+      run += t;
+    }
+    lds[MAX_WAVES] = run ? atomicAdd(counter, run) : 0u;
+  }
+  __syncthreads();
+  const uint32_t slot = lds[MAX_WAVES] + lds[wid] + incl - n;
+  __syncthreads();
+  return slot;
+}
+
+// Two predicates (one slot each) reserved with one barrier pair and at most
+// two atomics per block.
+__device__ __forceinline__ void block_append2(bool pa, bool pb, uint32_t* ca, uint32_t* cb,
+                                              uint32_t* lds, uint32_t* sa, uint32_t* sb) {
+  const uint32_t lane = lane_id();
+  const uint32_t wid = threadIdx.x >> 6;
+  const uint32_t nw = (blockDim.x + 63) >> 6;
+  const unsigned long long ma = __ballot(pa), mb = __ballot(pb);
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  uint32_t* la = lds;
+  uint32_t* lb = lds + MAX_WAVES + 1;
+  if (lane == 0) {
+    la[wid] = (uint32_t)__popcll(ma);
+    lb[wid] = (uint32_t)__popcll(mb);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t ra = 0, rb = 0;
+    for (uint32_t w = 0; w < nw; ++w) {
+      const uint32_t ta = la[w], tb = lb[w];
+      la[w] = ra;
+      lb[w] = rb;
+      ra += ta;
+      rb += tb;
+    }
+    la[MAX_WAVES] = ra ? atomicAdd(ca, ra) : 0u;
+    lb[MAX_WAVES] = rb ? atomicAdd(cb, rb) : 0u;
+  }
+  __syncthreads();
+  *sa = la[MAX_WAVES] + la[wid] + (uint32_t)__popcll(ma & lt);
+  *sb = lb[MAX_WAVES] + lb[wid] + (uint32_t)__popcll(mb & lt);
+  __syncthreads();
+}
+
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -285,16 +363,24 @@ __device__ __forceinline__ void wave_count(unsigned long long* base, unsigned lo
   if (lane_id() == 0 && v) atomicAdd(base + (blockIdx.x % STRIPES), v);
 }
 
-// Wave-reduced add of fixed-point terms (q < 2^62 per lane) into a striped
-// (lo, hi) accumulator pair.
-__device__ __forceinline__ void wave_acc(unsigned long long* k_base, uint64_t q) {
-  const unsigned long long lo = wave_sum((unsigned long long)(q & 0xFFFFFFFFull));
-  const unsigned long long hi = wave_sum((unsigned long long)(q >> 32));
+// Wave-reduced add of per-lane fixed-point sums given as 32-bit halves
+// (value = lo + hi * 2^32, each half below 2^56) into a striped pair.
+__device__ __forceinline__ void wave_acc_halves(unsigned long long* k_base, unsigned long long lo,
+                                                unsigned long long hi) {
+  lo = wave_sum(lo);
+  hi = wave_sum(hi);
   if (lane_id() == 0) {
-    unsigned long long* p = k_base + 2 * (blockIdx.x % STRIPES);
-    if (lo) atomicAdd(p + 0, lo);
-    if (hi) atomicAdd(p + 1, hi);
+    // lo + hi * 2^32 as a 128-bit (w1, w0)
+    const unsigned long long hl = hi << 32, hh = hi >> 32;
+    const unsigned long long w0 = lo + hl;
+    const unsigned long long w1 = hh + (w0 < lo ? 1ull : 0ull);
+    acc_add128(k_base + 2 * (blockIdx.x % STRIPES), w0, w1);
   }
+}
+
+// Wave-reduced add of one fixed-point term (q < 2^61) per lane.
+__device__ __forceinline__ void wave_acc(unsigned long long* k_base, uint64_t q) {
+  wave_acc_halves(k_base, q & 0xFFFFFFFFull, q >> 32);
 }
 
 }  // namespace mcx

@@ -72,7 +72,7 @@ __device__ __forceinline__ void die(const Part& p, int fate, const Accum& A, con
 // the boundary comes first.  Returns EV_COLLIDE, EV_CROSS or EV_LEAK.
 template <bool REC>
 __device__ __forceinline__ int segment(const Tables& T, Part& p, Stream& rs, const Accum& A,
-                                       const Records& R, bool* refl_out, uint64_t* q_ktl) {
+                                       const Records& R, bool* refl_out) {
   const int c = p.j * T.nx + p.i;
   const int un = T.pin_map[c];
   const int nr = T.n_rings[un];
@@ -105,14 +105,14 @@ __device__ __forceinline__ int segment(const Tables& T, Part& p, Stream& rs, con
   p.x = p.x + d * p.u;
   p.y = p.y + d * p.v;
 
-  // track-length tallies: flux and nu-fission production of this bin
+  // track-length flux tally of this bin (cell, region, group); nu_sig_f is
+  // constant in a bin, so the production tally and the track-length k
+  // estimator follow from the flux sums at the end of the generation
   const int bin = (c * T.mr1 + p.r) * T.G + p.g;
   unsigned long long* tb =
-      A.tally + (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(4 * T.n_bins);
+      A.tally + (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
   acc_add(tb + 2 * bin, quantize(d, T.q_flux));
-  const uint64_t qp = quantize(d * nusf, T.q_prod);
-  acc_add(tb + 2 * (T.n_bins + bin), qp);
-  *q_ktl = qp;
+  (void)nusf;
   if (REC) {
     R.n_seg[p.id] += 1;
     R.tl_sum[p.id] += d;
@@ -305,7 +305,6 @@ __global__ void __launch_bounds__(1024) k_advance(Tables T, uint32_t gen, uint32
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   int ev = EV_NONE;
   bool refl = false;
-  uint64_t q_ktl = 0;
   Part p;
   if (k < n_in) {
     p = load_part(in, k);
@@ -314,13 +313,14 @@ __global__ void __launch_bounds__(1024) k_advance(Tables T, uint32_t gen, uint32
       die<REC>(p, FATE_KILLED, A, R);
     } else {
       Stream rs(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
-      ev = segment<REC>(T, p, rs, A, R, &refl, &q_ktl);
+      ev = segment<REC>(T, p, rs, A, R, &refl);
       p.ctr = rs.draw;
       if (ev == EV_LEAK) die<REC>(p, FATE_LEAKED, A, R);
     }
   }
-  const uint32_t pl = wave_append(ev == EV_CROSS, n_live);
-  const uint32_t pc = wave_append(ev == EV_COLLIDE, n_col);
+  __shared__ uint32_t lds[2 * (MAX_WAVES + 1)];
+  uint32_t pl, pc;
+  block_append2(ev == EV_CROSS, ev == EV_COLLIDE, n_live, n_col, lds, &pl, &pc);
   if (ev == EV_CROSS) store_part(live, pl, p);
   if (ev == EV_COLLIDE) store_part(col, pc, p);
   wave_flag(A.cnt + CNT_SEG * STRIPES, ev == EV_COLLIDE || ev == EV_CROSS || ev == EV_LEAK);
@@ -329,7 +329,6 @@ __global__ void __launch_bounds__(1024) k_advance(Tables T, uint32_t gen, uint32
   wave_flag(A.cnt + CNT_LEAK * STRIPES, ev == EV_LEAK);
   wave_flag(A.cnt + CNT_KILLED * STRIPES, ev == EV_KILL);
   wave_flag(A.cnt + CNT_ADV_ITEMS * STRIPES, k < n_in);
-  wave_acc(A.k + K_TL * STRIPES * 2, q_ktl);
 }
 
 // Process the collision bank: collision estimator, fission-bank append
@@ -359,7 +358,8 @@ __global__ void __launch_bounds__(1024) k_collide(Tables T, uint32_t gen, Bank i
     }
     nf = fission_count(T, x, rs, k_used);
   }
-  const uint32_t slot = wave_reserve(nf, A.n_fis);
+  __shared__ uint32_t lds[2 * (MAX_WAVES + 1)];
+  const uint32_t slot = block_reserve(nf, A.n_fis, lds);
   bool alive = false;
   uint64_t q_kabs = 0;
   if (valid) {
@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(1024) k_collide(Tables T, uint32_t gen, Bank i
     p.ctr = rs.draw;
     if (!alive) die<REC>(p, FATE_ABSORBED, A, R);
   }
-  const uint32_t pl = wave_append(alive, n_live);
+  const uint32_t pl = block_reserve(alive ? 1u : 0u, n_live, lds);
   if (alive) store_part(live, pl, p);
   wave_flag(A.cnt + CNT_COL * STRIPES, valid);
   wave_flag(A.cnt + CNT_COL_ITEMS * STRIPES, valid);
@@ -376,17 +376,6 @@ __global__ void __launch_bounds__(1024) k_collide(Tables T, uint32_t gen, Bank i
   wave_count(A.cnt + CNT_SITES * STRIPES, nf);
   wave_acc(A.k + K_COL * STRIPES * 2, q_kcol);
   wave_acc(A.k + K_ABS * STRIPES * 2, q_kabs);
-}
-
-__device__ __forceinline__ void wave_acc2(unsigned long long* k_base, unsigned long long lo,
-                                          unsigned long long hi) {
-  lo = wave_sum(lo);
-  hi = wave_sum(hi);
-  if (lane_id() == 0) {
-    unsigned long long* q = k_base + 2 * (blockIdx.x % STRIPES);
-    if (lo) atomicAdd(q + 0, lo);
-    if (hi) atomicAdd(q + 1, hi);
-  }
 }
 
 // History-based finish of the last live particles: one lane runs its
@@ -400,7 +389,7 @@ __global__ void __launch_bounds__(256) k_tail(Tables T, uint32_t gen, uint32_t i
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long c_seg = 0, c_col = 0, c_cross = 0, c_refl = 0, c_leak = 0, c_abs = 0,
                      c_kill = 0, c_sites = 0, c_scat = 0;
-  unsigned long long ktl[2] = {0, 0}, kcol[2] = {0, 0}, kabs[2] = {0, 0};
+  unsigned long long kcol[2] = {0, 0}, kabs[2] = {0, 0};
   if (k < n_in) {
     const double k_used = *A.k_used;
     Part p = load_part(in, k);
@@ -414,12 +403,9 @@ __global__ void __launch_bounds__(256) k_tail(Tables T, uint32_t gen, uint32_t i
         break;
       }
       bool refl = false;
-      uint64_t q = 0;
-      const int ev = segment<REC>(T, p, rs, A, R, &refl, &q);
+      const int ev = segment<REC>(T, p, rs, A, R, &refl);
       ++nseg;
       ++c_seg;
-      ktl[0] += q & 0xFFFFFFFFull;
-      ktl[1] += q >> 32;
       if (ev == EV_LEAK) {
         ++c_cross;
         ++c_leak;
@@ -435,7 +421,7 @@ __global__ void __launch_bounds__(256) k_tail(Tables T, uint32_t gen, uint32_t i
       ++c_col;
       const ColXS x = col_xs(T, p);
       const double kc = x.nusf / x.st;
-      q = quantize(kc, T.q_kcol);
+      const uint64_t q = quantize(kc, T.q_kcol);
       kcol[0] += q & 0xFFFFFFFFull;
       kcol[1] += q >> 32;
       if (REC) {
@@ -467,9 +453,8 @@ __global__ void __launch_bounds__(256) k_tail(Tables T, uint32_t gen, uint32_t i
   wave_count(A.cnt + CNT_KILLED * STRIPES, c_kill);
   wave_count(A.cnt + CNT_SITES * STRIPES, c_sites);
   wave_count(A.cnt + CNT_SCAT * STRIPES, c_scat);
-  wave_acc2(A.k + K_TL * STRIPES * 2, ktl[0], ktl[1]);
-  wave_acc2(A.k + K_COL * STRIPES * 2, kcol[0], kcol[1]);
-  wave_acc2(A.k + K_ABS * STRIPES * 2, kabs[0], kabs[1]);
+  wave_acc_halves(A.k + K_COL * STRIPES * 2, kcol[0], kcol[1]);
+  wave_acc_halves(A.k + K_ABS * STRIPES * 2, kabs[0], kabs[1]);
 }
 
 // ---------------------------------------------------------------------------
@@ -593,21 +578,17 @@ __global__ void k_canon(Sites fis, const uint32_t* n_fis_p, const uint32_t* offs
   }
 }
 
-// 128-bit sum of the striped (lo, hi) halves, correctly rounded to double.
+// Sum of striped 128-bit accumulators (hi * 2^64 + lo), correctly rounded
+// to double.
 __device__ double stripes_to_double(const unsigned long long* pairs, int n_stripes,
                                     size_t stride) {
   unsigned long long w0 = 0, w1 = 0;  // value = w1 * 2^64 + w0
   for (int s = 0; s < n_stripes; ++s) {
     const unsigned long long lo = pairs[(size_t)s * stride + 0];
     const unsigned long long hi = pairs[(size_t)s * stride + 1];
-    unsigned long long t = w0 + lo;
-    w1 += (t < w0) ? 1ull : 0ull;
+    const unsigned long long t = w0 + lo;
+    w1 += hi + ((t < w0) ? 1ull : 0ull);
     w0 = t;
-    const unsigned long long hl = hi << 32, hh = hi >> 32;
-    t = w0 + hl;
-    w1 += (t < w0) ? 1ull : 0ull;
-    w0 = t;
-    w1 += hh;
   }
   if (w1 == 0) return (double)w0;  // u64 -> f64 conversion rounds to nearest
   // normalise the top 64 bits, fold the rest into a sticky bit
@@ -623,8 +604,8 @@ __global__ void k_gen_totals(Tables T, uint32_t gen, uint32_t n, Accum A, double
                              unsigned long long* gen_cnt, uint32_t* gen_m, double* k_used,
                              double* xi0) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  const double inv_q[3] = {1.0 / T.q_kcol, 1.0 / T.q_prod, 1.0 / T.q_kabs};
-  for (int e = 0; e < 3; ++e) {
+  const double inv_q[3] = {1.0 / T.q_kcol, 0.0, 1.0 / T.q_kabs};
+  for (int e = 0; e < 3; e += 2) {
     const double v = stripes_to_double(A.k + (size_t)e * STRIPES * 2, STRIPES, 2) * inv_q[e];
     gen_k[3 * gen + e] = v / (double)n;
   }
@@ -639,43 +620,98 @@ __global__ void k_gen_totals(Tables T, uint32_t gen, uint32_t n, Accum A, double
   *xi0 = rs.next();
 }
 
-// Generation tallies per source particle.
-__global__ void k_gen_tallies(Tables T, uint32_t gen, uint32_t n, Accum A, double* gen_tal) {
+// Generation tallies per source particle: flux from the exact sums, the
+// production nu_sig_f(bin) * flux, and the track-length k estimator as the
+// sum of the production over bins (compensated, fixed order; one block).
+__global__ void __launch_bounds__(1024) k_gen_tallies(Tables T, uint32_t gen, uint32_t n, Accum A,
+                                                      double* gen_tal, double* gen_k) {
+  __shared__ double ps[1024], pc[1024];
   const int nb = T.n_bins;
-  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < 2 * nb; b += gridDim.x * blockDim.x) {
-    const double inv_q = b < nb ? 1.0 / T.q_flux : 1.0 / T.q_prod;
-    const double v = stripes_to_double(A.tally + 2 * (size_t)b, T.tally_stripes, 4 * (size_t)nb);
-    gen_tal[(size_t)gen * 2 * nb + b] = v * inv_q / (double)n;
+  const int per_cell = T.mr1 * T.G;
+  double s = 0.0, cmp = 0.0;  // Neumaier pair of this thread
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const double flux =
+        stripes_to_double(A.tally + 2 * (size_t)b, T.tally_stripes, 2 * (size_t)nb) / T.q_flux;
+    const int cell = b / per_cell;
+    const int r = (b / T.G) % T.mr1;
+    const int g = b % T.G;
+    const int m = T.mats[T.pin_map[cell] * T.mr1 + r];
+    const double prod = T.nusf[m * T.G + g] * flux;
+    gen_tal[(size_t)gen * 2 * nb + b] = flux / (double)n;
+    gen_tal[(size_t)gen * 2 * nb + nb + b] = prod / (double)n;
+    const double t = s + prod;
+    cmp += fabs(s) >= fabs(prod) ? (s - t) + prod : (prod - t) + s;
+    s = t;
+  }
+  ps[threadIdx.x] = s;
+  pc[threadIdx.x] = cmp;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, ac = 0.0;
+    for (unsigned k = 0; k < blockDim.x; ++k) {
+      const double parts[2] = {ps[k], pc[k]};
+      for (int e = 0; e < 2; ++e) {
+        const double x = parts[e];
+        const double t = a + x;
+        ac += fabs(a) >= fabs(x) ? (a - t) + x : (x - t) + a;
+        a = t;
+      }
+    }
+    gen_k[3 * gen + 1] = (a + ac) / (double)n;
   }
 }
 
-// Shannon entropy of the canonical bank over the entropy mesh.
-__global__ void k_entropy_hist(Tables T, const double* cx, const double* cy,
-                               const uint32_t* n_p, uint32_t cap, uint32_t* hist) {
+// Shannon entropy of the canonical bank over the entropy mesh: per-block
+// histograms in LDS (meshes up to LDS_HIST bins), merged with one global
+// atomic per nonzero bin and block.
+constexpr int LDS_HIST = 8192;
+
+__global__ void __launch_bounds__(256) k_entropy_hist(Tables T, const double* cx, const double* cy,
+                                                     const uint32_t* n_p, uint32_t cap,
+                                                     uint32_t* hist) {
+  __shared__ uint32_t h[LDS_HIST];
+  const int nb = T.ent_nx * T.ent_ny;
+  const bool in_lds = nb <= LDS_HIST;
+  if (in_lds)
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) h[b] = 0u;
+  __syncthreads();
   const uint32_t n = min(*n_p, cap);
   for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
     int bx = (int)floor((cx[s] - T.x0) / T.width * (double)T.ent_nx);
     int by = (int)floor((cy[s] - T.y0) / T.height * (double)T.ent_ny);
     bx = bx < 0 ? 0 : (bx > T.ent_nx - 1 ? T.ent_nx - 1 : bx);
     by = by < 0 ? 0 : (by > T.ent_ny - 1 ? T.ent_ny - 1 : by);
-    atomicAdd(&hist[by * T.ent_nx + bx], 1u);
+    if (in_lds)
+      atomicAdd(&h[by * T.ent_nx + bx], 1u);
+    else
+      atomicAdd(&hist[by * T.ent_nx + bx], 1u);
   }
+  __syncthreads();
+  if (in_lds)
+    for (int b = threadIdx.x; b < nb; b += blockDim.x)
+      if (h[b]) atomicAdd(&hist[b], h[b]);
 }
 
-__global__ void k_entropy_final(Tables T, uint32_t gen, const uint32_t* hist,
-                                const uint32_t* n_p, double* gen_h) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// H = -sum_b p_b log2 p_b: the terms in parallel, the sum in bin order.
+__global__ void __launch_bounds__(256) k_entropy_final(Tables T, uint32_t gen,
+                                                      const uint32_t* hist, const uint32_t* n_p,
+                                                      double* term, double* gen_h) {
   const uint32_t m = *n_p;
-  double h = 0.0;
-  if (m > 0) {
-    for (int b = 0; b < T.ent_nx * T.ent_ny; ++b) {
-      if (hist[b] > 0) {
-        const double p = (double)hist[b] / (double)m;
-        h -= p * log2(p);
-      }
+  const int nb = T.ent_nx * T.ent_ny;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    double t = 0.0;
+    if (m > 0 && hist[b] > 0) {
+      const double p = (double)hist[b] / (double)m;
+      t = p * log2(p);
     }
+    term[b] = t;
   }
-  gen_h[gen] = h;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double h = 0.0;
+    for (int b = 0; b < nb; ++b) h -= term[b];
+    gen_h[gen] = h;
+  }
 }
 
 // Combing: source site i of the next generation is canonical entry
@@ -850,18 +886,17 @@ hipError_t launch_gen_totals(const Tables& T, uint32_t gen, uint32_t n, const Ac
 }
 
 hipError_t launch_gen_tallies(const Tables& T, uint32_t gen, uint32_t n, const Accum& A,
-                              double* gen_tal, hipStream_t s) {
-  hipLaunchKernelGGL(k_gen_tallies, dim3(std::max(1u, nblk(2 * T.n_bins, 256))), dim3(256), 0, s,
-                     T, gen, n, A, gen_tal);
+                              double* gen_tal, double* gen_k, hipStream_t s) {
+  hipLaunchKernelGGL(k_gen_tallies, dim3(1), dim3(1024), 0, s, T, gen, n, A, gen_tal, gen_k);
   return hipGetLastError();
 }
 
 hipError_t launch_entropy(const Tables& T, uint32_t gen, const double* cx, const double* cy,
-                          const uint32_t* n_p, uint32_t cap, uint32_t* hist, double* gen_h,
-                          uint32_t bound, hipStream_t s) {
-  const unsigned g = std::max(1u, std::min(nblk(bound, 256), 4096u));
+                          const uint32_t* n_p, uint32_t cap, uint32_t* hist, double* term,
+                          double* gen_h, uint32_t bound, hipStream_t s) {
+  const unsigned g = std::max(1u, std::min(nblk(bound, 256 * 16), 1024u));
   hipLaunchKernelGGL(k_entropy_hist, dim3(g), dim3(256), 0, s, T, cx, cy, n_p, cap, hist);
-  hipLaunchKernelGGL(k_entropy_final, dim3(1), dim3(64), 0, s, T, gen, hist, n_p, gen_h);
+  hipLaunchKernelGGL(k_entropy_final, dim3(1), dim3(256), 0, s, T, gen, hist, n_p, term, gen_h);
   return hipGetLastError();
 }
 

@@ -38,10 +38,10 @@ hipError_t launch_gen_totals(const Tables& T, uint32_t gen, uint32_t n, const Ac
                              double* gen_k, unsigned long long* gen_cnt, uint32_t* gen_m,
                              double* k_used, double* xi0, hipStream_t s);
 hipError_t launch_gen_tallies(const Tables& T, uint32_t gen, uint32_t n, const Accum& A,
-                              double* gen_tal, hipStream_t s);
+                              double* gen_tal, double* gen_k, hipStream_t s);
 hipError_t launch_entropy(const Tables& T, uint32_t gen, const double* cx, const double* cy,
-                          const uint32_t* n_p, uint32_t cap, uint32_t* hist, double* gen_h,
-                          uint32_t bound, hipStream_t s);
+                          const uint32_t* n_p, uint32_t cap, uint32_t* hist, double* term,
+                          double* gen_h, uint32_t bound, hipStream_t s);
 hipError_t launch_comb(uint32_t n, const uint32_t* m_p, uint32_t cap, const double* xi0,
                        const double* cx, const double* cy, const int32_t* cg, double* sx,
                        double* sy, int32_t* sg, hipStream_t s);
