@@ -73,6 +73,7 @@ struct Dev {
   double *tal_stat = nullptr;  // [mean flux | mean prod | sigma flux | sigma prod]
   uint32_t* ent_hist = nullptr;
   double* ent_term = nullptr;
+  uint32_t* gen_status = nullptr;  // [n_gen_max] status bits per generation
   unsigned long long* acc_base = nullptr;
   size_t acc_words = 0;
   unsigned long long* rec_base = nullptr;
@@ -366,19 +367,22 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   d.offs = cv.take<uint32_t>(N);
   d.chunk_sum = cv.take<uint32_t>(scan_chunks((uint32_t)N) + 1);
   d.scan_total = cv.take<uint32_t>(1);
-  A.status = cv.take<uint32_t>(1);
+  d.gen_status = cv.take<uint32_t>(n_gen_max);
+  A.status = d.gen_status;
   d.cnt_live = cv.take<uint32_t>(n_cnt_slots);
   d.cnt_col = cv.take<uint32_t>(n_cnt_slots);
   // per-generation accumulators, zeroed together
   const size_t w_tally = (size_t)stripes * 2 * nb;
+  const size_t w_tally_t = (size_t)2 * nb;
   const size_t w_k = 3 * STRIPES * 2;
   const size_t w_cnt = (size_t)N_CNT_ALL * STRIPES;
   const size_t w_misc = 1 + (n_ent + 1) / 2;
-  d.acc_words = w_tally + w_k + w_cnt + w_misc;
+  d.acc_words = w_tally + w_tally_t + w_k + w_cnt + w_misc;
   d.acc_base = cv.take<unsigned long long>(d.acc_words);
   if (base) {
     A.tally = d.acc_base;
-    A.k = A.tally + w_tally;
+    A.tally_t = A.tally + w_tally;
+    A.k = A.tally_t + w_tally_t;
     A.cnt = A.k + w_k;
     A.n_fis = reinterpret_cast<uint32_t*>(A.cnt + w_cnt);
     d.ent_hist = reinterpret_cast<uint32_t*>(A.cnt + w_cnt + 1);
@@ -554,6 +558,7 @@ static int run_generation(mcx_ctx* c, int gen) {
   Accum& A = c->d.A;
   const bool rec = c->opt.record_histories != 0;
   const uint32_t N = c->d.N;
+  A.status = c->d.gen_status + gen;
   HIP_TRY(c, launch_fill_u64(c->d.acc_base, c->d.acc_words, 0ull, s));
   HIP_TRY(c, launch_fill_u64(reinterpret_cast<unsigned long long*>(A.nsite_id), (N + 1) / 2,
                              0ull, s));
@@ -561,7 +566,8 @@ static int run_generation(mcx_ctx* c, int gen) {
   if (gen == 0 || T.fixed_source)
     HIP_TRY(c, launch_source(T, gen, N, c->d.src_x, c->d.src_y, c->d.src_g, A.status, s));
   HIP_TRY(c, launch_birth(T, gen, N, c->d.src_x, c->d.src_y, c->d.src_g, c->d.bank[0], c->d.cnt_live,
-                          c->d.cnt_col, s));
+                          c->d.cnt_col, gen > 0 ? c->d.gen_status + gen - 1 : nullptr, A.status,
+                          s));
 
   // event iterations; `bound` is the live count of iteration `known`, an
   // upper bound for every later iteration
@@ -618,6 +624,7 @@ static int run_generation(mcx_ctx* c, int gen) {
   HIP_TRY(c, launch_gen_tallies(T, gen, N, A, c->d.gen_tal, c->d.gen_k, s));
   if (!T.fixed_source) {
     HIP_TRY(c, launch_scan(A.nsite_id, N, c->d.chunk_sum, c->d.offs, c->d.scan_total, s));
+    HIP_TRY(c, launch_gen_check(T, A.n_fis, c->d.scan_total, A.status, s));
     HIP_TRY(c, launch_canon(A.fis, A.n_fis, c->d.offs, A.nsite_id, c->d.fis_cap, c->d.can_x, c->d.can_y,
                             c->d.can_g, A.status, c->d.fis_cap, s));
     HIP_TRY(c, launch_entropy(T, gen, c->d.can_x, c->d.can_y, A.n_fis, c->d.fis_cap, c->d.ent_hist,
@@ -627,17 +634,9 @@ static int run_generation(mcx_ctx* c, int gen) {
   } else {
     HIP_TRY(c, launch_fill_u64(reinterpret_cast<unsigned long long*>(c->d.gen_h + gen), 1, 0ull, s));
   }
-  // status check: one small read-back per generation
-  uint32_t* hs = c->h_pin + RING;
-  HIP_TRY(c, hipMemcpyAsync(hs + 0, A.status, 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(c, hipMemcpyAsync(hs + 1, A.n_fis, 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(c, hipMemcpyAsync(hs + 2, c->d.scan_total, 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(c, hipStreamSynchronize(s));
-  if (c->opt.time_kernels) {
-    int rc = collect_kernel_times(c);
-    if (rc) return rc;
-  }
+  // per-history records: copied back after every generation
   if (rec) {
+    HIP_TRY(c, hipStreamSynchronize(s));
     std::vector<char> tmp((size_t)c->d.rec_words * 8);
     HIP_TRY(c, hipMemcpy(tmp.data(), c->d.rec_base, tmp.size(), hipMemcpyDeviceToHost));
     std::vector<uint32_t> ns(N);
@@ -661,15 +660,15 @@ static int run_generation(mcx_ctx* c, int gen) {
                           g_final[i], ctr[i], tl[i], kc[i], xf[i], yf[i]};
     }
   }
-  const uint32_t st = hs[0];
+  return MCX_OK;
+}
+
+static int status_error(mcx_ctx* c, uint32_t st) {
   if (st & ST_SOURCE) return fail(c, MCX_ELOST, "source sampling found no fissile point");
   if (st & ST_OVERFLOW) return fail(c, MCX_EOVERFLOW, "fission bank overflow");
   if (st & (ST_SITE_SEQ | ST_SCAN)) return fail(c, MCX_EDEVICE, "inconsistent fission bank");
-  if (!T.fixed_source) {
-    if (hs[2] != hs[1]) return fail(c, MCX_EDEVICE, "fission bank count mismatch");
-    if (hs[1] == 0) return fail(c, MCX_EEXTINCT, "fission bank is empty");
-  }
-  return MCX_OK;
+  if (st & ST_EXTINCT) return fail(c, MCX_EEXTINCT, "fission bank is empty");
+  return fail(c, MCX_EDEVICE, "generation skipped");
 }
 
 int mcx_run_generations(mcx_ctx* c, int32_t n_gen, int32_t n_inactive) {
@@ -686,20 +685,36 @@ int mcx_run_generations(mcx_ctx* c, int32_t n_gen, int32_t n_inactive) {
   if (c->opt.record_histories) c->h_rec.assign((size_t)n_gen * c->d.N, mcx_record{});
   const double one = 1.0;
   HIP_TRY(c, hipMemcpyAsync(c->d.k_used, &one, sizeof(double), hipMemcpyHostToDevice, s));
-  HIP_TRY(c, launch_fill_u64(reinterpret_cast<unsigned long long*>(c->d.A.status), 1, 0ull, s));
+  HIP_TRY(c, launch_fill_u64(reinterpret_cast<unsigned long long*>(c->d.gen_status),
+                             ((size_t)n_gen + 1) / 2, 0ull, s));
   HIP_TRY(c, hipEventRecord(c->ev_start, s));
+  // generations are enqueued back to back; each one's status is checked
+  // once the run has finished (a failed generation makes the later ones run
+  // empty)
   int rc = MCX_OK;
-  int done = 0;
   for (int g = 0; g < n_gen; ++g) {
     rc = run_generation(c, g);
     if (rc != MCX_OK) break;
-    done = g + 1;
   }
   HIP_TRY(c, hipEventRecord(c->ev_stop, s));
   HIP_TRY(c, hipStreamSynchronize(s));
+  if (rc != MCX_OK) return rc;
   float ms = 0.f;
   HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_start, c->ev_stop));
   c->timing.run_ms = ms;
+  if (c->opt.time_kernels) {
+    int trc = collect_kernel_times(c);
+    if (trc) return trc;
+  }
+  std::vector<uint32_t> st(n_gen);
+  HIP_TRY(c, hipMemcpy(st.data(), c->d.gen_status, n_gen * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  int done = n_gen;
+  for (int g = 0; g < n_gen; ++g)
+    if (st[g]) {
+      rc = status_error(c, st[g]);
+      done = g;
+      break;
+    }
   if (done == 0) return rc;
   const int ng = done;
   const int ni = std::min(n_inactive, ng - 1);

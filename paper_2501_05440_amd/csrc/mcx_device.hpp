@@ -114,18 +114,28 @@ struct Records {
 
 // Per-generation accumulators (zeroed at the start of every generation).
 struct Accum {
-  unsigned long long* tally;  // flux: [stripe][bin][2 halves]
+  unsigned long long* tally;  // flux: [stripe][bin] (lo, hi) 128-bit pairs
+  unsigned long long* tally_t;  // flux from the tail kernel: [bin] (sum of low, high 32-bit halves)
   unsigned long long* k;      // [3][STRIPES][2 halves]
   unsigned long long* cnt;    // [N_CNT_ALL][STRIPES]
   uint32_t* n_fis;            // fission sites appended
   uint32_t* nsite_id;         // [N] sites banked per history
-  uint32_t* status;           // error bits
+  uint32_t* status;           // error bits of this generation
   const double* k_used;       // previous generation's collision estimate
   Sites fis;
   uint32_t fis_cap;
 };
 
-enum : uint32_t { ST_OVERFLOW = 1u, ST_SITE_SEQ = 2u, ST_SCAN = 4u, ST_SOURCE = 8u };
+// Per-generation status bits.  A generation that starts after a failed one
+// runs empty and is marked ST_SKIPPED.
+enum : uint32_t {
+  ST_OVERFLOW = 1u,
+  ST_SITE_SEQ = 2u,
+  ST_SCAN = 4u,
+  ST_SOURCE = 8u,
+  ST_EXTINCT = 16u,
+  ST_SKIPPED = 32u
+};
 
 // ---------------------------------------------------------------------------
 // geometry

@@ -70,7 +70,10 @@ __device__ __forceinline__ void die(const Part& p, int fate, const Accum& A, con
 // One flight: cross-section lookup, distance to collision, distance to the
 // bounding surfaces, move, track-length tallies, and the surface crossing if
 // the boundary comes first.  Returns EV_COLLIDE, EV_CROSS or EV_LEAK.
-template <bool REC>
+// HALVES: add the flux term as two non-returning 32-bit-half atomics (the
+// tail kernel, where a returning atomic's latency is not hidden by other
+// waves); otherwise one returning 64-bit atomic with a carry word.
+template <bool REC, bool HALVES>
 __device__ __forceinline__ int segment(const Tables& T, Part& p, Stream& rs, const Accum& A,
                                        const Records& R, bool* refl_out) {
   const int c = p.j * T.nx + p.i;
@@ -109,9 +112,17 @@ __device__ __forceinline__ int segment(const Tables& T, Part& p, Stream& rs, con
   // constant in a bin, so the production tally and the track-length k
   // estimator follow from the flux sums at the end of the generation
   const int bin = (c * T.mr1 + p.r) * T.G + p.g;
-  unsigned long long* tb =
-      A.tally + (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
-  acc_add(tb + 2 * bin, quantize(d, T.q_flux));
+  const uint64_t qf = quantize(d, T.q_flux);
+  if (HALVES) {
+    if (qf) {
+      atomicAdd(A.tally_t + 2 * bin, (unsigned long long)(qf & 0xFFFFFFFFull));
+      atomicAdd(A.tally_t + 2 * bin + 1, (unsigned long long)(qf >> 32));
+    }
+  } else {
+    unsigned long long* tb =
+        A.tally + (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
+    acc_add(tb + 2 * bin, qf);
+  }
   (void)nusf;
   if (REC) {
     R.n_seg[p.id] += 1;
@@ -177,7 +188,9 @@ __device__ __forceinline__ uint32_t fission_count(const Tables& T, const ColXS& 
                                                   double k_used) {
   if (T.fixed_source || !(x.nusf > 0.0)) return 0u;
   const double xf = rs.next();
-  return (uint32_t)(int)floor(x.nusf / (x.st * k_used) + xf);
+  const double f = floor(x.nusf / (x.st * k_used) + xf);
+  // a nonpositive k_used (only after a failed generation) must not loop forever
+  return f < 65536.0 ? (uint32_t)(int)f : 65536u;
 }
 
 // Collision, second part: write the nf sites reserved at slot, then scatter
@@ -260,14 +273,18 @@ __global__ void k_source(Tables T, uint32_t gen, uint32_t n, double* sx, double*
 
 // Birth: isotropic direction (transport draws 0 and 1), cell location.
 __global__ void k_birth(Tables T, uint32_t gen, uint32_t n, const double* sx, const double* sy,
-                        const int32_t* sg, Bank out, uint32_t* cnt_live, uint32_t* cnt_col) {
+                        const int32_t* sg, Bank out, uint32_t* cnt_live, uint32_t* cnt_col,
+                        const uint32_t* prev_status, uint32_t* status) {
   const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
+  // after a failed generation every later one runs empty
+  const bool skip = (prev_status && *prev_status != 0u) || (*status & ST_SOURCE);
   if (id == 0) {
-    cnt_live[0] = n;
+    cnt_live[0] = skip ? 0u : n;
     cnt_live[1] = 0;
     cnt_col[0] = 0;
+    if (skip) atomicOr(status, ST_SKIPPED);
   }
-  if (id >= n) return;
+  if (skip || id >= n) return;
   Part p;
   p.x = sx[id];
   p.y = sy[id];
@@ -313,7 +330,7 @@ __global__ void __launch_bounds__(1024) k_advance(Tables T, uint32_t gen, uint32
       die<REC>(p, FATE_KILLED, A, R);
     } else {
       Stream rs(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
-      ev = segment<REC>(T, p, rs, A, R, &refl);
+      ev = segment<REC, false>(T, p, rs, A, R, &refl);
       p.ctr = rs.draw;
       if (ev == EV_LEAK) die<REC>(p, FATE_LEAKED, A, R);
     }
@@ -403,7 +420,7 @@ __global__ void __launch_bounds__(256) k_tail(Tables T, uint32_t gen, uint32_t i
         break;
       }
       bool refl = false;
-      const int ev = segment<REC>(T, p, rs, A, R, &refl);
+      const int ev = segment<REC, true>(T, p, rs, A, R, &refl);
       ++nseg;
       ++c_seg;
       if (ev == EV_LEAK) {
@@ -578,6 +595,17 @@ __global__ void k_canon(Sites fis, const uint32_t* n_fis_p, const uint32_t* offs
   }
 }
 
+// w1 * 2^64 + w0 correctly rounded to double.
+__device__ double u128_to_double(unsigned long long w0, unsigned long long w1) {
+  if (w1 == 0) return (double)w0;  // u64 -> f64 conversion rounds to nearest
+  // normalise the top 64 bits, fold the rest into a sticky bit
+  const int lz = __clzll((long long)w1);
+  const unsigned long long top = lz ? ((w1 << lz) | (w0 >> (64 - lz))) : w1;
+  const unsigned long long rest = lz ? (w0 << lz) : w0;
+  const unsigned long long m = top | (rest ? 1ull : 0ull);
+  return ldexp((double)m, 64 - lz);
+}
+
 // Sum of striped 128-bit accumulators (hi * 2^64 + lo), correctly rounded
 // to double.
 __device__ double stripes_to_double(const unsigned long long* pairs, int n_stripes,
@@ -590,13 +618,29 @@ __device__ double stripes_to_double(const unsigned long long* pairs, int n_strip
     w1 += hi + ((t < w0) ? 1ull : 0ull);
     w0 = t;
   }
-  if (w1 == 0) return (double)w0;  // u64 -> f64 conversion rounds to nearest
-  // normalise the top 64 bits, fold the rest into a sticky bit
-  const int lz = __clzll((long long)w1);
-  const unsigned long long top = lz ? ((w1 << lz) | (w0 >> (64 - lz))) : w1;
-  const unsigned long long rest = lz ? (w0 << lz) : w0;
-  const unsigned long long m = top | (rest ? 1ull : 0ull);
-  return ldexp((double)m, 64 - lz);
+  return u128_to_double(w0, w1);
+}
+
+// Exact flux sum of one bin: the striped 128-bit pairs of the event kernels
+// plus the (low-half sum, high-half sum) pair of the tail kernel.
+__device__ double flux_total(const unsigned long long* pairs, int n_stripes, size_t stride,
+                             const unsigned long long* halves) {
+  unsigned long long w0 = 0, w1 = 0;
+  for (int s = 0; s < n_stripes; ++s) {
+    const unsigned long long lo = pairs[(size_t)s * stride + 0];
+    const unsigned long long hi = pairs[(size_t)s * stride + 1];
+    const unsigned long long t = w0 + lo;
+    w1 += hi + ((t < w0) ? 1ull : 0ull);
+    w0 = t;
+  }
+  const unsigned long long a = halves[0], b = halves[1];  // a + b * 2^32
+  unsigned long long t = w0 + a;
+  w1 += (t < w0) ? 1ull : 0ull;
+  w0 = t;
+  t = w0 + (b << 32);
+  w1 += ((t < w0) ? 1ull : 0ull) + (b >> 32);
+  w0 = t;
+  return u128_to_double(w0, w1);
 }
 
 // Generation totals: k estimators, counters, next k_used and combing offset.
@@ -630,8 +674,9 @@ __global__ void __launch_bounds__(1024) k_gen_tallies(Tables T, uint32_t gen, ui
   const int per_cell = T.mr1 * T.G;
   double s = 0.0, cmp = 0.0;  // Neumaier pair of this thread
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-    const double flux =
-        stripes_to_double(A.tally + 2 * (size_t)b, T.tally_stripes, 2 * (size_t)nb) / T.q_flux;
+    const double flux = flux_total(A.tally + 2 * (size_t)b, T.tally_stripes, 2 * (size_t)nb,
+                                   A.tally_t + 2 * (size_t)b) /
+                        T.q_flux;
     const int cell = b / per_cell;
     const int r = (b / T.G) % T.mr1;
     const int g = b % T.G;
@@ -712,6 +757,18 @@ __global__ void __launch_bounds__(256) k_entropy_final(Tables T, uint32_t gen,
     for (int b = 0; b < nb; ++b) h -= term[b];
     gen_h[gen] = h;
   }
+}
+
+// Consistency of the generation's bank: scan total equals the number of
+// appended sites, and a k-eigenvalue generation banked at least one site.
+__global__ void k_gen_check(Tables T, const uint32_t* n_fis, const uint32_t* scan_total,
+                            uint32_t* status) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  if (T.fixed_source) return;
+  uint32_t st = 0;
+  if (*scan_total != *n_fis) st |= ST_SCAN;
+  if (*n_fis == 0) st |= ST_EXTINCT;
+  if (st) atomicOr(status, st);
 }
 
 // Combing: source site i of the next generation is canonical entry
@@ -813,9 +870,10 @@ hipError_t launch_source(const Tables& T, uint32_t gen, uint32_t n, double* sx, 
 
 hipError_t launch_birth(const Tables& T, uint32_t gen, uint32_t n, const double* sx,
                         const double* sy, const int32_t* sg, const Bank& out, uint32_t* cnt_live,
-                        uint32_t* cnt_col, hipStream_t s) {
+                        uint32_t* cnt_col, const uint32_t* prev_status, uint32_t* status,
+                        hipStream_t s) {
   hipLaunchKernelGGL(k_birth, dim3(nblk(n, 256)), dim3(256), 0, s, T, gen, n, sx, sy, sg, out,
-                     cnt_live, cnt_col);
+                     cnt_live, cnt_col, prev_status, status);
   return hipGetLastError();
 }
 
@@ -867,6 +925,12 @@ hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* chunk_sum, uint
 }
 
 uint32_t scan_chunks(uint32_t n) { return nblk(n, SCAN_CHUNK); }
+
+hipError_t launch_gen_check(const Tables& T, const uint32_t* n_fis, const uint32_t* scan_total,
+                            uint32_t* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_gen_check, dim3(1), dim3(64), 0, s, T, n_fis, scan_total, status);
+  return hipGetLastError();
+}
 
 hipError_t launch_canon(const Sites& fis, const uint32_t* n_fis, const uint32_t* offs,
                         const uint32_t* nsite_id, uint32_t cap, double* cx, double* cy,

@@ -15,7 +15,10 @@ hipError_t launch_source(const Tables& T, uint32_t gen, uint32_t n, double* sx, 
                          int32_t* sg, uint32_t* status, hipStream_t s);
 hipError_t launch_birth(const Tables& T, uint32_t gen, uint32_t n, const double* sx,
                         const double* sy, const int32_t* sg, const Bank& out, uint32_t* cnt_live,
-                        uint32_t* cnt_col, hipStream_t s);
+                        uint32_t* cnt_col, const uint32_t* prev_status, uint32_t* status,
+                        hipStream_t s);
+hipError_t launch_gen_check(const Tables& T, const uint32_t* n_fis, const uint32_t* scan_total,
+                            uint32_t* status, hipStream_t s);
 hipError_t launch_advance(bool rec, const Tables& T, uint32_t gen, uint32_t it, const Bank& in,
                           const uint32_t* n_in, const Bank& live, uint32_t* n_live,
                           const Bank& col, uint32_t* n_col, const Accum& A, const Records& R,
