@@ -59,7 +59,47 @@ def parse():
     ap.add_argument("--tail", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-gens", type=int, default=2)
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip the 1e7-history FP64 / FP32-mixed comparison")
+    ap.add_argument("--n-fp32", type=int, default=10_000_000)
     return ap.parse_args()
+
+
+def timed_runs(ctx, steps):
+    import torch
+    ctx.run()  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.run()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def fp32_mixed_comparison(P, mcx, n, n_gen, n_inactive):
+    """Lattice at n histories per generation: FP64 and FP32-mixed throughput
+    and the k-eff difference (pcm) with its standard deviation."""
+    import math
+    prob = P.lattice_17x17(n_per_gen=n, n_gen=n_gen, n_inactive=n_inactive)
+    out = {}
+    res = {}
+    for prec in ("fp64", "fp32"):
+        ctx = mcx.Context(prob, precision=prec)
+        sec = timed_runs(ctx, 1)
+        km, ks, pg = ctx.keff()
+        res[prec] = (km, ks, pg)
+        ctx.close()
+        out[prec] = {"histories_per_s": round(n * n_gen / sec, 1), "ms_per_step": round(sec * 1e3, 2),
+                     "k_col": round(float(km[0]), 7), "sigma": round(float(ks[0]), 7)}
+    dk = res["fp32"][0][0] - res["fp64"][0][0]
+    sig = math.hypot(res["fp32"][1][0], res["fp64"][1][0])
+    d = res["fp32"][2][n_inactive:, 0] - res["fp64"][2][n_inactive:, 0]
+    out["dk_pcm"] = round(dk * 1e5, 3)
+    out["sigma_pcm"] = round(sig * 1e5, 3)
+    out["paired_sigma_pcm"] = round(float(d.std(ddof=1) / math.sqrt(len(d))) * 1e5, 3)
+    out["speedup_fp32_over_fp64"] = round(out["fp32"]["histories_per_s"] / out["fp64"]["histories_per_s"], 3)
+    out["workload"] = f"lattice_17x17_7g, {n} histories/gen x {n_gen} gens ({n_inactive} inactive)"
+    return out
 
 
 def main():
@@ -150,6 +190,11 @@ def main():
                "sample": f"first {a.cpu_gens} generations of the same lattice problem "
                          f"({a.cpu_gens * N} histories, {c1 - c0:.1f} s)"}
 
+    extra = None
+    if not a.no_fp32:
+        print(f"[bench] FP64 vs FP32-mixed at {a.n_fp32} histories/gen", file=sys.stderr, flush=True)
+        extra = fp32_mixed_comparison(P, mcx, a.n_fp32, G, a.n_inactive)
+
     out = {
         "metric": "histories/s per MI355X (FP64 event-based, k-eigenvalue power iteration)",
         "value": round(value, 1),
@@ -173,6 +218,7 @@ def main():
         "k_eff": {"collision": round(float(km[0]), 6), "sigma": round(float(ks[0]), 6)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "fp32_mixed": extra,
     }
     print(json.dumps(out), flush=True)
 

@@ -93,6 +93,7 @@ struct mcx_ctx {
   std::vector<double> radii;
   int n_mat = 0, G = 0;
   std::vector<double> sig_t, nusf, sst, cum_s, cum_chi;
+  std::vector<float> sig_t_f, nusf_f, sst_f, cum_s_f, cum_chi_f;  // FP32-mixed tables
   std::vector<int> last_s, last_chi, fissile;
   mcx_source src{};
 
@@ -147,7 +148,7 @@ int mcx_create(mcx_ctx** out, const mcx_options* opt) {
     delete c;
     return MCX_EINVAL;
   }
-  if (c->opt.precision != MCX_FP64) {
+  if (c->opt.precision != MCX_FP64 && c->opt.precision != MCX_FP32_MIXED) {
     delete c;
     return MCX_EINVAL;
   }
@@ -287,6 +288,30 @@ int mcx_load_mg_xs(mcx_ctx* c, int32_t n_mat, int32_t n_grp, const double* sig_t
       }
     }
   }
+  // binary32 tables: values rounded once, running sums accumulated in binary32
+  std::vector<float> sig_t_f(MG), nusf_f(MG), sst_f(MG), cum_s_f(MG * n_grp), cum_chi_f(MG);
+  for (int m = 0; m < n_mat; ++m) {
+    float cchi = 0.0f;
+    for (int g = 0; g < n_grp; ++g) {
+      const size_t mg = (size_t)m * n_grp + g;
+      sig_t_f[mg] = (float)sig_t[mg];
+      nusf_f[mg] = (float)nu_sig_f[mg];
+      float run = 0.0f;
+      for (int h = 0; h < n_grp; ++h) {
+        run += (float)sig_s[mg * n_grp + h];
+        cum_s_f[mg * n_grp + h] = run;
+      }
+      sst_f[mg] = run;
+      if (run > sig_t_f[mg]) return fail(c, MCX_EINVAL, "scattering exceeds sig_t in binary32");
+      cchi += (float)chi[mg];
+      cum_chi_f[mg] = cchi;
+    }
+  }
+  c->sig_t_f = std::move(sig_t_f);
+  c->nusf_f = std::move(nusf_f);
+  c->sst_f = std::move(sst_f);
+  c->cum_s_f = std::move(cum_s_f);
+  c->cum_chi_f = std::move(cum_chi_f);
   c->n_mat = n_mat;
   c->G = n_grp;
   c->sig_t.assign(sig_t, sig_t + MG);
@@ -339,12 +364,23 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   T.cum_chi = cv.take<double>(MG);
   T.last_chi = cv.take<int>(c->n_mat);
   T.fissile = cv.take<int>(c->n_mat);
+  T.sig_t_f = cv.take<float>(MG);
+  T.nusf_f = cv.take<float>(MG);
+  T.sst_f = cv.take<float>(MG);
+  T.cum_s_f = cv.take<float>(MG * c->G);
+  T.cum_chi_f = cv.take<float>(MG);
+  const bool fp32 = c->opt.precision == MCX_FP32_MIXED;
   for (int b = 0; b < 3; ++b) {
     Bank& k = d.bank[b];
     k.x = cv.take<double>(N);
     k.y = cv.take<double>(N);
-    k.u = cv.take<double>(N);
-    k.v = cv.take<double>(N);
+    if (fp32) {
+      k.u = cv.take<float>(N);
+      k.v = cv.take<float>(N);
+    } else {
+      k.u = cv.take<double>(N);
+      k.v = cv.take<double>(N);
+    }
     k.cell = cv.take<uint32_t>(N);
     k.gs = cv.take<uint32_t>(N);
     k.ctr = cv.take<uint32_t>(N);
@@ -493,6 +529,10 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
   T.ent_ny = c->src.ent_ny;
   T.n_bins = c->d.n_bins;
   T.tally_stripes = c->d.stripes;
+  // binary32 terms can exceed the binary64 bound by a few ulp: 1% headroom
+  d_max *= 1.01;
+  kc_max *= 1.01;
+  ka_max *= 1.01;
   T.q_flux = fixed_point_scale(d_max);
   T.q_kcol = fixed_point_scale(kc_max);
   T.q_kabs = fixed_point_scale(ka_max);
@@ -514,6 +554,11 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
   HIP_TRY(c, up(T.cum_chi, c->cum_chi.data(), c->cum_chi.size() * sizeof(double)));
   HIP_TRY(c, up(T.last_chi, c->last_chi.data(), c->last_chi.size() * sizeof(int)));
   HIP_TRY(c, up(T.fissile, c->fissile.data(), c->fissile.size() * sizeof(int)));
+  HIP_TRY(c, up(T.sig_t_f, c->sig_t_f.data(), c->sig_t_f.size() * sizeof(float)));
+  HIP_TRY(c, up(T.nusf_f, c->nusf_f.data(), c->nusf_f.size() * sizeof(float)));
+  HIP_TRY(c, up(T.sst_f, c->sst_f.data(), c->sst_f.size() * sizeof(float)));
+  HIP_TRY(c, up(T.cum_s_f, c->cum_s_f.data(), c->cum_s_f.size() * sizeof(float)));
+  HIP_TRY(c, up(T.cum_chi_f, c->cum_chi_f.data(), c->cum_chi_f.size() * sizeof(float)));
   HIP_TRY(c, hipStreamSynchronize(s));
   c->bound = true;
   c->ran = false;
@@ -565,7 +610,8 @@ static int run_generation(mcx_ctx* c, int gen) {
   if (rec) HIP_TRY(c, launch_fill_u64(c->d.rec_base, c->d.rec_words, 0ull, s));
   if (gen == 0 || T.fixed_source)
     HIP_TRY(c, launch_source(T, gen, N, c->d.src_x, c->d.src_y, c->d.src_g, A.status, s));
-  HIP_TRY(c, launch_birth(T, gen, N, c->d.src_x, c->d.src_y, c->d.src_g, c->d.bank[0], c->d.cnt_live,
+  const int prec = c->opt.precision == MCX_FP32_MIXED ? 1 : 0;
+  HIP_TRY(c, launch_birth(prec, T, gen, N, c->d.src_x, c->d.src_y, c->d.src_g, c->d.bank[0], c->d.cnt_live,
                           c->d.cnt_col, gen > 0 ? c->d.gen_status + gen - 1 : nullptr, A.status,
                           s));
 
@@ -583,20 +629,20 @@ static int run_generation(mcx_ctx* c, int gen) {
     if ((size_t)it + 3 >= c->d.n_cnt_slots) return fail(c, MCX_EDEVICE, "iteration slots exhausted");
     if (tail > 0 && bound <= (uint32_t)tail) {
       HIP_TRY(c, time_mark(c, 2, true));
-      HIP_TRY(c, launch_tail(rec, T, gen, (uint32_t)it, c->d.bank[cur], c->d.cnt_live + it, A, c->d.R,
+      HIP_TRY(c, launch_tail(prec, rec, T, gen, (uint32_t)it, c->d.bank[cur], c->d.cnt_live + it, A, c->d.R,
                              bound, s));
       HIP_TRY(c, time_mark(c, 2, false));
       c->timing.n_tail_launches += 1;
       break;
     }
     HIP_TRY(c, time_mark(c, 0, true));
-    HIP_TRY(c, launch_advance(rec, T, gen, (uint32_t)it, c->d.bank[cur], c->d.cnt_live + it,
+    HIP_TRY(c, launch_advance(prec, rec, T, gen, (uint32_t)it, c->d.bank[cur], c->d.cnt_live + it,
                               c->d.bank[1 - cur], c->d.cnt_live + it + 1, c->d.bank[2],
                               c->d.cnt_col + it, A, c->d.R, c->d.cnt_live + it + 2, c->d.cnt_col + it + 1,
                               bound, block, s));
     HIP_TRY(c, time_mark(c, 0, false));
     HIP_TRY(c, time_mark(c, 1, true));
-    HIP_TRY(c, launch_collide(rec, T, gen, c->d.bank[2], c->d.cnt_col + it, c->d.bank[1 - cur],
+    HIP_TRY(c, launch_collide(prec, rec, T, gen, c->d.bank[2], c->d.cnt_col + it, c->d.bank[1 - cur],
                               c->d.cnt_live + it + 1, A, c->d.R, bound, block, s));
     HIP_TRY(c, time_mark(c, 1, false));
     cur = 1 - cur;

@@ -67,6 +67,12 @@ struct Tables {
   const double* cum_chi;  // [m][g]
   const int* last_chi;    // [m]
   const int* fissile;     // [m]
+  // binary32 copies for the FP32-mixed mode (running sums summed in binary32)
+  const float* sig_t_f;
+  const float* nusf_f;
+  const float* sst_f;
+  const float* cum_s_f;
+  const float* cum_chi_f;
   uint64_t seed, prob;
   int fixed_source;
   int ent_nx, ent_ny;
@@ -80,8 +86,8 @@ struct Tables {
 struct Bank {
   double* x;
   double* y;
-  double* u;
-  double* v;
+  void* u;  // direction cosines in the working precision (double or float)
+  void* v;
   uint32_t* cell;
   uint32_t* gs;   // group (16 bits) | sites banked so far (16 bits)
   uint32_t* ctr;  // transport-stream draws consumed
@@ -208,8 +214,9 @@ MCX_HD void locate(const Tables& T, double x, double y, int* pi, int* pj, int* p
 
 // First index j with xi * total < cum[j] (cum = running sums in index order,
 // total = cum[n-1]); if rounding leaves none, the last nonzero entry.
-MCX_HD int sample_cum(double xi, const double* cum, int n, int last_nz) {
-  const double target = xi * cum[n - 1];
+template <class R>
+MCX_HD int sample_cum(R xi, const R* cum, int n, int last_nz) {
+  const R target = xi * cum[n - 1];
   for (int j = 0; j < n; ++j)
     if (target < cum[j]) return j;
   return last_nz;

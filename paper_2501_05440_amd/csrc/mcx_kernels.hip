@@ -15,21 +15,106 @@
 namespace mcx {
 
 // ---------------------------------------------------------------------------
+// precision policy
+//
+// FP64 (the paper's precision): every quantity in binary64, ln and cos/sin
+// correctly rounded.  FP32-mixed (R = float): directions, the distance to
+// collision, the plane distances (numerator differenced in FP64, then
+// rounded), cross sections, the reaction and group comparisons and the
+// direction sampling in binary32; positions, the cylinder quadratic, the
+// comparison of the distances, the move, the tallies and the k and entropy
+// estimators in binary64.
+// ---------------------------------------------------------------------------
+
+template <class R>
+struct Prec;
+
+template <>
+struct Prec<double> {
+  static __device__ __forceinline__ double xi(double u) { return u; }
+  static __device__ __forceinline__ double dcol(double xi, double st) {
+    return -cr_log(xi, log_tab()) / st;
+  }
+  static __device__ __forceinline__ double plane(double x, double lo, double hi, double u) {
+    return dist_plane(x, lo, hi, u);
+  }
+  static __device__ __forceinline__ void iso(double xm, double xp, double* u, double* v) {
+    isotropic_uv(xm, xp, u, v);
+  }
+};
+
+template <>
+struct Prec<float> {
+  // (float) of a draw may round up to 1; keep it in (0, 1)
+  static __device__ __forceinline__ float xi(double u) {
+    const float f = (float)u;
+    return f < 1.0f ? f : 0x1.fffffep-1f;
+  }
+  static __device__ __forceinline__ float dcol(float xi, float st) { return -logf(xi) / st; }
+  static __device__ __forceinline__ float plane(double x, double lo, double hi, float u) {
+    float t;
+    if (u > 0.0f) {
+      t = (float)(hi - x) / u;
+    } else if (u < 0.0f) {
+      t = (float)(lo - x) / u;
+    } else {
+      return __builtin_inff();
+    }
+    return t < 0.0f ? 0.0f : t;
+  }
+  static __device__ __forceinline__ void iso(float xm, float xp, float* u, float* v) {
+    const float w = 2.0f * xm - 1.0f;
+    const float s2 = 1.0f - w * w;
+    const float s = sqrtf(s2 > 0.0f ? s2 : 0.0f);
+    float sn, cs;
+    sincospif(2.0f * xp, &sn, &cs);
+    *u = s * cs;
+    *v = s * sn;
+  }
+};
+
+// Cross-section tables of the working precision.
+template <class R>
+struct XSView {
+  const R* sig_t;
+  const R* nusf;
+  const R* sst;
+  const R* cum_s;
+  const R* cum_chi;
+};
+
+template <class R>
+__device__ __forceinline__ XSView<R> xs_view(const Tables& T);
+
+template <>
+__device__ __forceinline__ XSView<double> xs_view<double>(const Tables& T) {
+  return XSView<double>{T.sig_t, T.nusf, T.sst, T.cum_s, T.cum_chi};
+}
+
+template <>
+__device__ __forceinline__ XSView<float> xs_view<float>(const Tables& T) {
+  return XSView<float>{T.sig_t_f, T.nusf_f, T.sst_f, T.cum_s_f, T.cum_chi_f};
+}
+
+// ---------------------------------------------------------------------------
 // particle state in registers
 // ---------------------------------------------------------------------------
 
+template <class R>
 struct Part {
-  double x, y, u, v;
+  double x, y;
+  R u, v;
   int i, j, r, g;
   uint32_t nsite, ctr, id;
 };
 
-__device__ __forceinline__ Part load_part(const Bank& b, uint32_t k) {
-  Part p;
+template <class R>
+__device__ __forceinline__ Part<R> load_part(const Bank& b, uint32_t k) {
+  Part<R> p;
   p.x = b.x[k];
   p.y = b.y[k];
-  p.u = b.u[k];
-  p.v = b.v[k];
+  p.u = static_cast<const R*>(b.u)[k];
+  p.v = static_cast<const R*>(b.v)[k];
   const uint32_t c = b.cell[k];
   p.i = cell_i(c);
   p.j = cell_j(c);
@@ -42,11 +127,12 @@ __device__ __forceinline__ Part load_part(const Bank& b, uint32_t k) {
   return p;
 }
 
-__device__ __forceinline__ void store_part(const Bank& b, uint32_t k, const Part& p) {
+template <class R>
+__device__ __forceinline__ void store_part(const Bank& b, uint32_t k, const Part<R>& p) {
   b.x[k] = p.x;
   b.y[k] = p.y;
-  b.u[k] = p.u;
-  b.v[k] = p.v;
+  static_cast<R*>(b.u)[k] = p.u;
+  static_cast<R*>(b.v)[k] = p.v;
   b.cell[k] = pack_cell(p.i, p.j, p.r);
   b.gs[k] = (uint32_t)p.g | (p.nsite << 16);
   b.ctr[k] = p.ctr;
@@ -55,58 +141,60 @@ __device__ __forceinline__ void store_part(const Bank& b, uint32_t k, const Part
 
 enum : int { EV_NONE = 0, EV_COLLIDE = 1, EV_CROSS = 2, EV_LEAK = 3, EV_KILL = 4 };
 
-template <bool REC>
-__device__ __forceinline__ void die(const Part& p, int fate, const Accum& A, const Records& R) {
+template <class R, bool REC>
+__device__ __forceinline__ void die(const Part<R>& p, int fate, const Accum& A,
+                                    const Records& Rc) {
   A.nsite_id[p.id] = p.nsite;
   if (REC) {
-    R.fate[p.id] = fate;
-    R.g_final[p.id] = p.g;
-    R.ctr_final[p.id] = p.ctr;
-    R.x_final[p.id] = p.x;
-    R.y_final[p.id] = p.y;
+    Rc.fate[p.id] = fate;
+    Rc.g_final[p.id] = p.g;
+    Rc.ctr_final[p.id] = p.ctr;
+    Rc.x_final[p.id] = p.x;
+    Rc.y_final[p.id] = p.y;
   }
 }
 
 // One flight: cross-section lookup, distance to collision, distance to the
-// bounding surfaces, move, track-length tallies, and the surface crossing if
+// bounding surfaces, move, track-length tally, and the surface crossing if
 // the boundary comes first.  Returns EV_COLLIDE, EV_CROSS or EV_LEAK.
 // HALVES: add the flux term as two non-returning 32-bit-half atomics (the
 // tail kernel, where a returning atomic's latency is not hidden by other
 // waves); otherwise one returning 64-bit atomic with a carry word.
-template <bool REC, bool HALVES>
-__device__ __forceinline__ int segment(const Tables& T, Part& p, Stream& rs, const Accum& A,
-                                       const Records& R, bool* refl_out) {
+template <class R, bool REC, bool HALVES>
+__device__ __forceinline__ int segment(const Tables& T, Part<R>& p, Stream& rs, const Accum& A,
+                                       const Records& Rc, bool* refl_out) {
+  const XSView<R> X = xs_view<R>(T);
   const int c = p.j * T.nx + p.i;
   const int un = T.pin_map[c];
   const int nr = T.n_rings[un];
   const int m = T.mats[un * T.mr1 + p.r];
-  const double st = T.sig_t[m * T.G + p.g];
-  const double nusf = T.nusf[m * T.G + p.g];
+  const R st = X.sig_t[m * T.G + p.g];
 
   // distance to collision: exponential with mean 1 / sig_t
-  const double xi = rs.next();
-  const double d_col = -cr_log(xi, log_tab()) / st;
+  const R xi = Prec<R>::xi(rs.next());
+  const R d_col = Prec<R>::dcol(xi, st);
 
   // distance to boundary: the cell's planes ahead and the region's rings
   const double xlo = T.x0 + (double)p.i * T.pitch, xhi = T.x0 + (double)(p.i + 1) * T.pitch;
   const double ylo = T.y0 + (double)p.j * T.pitch, yhi = T.y0 + (double)(p.j + 1) * T.pitch;
-  const double tx = dist_plane(p.x, xlo, xhi, p.u);
-  const double ty = dist_plane(p.y, ylo, yhi, p.v);
+  const R tx = Prec<R>::plane(p.x, xlo, xhi, p.u);
+  const R ty = Prec<R>::plane(p.y, ylo, yhi, p.v);
   const double cx = T.x0 + ((double)p.i + 0.5) * T.pitch;
   const double cy = T.y0 + ((double)p.j + 0.5) * T.pitch;
   const double dx = p.x - cx, dy = p.y - cy;
+  const double u = (double)p.u, v = (double)p.v;
   double t_out = __builtin_inf(), t_in = __builtin_inf();
-  if (p.r < nr) t_out = dist_cylinder(dx, dy, p.u, p.v, T.radii[un * T.max_rings + p.r], true);
-  if (p.r > 0) t_in = dist_cylinder(dx, dy, p.u, p.v, T.radii[un * T.max_rings + p.r - 1], false);
-  double d_bnd = tx;
-  if (ty < d_bnd) d_bnd = ty;
+  if (p.r < nr) t_out = dist_cylinder(dx, dy, u, v, T.radii[un * T.max_rings + p.r], true);
+  if (p.r > 0) t_in = dist_cylinder(dx, dy, u, v, T.radii[un * T.max_rings + p.r - 1], false);
+  double d_bnd = (double)tx;
+  if ((double)ty < d_bnd) d_bnd = (double)ty;
   if (t_out < d_bnd) d_bnd = t_out;
   if (t_in < d_bnd) d_bnd = t_in;
 
-  const bool collide = d_col < d_bnd;
-  const double d = collide ? d_col : d_bnd;
-  p.x = p.x + d * p.u;
-  p.y = p.y + d * p.v;
+  const bool collide = (double)d_col < d_bnd;
+  const double d = collide ? (double)d_col : d_bnd;
+  p.x = p.x + d * u;
+  p.y = p.y + d * v;
 
   // track-length flux tally of this bin (cell, region, group); nu_sig_f is
   // constant in a bin, so the production tally and the track-length k
@@ -123,22 +211,21 @@ __device__ __forceinline__ int segment(const Tables& T, Part& p, Stream& rs, con
         A.tally + (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
     acc_add(tb + 2 * bin, qf);
   }
-  (void)nusf;
   if (REC) {
-    R.n_seg[p.id] += 1;
-    R.tl_sum[p.id] += d;
+    Rc.n_seg[p.id] += 1;
+    Rc.tl_sum[p.id] += d;
   }
   *refl_out = false;
   if (collide) return EV_COLLIDE;
 
-  if (REC) R.n_cross[p.id] += 1;
-  const bool hit_x = tx == d_bnd;
-  const bool hit_y = ty == d_bnd;
+  if (REC) Rc.n_cross[p.id] += 1;
+  const bool hit_x = (double)tx == d_bnd;
+  const bool hit_y = (double)ty == d_bnd;
   if (hit_x || hit_y) {
-    const bool out_x = hit_x && (p.u > 0.0 ? p.i == T.nx - 1 : p.i == 0);
-    const bool out_y = hit_y && (p.v > 0.0 ? p.j == T.ny - 1 : p.j == 0);
-    const int side_x = p.u > 0.0 ? 1 : 0;
-    const int side_y = p.v > 0.0 ? 3 : 2;
+    const bool out_x = hit_x && (p.u > R(0) ? p.i == T.nx - 1 : p.i == 0);
+    const bool out_y = hit_y && (p.v > R(0) ? p.j == T.ny - 1 : p.j == 0);
+    const int side_x = p.u > R(0) ? 1 : 0;
+    const int side_y = p.v > R(0) ? 3 : 2;
     if ((out_x && T.bc[side_x] == BC_VACUUM) || (out_y && T.bc[side_y] == BC_VACUUM))
       return EV_LEAK;
     bool refl = false;
@@ -147,7 +234,7 @@ __device__ __forceinline__ int segment(const Tables& T, Part& p, Stream& rs, con
         p.u = -p.u;
         refl = true;
       } else {
-        p.i += p.u > 0.0 ? 1 : -1;
+        p.i += p.u > R(0) ? 1 : -1;
       }
     }
     if (hit_y) {
@@ -155,10 +242,10 @@ __device__ __forceinline__ int segment(const Tables& T, Part& p, Stream& rs, con
         p.v = -p.v;
         refl = true;
       } else {
-        p.j += p.v > 0.0 ? 1 : -1;
+        p.j += p.v > R(0) ? 1 : -1;
       }
     }
-    if (REC && refl) R.n_refl[p.id] += 1;
+    if (REC && refl) Rc.n_refl[p.id] += 1;
     *refl_out = refl;
     // a lattice face lies outside every ring
     p.r = T.n_rings[T.pin_map[p.j * T.nx + p.i]];
@@ -173,37 +260,42 @@ __device__ __forceinline__ int segment(const Tables& T, Part& p, Stream& rs, con
 // Collision, first part: the collision estimator term and the number of
 // fission sites floor(nu_sig_f / (sig_t k_used) + xi) (one draw, in fissile
 // material of a k-eigenvalue run only).
+template <class R>
 struct ColXS {
   int m;
-  double st, nusf;
+  R st, nusf;
 };
 
-__device__ __forceinline__ ColXS col_xs(const Tables& T, const Part& p) {
+template <class R>
+__device__ __forceinline__ ColXS<R> col_xs(const Tables& T, const Part<R>& p) {
+  const XSView<R> X = xs_view<R>(T);
   const int un = T.pin_map[p.j * T.nx + p.i];
   const int m = T.mats[un * T.mr1 + p.r];
-  return ColXS{m, T.sig_t[m * T.G + p.g], T.nusf[m * T.G + p.g]};
+  return ColXS<R>{m, X.sig_t[m * T.G + p.g], X.nusf[m * T.G + p.g]};
 }
 
-__device__ __forceinline__ uint32_t fission_count(const Tables& T, const ColXS& x, Stream& rs,
+template <class R>
+__device__ __forceinline__ uint32_t fission_count(const Tables& T, const ColXS<R>& x, Stream& rs,
                                                   double k_used) {
-  if (T.fixed_source || !(x.nusf > 0.0)) return 0u;
-  const double xf = rs.next();
-  const double f = floor(x.nusf / (x.st * k_used) + xf);
+  if (T.fixed_source || !(x.nusf > R(0))) return 0u;
+  const R xf = Prec<R>::xi(rs.next());
+  const R f = floor(x.nusf / (x.st * (R)k_used) + xf);
   // a nonpositive k_used (only after a failed generation) must not loop forever
-  return f < 65536.0 ? (uint32_t)(int)f : 65536u;
+  return f < R(65536) ? (uint32_t)(int)f : 65536u;
 }
 
 // Collision, second part: write the nf sites reserved at slot, then scatter
 // (probability sig_s / sig_t: new group from the scattering row, isotropic
 // direction) or absorb.  Returns true if the particle scatters.
-template <bool REC>
-__device__ __forceinline__ bool collide_rest(const Tables& T, Part& p, Stream& rs,
-                                             const ColXS& x, uint32_t nf, uint32_t slot,
+template <class R, bool REC>
+__device__ __forceinline__ bool collide_rest(const Tables& T, Part<R>& p, Stream& rs,
+                                             const ColXS<R>& x, uint32_t nf, uint32_t slot,
                                              const Accum& A, uint64_t* q_kabs) {
+  const XSView<R> X = xs_view<R>(T);
   const int G = T.G;
   for (uint32_t s = 0; s < nf; ++s) {
-    const double xs = rs.next();
-    const int gs = sample_cum(xs, T.cum_chi + x.m * G, G, T.last_chi[x.m]);
+    const R xs = Prec<R>::xi(rs.next());
+    const int gs = sample_cum(xs, X.cum_chi + x.m * G, G, T.last_chi[x.m]);
     const uint32_t k = slot + s;
     if (k < A.fis_cap) {
       A.fis.x[k] = p.x;
@@ -217,19 +309,19 @@ __device__ __forceinline__ bool collide_rest(const Tables& T, Part& p, Stream& r
   }
   if (p.nsite + nf > 0xFFFFu) atomicOr(A.status, ST_OVERFLOW);
   p.nsite += nf;
-  const double xr = rs.next();
-  const double sst = T.sst[x.m * G + p.g];
+  const R xr = Prec<R>::xi(rs.next());
+  const R sst = X.sst[x.m * G + p.g];
   if (xr * x.st < sst) {
-    const double xg = rs.next();
+    const R xg = Prec<R>::xi(rs.next());
     const int row = x.m * G + p.g;
-    p.g = sample_cum(xg, T.cum_s + (size_t)row * G, G, T.last_s[row]);
-    const double xm = rs.next();
-    const double xp = rs.next();
-    isotropic_uv(xm, xp, &p.u, &p.v);
+    p.g = sample_cum(xg, X.cum_s + (size_t)row * G, G, T.last_s[row]);
+    const R xm = Prec<R>::xi(rs.next());
+    const R xp = Prec<R>::xi(rs.next());
+    Prec<R>::iso(xm, xp, &p.u, &p.v);
     *q_kabs = 0;
     return true;
   }
-  *q_kabs = x.nusf > 0.0 ? quantize(x.nusf / (x.st - sst), T.q_kabs) : 0;
+  *q_kabs = x.nusf > R(0) ? quantize((double)(x.nusf / (x.st - sst)), T.q_kabs) : 0;
   return false;
 }
 
@@ -243,7 +335,8 @@ __device__ __forceinline__ void wave_flag(unsigned long long* base, bool f) {
 // ---------------------------------------------------------------------------
 
 // Source site of history id in batch gen: rejection in the lattice's bounding
-// box until the point is in fissile material, then a fission-spectrum group.
+// box until the point is in fissile material, then a fission-spectrum group
+// (FP64 in both precisions).
 __global__ void k_source(Tables T, uint32_t gen, uint32_t n, double* sx, double* sy,
                          int32_t* sg, uint32_t* status) {
   const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
@@ -272,6 +365,7 @@ __global__ void k_source(Tables T, uint32_t gen, uint32_t n, double* sx, double*
 }
 
 // Birth: isotropic direction (transport draws 0 and 1), cell location.
+template <class R>
 __global__ void k_birth(Tables T, uint32_t gen, uint32_t n, const double* sx, const double* sy,
                         const int32_t* sg, Bank out, uint32_t* cnt_live, uint32_t* cnt_col,
                         const uint32_t* prev_status, uint32_t* status) {
@@ -285,14 +379,14 @@ __global__ void k_birth(Tables T, uint32_t gen, uint32_t n, const double* sx, co
     if (skip) atomicOr(status, ST_SKIPPED);
   }
   if (skip || id >= n) return;
-  Part p;
+  Part<R> p;
   p.x = sx[id];
   p.y = sy[id];
   p.g = sg[id];
   Stream rs(T.seed, TAG_TRANSPORT, id, gen, T.prob, 0);
-  const double xm = rs.next();
-  const double xp = rs.next();
-  isotropic_uv(xm, xp, &p.u, &p.v);
+  const R xm = Prec<R>::xi(rs.next());
+  const R xp = Prec<R>::xi(rs.next());
+  Prec<R>::iso(xm, xp, &p.u, &p.v);
   locate(T, p.x, p.y, &p.i, &p.j, &p.r);
   p.nsite = 0;
   p.ctr = rs.draw;
@@ -308,11 +402,11 @@ __global__ void k_birth(Tables T, uint32_t gen, uint32_t n, const double* sx, co
 // cross a surface and stay inside go to the live bank of the next iteration,
 // particles that collide go to the collision bank; leaks and guard kills end
 // here.  Block 0 clears the counters the next iteration appends to.
-template <bool REC>
+template <class R, bool REC>
 __global__ void __launch_bounds__(1024) k_advance(Tables T, uint32_t gen, uint32_t it, Bank in,
                                                   const uint32_t* __restrict__ n_in_p, Bank live,
                                                   uint32_t* n_live, Bank col, uint32_t* n_col,
-                                                  Accum A, Records R, uint32_t* clr_live,
+                                                  Accum A, Records Rc, uint32_t* clr_live,
                                                   uint32_t* clr_col) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *clr_live = 0;
@@ -322,17 +416,17 @@ __global__ void __launch_bounds__(1024) k_advance(Tables T, uint32_t gen, uint32
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   int ev = EV_NONE;
   bool refl = false;
-  Part p;
+  Part<R> p;
   if (k < n_in) {
-    p = load_part(in, k);
+    p = load_part<R>(in, k);
     if ((int64_t)it >= T.max_events) {
       ev = EV_KILL;
-      die<REC>(p, FATE_KILLED, A, R);
+      die<R, REC>(p, FATE_KILLED, A, Rc);
     } else {
       Stream rs(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
-      ev = segment<REC, false>(T, p, rs, A, R, &refl);
+      ev = segment<R, REC, false>(T, p, rs, A, Rc, &refl);
       p.ctr = rs.draw;
-      if (ev == EV_LEAK) die<REC>(p, FATE_LEAKED, A, R);
+      if (ev == EV_LEAK) die<R, REC>(p, FATE_LEAKED, A, Rc);
     }
   }
   __shared__ uint32_t lds[2 * (MAX_WAVES + 1)];
@@ -349,29 +443,29 @@ __global__ void __launch_bounds__(1024) k_advance(Tables T, uint32_t gen, uint32
 }
 
 // Process the collision bank: collision estimator, fission-bank append
-// (wave-aggregated reservation), scatter to the live bank or absorb.
-template <bool REC>
+// (block-aggregated reservation), scatter to the live bank or absorb.
+template <class R, bool REC>
 __global__ void __launch_bounds__(1024) k_collide(Tables T, uint32_t gen, Bank in,
                                                   const uint32_t* __restrict__ n_in_p, Bank live,
-                                                  uint32_t* n_live, Accum A, Records R) {
+                                                  uint32_t* n_live, Accum A, Records Rc) {
   const uint32_t n_in = *n_in_p;
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = k < n_in;
   const double k_used = *A.k_used;
-  Part p;
-  ColXS x{0, 1.0, 0.0};
+  Part<R> p;
+  ColXS<R> x{0, R(1), R(0)};
   uint32_t nf = 0;
   uint64_t q_kcol = 0;
   Stream rs(T.seed, TAG_TRANSPORT, 0, gen, T.prob, 0);
   if (valid) {
-    p = load_part(in, k);
+    p = load_part<R>(in, k);
     rs = Stream(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
     x = col_xs(T, p);
-    const double kc = x.nusf / x.st;
+    const double kc = (double)(x.nusf / x.st);
     q_kcol = quantize(kc, T.q_kcol);
     if (REC) {
-      R.n_col[p.id] += 1;
-      R.kcol_sum[p.id] += kc;
+      Rc.n_col[p.id] += 1;
+      Rc.kcol_sum[p.id] += kc;
     }
     nf = fission_count(T, x, rs, k_used);
   }
@@ -380,9 +474,9 @@ __global__ void __launch_bounds__(1024) k_collide(Tables T, uint32_t gen, Bank i
   bool alive = false;
   uint64_t q_kabs = 0;
   if (valid) {
-    alive = collide_rest<REC>(T, p, rs, x, nf, slot, A, &q_kabs);
+    alive = collide_rest<R, REC>(T, p, rs, x, nf, slot, A, &q_kabs);
     p.ctr = rs.draw;
-    if (!alive) die<REC>(p, FATE_ABSORBED, A, R);
+    if (!alive) die<R, REC>(p, FATE_ABSORBED, A, Rc);
   }
   const uint32_t pl = block_reserve(alive ? 1u : 0u, n_live, lds);
   if (alive) store_part(live, pl, p);
@@ -398,10 +492,10 @@ __global__ void __launch_bounds__(1024) k_collide(Tables T, uint32_t gen, Bank i
 // History-based finish of the last live particles: one lane runs its
 // particle's remaining flights and collisions to the end (the same
 // operations as the event kernels, in the same order).
-template <bool REC>
+template <class R, bool REC>
 __global__ void __launch_bounds__(256) k_tail(Tables T, uint32_t gen, uint32_t it0, Bank in,
                                               const uint32_t* __restrict__ n_in_p, Accum A,
-                                              Records R) {
+                                              Records Rc) {
   const uint32_t n_in = *n_in_p;
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long c_seg = 0, c_col = 0, c_cross = 0, c_refl = 0, c_leak = 0, c_abs = 0,
@@ -409,25 +503,25 @@ __global__ void __launch_bounds__(256) k_tail(Tables T, uint32_t gen, uint32_t i
   unsigned long long kcol[2] = {0, 0}, kabs[2] = {0, 0};
   if (k < n_in) {
     const double k_used = *A.k_used;
-    Part p = load_part(in, k);
+    Part<R> p = load_part<R>(in, k);
     Stream rs(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
     int64_t nseg = it0;
     for (;;) {
       if (nseg >= T.max_events) {
         p.ctr = rs.draw;
-        die<REC>(p, FATE_KILLED, A, R);
+        die<R, REC>(p, FATE_KILLED, A, Rc);
         ++c_kill;
         break;
       }
       bool refl = false;
-      const int ev = segment<REC, true>(T, p, rs, A, R, &refl);
+      const int ev = segment<R, REC, true>(T, p, rs, A, Rc, &refl);
       ++nseg;
       ++c_seg;
       if (ev == EV_LEAK) {
         ++c_cross;
         ++c_leak;
         p.ctr = rs.draw;
-        die<REC>(p, FATE_LEAKED, A, R);
+        die<R, REC>(p, FATE_LEAKED, A, Rc);
         break;
       }
       if (ev == EV_CROSS) {
@@ -436,26 +530,26 @@ __global__ void __launch_bounds__(256) k_tail(Tables T, uint32_t gen, uint32_t i
         continue;
       }
       ++c_col;
-      const ColXS x = col_xs(T, p);
-      const double kc = x.nusf / x.st;
+      const ColXS<R> x = col_xs(T, p);
+      const double kc = (double)(x.nusf / x.st);
       const uint64_t q = quantize(kc, T.q_kcol);
       kcol[0] += q & 0xFFFFFFFFull;
       kcol[1] += q >> 32;
       if (REC) {
-        R.n_col[p.id] += 1;
-        R.kcol_sum[p.id] += kc;
+        Rc.n_col[p.id] += 1;
+        Rc.kcol_sum[p.id] += kc;
       }
       const uint32_t nf = fission_count(T, x, rs, k_used);
       const uint32_t slot = nf ? atomicAdd(A.n_fis, nf) : 0u;
       c_sites += nf;
       uint64_t qa = 0;
-      const bool alive = collide_rest<REC>(T, p, rs, x, nf, slot, A, &qa);
+      const bool alive = collide_rest<R, REC>(T, p, rs, x, nf, slot, A, &qa);
       if (!alive) {
         kabs[0] += qa & 0xFFFFFFFFull;
         kabs[1] += qa >> 32;
         ++c_abs;
         p.ctr = rs.draw;
-        die<REC>(p, FATE_ABSORBED, A, R);
+        die<R, REC>(p, FATE_ABSORBED, A, Rc);
         break;
       }
       ++c_scat;
@@ -868,50 +962,90 @@ hipError_t launch_source(const Tables& T, uint32_t gen, uint32_t n, double* sx, 
   return hipGetLastError();
 }
 
-hipError_t launch_birth(const Tables& T, uint32_t gen, uint32_t n, const double* sx,
+hipError_t launch_birth(int prec, const Tables& T, uint32_t gen, uint32_t n, const double* sx,
                         const double* sy, const int32_t* sg, const Bank& out, uint32_t* cnt_live,
                         uint32_t* cnt_col, const uint32_t* prev_status, uint32_t* status,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_birth, dim3(nblk(n, 256)), dim3(256), 0, s, T, gen, n, sx, sy, sg, out,
-                     cnt_live, cnt_col, prev_status, status);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_birth<double>, dim3(nblk(n, 256)), dim3(256), 0, s, T, gen, n, sx, sy,
+                       sg, out, cnt_live, cnt_col, prev_status, status);
+  else
+    hipLaunchKernelGGL(k_birth<float>, dim3(nblk(n, 256)), dim3(256), 0, s, T, gen, n, sx, sy, sg,
+                       out, cnt_live, cnt_col, prev_status, status);
   return hipGetLastError();
 }
 
-hipError_t launch_advance(bool rec, const Tables& T, uint32_t gen, uint32_t it, const Bank& in,
+template <class R, bool REC>
+static void advance_k(dim3 g, dim3 b, hipStream_t s, const Tables& T, uint32_t gen, uint32_t it,
+                      const Bank& in, const uint32_t* n_in, const Bank& live, uint32_t* n_live,
+                      const Bank& col, uint32_t* n_col, const Accum& A, const Records& Rc,
+                      uint32_t* clr_live, uint32_t* clr_col) {
+  hipLaunchKernelGGL((k_advance<R, REC>), g, b, 0, s, T, gen, it, in, n_in, live, n_live, col,
+                     n_col, A, Rc, clr_live, clr_col);
+}
+
+hipError_t launch_advance(int prec, bool rec, const Tables& T, uint32_t gen, uint32_t it,
+                          const Bank& in, const uint32_t* n_in, const Bank& live,
+                          uint32_t* n_live, const Bank& col, uint32_t* n_col, const Accum& A,
+                          const Records& Rc, uint32_t* clr_live, uint32_t* clr_col,
+                          uint32_t bound, int block, hipStream_t s) {
+  const dim3 g(std::max(1u, nblk(bound, block))), b(block);
+  if (prec == 0) {
+    if (rec)
+      advance_k<double, true>(g, b, s, T, gen, it, in, n_in, live, n_live, col, n_col, A, Rc,
+                              clr_live, clr_col);
+    else
+      advance_k<double, false>(g, b, s, T, gen, it, in, n_in, live, n_live, col, n_col, A, Rc,
+                               clr_live, clr_col);
+  } else {
+    if (rec)
+      advance_k<float, true>(g, b, s, T, gen, it, in, n_in, live, n_live, col, n_col, A, Rc,
+                             clr_live, clr_col);
+    else
+      advance_k<float, false>(g, b, s, T, gen, it, in, n_in, live, n_live, col, n_col, A, Rc,
+                              clr_live, clr_col);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_collide(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in,
                           const uint32_t* n_in, const Bank& live, uint32_t* n_live,
-                          const Bank& col, uint32_t* n_col, const Accum& A, const Records& R,
-                          uint32_t* clr_live, uint32_t* clr_col, uint32_t bound, int block,
+                          const Accum& A, const Records& Rc, uint32_t bound, int block,
                           hipStream_t s) {
   const dim3 g(std::max(1u, nblk(bound, block))), b(block);
-  if (rec)
-    hipLaunchKernelGGL(k_advance<true>, g, b, 0, s, T, gen, it, in, n_in, live, n_live, col,
-                       n_col, A, R, clr_live, clr_col);
-  else
-    hipLaunchKernelGGL(k_advance<false>, g, b, 0, s, T, gen, it, in, n_in, live, n_live, col,
-                       n_col, A, R, clr_live, clr_col);
+  if (prec == 0) {
+    if (rec)
+      hipLaunchKernelGGL((k_collide<double, true>), g, b, 0, s, T, gen, in, n_in, live, n_live, A,
+                         Rc);
+    else
+      hipLaunchKernelGGL((k_collide<double, false>), g, b, 0, s, T, gen, in, n_in, live, n_live,
+                         A, Rc);
+  } else {
+    if (rec)
+      hipLaunchKernelGGL((k_collide<float, true>), g, b, 0, s, T, gen, in, n_in, live, n_live, A,
+                         Rc);
+    else
+      hipLaunchKernelGGL((k_collide<float, false>), g, b, 0, s, T, gen, in, n_in, live, n_live, A,
+                         Rc);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_collide(bool rec, const Tables& T, uint32_t gen, const Bank& in,
-                          const uint32_t* n_in, const Bank& live, uint32_t* n_live,
-                          const Accum& A, const Records& R, uint32_t bound, int block,
-                          hipStream_t s) {
-  const dim3 g(std::max(1u, nblk(bound, block))), b(block);
-  if (rec)
-    hipLaunchKernelGGL(k_collide<true>, g, b, 0, s, T, gen, in, n_in, live, n_live, A, R);
-  else
-    hipLaunchKernelGGL(k_collide<false>, g, b, 0, s, T, gen, in, n_in, live, n_live, A, R);
-  return hipGetLastError();
-}
-
-hipError_t launch_tail(bool rec, const Tables& T, uint32_t gen, uint32_t it0, const Bank& in,
-                       const uint32_t* n_in, const Accum& A, const Records& R, uint32_t bound,
-                       hipStream_t s) {
+hipError_t launch_tail(int prec, bool rec, const Tables& T, uint32_t gen, uint32_t it0,
+                       const Bank& in, const uint32_t* n_in, const Accum& A, const Records& Rc,
+                       uint32_t bound, hipStream_t s) {
   const dim3 g(std::max(1u, nblk(bound, 64))), b(64);
-  if (rec)
-    hipLaunchKernelGGL(k_tail<true>, g, b, 0, s, T, gen, it0, in, n_in, A, R);
-  else
-    hipLaunchKernelGGL(k_tail<false>, g, b, 0, s, T, gen, it0, in, n_in, A, R);
+  if (prec == 0) {
+    if (rec)
+      hipLaunchKernelGGL((k_tail<double, true>), g, b, 0, s, T, gen, it0, in, n_in, A, Rc);
+    else
+      hipLaunchKernelGGL((k_tail<double, false>), g, b, 0, s, T, gen, it0, in, n_in, A, Rc);
+  } else {
+    if (rec)
+      hipLaunchKernelGGL((k_tail<float, true>), g, b, 0, s, T, gen, it0, in, n_in, A, Rc);
+    else
+      hipLaunchKernelGGL((k_tail<float, false>), g, b, 0, s, T, gen, it0, in, n_in, A, Rc);
+  }
   return hipGetLastError();
 }
 

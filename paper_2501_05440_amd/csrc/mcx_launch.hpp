@@ -13,24 +13,25 @@ namespace mcx {
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_source(const Tables& T, uint32_t gen, uint32_t n, double* sx, double* sy,
                          int32_t* sg, uint32_t* status, hipStream_t s);
-hipError_t launch_birth(const Tables& T, uint32_t gen, uint32_t n, const double* sx,
+// prec: 0 = FP64, 1 = FP32-mixed
+hipError_t launch_birth(int prec, const Tables& T, uint32_t gen, uint32_t n, const double* sx,
                         const double* sy, const int32_t* sg, const Bank& out, uint32_t* cnt_live,
                         uint32_t* cnt_col, const uint32_t* prev_status, uint32_t* status,
                         hipStream_t s);
 hipError_t launch_gen_check(const Tables& T, const uint32_t* n_fis, const uint32_t* scan_total,
                             uint32_t* status, hipStream_t s);
-hipError_t launch_advance(bool rec, const Tables& T, uint32_t gen, uint32_t it, const Bank& in,
+hipError_t launch_advance(int prec, bool rec, const Tables& T, uint32_t gen, uint32_t it,
+                          const Bank& in, const uint32_t* n_in, const Bank& live,
+                          uint32_t* n_live, const Bank& col, uint32_t* n_col, const Accum& A,
+                          const Records& Rc, uint32_t* clr_live, uint32_t* clr_col,
+                          uint32_t bound, int block, hipStream_t s);
+hipError_t launch_collide(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in,
                           const uint32_t* n_in, const Bank& live, uint32_t* n_live,
-                          const Bank& col, uint32_t* n_col, const Accum& A, const Records& R,
-                          uint32_t* clr_live, uint32_t* clr_col, uint32_t bound, int block,
+                          const Accum& A, const Records& Rc, uint32_t bound, int block,
                           hipStream_t s);
-hipError_t launch_collide(bool rec, const Tables& T, uint32_t gen, const Bank& in,
-                          const uint32_t* n_in, const Bank& live, uint32_t* n_live,
-                          const Accum& A, const Records& R, uint32_t bound, int block,
-                          hipStream_t s);
-hipError_t launch_tail(bool rec, const Tables& T, uint32_t gen, uint32_t it0, const Bank& in,
-                       const uint32_t* n_in, const Accum& A, const Records& R, uint32_t bound,
-                       hipStream_t s);
+hipError_t launch_tail(int prec, bool rec, const Tables& T, uint32_t gen, uint32_t it0,
+                       const Bank& in, const uint32_t* n_in, const Accum& A, const Records& Rc,
+                       uint32_t bound, hipStream_t s);
 uint32_t scan_chunks(uint32_t n);
 hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* chunk_sum, uint32_t* out,
                        uint32_t* total, hipStream_t s);

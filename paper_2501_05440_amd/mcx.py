@@ -131,7 +131,7 @@ class Context:
 
     def __init__(self, problem, device=0, record=False, block_size=0, tail_threshold=0,
                  lookahead=0, max_events=None, time_kernels=False, n_gen_max=None,
-                 stream=None):
+                 stream=None, precision="fp64"):
         import torch
 
         self.problem = problem
@@ -143,7 +143,9 @@ class Context:
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         rp = problem["run"]
         o = Options()
-        o.precision = FP64
+        if precision not in ("fp64", "fp32"):
+            raise ValueError("precision is 'fp64' or 'fp32' (FP32-mixed)")
+        o.precision = FP64 if precision == "fp64" else FP32_MIXED
         o.device = device
         o.stream = self.stream.cuda_stream
         o.block_size = block_size
