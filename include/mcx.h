@@ -53,6 +53,7 @@ enum mcx_status {
 };
 
 enum { MCX_FP64 = 0, MCX_FP32_MIXED = 1 };
+enum { MCX_ENGINE_EVENT = 0, MCX_ENGINE_PERSISTENT = 1 };
 enum { MCX_VACUUM = 0, MCX_REFLECT = 1 };
 enum { MCX_FATE_ABSORBED = 1, MCX_FATE_LEAKED = 2, MCX_FATE_KILLED = 3 };
 
@@ -84,6 +85,20 @@ typedef struct {
   int64_t max_events;       /* per-history segment guard; 0 = 100000 */
   int32_t record_histories; /* 1: keep one mcx_record per history per generation */
   int32_t time_kernels;     /* 1: time every event kernel with HIP events (mcx_get_timing) */
+  /* Engine.  MCX_ENGINE_EVENT launches one kernel per event class and
+     iteration over banks compacted in device memory (the structure of the
+     paper's Sec. 2).  MCX_ENGINE_PERSISTENT runs each generation (or batch)
+     as one kernel whose workgroups keep particles in LDS slots, process them
+     event by event over block-local queues, and refill free slots from a
+     global history counter; batches (mcx_load_batch) always use it.  Both
+     engines give identical per-history results.  record_histories requires
+     the event engine. */
+  int32_t engine;
+  int32_t p_block;          /* persistent: threads per block, 128 or 256; 0 = 256 */
+  int32_t p_slots;          /* persistent: particle slots per block, 256 or 512; 0 = 512 */
+  int32_t p_grid;           /* persistent: workgroups; 0 = 2 per compute unit */
+  double p_tau;             /* persistent: refill when fewer than p_tau * p_slots particles
+                               of a block are live, 0 < p_tau <= 1; 0 = 0.75 */
 } mcx_options;
 
 /* Lattice of pin universes (paper Sec. 1: CSG geometry).  Cell (i, j),
@@ -130,7 +145,7 @@ typedef struct {
   double x_final, y_final;
 } mcx_record;
 
-/* Timing of the last mcx_run_generations.  The *_ms kernel sums are filled
+/* Timing of the last mcx_run_generations or mcx_run_batch.  The *_ms kernel sums are filled
    when time_kernels = 1 (events recorded on the stream around each launch);
    *_items count the particles each kernel class processed. */
 typedef struct {
@@ -141,7 +156,35 @@ typedef struct {
   int64_t n_advance, n_collide;
   int64_t advance_items;    /* particles processed by advance kernels (= their segments + kills) */
   int64_t collide_items;    /* collisions processed by collide kernels */
+  double persistent_ms;     /* persistent-engine kernels (time_kernels = 1) */
+  int64_t n_persistent;
 } mcx_timing;
+
+/* One problem of a batch: its lattice, multigroup data (as for
+   mcx_load_geometry and mcx_load_mg_xs, material indices local to the
+   problem), random-number seed and problem id, and history count.  A batch
+   problem is a single fixed-source generation (fission treated as capture,
+   production tallied), with the source of mcx_source; problem_id keys its
+   random numbers exactly as in a single-problem run, so a problem gives the
+   same histories inside a batch and alone. */
+typedef struct {
+  mcx_geometry geo;
+  int32_t n_mat, n_grp;
+  const double* sig_t;
+  const double* sig_s;
+  const double* nu_sig_f;
+  const double* chi;
+  uint64_t seed;
+  int64_t n_hist;           /* >= 1 */
+  uint64_t problem_id;
+} mcx_problem;
+
+/* Persistent-engine launch configuration (mcx_autotune). */
+typedef struct {
+  int32_t block, slots, grid;
+  double tau;
+  double ms;                /* measured stream time of one batch (or generation) */
+} mcx_tune;
 
 /* Create a context on opt->device (NULL opt = defaults). */
 int mcx_create(mcx_ctx** out, const mcx_options* opt);
@@ -201,6 +244,40 @@ int mcx_get_records(mcx_ctx* ctx, int32_t gen, mcx_record* out, int64_t n);
 int mcx_get_bank(mcx_ctx* ctx, double* xyg, int64_t cap, int64_t* len);
 
 int mcx_get_timing(mcx_ctx* ctx, mcx_timing* out);
+
+/* Load a batch of independent fixed-source problems (the batched form of
+   the method: many problems of uneven size in one launch).  Every problem is
+   validated as by mcx_load_geometry / mcx_load_mg_xs; all must share n_grp;
+   1 <= n_probs <= 65535 and the total history count must stay below 2^32.
+   Replaces any single problem loaded before (and vice versa); bind a
+   workspace (mcx_workspace_size / mcx_bind_workspace with n_gen_max = 1)
+   afterwards. */
+int mcx_load_batch(mcx_ctx* ctx, int32_t n_probs, const mcx_problem* probs);
+
+/* Run the loaded batch: one generation of every problem in one persistent
+   launch, recorded once as a HIP graph (fill, transport, per-problem
+   reduction) and replayed on ctx's stream.  Blocks until done.  Returns
+   MCX_ELOST, MCX_EGUARD (results readable) or MCX_EDEVICE on failure. */
+int mcx_run_batch(mcx_ctx* ctx);
+
+/* Per-problem results of the last batch, per source particle: k[p][3] =
+   collision, track-length and absorption production estimators;
+   counts[p][MCX_N_CNT].  Either may be NULL. */
+int mcx_get_batch_results(mcx_ctx* ctx, double* k, int64_t* counts);
+
+/* Flux and production tallies of problem p of the last batch, per source
+   particle, in that problem's own bin order (as mcx_get_tallies);
+   n_bins = nx * ny * (max_rings + 1) * n_grp of problem p. */
+int mcx_get_batch_tallies(mcx_ctx* ctx, int32_t p, double* flux, double* prod, int64_t n_bins);
+
+/* Pick the persistent-engine configuration (block, slots, grid, tau) with
+   the shortest measured run of the bound problem or batch by timing a sweep
+   of candidates on ctx's stream, and use it from then on.  A non-NULL
+   cache_path names a text file of earlier results keyed by the workload's
+   shape and the device: a hit skips the sweep, a miss appends the winner.
+   Results do not depend on the configuration.  Overwrites the results of
+   the last run. */
+int mcx_autotune(mcx_ctx* ctx, const char* cache_path, mcx_tune* best);
 
 /* Diagnostics of the device arithmetic (device pointers, on ctx's stream):
    which = 0: out[i] = ln(in[i]); 1: out[2i], out[2i+1] = cos, sin(2 pi in[i]);

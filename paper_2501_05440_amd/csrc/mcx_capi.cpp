@@ -74,6 +74,19 @@ struct Dev {
   uint32_t* ent_hist = nullptr;
   double* ent_term = nullptr;
   uint32_t* gen_status = nullptr;  // [n_gen_max] status bits per generation
+  // persistent engine: per-history outputs, work counter
+  unsigned long long* h_kcol = nullptr;
+  unsigned long long* h_kabs = nullptr;
+  uint32_t* h_cnt = nullptr;
+  uint32_t* work = nullptr;
+  uint64_t n_hist = 0;
+  // batches: problem descriptors and per-problem results
+  ProbDesc* probs = nullptr;
+  unsigned long long* prob_cnt = nullptr;  // [P][N_CNT]
+  unsigned long long* prob_k = nullptr;    // [P][4] 128-bit k_col, k_abs sums
+  double* prob_kres = nullptr;             // [P][3]
+  double* b_flux = nullptr;                // [bins]
+  double* b_prod = nullptr;
   unsigned long long* acc_base = nullptr;
   size_t acc_words = 0;
   unsigned long long* rec_base = nullptr;
@@ -111,6 +124,27 @@ struct mcx_ctx {
   std::vector<uint32_t> h_gen_m;
   std::vector<mcx_record> h_rec;
   mcx_timing timing{};
+
+  // batches of fixed-source problems (persistent engine)
+  bool batch = false;
+  int n_probs = 0;
+  struct BProb {
+    int nx, ny, max_rings, pin_base, univ_base, radii_base, mats_base, bin_base, n_bins;
+    double pitch, x0, y0;
+    int bc[4];
+    uint64_t seed, prob, hist_base;
+    uint32_t n_hist;
+  };
+  std::vector<BProb> bprobs;
+  uint64_t batch_hist = 0;
+  int batch_bins = 0;
+  bool batch_ran = false;
+  std::vector<double> h_bk;
+  std::vector<unsigned long long> h_bcnt;
+  PersistentCfg pcfg{};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream the batch graph is recorded on
 
   // host-side synchronisation helpers
   uint32_t* h_pin = nullptr;  // [RING] live counts + [RING..] status words
@@ -156,6 +190,28 @@ int mcx_create(mcx_ctx** out, const mcx_options* opt) {
   if (c->opt.lookahead <= 0) c->opt.lookahead = DEFAULT_LOOKAHEAD;
   if (c->opt.lookahead > RING - 2) c->opt.lookahead = RING - 2;
   if (c->opt.max_events <= 0) c->opt.max_events = DEFAULT_MAX_EVENTS;
+  if (c->opt.engine != MCX_ENGINE_EVENT && c->opt.engine != MCX_ENGINE_PERSISTENT) {
+    delete c;
+    return MCX_EINVAL;
+  }
+  if (c->opt.engine == MCX_ENGINE_PERSISTENT && c->opt.record_histories) {
+    delete c;
+    return MCX_EINVAL;
+  }
+  {
+    int dev_cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->opt.device) == hipSuccess) dev_cus = prop.multiProcessorCount;
+    c->pcfg.block = c->opt.p_block ? c->opt.p_block : 256;
+    c->pcfg.slots = c->opt.p_slots ? c->opt.p_slots : 512;
+    c->pcfg.grid = c->opt.p_grid ? c->opt.p_grid : 2 * dev_cus;
+    c->pcfg.tau = c->opt.p_tau > 0.0 ? c->opt.p_tau : 0.75;
+    if (!persistent_config_valid(c->pcfg.block, c->pcfg.slots) || c->pcfg.tau > 1.0 ||
+        c->opt.p_grid < 0 || c->opt.p_grid > (1 << 20)) {
+      delete c;
+      return MCX_EINVAL;
+    }
+  }
   c->stream = (hipStream_t)c->opt.stream;
   if (hipSetDevice(c->opt.device) != hipSuccess) {
     delete c;
@@ -182,6 +238,9 @@ int mcx_create(mcx_ctx** out, const mcx_options* opt) {
 
 void mcx_destroy(mcx_ctx* c) {
   if (!c) return;
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (int k = 0; k < RING; ++k)
     if (c->ev_ring[k]) (void)hipEventDestroy(c->ev_ring[k]);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -218,6 +277,10 @@ int mcx_load_geometry(mcx_ctx* c, const mcx_geometry* g) {
     for (int k = 0; k <= nr; ++k)
       if (g->mats[u * mr1 + k] < 0) return fail(c, MCX_EINVAL, "ring material");
   }
+  if (c->batch) {  // a single problem replaces the batch: its tables go too
+    c->has_xs = false;
+    c->batch = false;
+  }
   c->nx = g->nx;
   c->ny = g->ny;
   c->pitch = g->pitch;
@@ -231,6 +294,7 @@ int mcx_load_geometry(mcx_ctx* c, const mcx_geometry* g) {
   c->mats.assign(g->mats, g->mats + (size_t)g->n_univ * mr1);
   c->pin_map.assign(g->pin_map, g->pin_map + (size_t)g->nx * g->ny);
   c->has_geo = true;
+  c->batch = false;
   c->bound = false;
   return MCX_OK;
 }
@@ -307,6 +371,10 @@ int mcx_load_mg_xs(mcx_ctx* c, int32_t n_mat, int32_t n_grp, const double* sig_t
       cum_chi_f[mg] = cchi;
     }
   }
+  if (c->batch) {  // a single problem replaces the batch: its lattices go too
+    c->has_geo = false;
+    c->batch = false;
+  }
   c->sig_t_f = std::move(sig_t_f);
   c->nusf_f = std::move(nusf_f);
   c->sst_f = std::move(sst_f);
@@ -342,20 +410,23 @@ int mcx_seed_source(mcx_ctx* c, const mcx_source* s) {
 // Carve the workspace (base == nullptr only measures it).
 static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   Carver cv(base);
-  const size_t N = (size_t)c->src.n_per_gen;
+  const bool batch = c->batch;
+  const size_t N = batch ? 0 : (size_t)c->src.n_per_gen;
   const int mr1 = c->max_rings + 1;
   const size_t MG = (size_t)c->n_mat * c->G;
-  const int nb = c->nx * c->ny * mr1 * c->G;
+  const int nb = batch ? c->batch_bins : c->nx * c->ny * mr1 * c->G;
+  const uint64_t n_hist = batch ? c->batch_hist : (uint64_t)N;
+  const bool persistent = batch || c->opt.engine == MCX_ENGINE_PERSISTENT;
   const int stripes = std::max(1, std::min(STRIPES, 65536 / std::max(1, 2 * nb)));
   const uint32_t fis_cap = (uint32_t)std::min<size_t>(2 * N + 4096, 0xFFFFFFF0u);
   const size_t n_ent = (size_t)c->src.ent_nx * c->src.ent_ny;
   const size_t n_cnt_slots = (size_t)c->opt.max_events + 4;
 
   Tables& T = d.T;
-  T.pin_map = cv.take<int>((size_t)c->nx * c->ny);
-  T.n_rings = cv.take<int>(c->n_univ);
-  T.radii = cv.take<double>((size_t)c->n_univ * c->max_rings);
-  T.mats = cv.take<int>((size_t)c->n_univ * mr1);
+  T.geo.pin_map = cv.take<int>(c->pin_map.size());
+  T.geo.n_rings = cv.take<int>(c->n_rings.size());
+  T.geo.radii = cv.take<double>(c->radii.size());
+  T.geo.mats = cv.take<int>(c->mats.size());
   T.sig_t = cv.take<double>(MG);
   T.nusf = cv.take<double>(MG);
   T.sst = cv.take<double>(MG);
@@ -399,11 +470,23 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   d.can_x = cv.take<double>(fis_cap);
   d.can_y = cv.take<double>(fis_cap);
   d.can_g = cv.take<int32_t>(fis_cap);
-  A.nsite_id = cv.take<uint32_t>(N);
+  A.nsite_id = cv.take<uint32_t>(std::max<size_t>(N, n_hist));
+  if (persistent) {
+    d.h_kcol = cv.take<unsigned long long>(2 * n_hist);
+    d.h_kabs = cv.take<unsigned long long>(n_hist);
+    d.h_cnt = cv.take<uint32_t>((size_t)7 * n_hist);
+  }
+  d.n_hist = n_hist;
+  if (batch) {
+    d.probs = cv.take<ProbDesc>(c->n_probs);
+    d.prob_kres = cv.take<double>((size_t)3 * c->n_probs);
+    d.b_flux = cv.take<double>(nb);
+    d.b_prod = cv.take<double>(nb);
+  }
   d.offs = cv.take<uint32_t>(N);
   d.chunk_sum = cv.take<uint32_t>(scan_chunks((uint32_t)N) + 1);
   d.scan_total = cv.take<uint32_t>(1);
-  d.gen_status = cv.take<uint32_t>(n_gen_max);
+  d.gen_status = cv.take<uint32_t>((size_t)n_gen_max + 1);  // cleared in 8-byte words
   A.status = d.gen_status;
   d.cnt_live = cv.take<uint32_t>(n_cnt_slots);
   d.cnt_col = cv.take<uint32_t>(n_cnt_slots);
@@ -412,16 +495,24 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   const size_t w_tally_t = (size_t)2 * nb;
   const size_t w_k = 3 * STRIPES * 2;
   const size_t w_cnt = (size_t)N_CNT_ALL * STRIPES;
-  const size_t w_misc = 1 + (n_ent + 1) / 2;
-  d.acc_words = w_tally + w_tally_t + w_k + w_cnt + w_misc;
+  const size_t w_misc = 2 + (n_ent + 1) / 2;
+  const size_t w_prob = batch ? (size_t)c->n_probs * (N_CNT + 4) : 0;
+  d.acc_words = w_tally + w_tally_t + w_k + w_cnt + w_prob + w_misc;
   d.acc_base = cv.take<unsigned long long>(d.acc_words);
   if (base) {
     A.tally = d.acc_base;
     A.tally_t = A.tally + w_tally;
     A.k = A.tally_t + w_tally_t;
     A.cnt = A.k + w_k;
-    A.n_fis = reinterpret_cast<uint32_t*>(A.cnt + w_cnt);
-    d.ent_hist = reinterpret_cast<uint32_t*>(A.cnt + w_cnt + 1);
+    unsigned long long* pw = A.cnt + w_cnt;
+    if (batch) {
+      d.prob_cnt = pw;
+      d.prob_k = pw + (size_t)c->n_probs * N_CNT;
+    }
+    pw += w_prob;
+    A.n_fis = reinterpret_cast<uint32_t*>(pw);
+    d.work = reinterpret_cast<uint32_t*>(pw + 1);
+    d.ent_hist = reinterpret_cast<uint32_t*>(pw + 2);
   }
   // results
   d.gen_k = cv.take<double>((size_t)3 * n_gen_max);
@@ -471,9 +562,13 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   return cv.off + 256;
 }
 
+static bool loaded(const mcx_ctx* c) {
+  return c->batch ? (c->has_geo && c->has_xs) : (c->has_geo && c->has_xs && c->has_src);
+}
+
 int mcx_workspace_size(mcx_ctx* c, int32_t n_gen_max, size_t* bytes) {
   if (!c || !bytes || n_gen_max < 1) return MCX_EINVAL;
-  if (!c->has_geo || !c->has_xs || !c->has_src) return fail(c, MCX_ESTATE, "load and seed first");
+  if (!loaded(c)) return fail(c, MCX_ESTATE, "load and seed first");
   Dev scratch;
   *bytes = carve(c, scratch, nullptr, n_gen_max);
   return MCX_OK;
@@ -483,13 +578,23 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
   if (!c || !ptr || n_gen_max < 1) return MCX_EINVAL;
   c->bound = false;
   c->ran = false;
-  if (!c->has_geo || !c->has_xs || !c->has_src) return fail(c, MCX_ESTATE, "load and seed first");
+  c->batch_ran = false;
+  if (c->graph_exec) {
+    (void)hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = nullptr;
+  }
+  if (c->graph) {
+    (void)hipGraphDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  if (!loaded(c)) return fail(c, MCX_ESTATE, "load and seed first");
   if ((uintptr_t)ptr % 256) return fail(c, MCX_EINVAL, "workspace must be 256-byte aligned");
-  // materials referenced by the geometry must exist
-  for (int u = 0; u < c->n_univ; ++u)
-    for (int k = 0; k <= c->n_rings[u]; ++k)
-      if (c->mats[(size_t)u * (c->max_rings + 1) + k] >= c->n_mat)
-        return fail(c, MCX_EINVAL, "geometry references a missing material");
+  // materials referenced by the geometry must exist (batches: checked per problem)
+  if (!c->batch)
+    for (int u = 0; u < c->n_univ; ++u)
+      for (int k = 0; k <= c->n_rings[u]; ++k)
+        if (c->mats[(size_t)u * (c->max_rings + 1) + k] >= c->n_mat)
+          return fail(c, MCX_EINVAL, "geometry references a missing material");
   Dev scratch;
   const size_t need = carve(c, scratch, nullptr, n_gen_max);
   if (bytes < need) return fail(c, MCX_ENOMEM, "workspace too small");
@@ -509,17 +614,21 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
     if (c->nusf[mg] > 0.0) ka_max = std::max(ka_max, c->nusf[mg] / (c->sig_t[mg] - c->sst[mg]));
   }
   Tables& T = c->d.T;
-  T.nx = c->nx;
-  T.ny = c->ny;
+  T.geo.nx = c->nx;
+  T.geo.ny = c->ny;
   T.n_univ = c->n_univ;
-  T.max_rings = c->max_rings;
-  T.mr1 = c->max_rings + 1;
-  T.pitch = c->pitch;
-  T.x0 = c->x0;
-  T.y0 = c->y0;
-  T.width = (double)c->nx * c->pitch;
-  T.height = (double)c->ny * c->pitch;
-  for (int k = 0; k < 4; ++k) T.bc[k] = c->bc[k];
+  T.geo.max_rings = c->max_rings;
+  T.geo.mr1 = c->max_rings + 1;
+  T.geo.pitch = c->pitch;
+  T.geo.x0 = c->x0;
+  T.geo.y0 = c->y0;
+  T.geo.width = (double)c->nx * c->pitch;
+  T.geo.height = (double)c->ny * c->pitch;
+  for (int k = 0; k < 4; ++k) T.geo.bc[k] = c->bc[k];
+  T.geo.bin_base = 0;
+  T.probs = nullptr;
+  T.n_probs = 0;
+  T.n_hist_total = c->d.n_hist;
   T.n_mat = c->n_mat;
   T.G = c->G;
   T.seed = c->src.seed;
@@ -527,6 +636,43 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
   T.fixed_source = c->src.fixed_source ? 1 : 0;
   T.ent_nx = c->src.ent_nx;
   T.ent_ny = c->src.ent_ny;
+  std::vector<ProbDesc> pd;
+  if (c->batch) {
+    // each problem's lattice points into the concatenated tables
+    pd.resize(c->n_probs);
+    for (int p = 0; p < c->n_probs; ++p) {
+      const mcx_ctx::BProb& b = c->bprobs[p];
+      Geo& L = pd[p].geo;
+      L.nx = b.nx;
+      L.ny = b.ny;
+      L.max_rings = b.max_rings;
+      L.mr1 = b.max_rings + 1;
+      L.pitch = b.pitch;
+      L.x0 = b.x0;
+      L.y0 = b.y0;
+      L.width = (double)b.nx * b.pitch;
+      L.height = (double)b.ny * b.pitch;
+      for (int k = 0; k < 4; ++k) L.bc[k] = b.bc[k];
+      L.pin_map = T.geo.pin_map + b.pin_base;
+      L.n_rings = T.geo.n_rings + b.univ_base;
+      L.radii = T.geo.radii + b.radii_base;
+      L.mats = T.geo.mats + b.mats_base;
+      L.bin_base = b.bin_base;
+      pd[p].seed = b.seed;
+      pd[p].prob = b.prob;
+      pd[p].hist_base = b.hist_base;
+      pd[p].n_hist = b.n_hist;
+      pd[p].n_bins = b.n_bins;
+    }
+    const Geo first = pd[0].geo;
+    T.geo = first;
+    T.probs = c->d.probs;
+    T.n_probs = c->n_probs;
+    T.seed = 0;
+    T.prob = 0;
+    T.fixed_source = 1;
+    T.ent_nx = T.ent_ny = 0;
+  }
   T.n_bins = c->d.n_bins;
   T.tally_stripes = c->d.stripes;
   // binary32 terms can exceed the binary64 bound by a few ulp: 1% headroom
@@ -542,10 +688,10 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
   auto up = [&](const void* dst, const void* srcp, size_t n) {
     return hipMemcpyAsync(const_cast<void*>(dst), srcp, n, hipMemcpyHostToDevice, s);
   };
-  HIP_TRY(c, up(T.pin_map, c->pin_map.data(), c->pin_map.size() * sizeof(int)));
-  HIP_TRY(c, up(T.n_rings, c->n_rings.data(), c->n_rings.size() * sizeof(int)));
-  HIP_TRY(c, up(T.radii, c->radii.data(), c->radii.size() * sizeof(double)));
-  HIP_TRY(c, up(T.mats, c->mats.data(), c->mats.size() * sizeof(int)));
+  HIP_TRY(c, up(T.geo.pin_map, c->pin_map.data(), c->pin_map.size() * sizeof(int)));
+  HIP_TRY(c, up(T.geo.n_rings, c->n_rings.data(), c->n_rings.size() * sizeof(int)));
+  HIP_TRY(c, up(T.geo.radii, c->radii.data(), c->radii.size() * sizeof(double)));
+  HIP_TRY(c, up(T.geo.mats, c->mats.data(), c->mats.size() * sizeof(int)));
   HIP_TRY(c, up(T.sig_t, c->sig_t.data(), c->sig_t.size() * sizeof(double)));
   HIP_TRY(c, up(T.nusf, c->nusf.data(), c->nusf.size() * sizeof(double)));
   HIP_TRY(c, up(T.sst, c->sst.data(), c->sst.size() * sizeof(double)));
@@ -559,6 +705,9 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
   HIP_TRY(c, up(T.sst_f, c->sst_f.data(), c->sst_f.size() * sizeof(float)));
   HIP_TRY(c, up(T.cum_s_f, c->cum_s_f.data(), c->cum_s_f.size() * sizeof(float)));
   HIP_TRY(c, up(T.cum_chi_f, c->cum_chi_f.data(), c->cum_chi_f.size() * sizeof(float)));
+  if (c->batch) HIP_TRY(c, up(c->d.probs, pd.data(), pd.size() * sizeof(ProbDesc)));
+  const double one = 1.0;
+  HIP_TRY(c, up(c->d.k_used, &one, sizeof(double)));
   HIP_TRY(c, hipStreamSynchronize(s));
   c->bound = true;
   c->ran = false;
@@ -589,13 +738,18 @@ static int collect_kernel_times(mcx_ctx* c) {
     } else if (c->ev_kind[p] == 1) {
       c->timing.collide_ms += ms;
       c->timing.n_collide += 1;
-    } else {
+    } else if (c->ev_kind[p] == 2) {
       c->timing.tail_ms += ms;
+    } else {
+      c->timing.persistent_ms += ms;
+      c->timing.n_persistent += 1;
     }
   }
   c->ev_kind.clear();
   return MCX_OK;
 }
+
+static int generation_end(mcx_ctx* c, int gen);
 
 static int run_generation(mcx_ctx* c, int gen) {
   hipStream_t s = c->stream;
@@ -608,9 +762,24 @@ static int run_generation(mcx_ctx* c, int gen) {
   HIP_TRY(c, launch_fill_u64(reinterpret_cast<unsigned long long*>(A.nsite_id), (N + 1) / 2,
                              0ull, s));
   if (rec) HIP_TRY(c, launch_fill_u64(c->d.rec_base, c->d.rec_words, 0ull, s));
+  const int prec = c->opt.precision == MCX_FP32_MIXED ? 1 : 0;
+  if (c->opt.engine == MCX_ENGINE_PERSISTENT) {
+    // one launch per generation; a fixed source is sampled inside it
+    const bool keig = !T.fixed_source;
+    if (gen == 0 && keig)
+      HIP_TRY(c, launch_source(T, gen, N, c->d.src_x, c->d.src_y, c->d.src_g, A.status, s));
+    HIP_TRY(c, time_mark(c, 3, true));
+    HIP_TRY(c, launch_persistent(prec, c->pcfg, T, gen, A, c->d.h_kcol, c->d.h_kabs, c->d.h_cnt,
+                                 c->d.work, keig ? c->d.src_x : nullptr,
+                                 keig ? c->d.src_y : nullptr, keig ? c->d.src_g : nullptr,
+                                 gen > 0 ? c->d.gen_status + gen - 1 : nullptr, s));
+    HIP_TRY(c, time_mark(c, 3, false));
+    HIP_TRY(c, launch_hist_reduce(T, 1, c->d.h_kcol, c->d.h_kabs, c->d.h_cnt, A, nullptr, nullptr,
+                                  s));
+    return generation_end(c, gen);
+  }
   if (gen == 0 || T.fixed_source)
     HIP_TRY(c, launch_source(T, gen, N, c->d.src_x, c->d.src_y, c->d.src_g, A.status, s));
-  const int prec = c->opt.precision == MCX_FP32_MIXED ? 1 : 0;
   HIP_TRY(c, launch_birth(prec, T, gen, N, c->d.src_x, c->d.src_y, c->d.src_g, c->d.bank[0], c->d.cnt_live,
                           c->d.cnt_col, gen > 0 ? c->d.gen_status + gen - 1 : nullptr, A.status,
                           s));
@@ -665,7 +834,16 @@ static int run_generation(mcx_ctx* c, int gen) {
     }
   }
 
-  // generation end
+  return generation_end(c, gen);
+}
+
+// Generation end: estimators, tallies, canonical bank, entropy, combing.
+static int generation_end(mcx_ctx* c, int gen) {
+  hipStream_t s = c->stream;
+  const Tables& T = c->d.T;
+  Accum& A = c->d.A;
+  const bool rec = c->opt.record_histories != 0;
+  const uint32_t N = c->d.N;
   HIP_TRY(c, launch_gen_totals(T, gen, N, A, c->d.gen_k, c->d.gen_cnt, c->d.gen_m, c->d.k_used, c->d.xi0, s));
   HIP_TRY(c, launch_gen_tallies(T, gen, N, A, c->d.gen_tal, c->d.gen_k, s));
   if (!T.fixed_source) {
@@ -720,6 +898,7 @@ static int status_error(mcx_ctx* c, uint32_t st) {
 int mcx_run_generations(mcx_ctx* c, int32_t n_gen, int32_t n_inactive) {
   if (!c) return MCX_EINVAL;
   if (!c->bound) return fail(c, MCX_ESTATE, "bind a workspace first");
+  if (c->batch) return fail(c, MCX_ESTATE, "a batch is loaded: use mcx_run_batch");
   if (n_gen < 1 || n_gen > c->n_gen_max || n_inactive < 0 || n_inactive >= n_gen)
     return fail(c, MCX_EINVAL, "generation counts");
   HIP_TRY(c, hipSetDevice(c->opt.device));
@@ -894,6 +1073,346 @@ int mcx_diag_philox(mcx_ctx* c, const uint64_t* d_in, uint64_t* d_out, int64_t n
   HIP_TRY(c, hipSetDevice(c->opt.device));
   HIP_TRY(c, launch_diag_philox(d_in, d_out, n, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return MCX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches of fixed-source problems
+// ---------------------------------------------------------------------------
+
+int mcx_load_batch(mcx_ctx* c, int32_t n_probs, const mcx_problem* probs) {
+  if (!c || !probs || n_probs < 1 || n_probs > 65535) return MCX_EINVAL;
+  c->bound = false;
+  // each problem goes through the single-problem validators, then is
+  // appended to the concatenated tables
+  std::vector<int> n_rings, mats, pin_map, last_s, last_chi, fissile;
+  std::vector<double> radii, sig_t, nusf, sst, cum_s, cum_chi;
+  std::vector<float> sig_t_f, nusf_f, sst_f, cum_s_f, cum_chi_f;
+  std::vector<mcx_ctx::BProb> bp(n_probs);
+  uint64_t hist = 0;
+  int64_t bins = 0;
+  int G = 0, n_mat = 0, n_univ = 0, max_rings = 0;
+  auto app = [](auto& dst, const auto& src) { dst.insert(dst.end(), src.begin(), src.end()); };
+  int rc = MCX_OK;
+  for (int p = 0; p < n_probs && rc == MCX_OK; ++p) {
+    const mcx_problem& q = probs[p];
+    rc = mcx_load_geometry(c, &q.geo);
+    if (rc == MCX_OK) rc = mcx_load_mg_xs(c, q.n_mat, q.n_grp, q.sig_t, q.sig_s, q.nu_sig_f, q.chi);
+    if (rc != MCX_OK) {
+      c->err = "problem " + std::to_string(p) + ": " + c->err;
+      break;
+    }
+    if (p > 0 && q.n_grp != G) {
+      rc = fail(c, MCX_EINVAL, "problem " + std::to_string(p) + ": group counts differ");
+      break;
+    }
+    if (q.n_hist < 1) {
+      rc = fail(c, MCX_EINVAL, "problem " + std::to_string(p) + ": n_hist < 1");
+      break;
+    }
+    for (int u = 0; u < c->n_univ && rc == MCX_OK; ++u)
+      for (int k = 0; k <= c->n_rings[u]; ++k)
+        if (c->mats[(size_t)u * (c->max_rings + 1) + k] >= c->n_mat) {
+          rc = fail(c, MCX_EINVAL,
+                    "problem " + std::to_string(p) + ": geometry references a missing material");
+          break;
+        }
+    if (rc != MCX_OK) break;
+    G = q.n_grp;
+    mcx_ctx::BProb& b = bp[p];
+    b.nx = c->nx;
+    b.ny = c->ny;
+    b.max_rings = c->max_rings;
+    b.pin_base = (int)pin_map.size();
+    b.univ_base = (int)n_rings.size();
+    b.radii_base = (int)radii.size();
+    b.mats_base = (int)mats.size();
+    b.bin_base = (int)bins;
+    b.n_bins = c->nx * c->ny * (c->max_rings + 1) * G;
+    b.pitch = c->pitch;
+    b.x0 = c->x0;
+    b.y0 = c->y0;
+    for (int k = 0; k < 4; ++k) b.bc[k] = c->bc[k];
+    b.seed = q.seed;
+    b.prob = q.problem_id;
+    b.hist_base = hist;
+    b.n_hist = (uint32_t)std::min<int64_t>(q.n_hist, 0xFFFFFFFFll);
+    hist += (uint64_t)q.n_hist;
+    bins += b.n_bins;
+    if (hist >= (uint64_t(1) << 32) || bins >= (int64_t(1) << 30)) {
+      rc = fail(c, MCX_EINVAL, "batch too large (histories or tally bins)");
+      break;
+    }
+    app(pin_map, c->pin_map);
+    app(n_rings, c->n_rings);
+    app(radii, c->radii);
+    for (int m : c->mats) mats.push_back(m + n_mat);
+    app(sig_t, c->sig_t);
+    app(nusf, c->nusf);
+    app(sst, c->sst);
+    app(cum_s, c->cum_s);
+    app(cum_chi, c->cum_chi);
+    app(last_s, c->last_s);
+    app(last_chi, c->last_chi);
+    app(fissile, c->fissile);
+    app(sig_t_f, c->sig_t_f);
+    app(nusf_f, c->nusf_f);
+    app(sst_f, c->sst_f);
+    app(cum_s_f, c->cum_s_f);
+    app(cum_chi_f, c->cum_chi_f);
+    n_mat += c->n_mat;
+    n_univ += c->n_univ;
+    max_rings = std::max(max_rings, c->max_rings);
+  }
+  if (rc != MCX_OK) {
+    c->has_geo = c->has_xs = false;
+    c->batch = false;
+    c->bound = false;
+    return rc;
+  }
+  c->pin_map = std::move(pin_map);
+  c->n_rings = std::move(n_rings);
+  c->radii = std::move(radii);
+  c->mats = std::move(mats);
+  c->sig_t = std::move(sig_t);
+  c->nusf = std::move(nusf);
+  c->sst = std::move(sst);
+  c->cum_s = std::move(cum_s);
+  c->cum_chi = std::move(cum_chi);
+  c->last_s = std::move(last_s);
+  c->last_chi = std::move(last_chi);
+  c->fissile = std::move(fissile);
+  c->sig_t_f = std::move(sig_t_f);
+  c->nusf_f = std::move(nusf_f);
+  c->sst_f = std::move(sst_f);
+  c->cum_s_f = std::move(cum_s_f);
+  c->cum_chi_f = std::move(cum_chi_f);
+  c->n_mat = n_mat;
+  c->n_univ = n_univ;
+  c->max_rings = max_rings;
+  c->G = G;
+  c->bprobs = std::move(bp);
+  c->n_probs = n_probs;
+  c->batch_hist = hist;
+  c->batch_bins = (int)bins;
+  c->batch = true;
+  c->has_geo = c->has_xs = true;
+  c->bound = false;
+  c->batch_ran = false;
+  c->ran = false;
+  return MCX_OK;
+}
+
+// Enqueue one batch: clear the accumulators, transport every history,
+// reduce per problem.  Kernels only (no memset or copy nodes), so the
+// sequence can be recorded as a graph.
+static hipError_t enqueue_batch(mcx_ctx* c, hipStream_t s) {
+  Dev& d = c->d;
+  Accum A = d.A;
+  A.status = d.gen_status;
+  const int prec = c->opt.precision == MCX_FP32_MIXED ? 1 : 0;
+  hipError_t e = launch_fill_u64(d.acc_base, d.acc_words, 0ull, s);
+  if (e == hipSuccess)
+    e = launch_fill_u64(reinterpret_cast<unsigned long long*>(d.gen_status), 1, 0ull, s);
+  if (e == hipSuccess)
+    e = launch_persistent(prec, c->pcfg, d.T, 0, A, d.h_kcol, d.h_kabs, d.h_cnt, d.work, nullptr,
+                          nullptr, nullptr, nullptr, s);
+  if (e == hipSuccess)
+    e = launch_hist_reduce(d.T, c->n_probs, d.h_kcol, d.h_kabs, d.h_cnt, A, d.prob_cnt, d.prob_k, s);
+  if (e == hipSuccess)
+    e = launch_batch_results(d.T, c->n_probs, A, d.prob_k, d.b_flux, d.b_prod, d.prob_kres, s);
+  return e;
+}
+
+static void drop_graph(mcx_ctx* c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+}
+
+static int build_batch_graph(mcx_ctx* c) {
+  drop_graph(c);
+  if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  const hipError_t e = enqueue_batch(c, c->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(c->cap_stream, &g);
+  if (e != hipSuccess || ee != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(c, e != hipSuccess ? e : ee, "recording the batch graph");
+  }
+  c->graph = g;
+  HIP_TRY(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+  return MCX_OK;
+}
+
+int mcx_run_batch(mcx_ctx* c) {
+  if (!c) return MCX_EINVAL;
+  if (!c->batch) return fail(c, MCX_ESTATE, "no batch loaded");
+  if (!c->bound) return fail(c, MCX_ESTATE, "bind a workspace first");
+  HIP_TRY(c, hipSetDevice(c->opt.device));
+  c->batch_ran = false;
+  c->timing = mcx_timing{};
+  if (!c->graph_exec) {
+    const int rc = build_batch_graph(c);
+    if (rc != MCX_OK) return rc;
+  }
+  hipStream_t s = c->stream;
+  HIP_TRY(c, hipEventRecord(c->ev_start, s));
+  HIP_TRY(c, hipGraphLaunch(c->graph_exec, s));
+  HIP_TRY(c, hipEventRecord(c->ev_stop, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_start, c->ev_stop));
+  c->timing.run_ms = ms;
+  c->timing.persistent_ms = ms;
+  c->timing.n_persistent = 1;
+  uint32_t st = 0;
+  HIP_TRY(c, hipMemcpy(&st, c->d.gen_status, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  c->h_bk.resize((size_t)3 * c->n_probs);
+  c->h_bcnt.resize((size_t)N_CNT * c->n_probs);
+  HIP_TRY(c, hipMemcpy(c->h_bk.data(), c->d.prob_kres, c->h_bk.size() * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(c->h_bcnt.data(), c->d.prob_cnt, c->h_bcnt.size() * 8, hipMemcpyDeviceToHost));
+  if (st) return status_error(c, st);
+  c->batch_ran = true;
+  for (int p = 0; p < c->n_probs; ++p)
+    if (c->h_bcnt[(size_t)p * N_CNT + CNT_KILLED] > 0)
+      return fail(c, MCX_EGUARD, "histories reached the event guard");
+  return MCX_OK;
+}
+
+int mcx_get_batch_results(mcx_ctx* c, double* k, int64_t* counts) {
+  if (!c) return MCX_EINVAL;
+  if (!c->batch_ran) return fail(c, MCX_ESTATE, "no completed batch");
+  if (k) std::memcpy(k, c->h_bk.data(), c->h_bk.size() * sizeof(double));
+  if (counts)
+    for (size_t e = 0; e < c->h_bcnt.size(); ++e) counts[e] = (int64_t)c->h_bcnt[e];
+  return MCX_OK;
+}
+
+int mcx_get_batch_tallies(mcx_ctx* c, int32_t p, double* flux, double* prod, int64_t n_bins) {
+  if (!c) return MCX_EINVAL;
+  if (!c->batch_ran) return fail(c, MCX_ESTATE, "no completed batch");
+  if (p < 0 || p >= c->n_probs) return fail(c, MCX_EINVAL, "problem index");
+  const mcx_ctx::BProb& b = c->bprobs[p];
+  if (n_bins != b.n_bins) return fail(c, MCX_EINVAL, "n_bins mismatch");
+  if (flux)
+    HIP_TRY(c, hipMemcpy(flux, c->d.b_flux + b.bin_base, (size_t)n_bins * 8, hipMemcpyDeviceToHost));
+  if (prod)
+    HIP_TRY(c, hipMemcpy(prod, c->d.b_prod + b.bin_base, (size_t)n_bins * 8, hipMemcpyDeviceToHost));
+  return MCX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner of the persistent engine
+// ---------------------------------------------------------------------------
+
+static std::string tune_key(mcx_ctx* c) {
+  hipDeviceProp_t prop;
+  std::string dev = "unknown";
+  if (hipGetDeviceProperties(&prop, c->opt.device) == hipSuccess)
+    dev = std::string(prop.gcnArchName) + "x" + std::to_string(prop.multiProcessorCount);
+  // the shape of the workload: problems, histories, bins, materials, groups
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "dev=%s prec=%d batch=%d probs=%d hist=%llu bins=%d mat=%d grp=%d fixed=%d",
+                dev.c_str(), c->opt.precision, c->batch ? 1 : 0, c->batch ? c->n_probs : 1,
+                (unsigned long long)c->d.n_hist, c->d.n_bins, c->n_mat, c->G,
+                c->batch ? 1 : (c->src.fixed_source ? 1 : 0));
+  for (char* q = buf; *q; ++q)
+    if (*q == '\n' || *q == '\t') *q = ' ';
+  return buf;
+}
+
+static bool tune_lookup(const char* path, const std::string& key, mcx_tune* t) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool hit = false;
+  while (std::fgets(line, sizeof line, f)) {
+    const char* bar = std::strstr(line, " | ");
+    if (!bar || std::string(line, bar - line) != key) continue;
+    mcx_tune v{};
+    if (std::sscanf(bar + 3, "block=%d slots=%d grid=%d tau=%lf ms=%lf", &v.block, &v.slots,
+                    &v.grid, &v.tau, &v.ms) == 5 &&
+        persistent_config_valid(v.block, v.slots) && v.grid >= 1 && v.tau > 0.0 && v.tau <= 1.0) {
+      *t = v;  // the last matching line wins
+      hit = true;
+    }
+  }
+  std::fclose(f);
+  return hit;
+}
+
+// One timed run of the bound workload with configuration cfg.
+static int tune_trial(mcx_ctx* c, const PersistentCfg& cfg, double* ms) {
+  c->pcfg = cfg;
+  drop_graph(c);
+  int rc;
+  if (c->batch) {
+    rc = mcx_run_batch(c);  // records the graph, then a first replay
+    if (rc == MCX_OK || rc == MCX_EGUARD) rc = mcx_run_batch(c);
+  } else {
+    rc = mcx_run_generations(c, 1, 0);
+  }
+  if (rc != MCX_OK && rc != MCX_EGUARD) return rc;
+  *ms = c->timing.run_ms;
+  return MCX_OK;
+}
+
+int mcx_autotune(mcx_ctx* c, const char* cache_path, mcx_tune* best) {
+  if (!c) return MCX_EINVAL;
+  if (!c->bound) return fail(c, MCX_ESTATE, "bind a workspace first");
+  if (!c->batch && c->opt.engine != MCX_ENGINE_PERSISTENT)
+    return fail(c, MCX_ESTATE, "the autotuner configures the persistent engine");
+  HIP_TRY(c, hipSetDevice(c->opt.device));
+  const std::string key = tune_key(c);
+  mcx_tune t{};
+  if (cache_path && tune_lookup(cache_path, key, &t)) {
+    c->pcfg = PersistentCfg{t.block, t.slots, t.grid, t.tau};
+    drop_graph(c);
+    if (best) *best = t;
+    return MCX_OK;
+  }
+  int cus = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->opt.device) == hipSuccess) cus = prop.multiProcessorCount;
+  const int blocks[] = {128, 256};
+  const int slots[] = {256, 512};
+  const int per_cu[] = {1, 2, 3, 4};
+  const double taus[] = {0.5, 0.75, 0.9};
+  const PersistentCfg keep = c->pcfg;
+  double best_ms = 1e300;
+  PersistentCfg win = keep;
+  for (int b : blocks)
+    for (int sl : slots)
+      for (int m : per_cu)
+        for (double tau : taus) {
+          PersistentCfg cfg{b, sl, m * cus, tau};
+          double ms = 0;
+          const int rc = tune_trial(c, cfg, &ms);
+          if (rc != MCX_OK) {
+            c->pcfg = keep;
+            drop_graph(c);
+            return rc;
+          }
+          if (ms < best_ms) {
+            best_ms = ms;
+            win = cfg;
+          }
+        }
+  c->pcfg = win;
+  drop_graph(c);
+  t = mcx_tune{win.block, win.slots, win.grid, win.tau, best_ms};
+  if (cache_path) {
+    FILE* f = std::fopen(cache_path, "a");
+    if (f) {
+      std::fprintf(f, "%s | block=%d slots=%d grid=%d tau=%.4f ms=%.4f\n", key.c_str(), t.block,
+                   t.slots, t.grid, t.tau, t.ms);
+      std::fclose(f);
+    }
+  }
+  if (best) *best = t;
   return MCX_OK;
 }
 

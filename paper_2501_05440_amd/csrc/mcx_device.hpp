@@ -49,15 +49,34 @@ MCX_HD int cell_i(uint32_t c) { return (int)((c >> 8) & 0xFFFu); }
 MCX_HD int cell_j(uint32_t c) { return (int)(c >> 20); }
 MCX_HD int cell_r(uint32_t c) { return (int)(c & 0xFFu); }
 
-// Read-only problem description (device pointers into the workspace).
-struct Tables {
-  int nx, ny, n_univ, max_rings, mr1;
+// Lattice of one problem: nx x ny cells of pitch `pitch` from (x0, y0),
+// per-side boundaries, pin universes (ring counts, radii, ring materials as
+// global material indices), and the offset of the problem's tally bins.
+struct Geo {
+  int nx, ny, max_rings, mr1;
   double pitch, x0, y0, width, height;
   int bc[4];  // xmin, xmax, ymin, ymax
   const int* pin_map;
   const int* n_rings;
   const double* radii;
   const int* mats;
+  int bin_base;
+};
+
+// One problem of a batch: its lattice, random-number key and counter word,
+// and its range of histories in the batch.
+struct ProbDesc {
+  Geo geo;
+  uint64_t seed, prob;
+  uint64_t hist_base;
+  uint32_t n_hist;
+  int n_bins;
+};
+
+// Read-only problem description (device pointers into the workspace).
+struct Tables {
+  Geo geo;  // the lattice of a single-problem run
+  int n_univ;
   int n_mat, G;
   const double* sig_t;    // [m][g]
   const double* nusf;     // [m][g]
@@ -76,7 +95,10 @@ struct Tables {
   uint64_t seed, prob;
   int fixed_source;
   int ent_nx, ent_ny;
-  int n_bins;          // bins per tally: nx * ny * mr1 * G
+  int n_bins;          // bins per tally (all problems of a batch)
+  const ProbDesc* probs;  // batch problems (persistent engine), or null
+  int n_probs;
+  uint64_t n_hist_total;
   int tally_stripes;   // copies of the tally accumulators
   double q_flux, q_kcol, q_kabs;  // fixed-point scales 2^s
   int64_t max_events;
@@ -185,19 +207,19 @@ MCX_HD double dist_cylinder(double dx, double dy, double u, double v, double R, 
   return c / (-k + sqrt(disc));
 }
 
-MCX_HD void locate(const Tables& T, double x, double y, int* pi, int* pj, int* pr) {
-  int i = (int)floor((x - T.x0) / T.pitch);
-  int j = (int)floor((y - T.y0) / T.pitch);
-  i = i < 0 ? 0 : (i > T.nx - 1 ? T.nx - 1 : i);
-  j = j < 0 ? 0 : (j > T.ny - 1 ? T.ny - 1 : j);
-  const int un = T.pin_map[j * T.nx + i];
-  const double dx = x - (T.x0 + ((double)i + 0.5) * T.pitch);
-  const double dy = y - (T.y0 + ((double)j + 0.5) * T.pitch);
+MCX_HD void locate(const Geo& L, double x, double y, int* pi, int* pj, int* pr) {
+  int i = (int)floor((x - L.x0) / L.pitch);
+  int j = (int)floor((y - L.y0) / L.pitch);
+  i = i < 0 ? 0 : (i > L.nx - 1 ? L.nx - 1 : i);
+  j = j < 0 ? 0 : (j > L.ny - 1 ? L.ny - 1 : j);
+  const int un = L.pin_map[j * L.nx + i];
+  const double dx = x - (L.x0 + ((double)i + 0.5) * L.pitch);
+  const double dy = y - (L.y0 + ((double)j + 0.5) * L.pitch);
   const double rr = dx * dx + dy * dy;
-  const int nr = T.n_rings[un];
+  const int nr = L.n_rings[un];
   int r = nr;
   for (int k = 0; k < nr; ++k) {
-    const double rad = T.radii[un * T.max_rings + k];
+    const double rad = L.radii[un * L.max_rings + k];
     if (rr < rad * rad) {
       r = k;
       break;

@@ -1,0 +1,441 @@
+// mcx_kernels_common.hpp - per-particle transport operations shared by the
+// event kernels (mcx_kernels.hip) and the persistent engine
+// (mcx_persistent.hip): precision policy, particle state, one flight, one
+// collision, source sampling, block scans and exact-sum conversions.
+#pragma once
+
+#include "mcx_launch.hpp"
+
+namespace mcx {
+
+// ---------------------------------------------------------------------------
+// precision policy
+//
+// FP64 (the paper's precision): every quantity in binary64, ln and cos/sin
+// correctly rounded.  FP32-mixed (R = float): directions, the distance to
+// collision, the plane distances (numerator differenced in FP64, then
+// rounded), cross sections, the reaction and group comparisons and the
+// direction sampling in binary32; positions, the cylinder quadratic, the
+// comparison of the distances, the move, the tallies and the k and entropy
+// estimators in binary64.
+// ---------------------------------------------------------------------------
+
+template <class R>
+struct Prec;
+
+template <>
+struct Prec<double> {
+  static __device__ __forceinline__ double xi(double u) { return u; }
+  static __device__ __forceinline__ double dcol(double xi, double st) {
+    return -cr_log(xi, log_tab()) / st;
+  }
+  static __device__ __forceinline__ double plane(double x, double lo, double hi, double u) {
+    return dist_plane(x, lo, hi, u);
+  }
+  static __device__ __forceinline__ void iso(double xm, double xp, double* u, double* v) {
+    isotropic_uv(xm, xp, u, v);
+  }
+};
+
+template <>
+struct Prec<float> {
+  // (float) of a draw may round up to 1; keep it in (0, 1)
+  static __device__ __forceinline__ float xi(double u) {
+    const float f = (float)u;
+    return f < 1.0f ? f : 0x1.fffffep-1f;
+  }
+  static __device__ __forceinline__ float dcol(float xi, float st) { return -logf(xi) / st; }
+  static __device__ __forceinline__ float plane(double x, double lo, double hi, float u) {
+    float t;
+    if (u > 0.0f) {
+      t = (float)(hi - x) / u;
+    } else if (u < 0.0f) {
+      t = (float)(lo - x) / u;
+    } else {
+      return __builtin_inff();
+    }
+    return t < 0.0f ? 0.0f : t;
+  }
+  static __device__ __forceinline__ void iso(float xm, float xp, float* u, float* v) {
+    const float w = 2.0f * xm - 1.0f;
+    const float s2 = 1.0f - w * w;
+    const float s = sqrtf(s2 > 0.0f ? s2 : 0.0f);
+    float sn, cs;
+    sincospif(2.0f * xp, &sn, &cs);
+    *u = s * cs;
+    *v = s * sn;
+  }
+};
+
+// Cross-section tables of the working precision.
+template <class R>
+struct XSView {
+  const R* sig_t;
+  const R* nusf;
+  const R* sst;
+  const R* cum_s;
+  const R* cum_chi;
+};
+
+template <class R>
+__device__ __forceinline__ XSView<R> xs_view(const Tables& T);
+
+template <>
+__device__ __forceinline__ XSView<double> xs_view<double>(const Tables& T) {
+  return XSView<double>{T.sig_t, T.nusf, T.sst, T.cum_s, T.cum_chi};
+}
+
+template <>
+__device__ __forceinline__ XSView<float> xs_view<float>(const Tables& T) {
+  return XSView<float>{T.sig_t_f, T.nusf_f, T.sst_f, T.cum_s_f, T.cum_chi_f};
+}
+
+// ---------------------------------------------------------------------------
+// particle state in registers
+// ---------------------------------------------------------------------------
+
+template <class R>
+struct Part {
+  double x, y;
+  R u, v;
+  int i, j, r, g;
+  uint32_t nsite, ctr, id;
+};
+
+template <class R>
+__device__ __forceinline__ Part<R> load_part(const Bank& b, uint32_t k) {
+  Part<R> p;
+  p.x = b.x[k];
+  p.y = b.y[k];
+  p.u = static_cast<const R*>(b.u)[k];
+  p.v = static_cast<const R*>(b.v)[k];
+  const uint32_t c = b.cell[k];
+  p.i = cell_i(c);
+  p.j = cell_j(c);
+  p.r = cell_r(c);
+  const uint32_t gs = b.gs[k];
+  p.g = (int)(gs & 0xFFFFu);
+  p.nsite = gs >> 16;
+  p.ctr = b.ctr[k];
+  p.id = b.id[k];
+  return p;
+}
+
+template <class R>
+__device__ __forceinline__ void store_part(const Bank& b, uint32_t k, const Part<R>& p) {
+  b.x[k] = p.x;
+  b.y[k] = p.y;
+  static_cast<R*>(b.u)[k] = p.u;
+  static_cast<R*>(b.v)[k] = p.v;
+  b.cell[k] = pack_cell(p.i, p.j, p.r);
+  b.gs[k] = (uint32_t)p.g | (p.nsite << 16);
+  b.ctr[k] = p.ctr;
+  b.id[k] = p.id;
+}
+
+enum : int { EV_NONE = 0, EV_COLLIDE = 1, EV_CROSS = 2, EV_LEAK = 3, EV_KILL = 4 };
+
+template <class R, bool REC>
+__device__ __forceinline__ void die(const Part<R>& p, int fate, const Accum& A,
+                                    const Records& Rc) {
+  A.nsite_id[p.id] = p.nsite;
+  if (REC) {
+    Rc.fate[p.id] = fate;
+    Rc.g_final[p.id] = p.g;
+    Rc.ctr_final[p.id] = p.ctr;
+    Rc.x_final[p.id] = p.x;
+    Rc.y_final[p.id] = p.y;
+  }
+}
+
+// One flight: cross-section lookup, distance to collision, distance to the
+// bounding surfaces, move, track-length tally, and the surface crossing if
+// the boundary comes first.  Returns EV_COLLIDE, EV_CROSS or EV_LEAK.
+// HALVES: add the flux term as two non-returning 32-bit-half atomics (the
+// tail kernel, where a returning atomic's latency is not hidden by other
+// waves); otherwise one returning 64-bit atomic with a carry word.
+template <class R, bool REC, bool HALVES>
+__device__ __forceinline__ int segment(const Tables& T, const Geo& L, Part<R>& p, Stream& rs,
+                                       const Accum& A, const Records& Rc, bool* refl_out) {
+  const XSView<R> X = xs_view<R>(T);
+  const int c = p.j * L.nx + p.i;
+  const int un = L.pin_map[c];
+  const int nr = L.n_rings[un];
+  const int m = L.mats[un * L.mr1 + p.r];
+  const R st = X.sig_t[m * T.G + p.g];
+
+  // distance to collision: exponential with mean 1 / sig_t
+  const R xi = Prec<R>::xi(rs.next());
+  const R d_col = Prec<R>::dcol(xi, st);
+
+  // distance to boundary: the cell's planes ahead and the region's rings
+  const double xlo = L.x0 + (double)p.i * L.pitch, xhi = L.x0 + (double)(p.i + 1) * L.pitch;
+  const double ylo = L.y0 + (double)p.j * L.pitch, yhi = L.y0 + (double)(p.j + 1) * L.pitch;
+  const R tx = Prec<R>::plane(p.x, xlo, xhi, p.u);
+  const R ty = Prec<R>::plane(p.y, ylo, yhi, p.v);
+  const double cx = L.x0 + ((double)p.i + 0.5) * L.pitch;
+  const double cy = L.y0 + ((double)p.j + 0.5) * L.pitch;
+  const double dx = p.x - cx, dy = p.y - cy;
+  const double u = (double)p.u, v = (double)p.v;
+  double t_out = __builtin_inf(), t_in = __builtin_inf();
+  if (p.r < nr) t_out = dist_cylinder(dx, dy, u, v, L.radii[un * L.max_rings + p.r], true);
+  if (p.r > 0) t_in = dist_cylinder(dx, dy, u, v, L.radii[un * L.max_rings + p.r - 1], false);
+  double d_bnd = (double)tx;
+  if ((double)ty < d_bnd) d_bnd = (double)ty;
+  if (t_out < d_bnd) d_bnd = t_out;
+  if (t_in < d_bnd) d_bnd = t_in;
+
+  const bool collide = (double)d_col < d_bnd;
+  const double d = collide ? (double)d_col : d_bnd;
+  p.x = p.x + d * u;
+  p.y = p.y + d * v;
+
+  // track-length flux tally of this bin (cell, region, group); nu_sig_f is
+  // constant in a bin, so the production tally and the track-length k
+  // estimator follow from the flux sums at the end of the generation
+  const int bin = L.bin_base + (c * L.mr1 + p.r) * T.G + p.g;
+  const uint64_t qf = quantize(d, T.q_flux);
+  if (HALVES) {
+    if (qf) {
+      atomicAdd(A.tally_t + 2 * bin, (unsigned long long)(qf & 0xFFFFFFFFull));
+      atomicAdd(A.tally_t + 2 * bin + 1, (unsigned long long)(qf >> 32));
+    }
+  } else {
+    unsigned long long* tb =
+        A.tally + (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
+    acc_add(tb + 2 * bin, qf);
+  }
+  if (REC) {
+    Rc.n_seg[p.id] += 1;
+    Rc.tl_sum[p.id] += d;
+  }
+  *refl_out = false;
+  if (collide) return EV_COLLIDE;
+
+  if (REC) Rc.n_cross[p.id] += 1;
+  const bool hit_x = (double)tx == d_bnd;
+  const bool hit_y = (double)ty == d_bnd;
+  if (hit_x || hit_y) {
+    const bool out_x = hit_x && (p.u > R(0) ? p.i == L.nx - 1 : p.i == 0);
+    const bool out_y = hit_y && (p.v > R(0) ? p.j == L.ny - 1 : p.j == 0);
+    const int side_x = p.u > R(0) ? 1 : 0;
+    const int side_y = p.v > R(0) ? 3 : 2;
+    if ((out_x && L.bc[side_x] == BC_VACUUM) || (out_y && L.bc[side_y] == BC_VACUUM))
+      return EV_LEAK;
+    bool refl = false;
+    if (hit_x) {
+      if (out_x) {
+        p.u = -p.u;
+        refl = true;
+      } else {
+        p.i += p.u > R(0) ? 1 : -1;
+      }
+    }
+    if (hit_y) {
+      if (out_y) {
+        p.v = -p.v;
+        refl = true;
+      } else {
+        p.j += p.v > R(0) ? 1 : -1;
+      }
+    }
+    if (REC && refl) Rc.n_refl[p.id] += 1;
+    *refl_out = refl;
+    // a lattice face lies outside every ring
+    p.r = L.n_rings[L.pin_map[p.j * L.nx + p.i]];
+  } else if (t_out == d_bnd) {
+    p.r += 1;
+  } else {
+    p.r -= 1;
+  }
+  return EV_CROSS;
+}
+
+// Collision, first part: the collision estimator term and the number of
+// fission sites floor(nu_sig_f / (sig_t k_used) + xi) (one draw, in fissile
+// material of a k-eigenvalue run only).
+template <class R>
+struct ColXS {
+  int m;
+  R st, nusf;
+};
+
+template <class R>
+__device__ __forceinline__ ColXS<R> col_xs(const Tables& T, const Geo& L, const Part<R>& p) {
+  const XSView<R> X = xs_view<R>(T);
+  const int un = L.pin_map[p.j * L.nx + p.i];
+  const int m = L.mats[un * L.mr1 + p.r];
+  return ColXS<R>{m, X.sig_t[m * T.G + p.g], X.nusf[m * T.G + p.g]};
+}
+
+template <class R>
+__device__ __forceinline__ uint32_t fission_count(const Tables& T, const ColXS<R>& x, Stream& rs,
+                                                  double k_used) {
+  if (T.fixed_source || !(x.nusf > R(0))) return 0u;
+  const R xf = Prec<R>::xi(rs.next());
+  const R f = floor(x.nusf / (x.st * (R)k_used) + xf);
+  // a nonpositive k_used (only after a failed generation) must not loop forever
+  return f < R(65536) ? (uint32_t)(int)f : 65536u;
+}
+
+// Collision, second part: write the nf sites reserved at slot, then scatter
+// (probability sig_s / sig_t: new group from the scattering row, isotropic
+// direction) or absorb.  Returns true if the particle scatters.
+template <class R, bool REC>
+__device__ __forceinline__ bool collide_rest(const Tables& T, Part<R>& p, Stream& rs,
+                                             const ColXS<R>& x, uint32_t nf, uint32_t slot,
+                                             const Accum& A, uint64_t* q_kabs) {
+  const XSView<R> X = xs_view<R>(T);
+  const int G = T.G;
+  for (uint32_t s = 0; s < nf; ++s) {
+    const R xs = Prec<R>::xi(rs.next());
+    const int gs = sample_cum(xs, X.cum_chi + x.m * G, G, T.last_chi[x.m]);
+    const uint32_t k = slot + s;
+    if (k < A.fis_cap) {
+      A.fis.x[k] = p.x;
+      A.fis.y[k] = p.y;
+      A.fis.g[k] = gs;
+      A.fis.parent[k] = p.id;
+      A.fis.seq[k] = p.nsite + s;
+    } else {
+      atomicOr(A.status, ST_OVERFLOW);
+    }
+  }
+  if (p.nsite + nf > 0xFFFFu) atomicOr(A.status, ST_OVERFLOW);
+  p.nsite += nf;
+  const R xr = Prec<R>::xi(rs.next());
+  const R sst = X.sst[x.m * G + p.g];
+  if (xr * x.st < sst) {
+    const R xg = Prec<R>::xi(rs.next());
+    const int row = x.m * G + p.g;
+    p.g = sample_cum(xg, X.cum_s + (size_t)row * G, G, T.last_s[row]);
+    const R xm = Prec<R>::xi(rs.next());
+    const R xp = Prec<R>::xi(rs.next());
+    Prec<R>::iso(xm, xp, &p.u, &p.v);
+    *q_kabs = 0;
+    return true;
+  }
+  *q_kabs = x.nusf > R(0) ? quantize((double)(x.nusf / (x.st - sst)), T.q_kabs) : 0;
+  return false;
+}
+
+__device__ __forceinline__ void wave_flag(unsigned long long* base, bool f) {
+  const unsigned long long n = (unsigned long long)__popcll(__ballot(f));
+  if (lane_id() == 0 && n) atomicAdd(base + (blockIdx.x % STRIPES), n);
+}
+
+// ---------------------------------------------------------------------------
+// source and birth
+// ---------------------------------------------------------------------------
+
+// Source site of history id in batch gen: rejection in the lattice's bounding
+// box until the point is in fissile material, then a fission-spectrum group
+// (FP64 in both precisions).  Returns false (and the lattice corner) when no
+// fissile point is found in 10^4 tries.
+__device__ __forceinline__ bool sample_source(const Tables& T, const Geo& L, uint64_t seed,
+                                              uint64_t prob, uint64_t id, uint32_t gen,
+                                              double* sx, double* sy, int32_t* sg) {
+  Stream s(seed, TAG_SRC, id, gen, prob, 0);
+  for (int t = 0; t < 10000; ++t) {
+    const double xa = s.next();
+    const double ya = s.next();
+    const double x = L.x0 + xa * L.width;
+    const double y = L.y0 + ya * L.height;
+    int i, j, r;
+    locate(L, x, y, &i, &j, &r);
+    const int m = L.mats[L.pin_map[j * L.nx + i] * L.mr1 + r];
+    if (T.fissile[m]) {
+      const double xi = s.next();
+      *sx = x;
+      *sy = y;
+      *sg = sample_cum(xi, T.cum_chi + m * T.G, T.G, T.last_chi[m]);
+      return true;
+    }
+  }
+  *sx = L.x0;
+  *sy = L.y0;
+  *sg = 0;
+  return false;
+}
+
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds, uint32_t* total) {
+  // lds: one slot per wave
+  const uint32_t lane = lane_id();
+  const uint32_t wid = threadIdx.x / 64u;
+  const uint32_t nw = blockDim.x / 64u;
+  uint32_t incl = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(incl, off);
+    if ((int)lane >= off) incl += t;
+  }
+  if (lane == 63) lds[wid] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (uint32_t w = 0; w < nw; ++w) {
+      const uint32_t t = lds[w];
+      lds[w] = run;
+      run += t;
+    }
+    lds[nw] = run;
+  }
+  __syncthreads();
+  const uint32_t r = lds[wid] + incl - v;
+  *total = lds[nw];
+  __syncthreads();
+  return r;
+}
+
+
+// w1 * 2^64 + w0 correctly rounded to double.
+__device__ __forceinline__ double u128_to_double(unsigned long long w0, unsigned long long w1) {
+  if (w1 == 0) return (double)w0;  // u64 -> f64 conversion rounds to nearest
+  // normalise the top 64 bits, fold the rest into a sticky bit
+  const int lz = __clzll((long long)w1);
+  const unsigned long long top = lz ? ((w1 << lz) | (w0 >> (64 - lz))) : w1;
+  const unsigned long long rest = lz ? (w0 << lz) : w0;
+  const unsigned long long m = top | (rest ? 1ull : 0ull);
+  return ldexp((double)m, 64 - lz);
+}
+
+// Sum of striped 128-bit accumulators (hi * 2^64 + lo), correctly rounded
+// to double.
+__device__ __forceinline__ double stripes_to_double(const unsigned long long* pairs, int n_stripes,
+                                    size_t stride) {
+  unsigned long long w0 = 0, w1 = 0;  // value = w1 * 2^64 + w0
+  for (int s = 0; s < n_stripes; ++s) {
+    const unsigned long long lo = pairs[(size_t)s * stride + 0];
+    const unsigned long long hi = pairs[(size_t)s * stride + 1];
+    const unsigned long long t = w0 + lo;
+    w1 += hi + ((t < w0) ? 1ull : 0ull);
+    w0 = t;
+  }
+  return u128_to_double(w0, w1);
+}
+
+// Exact flux sum of one bin: the striped 128-bit pairs of the event kernels
+// plus the (low-half sum, high-half sum) pair of the tail kernel.
+__device__ __forceinline__ double flux_total(const unsigned long long* pairs, int n_stripes, size_t stride,
+                             const unsigned long long* halves) {
+  unsigned long long w0 = 0, w1 = 0;
+  for (int s = 0; s < n_stripes; ++s) {
+    const unsigned long long lo = pairs[(size_t)s * stride + 0];
+    const unsigned long long hi = pairs[(size_t)s * stride + 1];
+    const unsigned long long t = w0 + lo;
+    w1 += hi + ((t < w0) ? 1ull : 0ull);
+    w0 = t;
+  }
+  const unsigned long long a = halves[0], b = halves[1];  // a + b * 2^32
+  unsigned long long t = w0 + a;
+  w1 += (t < w0) ? 1ull : 0ull;
+  w0 = t;
+  t = w0 + (b << 32);
+  w1 += ((t < w0) ? 1ull : 0ull) + (b >> 32);
+  w0 = t;
+  return u128_to_double(w0, w1);
+}
+
+
+}  // namespace mcx

@@ -52,6 +52,29 @@ hipError_t launch_comb(uint32_t n, const uint32_t* m_p, uint32_t cap, const doub
 hipError_t launch_stats(int n_bins2, int n_gen, int n_inactive, const double* gen_tal,
                         double* tal_mean, double* tal_sigma, const double* gen_k, double* k_stat,
                         hipStream_t s);
+// Persistent engine configuration: threads per workgroup, LDS particle
+// slots per workgroup, workgroups, and the refill threshold as a fraction of
+// the slots (refill when fewer slots than that are live).
+struct PersistentCfg {
+  int block = 256;
+  int slots = 512;
+  int grid = 512;
+  double tau = 0.75;
+};
+bool persistent_config_valid(int block, int slots);
+size_t persistent_lds_bytes(int prec, int block, int slots);
+hipError_t launch_persistent(int prec, const PersistentCfg& cfg, const Tables& T, uint32_t gen,
+                             const Accum& A, unsigned long long* h_kcol,
+                             unsigned long long* h_kabs, uint32_t* h_cnt, uint32_t* work,
+                             const double* sx, const double* sy, const int32_t* sg,
+                             const uint32_t* prev_status, hipStream_t s);
+hipError_t launch_hist_reduce(const Tables& T, int n_probs, unsigned long long* h_kcol,
+                              unsigned long long* h_kabs, uint32_t* h_cnt, const Accum& A,
+                              unsigned long long* prob_cnt, unsigned long long* prob_k,
+                              hipStream_t s);
+hipError_t launch_batch_results(const Tables& T, int n_probs, const Accum& A,
+                                const unsigned long long* prob_k, double* flux, double* prod,
+                                double* k_out, hipStream_t s);
 hipError_t launch_diag_math(int which, const double* in, double* out, int64_t n, hipStream_t s);
 hipError_t launch_diag_philox(const uint64_t* in, uint64_t* out, int64_t n, hipStream_t s);
 void host_math(int which, const double* in, double* out, int64_t n);

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmcx.so")
 OK, EINVAL, ESTATE, ENOMEM, EDEVICE, ELOST, EGUARD, EEXTINCT, EOVERFLOW = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 FP64, FP32_MIXED = 0, 1
+ENGINE_EVENT, ENGINE_PERSISTENT = 0, 1
 N_CNT = 9
 COUNT_NAMES = ["seg", "col", "cross", "refl", "leak", "abs", "killed", "sites", "scat"]
 
@@ -26,7 +27,8 @@ EXPORTS = [
     "mcx_workspace_size", "mcx_bind_workspace", "mcx_run_generations", "mcx_get_keff",
     "mcx_get_generation_stats", "mcx_get_tallies", "mcx_get_generation_tallies",
     "mcx_get_records", "mcx_get_bank", "mcx_get_timing", "mcx_diag_math", "mcx_host_math",
-    "mcx_diag_philox", "mcx_last_error", "mcx_destroy",
+    "mcx_diag_philox", "mcx_last_error", "mcx_destroy", "mcx_load_batch", "mcx_run_batch",
+    "mcx_get_batch_results", "mcx_get_batch_tallies", "mcx_autotune",
 ]
 
 
@@ -40,7 +42,9 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p),
                 ("block_size", C.c_int32), ("tail_threshold", C.c_int32),
                 ("lookahead", C.c_int32), ("max_events", C.c_int64),
-                ("record_histories", C.c_int32), ("time_kernels", C.c_int32)]
+                ("record_histories", C.c_int32), ("time_kernels", C.c_int32),
+                ("engine", C.c_int32), ("p_block", C.c_int32), ("p_slots", C.c_int32),
+                ("p_grid", C.c_int32), ("p_tau", C.c_double)]
 
 
 class Geometry(C.Structure):
@@ -60,7 +64,20 @@ class Timing(C.Structure):
                 ("n_tail_launches", C.c_int64), ("advance_ms", C.c_double),
                 ("collide_ms", C.c_double), ("tail_ms", C.c_double),
                 ("n_advance", C.c_int64), ("n_collide", C.c_int64),
-                ("advance_items", C.c_int64), ("collide_items", C.c_int64)]
+                ("advance_items", C.c_int64), ("collide_items", C.c_int64),
+                ("persistent_ms", C.c_double), ("n_persistent", C.c_int64)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("geo", Geometry), ("n_mat", C.c_int32), ("n_grp", C.c_int32),
+                ("sig_t", C.c_void_p), ("sig_s", C.c_void_p), ("nu_sig_f", C.c_void_p),
+                ("chi", C.c_void_p), ("seed", C.c_uint64), ("n_hist", C.c_int64),
+                ("problem_id", C.c_uint64)]
+
+
+class Tune(C.Structure):
+    _fields_ = [("block", C.c_int32), ("slots", C.c_int32), ("grid", C.c_int32),
+                ("tau", C.c_double), ("ms", C.c_double)]
 
 
 RECORD_DTYPE = np.dtype([
@@ -101,6 +118,11 @@ def lib():
         "mcx_diag_philox": ([vp, dp, dp, i64], C.c_int),
         "mcx_last_error": ([vp], C.c_char_p),
         "mcx_destroy": ([vp], None),
+        "mcx_load_batch": ([vp, i32, C.POINTER(Problem)], C.c_int),
+        "mcx_run_batch": ([vp], C.c_int),
+        "mcx_get_batch_results": ([vp, dp, dp], C.c_int),
+        "mcx_get_batch_tallies": ([vp, i32, dp, dp, i64], C.c_int),
+        "mcx_autotune": ([vp, C.c_char_p, C.POINTER(Tune)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -126,12 +148,48 @@ def _arr(a, dt, keep):
     return a
 
 
+def _geometry(geo, keep):
+    n_rings = _arr(geo["n_rings"], np.int32, keep)
+    radii = _arr(geo["radii"], np.float64, keep)
+    mats = _arr(geo["mats"], np.int32, keep)
+    pin_map = _arr(geo["pin_map"], np.int32, keep)
+    g = Geometry()
+    g.nx, g.ny = geo["nx"], geo["ny"]
+    g.pitch, g.x0, g.y0 = geo["pitch"], geo["x0"], geo["y0"]
+    g.bc = (C.c_int32 * 4)(*geo["bc"])
+    g.n_univ, g.max_rings = len(n_rings), radii.shape[1]
+    g.n_rings, g.radii = n_rings.ctypes.data, radii.ctypes.data
+    g.mats, g.pin_map = mats.ctypes.data, pin_map.ctypes.data
+    return g
+
+
+def _xs(xs, keep):
+    arrs = [_arr(xs[k], np.float64, keep) for k in ("sig_t", "sig_s", "nu_sig_f", "chi")]
+    return arrs[0].shape, [a.ctypes.data for a in arrs]
+
+
+def _options(o, precision, device, stream, engine, persistent):
+    if precision not in ("fp64", "fp32"):
+        raise ValueError("precision is 'fp64' or 'fp32' (FP32-mixed)")
+    if engine not in ("event", "persistent"):
+        raise ValueError("engine is 'event' or 'persistent'")
+    o.precision = FP64 if precision == "fp64" else FP32_MIXED
+    o.device = device
+    o.stream = stream.cuda_stream
+    o.engine = ENGINE_EVENT if engine == "event" else ENGINE_PERSISTENT
+    p = persistent or {}
+    o.p_block = p.get("block", 0)
+    o.p_slots = p.get("slots", 0)
+    o.p_grid = p.get("grid", 0)
+    o.p_tau = p.get("tau", 0.0)
+
+
 class Context:
     """One libmcx context bound to a torch-allocated workspace on one GPU."""
 
     def __init__(self, problem, device=0, record=False, block_size=0, tail_threshold=0,
                  lookahead=0, max_events=None, time_kernels=False, n_gen_max=None,
-                 stream=None, precision="fp64"):
+                 stream=None, precision="fp64", engine="event", persistent=None):
         import torch
 
         self.problem = problem
@@ -143,11 +201,7 @@ class Context:
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         rp = problem["run"]
         o = Options()
-        if precision not in ("fp64", "fp32"):
-            raise ValueError("precision is 'fp64' or 'fp32' (FP32-mixed)")
-        o.precision = FP64 if precision == "fp64" else FP32_MIXED
-        o.device = device
-        o.stream = self.stream.cuda_stream
+        _options(o, precision, device, self.stream, engine, persistent)
         o.block_size = block_size
         o.tail_threshold = tail_threshold
         o.lookahead = lookahead
@@ -159,25 +213,10 @@ class Context:
         self.h = h
         geo, xs = problem["geometry"], problem["xs"]
         k = self._keep
-        n_rings = _arr(geo["n_rings"], np.int32, k)
-        radii = _arr(geo["radii"], np.float64, k)
-        mats = _arr(geo["mats"], np.int32, k)
-        pin_map = _arr(geo["pin_map"], np.int32, k)
-        g = Geometry()
-        g.nx, g.ny = geo["nx"], geo["ny"]
-        g.pitch, g.x0, g.y0 = geo["pitch"], geo["x0"], geo["y0"]
-        g.bc = (C.c_int32 * 4)(*geo["bc"])
-        g.n_univ, g.max_rings = len(n_rings), radii.shape[1]
-        g.n_rings, g.radii = n_rings.ctypes.data, radii.ctypes.data
-        g.mats, g.pin_map = mats.ctypes.data, pin_map.ctypes.data
+        g = _geometry(geo, k)
         self._check(L.mcx_load_geometry(h, C.byref(g)))
-        sig_t = _arr(xs["sig_t"], np.float64, k)
-        sig_s = _arr(xs["sig_s"], np.float64, k)
-        nusf = _arr(xs["nu_sig_f"], np.float64, k)
-        chi = _arr(xs["chi"], np.float64, k)
-        n_mat, n_grp = sig_t.shape
-        self._check(L.mcx_load_mg_xs(h, n_mat, n_grp, sig_t.ctypes.data, sig_s.ctypes.data,
-                                     nusf.ctypes.data, chi.ctypes.data))
+        (n_mat, n_grp), ptrs = _xs(xs, k)
+        self._check(L.mcx_load_mg_xs(h, n_mat, n_grp, *ptrs))
         s = Source()
         s.seed, s.n_per_gen = rp["seed"], rp["n_per_gen"]
         s.fixed_source, s.problem_id = int(rp["fixed_source"]), rp["problem_id"]
@@ -189,7 +228,7 @@ class Context:
         self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=f"cuda:{device}")
         self._check(L.mcx_bind_workspace(h, self.workspace.data_ptr(), nbytes.value,
                                          self.n_gen_max))
-        self.n_bins = geo["nx"] * geo["ny"] * (radii.shape[1] + 1) * n_grp
+        self.n_bins = geo["nx"] * geo["ny"] * (g.max_rings + 1) * n_grp
         self.n_per_gen = rp["n_per_gen"]
         self.n_gen = None
 
@@ -254,6 +293,14 @@ class Context:
         self._check(self.L.mcx_get_timing(self.h, C.byref(t)))
         return {name: getattr(t, name) for name, _ in Timing._fields_}
 
+    def autotune(self, cache_path=None):
+        """Persistent-engine configuration with the shortest measured run
+        (C++ sweep in the library, optionally cached in a text file)."""
+        t = Tune()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        self._check(self.L.mcx_autotune(self.h, path, C.byref(t)))
+        return {name: getattr(t, name) for name, _ in Tune._fields_}
+
     def diag_math(self, which, values):
         import torch
         x = torch.as_tensor(np.ascontiguousarray(values, dtype=np.float64)).to(
@@ -309,3 +356,62 @@ def run(problem, device=0, record=False, per_gen_tallies=False, bank=False, **kw
         return res
     finally:
         ctx.close()
+
+
+class Batch(Context):
+    """A batch of independent fixed-source problems run in one persistent
+    launch (mcx_load_batch / mcx_run_batch)."""
+
+    def __init__(self, problems, device=0, max_events=None, stream=None, precision="fp64",
+                 persistent=None):
+        import torch
+
+        self.problems = problems
+        self.device = device
+        L = lib()
+        self.L = L
+        self._keep = []
+        torch.cuda.set_device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        o = Options()
+        _options(o, precision, device, self.stream, "persistent", persistent)
+        o.max_events = problems[0]["run"]["max_events"] if max_events is None else max_events
+        h = C.c_void_p()
+        self._check(L.mcx_create(C.byref(h), C.byref(o)), None)
+        self.h = h
+        arr = (Problem * len(problems))()
+        self.n_bins_of = []
+        for q, prob in zip(arr, problems):
+            rp = prob["run"]
+            q.geo = _geometry(prob["geometry"], self._keep)
+            (n_mat, n_grp), ptrs = _xs(prob["xs"], self._keep)
+            q.n_mat, q.n_grp = n_mat, n_grp
+            q.sig_t, q.sig_s, q.nu_sig_f, q.chi = ptrs
+            q.seed, q.n_hist, q.problem_id = rp["seed"], rp["n_per_gen"], rp["problem_id"]
+            self.n_bins_of.append(q.geo.nx * q.geo.ny * (q.geo.max_rings + 1) * n_grp)
+        self._check(L.mcx_load_batch(h, len(problems), arr))
+        nbytes = C.c_size_t()
+        self._check(L.mcx_workspace_size(h, 1, C.byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=f"cuda:{device}")
+        self._check(L.mcx_bind_workspace(h, self.workspace.data_ptr(), nbytes.value, 1))
+        self.n_probs = len(problems)
+
+    def run(self, check=True):
+        rc = self.L.mcx_run_batch(self.h)
+        if check:
+            self._check(rc)
+        return rc
+
+    def results(self):
+        """k[p] = (collision, track-length, absorption) per source particle,
+        counts[p][MCX_N_CNT]."""
+        k = np.zeros((self.n_probs, 3))
+        c = np.zeros((self.n_probs, N_CNT), np.int64)
+        self._check(self.L.mcx_get_batch_results(self.h, k.ctypes.data, c.ctypes.data))
+        return k, c
+
+    def tallies_of(self, p):
+        nb = self.n_bins_of[p]
+        f, q = np.zeros(nb), np.zeros(nb)
+        self._check(self.L.mcx_get_batch_tallies(self.h, p, f.ctypes.data, q.ctypes.data, nb))
+        return f, q
