@@ -2,11 +2,14 @@
 """Throughput of the event-based Monte Carlo k-eigenvalue path on one MI355X.
 
 One step is one full power iteration of the 17x17-pin, 7-group lattice
-(1e6 histories per generation, 60 generations, 20 inactive) in FP64, with the
-problem data and workspace resident on the GPU.  Prints one JSON line with
-histories/s (value), events/s, the roofline of the dominant event kernel
-(timed with HIP events on the run's stream) and the CPU oracle timed on a
-bounded sample of the same workload.
+(1e6 histories per generation, 60 generations, 20 inactive) in FP64 with the
+event engine, with the problem data and workspace resident on the GPU.
+Prints one JSON line with histories/s (value), events/s, the roofline of the
+dominant event kernel (timed with HIP events on the run's stream) and the
+CPU oracle timed on a bounded sample of the same workload; beside them the
+same lattice on the persistent engine, the FP64 / FP32-mixed comparison at
+1e7 histories per generation, and the 512-problem fixed-source batch in one
+persistent launch against the same problems run one at a time.
 """
 import argparse
 import json
@@ -19,12 +22,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per processed particle (FP64 bank entry: x, y, u, v as f64,
-# cell, group|sites, draw counter, id as u32 = 48 B)
-STATE_BYTES = 48
+# cell, group|sites, draw counter, id, flight count as u32 = 52 B)
+STATE_BYTES = 52
 SITE_BYTES = 28  # banked fission site: x, y (f64), group, parent, sequence (u32)
-TALLY_BYTES_ADV = 16  # one 64-bit fixed-point flux atomic (read-modify-write)
+TALLY_BYTES_ADV = 16  # one 64-bit fixed-point flux atomic (read-modify-write) per flight
 COUNTERS = os.path.join(ROOT, "profiles", "k_advance_lattice17x17_counters.md")
 KERNEL_SOURCES = ["paper_2501_05440_amd/csrc/mcx_kernels.hip",
+                  "paper_2501_05440_amd/csrc/mcx_kernels_common.hpp",
                   "paper_2501_05440_amd/csrc/mcx_device.hpp",
                   "paper_2501_05440_amd/csrc/mcx_math.hpp"]
 
@@ -57,11 +61,19 @@ def parse():
     ap.add_argument("--n-inactive", type=int, default=20)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--tail", type=int, default=0)
+    ap.add_argument("--flights", type=int, default=0,
+                    help="flights per particle per advance launch (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-gens", type=int, default=2)
+    ap.add_argument("--cpu-gens", type=int, default=40,
+                    help="generations of the lattice the CPU oracle runs (about 10-15 s)")
     ap.add_argument("--no-fp32", action="store_true",
                     help="skip the 1e7-history FP64 / FP32-mixed comparison")
     ap.add_argument("--n-fp32", type=int, default=10_000_000)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-problem batch")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="skip the lattice on the persistent engine")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file (default: a fresh one per run)")
     return ap.parse_args()
 
 
@@ -102,6 +114,64 @@ def fp32_mixed_comparison(P, mcx, n, n_gen, n_inactive):
     return out
 
 
+def persistent_comparison(P, mcx, prob, event_hps, tune_cache):
+    """The lattice on the persistent engine (autotuned): histories/s."""
+    ctx = mcx.Context(prob, engine="persistent")
+    tune = ctx.autotune(tune_cache)
+    sec = timed_runs(ctx, 1)
+    km, ks, _ = ctx.keff()
+    ctx.close()
+    n = prob["run"]["n_per_gen"] * prob["run"]["n_gen"]
+    return {"histories_per_s": round(n / sec, 1), "ms_per_step": round(sec * 1e3, 2),
+            "speedup_over_event_engine": round(n / sec / event_hps, 3),
+            "k_col": round(float(km[0]), 7),
+            "tuned": {k: tune[k] for k in ("block", "slots", "grid", "tau")}}
+
+
+def batch_comparison(P, mcx, tune_cache, steps):
+    """512 fixed-source pin cells in one persistent launch (autotuned) against
+    the same problems run one at a time with the FP64 event engine."""
+    import numpy as np
+    import torch
+    probs = P.batch_pin_cells()
+    n = np.array([q["run"]["n_per_gen"] for q in probs])
+    b = mcx.Batch(probs)
+    tune = b.autotune(tune_cache)
+    b.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.run()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    k, cnt = b.results()
+    b.close()
+    print(f"[bench] batch: {sec * 1e3:.1f} ms per launch; one-at-a-time baseline", file=sys.stderr,
+          flush=True)
+    ctxs = [mcx.Context(q) for q in probs]
+    for c in ctxs[:4]:
+        c.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in ctxs:
+        c.run()
+    torch.cuda.synchronize()
+    base = time.perf_counter() - t0
+    for c in ctxs:
+        c.close()
+    return {"workload": "512 fixed-source 7-group pin cells, own XS and radius each, "
+                        f"{int(n.min())}..{int(n.max())} histories (total {int(n.sum())}), one "
+                        "persistent launch in a HIP graph, FP64",
+            "histories_per_s": round(n.sum() / sec, 1),
+            "events_per_s": round(float(cnt[:, 0].sum()) / sec, 1),
+            "ms_per_batch": round(sec * 1e3, 2),
+            "one_at_a_time_event_fp64": {"histories_per_s": round(n.sum() / base, 1),
+                                         "ms": round(base * 1e3, 1)},
+            "speedup_over_one_at_a_time": round(base / sec, 3),
+            "tuned": {kk: tune[kk] for kk in ("block", "slots", "grid", "tau")},
+            "killed": int(cnt[:, 6].sum())}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -121,12 +191,12 @@ def main():
     print(f"[bench] lattice 17x17, {N} histories x {G} generations, steps={a.steps} "
           f"warmup={a.warmup}", file=sys.stderr, flush=True)
     ctx = mcx.Context(prob, device=0, block_size=a.block, tail_threshold=a.tail,
-                      time_kernels=True)
+                      time_kernels=True, flights=a.flights)
     for w in range(a.warmup):
         ctx.run()
         print(f"[bench] warmup {w + 1}/{a.warmup} done", file=sys.stderr, flush=True)
     tot = dict(advance_ms=0.0, collide_ms=0.0, tail_ms=0.0, n_advance=0, n_collide=0,
-               advance_items=0, collide_items=0, n_iterations=0, run_ms=0.0)
+               advance_items=0, collide_items=0, advance_segments=0, n_iterations=0, run_ms=0.0)
     segs = cols = scats = sites = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -153,7 +223,8 @@ def main():
     col_avg_ms = tot["collide_ms"] / max(1, tot["n_collide"])
     adv_items = tot["advance_items"] / max(1, tot["n_advance"])
     col_items = tot["collide_items"] / max(1, tot["n_collide"])
-    adv_bytes = 2 * STATE_BYTES + TALLY_BYTES_ADV
+    adv_flights = tot["advance_segments"] / max(1, tot["advance_items"])
+    adv_bytes = 2 * STATE_BYTES + TALLY_BYTES_ADV * adv_flights
     col_bytes = STATE_BYTES + STATE_BYTES * (scats / max(1, cols)) + SITE_BYTES * (sites / max(1, cols))
     if tot["advance_ms"] >= tot["collide_ms"]:
         name, avg_ms, per_launch = "k_advance", adv_avg_ms, adv_items * adv_bytes
@@ -171,6 +242,8 @@ def main():
                 "traffic": traffic, "bytes_per_item": round(per_item, 2),
                 "items_per_launch": round(adv_items if name == "k_advance" else col_items, 1),
                 "avg_launch_us": round(avg_ms * 1e3, 2),
+                "flights_per_advance_item": round(adv_flights, 4),
+                "iterations_per_generation": round(tot["n_iterations"] / (a.steps * G), 2),
                 "kernel_ms_per_step": {"advance": round(tot["advance_ms"] / a.steps, 2),
                                        "collide": round(tot["collide_ms"] / a.steps, 2),
                                        "tail": round(tot["tail_ms"] / a.steps, 2)}}
@@ -189,6 +262,17 @@ def main():
                "cores": cores, "kind": "oracle",
                "sample": f"first {a.cpu_gens} generations of the same lattice problem "
                          f"({a.cpu_gens * N} histories, {c1 - c0:.1f} s)"}
+
+    import tempfile
+    tune_cache = a.tune_cache or os.path.join(tempfile.mkdtemp(), "mcx_tune.txt")
+    pers = None
+    if not a.no_persistent:
+        print("[bench] lattice on the persistent engine", file=sys.stderr, flush=True)
+        pers = persistent_comparison(P, mcx, prob, value, tune_cache)
+    batch = None
+    if not a.no_batch:
+        print("[bench] 512-problem batch", file=sys.stderr, flush=True)
+        batch = batch_comparison(P, mcx, tune_cache, a.steps)
 
     extra = None
     if not a.no_fp32:
@@ -212,13 +296,16 @@ def main():
                                f"vacuum boundary, {N} histories/gen x {G} gens ({a.n_inactive} "
                                f"inactive), FP64 event-based",
                    "histories_per_step": N * G, "block_size": a.block or 256,
-                   "tail_threshold": a.tail or max(4096, N // 8)},
+                   "tail_threshold": a.tail or max(4096, N // 8),
+                   "flights_per_advance_launch": a.flights or 8},
         "events_per_s": round(segs / elapsed, 1),
         "segments_per_history": round(segs / histories, 4),
         "k_eff": {"collision": round(float(km[0]), 6), "sigma": round(float(ks[0]), 6)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "persistent_engine": pers,
         "fp32_mixed": extra,
+        "batch": batch,
     }
     print(json.dumps(out), flush=True)
 

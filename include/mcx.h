@@ -99,6 +99,12 @@ typedef struct {
   int32_t p_grid;           /* persistent: workgroups; 0 = 2 per compute unit */
   double p_tau;             /* persistent: refill when fewer than p_tau * p_slots particles
                                of a block are live, 0 < p_tau <= 1; 0 = 0.75 */
+  int32_t flights;          /* event engine: flights one advance launch makes per particle
+                               before it returns to the live bank (it stops earlier at a
+                               collision, a leak or the guard).  1 = one event per launch,
+                               the paper's decomposition; larger values keep a particle in
+                               the kernel across surface crossings.  Results are identical
+                               for every value.  0 = default (8); at most 65536 */
 } mcx_options;
 
 /* Lattice of pin universes (paper Sec. 1: CSG geometry).  Cell (i, j),
@@ -158,6 +164,7 @@ typedef struct {
   int64_t collide_items;    /* collisions processed by collide kernels */
   double persistent_ms;     /* persistent-engine kernels (time_kernels = 1) */
   int64_t n_persistent;
+  int64_t advance_segments; /* flights made inside advance kernels */
 } mcx_timing;
 
 /* One problem of a batch: its lattice, multigroup data (as for

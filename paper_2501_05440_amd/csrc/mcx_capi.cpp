@@ -27,6 +27,7 @@ constexpr int RING = 64;
 constexpr int DEFAULT_TAIL = 4096;
 constexpr int DEFAULT_LOOKAHEAD = 4;
 constexpr int64_t DEFAULT_MAX_EVENTS = 100000;
+constexpr int DEFAULT_FLIGHTS = 8;
 
 struct Carver {
   char* base;
@@ -190,6 +191,11 @@ int mcx_create(mcx_ctx** out, const mcx_options* opt) {
   if (c->opt.lookahead <= 0) c->opt.lookahead = DEFAULT_LOOKAHEAD;
   if (c->opt.lookahead > RING - 2) c->opt.lookahead = RING - 2;
   if (c->opt.max_events <= 0) c->opt.max_events = DEFAULT_MAX_EVENTS;
+  if (c->opt.flights == 0) c->opt.flights = DEFAULT_FLIGHTS;
+  if (c->opt.flights < 0 || c->opt.flights > 65536) {
+    delete c;
+    return MCX_EINVAL;
+  }
   if (c->opt.engine != MCX_ENGINE_EVENT && c->opt.engine != MCX_ENGINE_PERSISTENT) {
     delete c;
     return MCX_EINVAL;
@@ -417,7 +423,11 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   const int nb = batch ? c->batch_bins : c->nx * c->ny * mr1 * c->G;
   const uint64_t n_hist = batch ? c->batch_hist : (uint64_t)N;
   const bool persistent = batch || c->opt.engine == MCX_ENGINE_PERSISTENT;
-  const int stripes = std::max(1, std::min(STRIPES, 65536 / std::max(1, 2 * nb)));
+  // copies of the flux accumulators, spread over workgroups by index: a
+  // batch's workgroups all work on the few problems whose histories are in
+  // flight, so its few bins get every copy (up to 16 Mi words)
+  const int stripe_words = batch ? (1 << 24) : 65536;
+  const int stripes = std::max(1, std::min(STRIPES, stripe_words / std::max(1, 2 * nb)));
   const uint32_t fis_cap = (uint32_t)std::min<size_t>(2 * N + 4096, 0xFFFFFFF0u);
   const size_t n_ent = (size_t)c->src.ent_nx * c->src.ent_ny;
   const size_t n_cnt_slots = (size_t)c->opt.max_events + 4;
@@ -456,6 +466,7 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
     k.gs = cv.take<uint32_t>(N);
     k.ctr = cv.take<uint32_t>(N);
     k.id = cv.take<uint32_t>(N);
+    k.nseg = cv.take<uint32_t>(N);
   }
   d.src_x = cv.take<double>(N);
   d.src_y = cv.take<double>(N);
@@ -795,17 +806,21 @@ static int run_generation(mcx_ctx* c, int gen) {
   const int block = c->opt.block_size;
   for (;;) {
     if (bound == 0) break;
+    // every live particle makes at least one flight per iteration, so after
+    // iteration max_events the guard has ended every history (the host's
+    // count lags a few iterations behind the device)
+    if (it > c->opt.max_events) break;
     if ((size_t)it + 3 >= c->d.n_cnt_slots) return fail(c, MCX_EDEVICE, "iteration slots exhausted");
     if (tail > 0 && bound <= (uint32_t)tail) {
       HIP_TRY(c, time_mark(c, 2, true));
-      HIP_TRY(c, launch_tail(prec, rec, T, gen, (uint32_t)it, c->d.bank[cur], c->d.cnt_live + it, A, c->d.R,
+      HIP_TRY(c, launch_tail(prec, rec, T, gen, c->d.bank[cur], c->d.cnt_live + it, A, c->d.R,
                              bound, s));
       HIP_TRY(c, time_mark(c, 2, false));
       c->timing.n_tail_launches += 1;
       break;
     }
     HIP_TRY(c, time_mark(c, 0, true));
-    HIP_TRY(c, launch_advance(prec, rec, T, gen, (uint32_t)it, c->d.bank[cur], c->d.cnt_live + it,
+    HIP_TRY(c, launch_advance(prec, rec, T, gen, (uint32_t)c->opt.flights, c->d.bank[cur], c->d.cnt_live + it,
                               c->d.bank[1 - cur], c->d.cnt_live + it + 1, c->d.bank[2],
                               c->d.cnt_col + it, A, c->d.R, c->d.cnt_live + it + 2, c->d.cnt_col + it + 1,
                               bound, block, s));
@@ -963,6 +978,7 @@ int mcx_run_generations(mcx_ctx* c, int32_t n_gen, int32_t n_inactive) {
   for (int g = 0; g < ng; ++g) {
     c->timing.advance_items += (int64_t)c->h_gen_cnt[(size_t)g * N_CNT_ALL + CNT_ADV_ITEMS];
     c->timing.collide_items += (int64_t)c->h_gen_cnt[(size_t)g * N_CNT_ALL + CNT_COL_ITEMS];
+    c->timing.advance_segments += (int64_t)c->h_gen_cnt[(size_t)g * N_CNT_ALL + CNT_ADV_SEGS];
   }
   if (rc != MCX_OK) return rc;
   for (int g = 0; g < ng; ++g)

@@ -36,7 +36,8 @@ enum : int {
   N_CNT = 9,
   CNT_ADV_ITEMS = 9,   // lanes processed by advance kernels
   CNT_COL_ITEMS = 10,  // lanes processed by collide kernels
-  N_CNT_ALL = 11
+  CNT_ADV_SEGS = 11,   // flights made inside advance kernels
+  N_CNT_ALL = 12
 };
 enum : int { K_COL = 0, K_TL = 1, K_ABS = 2 };
 constexpr int STRIPES = 64;  // copies of each global accumulator (atomic contention)
@@ -114,6 +115,7 @@ struct Bank {
   uint32_t* gs;   // group (16 bits) | sites banked so far (16 bits)
   uint32_t* ctr;  // transport-stream draws consumed
   uint32_t* id;   // source index of the history
+  uint32_t* nseg; // flights made so far (event guard)
 };
 
 // Fission sites as banked (unordered) and in canonical (parent, seq) order.

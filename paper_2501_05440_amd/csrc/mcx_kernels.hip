@@ -49,6 +49,7 @@ __global__ void k_birth(Tables T, uint32_t gen, uint32_t n, const double* sx, co
   p.nsite = 0;
   p.ctr = rs.draw;
   p.id = id;
+  p.nseg = 0;
   store_part(out, id, p);
 }
 
@@ -56,12 +57,15 @@ __global__ void k_birth(Tables T, uint32_t gen, uint32_t n, const double* sx, co
 // event kernels
 // ---------------------------------------------------------------------------
 
-// Advance every particle of the input bank by one flight.  Particles that
-// cross a surface and stay inside go to the live bank of the next iteration,
+// Advance every particle of the input bank: flights through the lattice
+// until a collision, a leak, the event guard, or `flights` flights (1 is the
+// one-event-per-launch form; more keeps a particle in the kernel across its
+// surface crossings, with the same operations in the same order).
+// Particles still flying go to the live bank of the next iteration,
 // particles that collide go to the collision bank; leaks and guard kills end
 // here.  Block 0 clears the counters the next iteration appends to.
 template <class R, bool REC>
-__global__ void __launch_bounds__(1024) k_advance(Tables T, uint32_t gen, uint32_t it, Bank in,
+__global__ void __launch_bounds__(1024) k_advance(Tables T, uint32_t gen, uint32_t flights, Bank in,
                                                   const uint32_t* __restrict__ n_in_p, Bank live,
                                                   uint32_t* n_live, Bank col, uint32_t* n_col,
                                                   Accum A, Records Rc, uint32_t* clr_live,
@@ -73,31 +77,40 @@ __global__ void __launch_bounds__(1024) k_advance(Tables T, uint32_t gen, uint32
   const uint32_t n_in = *n_in_p;
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   int ev = EV_NONE;
-  bool refl = false;
+  uint32_t c_seg = 0, c_cross = 0, c_refl = 0;
   Part<R> p;
   if (k < n_in) {
     p = load_part<R>(in, k);
-    if ((int64_t)it >= T.max_events) {
-      ev = EV_KILL;
-      die<R, REC>(p, FATE_KILLED, A, Rc);
-    } else {
-      Stream rs(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
+    Stream rs(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
+    for (uint32_t f = 0; f < flights; ++f) {
+      if ((int64_t)p.nseg >= T.max_events) {
+        ev = EV_KILL;
+        break;
+      }
+      bool refl = false;
       ev = segment<R, REC, false>(T, T.geo, p, rs, A, Rc, &refl);
-      p.ctr = rs.draw;
-      if (ev == EV_LEAK) die<R, REC>(p, FATE_LEAKED, A, Rc);
+      p.nseg += 1;
+      c_seg += 1;
+      c_cross += ev != EV_COLLIDE ? 1u : 0u;
+      c_refl += refl ? 1u : 0u;
+      if (ev != EV_CROSS) break;
     }
+    p.ctr = rs.draw;
+    if (ev == EV_KILL) die<R, REC>(p, FATE_KILLED, A, Rc);
+    if (ev == EV_LEAK) die<R, REC>(p, FATE_LEAKED, A, Rc);
   }
   __shared__ uint32_t lds[2 * (MAX_WAVES + 1)];
   uint32_t pl, pc;
   block_append2(ev == EV_CROSS, ev == EV_COLLIDE, n_live, n_col, lds, &pl, &pc);
   if (ev == EV_CROSS) store_part(live, pl, p);
   if (ev == EV_COLLIDE) store_part(col, pc, p);
-  wave_flag(A.cnt + CNT_SEG * STRIPES, ev == EV_COLLIDE || ev == EV_CROSS || ev == EV_LEAK);
-  wave_flag(A.cnt + CNT_CROSS * STRIPES, ev == EV_CROSS || ev == EV_LEAK);
-  wave_flag(A.cnt + CNT_REFL * STRIPES, refl);
+  wave_count(A.cnt + CNT_SEG * STRIPES, c_seg);
+  wave_count(A.cnt + CNT_CROSS * STRIPES, c_cross);
+  wave_count(A.cnt + CNT_REFL * STRIPES, c_refl);
   wave_flag(A.cnt + CNT_LEAK * STRIPES, ev == EV_LEAK);
   wave_flag(A.cnt + CNT_KILLED * STRIPES, ev == EV_KILL);
   wave_flag(A.cnt + CNT_ADV_ITEMS * STRIPES, k < n_in);
+  wave_count(A.cnt + CNT_ADV_SEGS * STRIPES, c_seg);
 }
 
 // Process the collision bank: collision estimator, fission-bank append
@@ -151,7 +164,7 @@ __global__ void __launch_bounds__(1024) k_collide(Tables T, uint32_t gen, Bank i
 // particle's remaining flights and collisions to the end (the same
 // operations as the event kernels, in the same order).
 template <class R, bool REC>
-__global__ void __launch_bounds__(256) k_tail(Tables T, uint32_t gen, uint32_t it0, Bank in,
+__global__ void __launch_bounds__(256) k_tail(Tables T, uint32_t gen, Bank in,
                                               const uint32_t* __restrict__ n_in_p, Accum A,
                                               Records Rc) {
   const uint32_t n_in = *n_in_p;
@@ -163,7 +176,7 @@ __global__ void __launch_bounds__(256) k_tail(Tables T, uint32_t gen, uint32_t i
     const double k_used = *A.k_used;
     Part<R> p = load_part<R>(in, k);
     Stream rs(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
-    int64_t nseg = it0;
+    int64_t nseg = p.nseg;
     for (;;) {
       if (nseg >= T.max_events) {
         p.ctr = rs.draw;
@@ -557,15 +570,15 @@ hipError_t launch_birth(int prec, const Tables& T, uint32_t gen, uint32_t n, con
 }
 
 template <class R, bool REC>
-static void advance_k(dim3 g, dim3 b, hipStream_t s, const Tables& T, uint32_t gen, uint32_t it,
+static void advance_k(dim3 g, dim3 b, hipStream_t s, const Tables& T, uint32_t gen, uint32_t flights,
                       const Bank& in, const uint32_t* n_in, const Bank& live, uint32_t* n_live,
                       const Bank& col, uint32_t* n_col, const Accum& A, const Records& Rc,
                       uint32_t* clr_live, uint32_t* clr_col) {
-  hipLaunchKernelGGL((k_advance<R, REC>), g, b, 0, s, T, gen, it, in, n_in, live, n_live, col,
+  hipLaunchKernelGGL((k_advance<R, REC>), g, b, 0, s, T, gen, flights, in, n_in, live, n_live, col,
                      n_col, A, Rc, clr_live, clr_col);
 }
 
-hipError_t launch_advance(int prec, bool rec, const Tables& T, uint32_t gen, uint32_t it,
+hipError_t launch_advance(int prec, bool rec, const Tables& T, uint32_t gen, uint32_t flights,
                           const Bank& in, const uint32_t* n_in, const Bank& live,
                           uint32_t* n_live, const Bank& col, uint32_t* n_col, const Accum& A,
                           const Records& Rc, uint32_t* clr_live, uint32_t* clr_col,
@@ -573,17 +586,17 @@ hipError_t launch_advance(int prec, bool rec, const Tables& T, uint32_t gen, uin
   const dim3 g(std::max(1u, nblk(bound, block))), b(block);
   if (prec == 0) {
     if (rec)
-      advance_k<double, true>(g, b, s, T, gen, it, in, n_in, live, n_live, col, n_col, A, Rc,
+      advance_k<double, true>(g, b, s, T, gen, flights, in, n_in, live, n_live, col, n_col, A, Rc,
                               clr_live, clr_col);
     else
-      advance_k<double, false>(g, b, s, T, gen, it, in, n_in, live, n_live, col, n_col, A, Rc,
+      advance_k<double, false>(g, b, s, T, gen, flights, in, n_in, live, n_live, col, n_col, A, Rc,
                                clr_live, clr_col);
   } else {
     if (rec)
-      advance_k<float, true>(g, b, s, T, gen, it, in, n_in, live, n_live, col, n_col, A, Rc,
+      advance_k<float, true>(g, b, s, T, gen, flights, in, n_in, live, n_live, col, n_col, A, Rc,
                              clr_live, clr_col);
     else
-      advance_k<float, false>(g, b, s, T, gen, it, in, n_in, live, n_live, col, n_col, A, Rc,
+      advance_k<float, false>(g, b, s, T, gen, flights, in, n_in, live, n_live, col, n_col, A, Rc,
                               clr_live, clr_col);
   }
   return hipGetLastError();
@@ -612,20 +625,19 @@ hipError_t launch_collide(int prec, bool rec, const Tables& T, uint32_t gen, con
   return hipGetLastError();
 }
 
-hipError_t launch_tail(int prec, bool rec, const Tables& T, uint32_t gen, uint32_t it0,
-                       const Bank& in, const uint32_t* n_in, const Accum& A, const Records& Rc,
+hipError_t launch_tail(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in, const uint32_t* n_in, const Accum& A, const Records& Rc,
                        uint32_t bound, hipStream_t s) {
   const dim3 g(std::max(1u, nblk(bound, 64))), b(64);
   if (prec == 0) {
     if (rec)
-      hipLaunchKernelGGL((k_tail<double, true>), g, b, 0, s, T, gen, it0, in, n_in, A, Rc);
+      hipLaunchKernelGGL((k_tail<double, true>), g, b, 0, s, T, gen, in, n_in, A, Rc);
     else
-      hipLaunchKernelGGL((k_tail<double, false>), g, b, 0, s, T, gen, it0, in, n_in, A, Rc);
+      hipLaunchKernelGGL((k_tail<double, false>), g, b, 0, s, T, gen, in, n_in, A, Rc);
   } else {
     if (rec)
-      hipLaunchKernelGGL((k_tail<float, true>), g, b, 0, s, T, gen, it0, in, n_in, A, Rc);
+      hipLaunchKernelGGL((k_tail<float, true>), g, b, 0, s, T, gen, in, n_in, A, Rc);
     else
-      hipLaunchKernelGGL((k_tail<float, false>), g, b, 0, s, T, gen, it0, in, n_in, A, Rc);
+      hipLaunchKernelGGL((k_tail<float, false>), g, b, 0, s, T, gen, in, n_in, A, Rc);
   }
   return hipGetLastError();
 }

@@ -99,7 +99,7 @@ struct Part {
   double x, y;
   R u, v;
   int i, j, r, g;
-  uint32_t nsite, ctr, id;
+  uint32_t nsite, ctr, id, nseg;
 };
 
 template <class R>
@@ -118,6 +118,7 @@ __device__ __forceinline__ Part<R> load_part(const Bank& b, uint32_t k) {
   p.nsite = gs >> 16;
   p.ctr = b.ctr[k];
   p.id = b.id[k];
+  p.nseg = b.nseg[k];
   return p;
 }
 
@@ -131,6 +132,7 @@ __device__ __forceinline__ void store_part(const Bank& b, uint32_t k, const Part
   b.gs[k] = (uint32_t)p.g | (p.nsite << 16);
   b.ctr[k] = p.ctr;
   b.id[k] = p.id;
+  b.nseg[k] = p.nseg;
 }
 
 enum : int { EV_NONE = 0, EV_COLLIDE = 1, EV_CROSS = 2, EV_LEAK = 3, EV_KILL = 4 };

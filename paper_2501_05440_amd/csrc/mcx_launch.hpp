@@ -20,7 +20,7 @@ hipError_t launch_birth(int prec, const Tables& T, uint32_t gen, uint32_t n, con
                         hipStream_t s);
 hipError_t launch_gen_check(const Tables& T, const uint32_t* n_fis, const uint32_t* scan_total,
                             uint32_t* status, hipStream_t s);
-hipError_t launch_advance(int prec, bool rec, const Tables& T, uint32_t gen, uint32_t it,
+hipError_t launch_advance(int prec, bool rec, const Tables& T, uint32_t gen, uint32_t flights,
                           const Bank& in, const uint32_t* n_in, const Bank& live,
                           uint32_t* n_live, const Bank& col, uint32_t* n_col, const Accum& A,
                           const Records& Rc, uint32_t* clr_live, uint32_t* clr_col,
@@ -29,8 +29,7 @@ hipError_t launch_collide(int prec, bool rec, const Tables& T, uint32_t gen, con
                           const uint32_t* n_in, const Bank& live, uint32_t* n_live,
                           const Accum& A, const Records& Rc, uint32_t bound, int block,
                           hipStream_t s);
-hipError_t launch_tail(int prec, bool rec, const Tables& T, uint32_t gen, uint32_t it0,
-                       const Bank& in, const uint32_t* n_in, const Accum& A, const Records& Rc,
+hipError_t launch_tail(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in, const uint32_t* n_in, const Accum& A, const Records& Rc,
                        uint32_t bound, hipStream_t s);
 uint32_t scan_chunks(uint32_t n);
 hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* chunk_sum, uint32_t* out,

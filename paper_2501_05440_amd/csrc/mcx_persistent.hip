@@ -59,6 +59,7 @@ __device__ __forceinline__ Part<R> slot_load(const SlotMem<R, S>& M, int s, cons
   p.ctr = M.ctr[s];
   // the random-number id of a history is its index within its problem
   p.id = (uint32_t)(M.hid[s] - (P ? P[M.prob[s]].hist_base : 0ull));
+  p.nseg = M.nseg[s];
   return p;
 }
 

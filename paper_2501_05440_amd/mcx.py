@@ -44,7 +44,7 @@ class Options(C.Structure):
                 ("lookahead", C.c_int32), ("max_events", C.c_int64),
                 ("record_histories", C.c_int32), ("time_kernels", C.c_int32),
                 ("engine", C.c_int32), ("p_block", C.c_int32), ("p_slots", C.c_int32),
-                ("p_grid", C.c_int32), ("p_tau", C.c_double)]
+                ("p_grid", C.c_int32), ("p_tau", C.c_double), ("flights", C.c_int32)]
 
 
 class Geometry(C.Structure):
@@ -65,7 +65,8 @@ class Timing(C.Structure):
                 ("collide_ms", C.c_double), ("tail_ms", C.c_double),
                 ("n_advance", C.c_int64), ("n_collide", C.c_int64),
                 ("advance_items", C.c_int64), ("collide_items", C.c_int64),
-                ("persistent_ms", C.c_double), ("n_persistent", C.c_int64)]
+                ("persistent_ms", C.c_double), ("n_persistent", C.c_int64),
+                ("advance_segments", C.c_int64)]
 
 
 class Problem(C.Structure):
@@ -189,7 +190,7 @@ class Context:
 
     def __init__(self, problem, device=0, record=False, block_size=0, tail_threshold=0,
                  lookahead=0, max_events=None, time_kernels=False, n_gen_max=None,
-                 stream=None, precision="fp64", engine="event", persistent=None):
+                 stream=None, precision="fp64", engine="event", persistent=None, flights=0):
         import torch
 
         self.problem = problem
@@ -207,6 +208,7 @@ class Context:
         o.lookahead = lookahead
         o.max_events = rp["max_events"] if max_events is None else max_events
         o.record_histories = int(bool(record))
+        o.flights = flights
         o.time_kernels = int(bool(time_kernels))
         h = C.c_void_p()
         self._check(L.mcx_create(C.byref(h), C.byref(o)), None)

@@ -100,11 +100,13 @@ def test_device_philox_matches_oracle(oracle, ctx_c0):
         assert [int(v) for v in got[i]] == want
 
 
-def test_pin_cell_full_parity(oracle):
-    """The 7-group pin cell (1e4 histories x 30 generations, 10 inactive)."""
-    banner("pin cell 1e4 x 30 records parity")
+@pytest.mark.parametrize("flights", [1, 0])
+def test_pin_cell_full_parity(oracle, flights):
+    """The 7-group pin cell (1e4 histories x 30 generations, 10 inactive),
+    one flight per advance launch and the default."""
+    banner(f"pin cell 1e4 x 30 records parity flights={flights}")
     prob = P.pin_cell()
-    g = mcx.run(prob, record=True, bank=True)
+    g = mcx.run(prob, record=True, bank=True, flights=flights)
     o = oracle.run(prob, records=True, bank_cap=3 * prob["run"]["n_per_gen"])
     compare_runs(g, o)
     assert np.array_equal(g["bank"], o["bank"])
@@ -122,15 +124,18 @@ def test_lattice_parity_spans_tiles_and_ragged_tail(oracle):
     assert_close(g["gen_prod"], o["gen_prod"], what="gen_prod")
 
 
-@pytest.mark.parametrize("block,tail,look", [(64, -1, 1), (512, 0, 8), (1024, 1 << 30, 4),
-                                             (256, 100, 2)])
-def test_launch_configuration_does_not_change_results(block, tail, look):
-    """Block size, tail threshold (never / default / all-tail) and lookahead:
-    bit-identical generation results (the GPU sums are exact)."""
-    banner(f"determinism block={block} tail={tail} lookahead={look}")
+@pytest.mark.parametrize("block,tail,look,flights", [(64, -1, 1, 1), (512, 0, 8, 3),
+                                                     (1024, 1 << 30, 4, 64), (256, 100, 2, 1),
+                                                     (128, -1, 3, 65536)])
+def test_launch_configuration_does_not_change_results(block, tail, look, flights):
+    """Block size, tail threshold (never / default / all-tail), lookahead and
+    flights per advance launch: bit-identical generation results and
+    per-history records (the GPU sums are exact)."""
+    banner(f"determinism block={block} tail={tail} lookahead={look} flights={flights}")
     prob = P.lattice_17x17(n_per_gen=5000, n_gen=3, n_inactive=1)
     ref = mcx.run(prob, record=True)
-    got = mcx.run(prob, record=True, block_size=block, tail_threshold=tail, lookahead=look)
+    got = mcx.run(prob, record=True, block_size=block, tail_threshold=tail, lookahead=look,
+                  flights=flights)
     for k in ("gen_k", "gen_entropy", "gen_counts", "flux_mean", "prod_mean", "k_mean"):
         assert np.array_equal(ref[k], got[k]), k
     assert np.array_equal(ref["records"], got["records"])
@@ -174,10 +179,13 @@ def test_fixed_source_batch_parity(oracle):
     assert np.all(g["gen_counts"][:, 7] == 0)
 
 
-def test_event_guard_matches_oracle(oracle):
-    banner("event guard parity")
+@pytest.mark.parametrize("flights,tail", [(1, -1), (8, -1), (2, 0), (8, 1 << 30)])
+def test_event_guard_matches_oracle(oracle, flights, tail):
+    """The guard inside a multi-flight advance launch, between launches and in
+    the tail kernel."""
+    banner(f"event guard parity flights={flights} tail={tail}")
     prob = P.with_run(P.pin_cell(n_per_gen=2000, n_gen=3, n_inactive=1), max_events=3)
-    g = mcx.run(prob, record=True)
+    g = mcx.run(prob, record=True, flights=flights, tail_threshold=tail)
     o = oracle.run(prob, records=True)
     assert g["rc"] == mcx.EGUARD
     compare_runs(g, o)
