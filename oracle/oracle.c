@@ -298,6 +298,104 @@ double orc_neumaier(const double* v, int64_t n) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* continuous energy (Sec. 1 capability; Sec. 4 continuous-energy pin cell)   */
+/* ------------------------------------------------------------------------ */
+
+/* The interval of an increasing grid that holds e: the largest i with
+   grid[i] <= e, limited to [0, n - 2], so energies beyond either end use the
+   end intervals.  Found by bisection; the index is unique, so any search
+   that returns it is equivalent. */
+int orc_ce_interval(const double* grid, int n, double e) {
+  int lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    int mid = lo + (hi - lo) / 2;
+    if (grid[mid] <= e)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+/* Linear interpolation in energy within interval i: the fraction
+   (e - E_i) / (E_{i+1} - E_i) clipped to [0, 1], then v_i + f (v_{i+1} - v_i). */
+static double ce_frac(const double* grid, int i, double e) {
+  double f = (e - grid[i]) / (grid[i + 1] - grid[i]);
+  if (f < 0.0) f = 0.0;
+  if (f > 1.0) f = 1.0;
+  return f;
+}
+
+static double ce_lerp(const double* row, int i, double f) { return row[i] + f * (row[i + 1] - row[i]); }
+
+/* Macroscopic total, scattering and fission cross sections of material m at
+   energy e: sums of density times interpolated microscopic values, taken in
+   the material's nuclide order. */
+void orc_ce_macro(const orc_ce* ce, int m, double e, double out[3]) {
+  int i = orc_ce_interval(ce->e_grid, ce->n_pts, e);
+  double f = ce_frac(ce->e_grid, i, e);
+  double st = 0.0, ss = 0.0, sf = 0.0;
+  for (int k = 0; k < ce->mat_n[m]; ++k) {
+    int n = ce->mat_nuc[m * ce->max_nuc + k];
+    double dens = ce->mat_dens[m * ce->max_nuc + k];
+    int64_t row = (int64_t)n * ce->n_pts;
+    st = st + dens * ce_lerp(ce->sig_t + row, i, f);
+    ss = ss + dens * ce_lerp(ce->sig_s + row, i, f);
+    sf = sf + dens * ce_lerp(ce->sig_f + row, i, f);
+  }
+  out[0] = st;
+  out[1] = ss;
+  out[2] = sf;
+}
+
+/* One attempt of the Watt spectrum sampler: a Maxwellian variate of
+   temperature a by the three-uniform rule W = -a (ln x1 + ln x2 cos^2(pi x3 / 2)),
+   then E = W + a^2 b / 4 + (2 x4 - 1) sqrt(a^2 b W).  cos(pi x3 / 2) is
+   cos(2 pi (x3 / 4)), with x3 / 4 exact. */
+double orc_watt_attempt(double a, double b, double xi1, double xi2, double xi3, double xi4) {
+  double c, s;
+  orc_cr_cossin_2pi(0.25 * xi3, &c, &s);
+  double w = -a * (orc_cr_log(xi1) + orc_cr_log(xi2) * (c * c));
+  double q = a * a * b;
+  return (w + 0.25 * q) + (2.0 * xi4 - 1.0) * sqrt(q * w);
+}
+
+/* Elastic scattering off a target of mass ratio A at rest, isotropic in the
+   centre-of-mass frame: mu_cm = 2 xi - 1, outgoing energy
+   E (A^2 + 2 A mu_cm + 1) / (A + 1)^2, lab cosine
+   (1 + A mu_cm) / sqrt(A^2 + 2 A mu_cm + 1). */
+double orc_elastic(double awr, double e, double xi_mu, double* mu_lab) {
+  double mu = 2.0 * xi_mu - 1.0;
+  double num = (awr * awr + 2.0 * awr * mu) + 1.0;
+  double ap1 = awr + 1.0;
+  *mu_lab = (1.0 + awr * mu) / sqrt(num);
+  return e * num / (ap1 * ap1);
+}
+
+/* Turn the unit direction dir by the polar cosine mu about itself, azimuth
+   2 pi xi_phi (the textbook rotation; when the direction lies within 1e-10
+   of the z axis, the same formula with x taking z's role). */
+void orc_rotate(double mu, double xi_phi, double dir[3]) {
+  double c, s;
+  orc_cr_cossin_2pi(xi_phi, &c, &s);
+  double u = dir[0], v = dir[1], w = dir[2];
+  double sm = 1.0 - mu * mu;
+  sm = sm > 0.0 ? sqrt(sm) : 0.0;
+  double a = 1.0 - w * w;
+  if (a > 1e-10) {
+    double t = sqrt(a);
+    dir[0] = mu * u + sm * (u * w * c - v * s) / t;
+    dir[1] = mu * v + sm * (v * w * c + u * s) / t;
+    dir[2] = mu * w - sm * t * c;
+  } else {
+    double t = sqrt(1.0 - u * u);
+    dir[1] = mu * v + sm * (v * u * c - w * s) / t;
+    dir[2] = mu * w + sm * (w * u * c + v * s) / t;
+    dir[0] = mu * u - sm * t * c;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* the run                                                                  */
 /* ------------------------------------------------------------------------ */
 
@@ -305,10 +403,11 @@ typedef struct {
   double* x;
   double* y;
   int32_t* g;
+  double* e;
   int64_t n, cap;
 } sites_t;
 
-static int sites_push(sites_t* s, double x, double y, int32_t g) {
+static int sites_push(sites_t* s, double x, double y, int32_t g, double e) {
   if (s->n == s->cap) {
     int64_t nc = s->cap ? 2 * s->cap : 1024;
     double* nx = realloc(s->x, (size_t)nc * sizeof(double));
@@ -320,11 +419,15 @@ static int sites_push(sites_t* s, double x, double y, int32_t g) {
     int32_t* ng = realloc(s->g, (size_t)nc * sizeof(int32_t));
     if (!ng) return -1;
     s->g = ng;
+    double* ne = realloc(s->e, (size_t)nc * sizeof(double));
+    if (!ne) return -1;
+    s->e = ne;
     s->cap = nc;
   }
   s->x[s->n] = x;
   s->y[s->n] = y;
   s->g[s->n] = g;
+  s->e[s->n] = e;
   s->n += 1;
   return 0;
 }
@@ -333,6 +436,7 @@ static void sites_free(sites_t* s) {
   free(s->x);
   free(s->y);
   free(s->g);
+  free(s->e);
   memset(s, 0, sizeof(*s));
 }
 
@@ -359,6 +463,7 @@ typedef struct {
   const double* src_x;
   const double* src_y;
   const int32_t* src_g;
+  const double* src_e;         /* continuous energy: source energies */
   const double* src_dir;       /* [N][3] or NULL */
   chunk_t* chunks;
   int64_t n_chunks, chunk_size;
@@ -400,8 +505,22 @@ static int material_at(const ctx_t* C, int i, int j, int r) {
 /* Source site of particle id in batch gen: rejection in the lattice's
    bounding box until the point lies in a fissile material, then a group
    from that material's fission spectrum. */
+/* A Watt-spectrum energy: attempts of four draws each until one lies in
+   (0, e_max]. */
+static double watt_sample(const orc_ce* ce, stream_t* s) {
+  for (int t = 0; t < 10000; ++t) {
+    double x1 = next_uniform(s);
+    double x2 = next_uniform(s);
+    double x3 = next_uniform(s);
+    double x4 = next_uniform(s);
+    double e = orc_watt_attempt(ce->watt_a, ce->watt_b, x1, x2, x3, x4);
+    if (e > 0.0 && e <= ce->e_max) return e;
+  }
+  return ce->e_max;
+}
+
 static int sample_source(const ctx_t* C, int64_t id, int gen, double* sx, double* sy,
-                         int32_t* sg) {
+                         int32_t* sg, double* se) {
   const orc_problem* p = C->p;
   stream_t s;
   stream_init(&s, p->seed, ORC_TAG_SRC, (uint64_t)id, (uint64_t)gen, p->problem_id);
@@ -416,10 +535,16 @@ static int sample_source(const ctx_t* C, int64_t id, int gen, double* sx, double
     locate(p, x, y, &i, &j, &r);
     int m = material_at(C, i, j, r);
     if (C->fissile[m]) {
-      double xi = next_uniform(&s);
       *sx = x;
       *sy = y;
-      *sg = orc_sample_cdf(xi, p->chi + (int64_t)m * p->n_grp, p->n_grp);
+      if (p->ce) {
+        *sg = 0;
+        *se = watt_sample(p->ce, &s);
+      } else {
+        double xi = next_uniform(&s);
+        *sg = orc_sample_cdf(xi, p->chi + (int64_t)m * p->n_grp, p->n_grp);
+        *se = 0.0;
+      }
       return 0;
     }
   }
@@ -512,7 +637,7 @@ static void run_history(ctx_t* C, int64_t id, chunk_t* ch) {
         for (int s = 0; s < nf; ++s) {
           double xs = next_uniform(&rs);
           int gs = orc_sample_cdf(xs, p->chi + (int64_t)m * G, G);
-          if (sites_push(&ch->sites, x, y, gs)) ch->err = ORC_ENOMEM;
+          if (sites_push(&ch->sites, x, y, gs, 0.0)) ch->err = ORC_ENOMEM;
           n_sites += 1;
         }
       }
@@ -598,6 +723,205 @@ static void run_history(ctx_t* C, int64_t id, chunk_t* ch) {
     rec->kcol_sum = kcol_sum;
     rec->x_final = x;
     rec->y_final = y;
+    rec->e_final = 0.0;
+  }
+}
+
+/* One continuous-energy history.  The flight is the multigroup one with the
+   macroscopic cross sections of the current energy; a collision banks
+   fission sites with Watt energies, picks the nuclide by its share of the
+   total cross section, then scatters elastically off it (target at rest) or
+   absorbs.  Draw order per collision: fission (k-eigenvalue, fissile), four
+   per Watt attempt per site, nuclide, scatter test, then for a scatter the
+   centre-of-mass cosine and, above the cutoff, the azimuth. */
+static void run_history_ce(ctx_t* C, int64_t id, chunk_t* ch) {
+  const orc_problem* p = C->p;
+  const orc_ce* ce = p->ce;
+  const int NB = ce->n_ebins;
+  stream_t rs;
+  stream_init(&rs, p->seed, ORC_TAG_TRANSPORT, (uint64_t)id, (uint64_t)C->gen, p->problem_id);
+
+  double x = C->src_x[id], y = C->src_y[id], e = C->src_e[id];
+  int i, j, r;
+  locate(p, x, y, &i, &j, &r);
+  double dir[3];
+  if (C->src_dir) {
+    dir[0] = C->src_dir[3 * id + 0];
+    dir[1] = C->src_dir[3 * id + 1];
+    dir[2] = C->src_dir[3 * id + 2];
+  } else {
+    double xm = next_uniform(&rs);
+    double xp = next_uniform(&rs);
+    orc_isotropic(xm, xp, dir);
+  }
+
+  int32_t n_seg = 0, n_col = 0, n_cross = 0, n_refl = 0, n_sites = 0;
+  int fate = ORC_ALIVE;
+  double tl_sum = 0.0, kcol_sum = 0.0;
+
+  for (;;) {
+    if (n_seg >= p->max_events) {
+      fate = ORC_KILLED;
+      break;
+    }
+    int c = j * p->nx + i;
+    int un = p->pin_map[c];
+    int nr = p->n_rings[un];
+    int m = p->mats[un * C->mr1 + r];
+    double xs[3];
+    orc_ce_macro(ce, m, e, xs);
+    double st = xs[0];
+    double nusf = ce->nu * xs[2];
+    double u = dir[0], v = dir[1];
+
+    double xi = next_uniform(&rs);
+    double d_col = -orc_cr_log(xi) / st;
+
+    double xlo = p->x0 + (double)i * p->pitch, xhi = p->x0 + (double)(i + 1) * p->pitch;
+    double ylo = p->y0 + (double)j * p->pitch, yhi = p->y0 + (double)(j + 1) * p->pitch;
+    double tx = orc_dist_plane(x, xlo, xhi, u);
+    double ty = orc_dist_plane(y, ylo, yhi, v);
+    double cx = p->x0 + ((double)i + 0.5) * p->pitch;
+    double cy = p->y0 + ((double)j + 0.5) * p->pitch;
+    double dx = x - cx, dy = y - cy;
+    double t_out = INFINITY, t_in = INFINITY;
+    if (r < nr) t_out = orc_dist_cylinder(dx, dy, u, v, p->radii[un * p->max_rings + r], 1);
+    if (r > 0) t_in = orc_dist_cylinder(dx, dy, u, v, p->radii[un * p->max_rings + r - 1], 0);
+    double d_bnd = tx;
+    if (ty < d_bnd) d_bnd = ty;
+    if (t_out < d_bnd) d_bnd = t_out;
+    if (t_in < d_bnd) d_bnd = t_in;
+
+    n_seg += 1;
+    int collide = d_col < d_bnd;
+    double d = collide ? d_col : d_bnd;
+    x = x + d * u;
+    y = y + d * v;
+
+    /* track-length flux per (cell, region, energy bin); the track-length k
+       estimator sums d nu Sigma_f(E) */
+    int b = orc_ce_interval(ce->e_edges, NB + 1, e);
+    int64_t bin = ((int64_t)c * C->mr1 + r) * NB + b;
+    nadd(&ch->flux[bin], d);
+    nadd(&ch->k[1], d * nusf);
+    tl_sum += d;
+
+    if (collide) {
+      n_col += 1;
+      double kc = nusf / st;
+      kcol_sum += kc;
+      nadd(&ch->k[0], kc);
+      if (!p->fixed_source && nusf > 0.0) {
+        double xf = next_uniform(&rs);
+        int nf = (int)floor(nusf / (st * C->k_used) + xf);
+        for (int q = 0; q < nf; ++q) {
+          double es = watt_sample(ce, &rs);
+          if (sites_push(&ch->sites, x, y, 0, es)) ch->err = ORC_ENOMEM;
+          n_sites += 1;
+        }
+      }
+      /* nuclide: first k with xi * Sigma_t below the running sum of
+         N_k sigma_t,k (the same sums as the macroscopic total) */
+      int gi = orc_ce_interval(ce->e_grid, ce->n_pts, e);
+      double f = ce_frac(ce->e_grid, gi, e);
+      double xn = next_uniform(&rs);
+      double target = xn * st;
+      double cum = 0.0;
+      int pick = -1, last_nz = -1;
+      for (int k = 0; k < ce->mat_n[m]; ++k) {
+        int n = ce->mat_nuc[m * ce->max_nuc + k];
+        double term = ce->mat_dens[m * ce->max_nuc + k] *
+                      ce_lerp(ce->sig_t + (int64_t)n * ce->n_pts, gi, f);
+        cum = cum + term;
+        if (term > 0.0) last_nz = k;
+        if (pick < 0 && target < cum) pick = k;
+      }
+      if (pick < 0) pick = last_nz;
+      int nuc = ce->mat_nuc[m * ce->max_nuc + pick];
+      double mt = ce_lerp(ce->sig_t + (int64_t)nuc * ce->n_pts, gi, f);
+      double ms = ce_lerp(ce->sig_s + (int64_t)nuc * ce->n_pts, gi, f);
+      double xr = next_uniform(&rs);
+      if (xr * mt < ms) {
+        ch->counts[ORC_C_SCAT] += 1;
+        double xm = next_uniform(&rs);
+        double mu;
+        double e_out = orc_elastic(ce->awr[nuc], e, xm, &mu);
+        e = e_out;
+        if (e < ce->e_cut) {
+          fate = ORC_CUTOFF;
+          break;
+        }
+        double xp = next_uniform(&rs);
+        orc_rotate(mu, xp, dir);
+      } else {
+        nadd(&ch->k[2], nusf > 0.0 ? nusf / (st - xs[1]) : 0.0);
+        fate = ORC_ABSORBED;
+        break;
+      }
+    } else {
+      n_cross += 1;
+      int hit_x = tx == d_bnd;
+      int hit_y = ty == d_bnd;
+      if (hit_x || hit_y) {
+        int out_x = hit_x && (u > 0.0 ? i == p->nx - 1 : i == 0);
+        int out_y = hit_y && (v > 0.0 ? j == p->ny - 1 : j == 0);
+        int side_x = u > 0.0 ? 1 : 0;
+        int side_y = v > 0.0 ? 3 : 2;
+        if ((out_x && p->bc[side_x] == ORC_VACUUM) || (out_y && p->bc[side_y] == ORC_VACUUM)) {
+          fate = ORC_LEAKED;
+          break;
+        }
+        int refl = 0;
+        if (hit_x) {
+          if (out_x) {
+            dir[0] = -u;
+            refl = 1;
+          } else {
+            i += u > 0.0 ? 1 : -1;
+          }
+        }
+        if (hit_y) {
+          if (out_y) {
+            dir[1] = -v;
+            refl = 1;
+          } else {
+            j += v > 0.0 ? 1 : -1;
+          }
+        }
+        if (refl) n_refl += 1;
+        r = p->n_rings[p->pin_map[j * p->nx + i]];
+      } else if (t_out == d_bnd) {
+        r += 1;
+      } else {
+        r -= 1;
+      }
+    }
+  }
+
+  ch->counts[ORC_C_SEG] += n_seg;
+  ch->counts[ORC_C_COL] += n_col;
+  ch->counts[ORC_C_CROSS] += n_cross;
+  ch->counts[ORC_C_REFL] += n_refl;
+  ch->counts[ORC_C_SITES] += n_sites;
+  if (fate == ORC_LEAKED) ch->counts[ORC_C_LEAK] += 1;
+  if (fate == ORC_ABSORBED) ch->counts[ORC_C_ABS] += 1;
+  if (fate == ORC_KILLED) ch->counts[ORC_C_KILLED] += 1;
+  if (fate == ORC_CUTOFF) ch->counts[ORC_C_CUTOFF] += 1;
+  if (C->records) {
+    orc_record* rec = &C->records[id];
+    rec->n_seg = n_seg;
+    rec->n_col = n_col;
+    rec->n_cross = n_cross;
+    rec->n_refl = n_refl;
+    rec->fate = fate;
+    rec->n_sites = n_sites;
+    rec->g_final = orc_ce_interval(ce->e_edges, NB + 1, e);
+    rec->ctr_final = rs.draw;
+    rec->tl_sum = tl_sum;
+    rec->kcol_sum = kcol_sum;
+    rec->x_final = x;
+    rec->y_final = y;
+    rec->e_final = e;
   }
 }
 
@@ -611,7 +935,10 @@ static void* worker(void* arg) {
     int64_t lo = k * C->chunk_size;
     int64_t hi = lo + C->chunk_size;
     if (hi > n) hi = n;
-    for (int64_t id = lo; id < hi; ++id) run_history(C, id, ch);
+    if (C->p->ce)
+      for (int64_t id = lo; id < hi; ++id) run_history_ce(C, id, ch);
+    else
+      for (int64_t id = lo; id < hi; ++id) run_history(C, id, ch);
   }
   return NULL;
 }
@@ -626,7 +953,7 @@ static void chunk_reset(chunk_t* ch, int64_t n_bins) {
 }
 
 int64_t orc_n_bins(const orc_problem* p) {
-  return (int64_t)p->nx * p->ny * (p->max_rings + 1) * p->n_grp;
+  return (int64_t)p->nx * p->ny * (p->max_rings + 1) * (p->ce ? p->ce->n_ebins : p->n_grp);
 }
 
 static int fail(orc_output* out, int code, const char* msg) {
@@ -636,7 +963,7 @@ static int fail(orc_output* out, int code, const char* msg) {
 
 static int validate(const orc_problem* p, orc_output* out) {
   if (p->nx < 1 || p->ny < 1 || !(p->pitch > 0.0)) return fail(out, ORC_EINVAL, "bad lattice");
-  if (p->n_univ < 1 || p->max_rings < 1 || p->n_mat < 1 || p->n_grp < 1)
+  if (p->n_univ < 1 || p->max_rings < 1 || p->n_mat < 1 || (!p->ce && p->n_grp < 1))
     return fail(out, ORC_EINVAL, "bad sizes");
   if (p->n_per_gen < 1 || p->n_gen < 1 || p->n_inactive < 0 || p->n_inactive >= p->n_gen)
     return fail(out, ORC_EINVAL, "bad run sizes");
@@ -655,6 +982,30 @@ static int validate(const orc_problem* p, orc_output* out) {
       if (!(rad > prev) || !(rad < 0.5 * p->pitch)) return fail(out, ORC_EINVAL, "ring radius");
       prev = rad;
     }
+  }
+  if (p->ce) {
+    const orc_ce* ce = p->ce;
+    if (ce->n_nuc < 1 || ce->n_pts < 2 || ce->max_nuc < 1 || ce->n_ebins < 1 || !(ce->nu >= 0.0) ||
+        !(ce->watt_a > 0.0) || !(ce->watt_b >= 0.0) || !(ce->e_max > 0.0) || !(ce->e_cut >= 0.0))
+      return fail(out, ORC_EINVAL, "continuous-energy sizes");
+    for (int k = 0; k + 1 < ce->n_pts; ++k)
+      if (!(ce->e_grid[k] < ce->e_grid[k + 1])) return fail(out, ORC_EINVAL, "energy grid order");
+    for (int k = 0; k < ce->n_ebins; ++k)
+      if (!(ce->e_edges[k] < ce->e_edges[k + 1])) return fail(out, ORC_EINVAL, "tally edges order");
+    for (int64_t k = 0; k < (int64_t)ce->n_nuc * ce->n_pts; ++k)
+      if (!(ce->sig_s[k] >= 0.0) || !(ce->sig_f[k] >= 0.0) || !(ce->sig_t[k] >= ce->sig_s[k]))
+        return fail(out, ORC_EINVAL, "pointwise cross sections");
+    for (int n = 0; n < ce->n_nuc; ++n)
+      if (!(ce->awr[n] > 0.0)) return fail(out, ORC_EINVAL, "target mass");
+    for (int m = 0; m < p->n_mat; ++m) {
+      if (ce->mat_n[m] < 1 || ce->mat_n[m] > ce->max_nuc) return fail(out, ORC_EINVAL, "material size");
+      for (int k = 0; k < ce->mat_n[m]; ++k) {
+        int n = ce->mat_nuc[m * ce->max_nuc + k];
+        if (n < 0 || n >= ce->n_nuc || !(ce->mat_dens[m * ce->max_nuc + k] >= 0.0))
+          return fail(out, ORC_EINVAL, "material nuclide");
+      }
+    }
+    return ORC_OK;
   }
   for (int64_t k = 0; k < (int64_t)p->n_mat * p->n_grp; ++k) {
     if (!(p->sig_t[k] > 0.0) || !(p->nu_sig_f[k] >= 0.0) || !(p->chi[k] >= 0.0))
@@ -678,8 +1029,22 @@ int orc_run(const orc_problem* p, orc_output* out) {
   C.n_bins = orc_n_bins(p);
   C.mr1 = p->max_rings + 1;
   C.fissile = calloc((size_t)p->n_mat, sizeof(int32_t));
-  C.sig_s_tot = calloc((size_t)p->n_mat * G, sizeof(double));
-  for (int m = 0; m < p->n_mat; ++m) {
+  C.sig_s_tot = calloc((size_t)p->n_mat * (p->ce ? 1 : G), sizeof(double));
+  if (p->ce) {
+    /* fissile: a nuclide with a nonzero density and some fission cross section */
+    const orc_ce* ce = p->ce;
+    for (int m = 0; m < p->n_mat; ++m)
+      for (int k = 0; k < ce->mat_n[m]; ++k) {
+        int n = ce->mat_nuc[m * ce->max_nuc + k];
+        if (!(ce->mat_dens[m * ce->max_nuc + k] > 0.0) || !(ce->nu > 0.0)) continue;
+        for (int q = 0; q < ce->n_pts; ++q)
+          if (ce->sig_f[(int64_t)n * ce->n_pts + q] > 0.0) {
+            C.fissile[m] = 1;
+            break;
+          }
+      }
+  }
+  for (int m = 0; m < (p->ce ? 0 : p->n_mat); ++m) {
     for (int g = 0; g < G; ++g) {
       if (p->nu_sig_f[m * G + g] > 0.0) C.fissile[m] = 1;
       double s = 0.0;
@@ -706,13 +1071,14 @@ int orc_run(const orc_problem* p, orc_output* out) {
   double* src_x = malloc((size_t)N * sizeof(double));
   double* src_y = malloc((size_t)N * sizeof(double));
   int32_t* src_g = malloc((size_t)N * sizeof(int32_t));
+  double* src_e = malloc((size_t)N * sizeof(double));
   double* src_dir = NULL;
   double* gflux = malloc((size_t)p->n_gen * C.n_bins * sizeof(double));
   double* gprod = malloc((size_t)p->n_gen * C.n_bins * sizeof(double));
   sites_t bank = {0};
   int64_t* ent_counts = calloc((size_t)p->ent_nx * p->ent_ny, sizeof(int64_t));
   int64_t* comb_idx = malloc((size_t)N * sizeof(int64_t));
-  if (!src_x || !src_y || !src_g || !gflux || !gprod || !ent_counts || !comb_idx) {
+  if (!src_x || !src_y || !src_g || !src_e || !gflux || !gprod || !ent_counts || !comb_idx) {
     rc = fail(out, ORC_ENOMEM, "out of host memory");
     goto done;
   }
@@ -732,11 +1098,12 @@ int orc_run(const orc_problem* p, orc_output* out) {
           src_dir[3 * id + 0] = p->ext_state[6 * id + 2];
           src_dir[3 * id + 1] = p->ext_state[6 * id + 3];
           src_dir[3 * id + 2] = p->ext_state[6 * id + 4];
-          src_g[id] = (int32_t)p->ext_state[6 * id + 5];
+          src_g[id] = p->ce ? 0 : (int32_t)p->ext_state[6 * id + 5];
+          src_e[id] = p->ce ? p->ext_state[6 * id + 5] : 0.0;
         }
       } else {
         for (int64_t id = 0; id < N; ++id) {
-          if (sample_source(&C, id, gen, &src_x[id], &src_y[id], &src_g[id])) {
+          if (sample_source(&C, id, gen, &src_x[id], &src_y[id], &src_g[id], &src_e[id])) {
             rc = fail(out, ORC_EINVAL, "source rejection sampling found no fissile point");
             goto done;
           }
@@ -749,6 +1116,7 @@ int orc_run(const orc_problem* p, orc_output* out) {
     C.src_x = src_x;
     C.src_y = src_y;
     C.src_g = src_g;
+    C.src_e = src_e;
     C.src_dir = src_dir;
     C.records = out->records ? out->records + (int64_t)gen * N : NULL;
     for (int64_t k = 0; k < C.n_chunks; ++k) chunk_reset(&C.chunks[k], C.n_bins);
@@ -778,7 +1146,7 @@ int orc_run(const orc_problem* p, orc_output* out) {
       }
       for (int e = 0; e < ORC_NCOUNT; ++e) counts[e] += ch->counts[e];
       for (int64_t s = 0; s < ch->sites.n; ++s)
-        if (sites_push(&bank, ch->sites.x[s], ch->sites.y[s], ch->sites.g[s])) {
+        if (sites_push(&bank, ch->sites.x[s], ch->sites.y[s], ch->sites.g[s], ch->sites.e[s])) {
           rc = fail(out, ORC_ENOMEM, "out of host memory in the bank");
           goto done;
         }
@@ -828,6 +1196,7 @@ int orc_run(const orc_problem* p, orc_output* out) {
         src_x[id] = bank.x[comb_idx[id]];
         src_y[id] = bank.y[comb_idx[id]];
         src_g[id] = bank.g[comb_idx[id]];
+        src_e[id] = bank.e[comb_idx[id]];
       }
       free(src_dir);
       src_dir = NULL;
@@ -876,7 +1245,7 @@ int orc_run(const orc_problem* p, orc_output* out) {
       for (int64_t s = 0; s < nb; ++s) {
         out->bank[3 * s + 0] = bank.x[s];
         out->bank[3 * s + 1] = bank.y[s];
-        out->bank[3 * s + 2] = (double)bank.g[s];
+        out->bank[3 * s + 2] = p->ce ? bank.e[s] : (double)bank.g[s];
       }
     }
   }
@@ -893,6 +1262,7 @@ done:
   free(src_x);
   free(src_y);
   free(src_g);
+  free(src_e);
   free(src_dir);
   free(gflux);
   free(gprod);

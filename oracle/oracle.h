@@ -33,7 +33,7 @@ enum {
 
 enum { ORC_VACUUM = 0, ORC_REFLECT = 1 };
 enum { ORC_TAG_SRC = 1, ORC_TAG_TRANSPORT = 2, ORC_TAG_RESAMPLE = 3 };
-enum { ORC_ALIVE = 0, ORC_ABSORBED = 1, ORC_LEAKED = 2, ORC_KILLED = 3 };
+enum { ORC_ALIVE = 0, ORC_ABSORBED = 1, ORC_LEAKED = 2, ORC_KILLED = 3, ORC_CUTOFF = 4 };
 
 /* per-generation counters (gen_counts[g * ORC_NCOUNT + k]) */
 enum {
@@ -46,8 +46,33 @@ enum {
   ORC_C_KILLED = 6,  /* histories ended by the event guard */
   ORC_C_SITES = 7,   /* fission sites banked (M) */
   ORC_C_SCAT = 8,    /* scatters */
-  ORC_NCOUNT = 9
+  ORC_C_CUTOFF = 9,  /* histories ended below the energy cutoff (continuous energy) */
+  ORC_NCOUNT = 10
 };
+
+/* Continuous-energy data (Sec. 1 lists continuous-energy physics among the
+   method's capabilities; Sec. 4 runs a continuous-energy pin cell).
+   Pointwise microscopic cross sections on one shared energy grid,
+   interpolated linearly in energy; elastic scattering off a target at rest;
+   a Watt fission spectrum; constant nu. */
+typedef struct {
+  int32_t n_nuc, n_pts;
+  const double* e_grid;          /* [n_pts] strictly increasing, eV */
+  const double* sig_t;           /* [n_nuc][n_pts] total, barns */
+  const double* sig_s;           /* [n_nuc][n_pts] elastic scattering */
+  const double* sig_f;           /* [n_nuc][n_pts] fission */
+  const double* awr;             /* [n_nuc] target mass in neutron masses */
+  double nu;                     /* neutrons per fission */
+  int32_t max_nuc;               /* row length of the material tables */
+  const int32_t* mat_n;          /* [n_mat] nuclides in each material */
+  const int32_t* mat_nuc;        /* [n_mat][max_nuc] nuclide indices */
+  const double* mat_dens;        /* [n_mat][max_nuc] atoms per barn-cm */
+  double watt_a, watt_b;         /* Watt spectrum parameters, eV and 1/eV */
+  double e_max;                  /* Watt energies above e_max are drawn again */
+  double e_cut;                  /* a scatter below e_cut ends the history (cutoff) */
+  int32_t n_ebins;               /* energy bins of the flux tally */
+  const double* e_edges;         /* [n_ebins + 1] increasing bin edges, eV */
+} orc_ce;
 
 typedef struct {
   /* geometry: nx x ny lattice, square pitch, lower-left corner (x0, y0) */
@@ -74,9 +99,14 @@ typedef struct {
   int32_t ent_nx, ent_ny;
   int64_t max_events;
   int32_t n_threads;
-  /* optional start states [n_per_gen][6] = x, y, u, v, w, g (fixed source,
-     first batch only); NULL samples the source */
+  /* optional start states [n_per_gen][6] = x, y, u, v, w, g (energy in eV
+     for continuous energy) (fixed source, first batch only); NULL samples
+     the source */
   const double* ext_state;
+  /* continuous-energy physics instead of the multigroup tables above
+     (n_mat still counts the materials; n_grp, sig_t, sig_s, nu_sig_f and
+     chi are unused); NULL = multigroup */
+  const orc_ce* ce;
 } orc_problem;
 
 typedef struct {
@@ -86,6 +116,7 @@ typedef struct {
   double tl_sum;                 /* total track length */
   double kcol_sum;               /* sum of nu_sig_f / sig_t over collisions */
   double x_final, y_final;
+  double e_final;                /* final energy (continuous energy), else 0 */
 } orc_record;
 
 typedef struct {
@@ -107,7 +138,8 @@ typedef struct {
 } orc_output;
 
 /* Tally bins: ((cell * (max_rings + 1)) + region) * n_grp + group,
-   cell = j * nx + i. */
+   cell = j * nx + i (continuous energy: n_ebins energy bins in place of the
+   groups; the production tally is then not kept and reads zero). */
 int64_t orc_n_bins(const orc_problem* p);
 
 int orc_run(const orc_problem* p, orc_output* out);
@@ -127,6 +159,11 @@ int orc_sample_cdf(double xi, const double* weights, int n);
 void orc_comb(int64_t n, int64_t m, double xi0, int64_t* idx);
 double orc_entropy(const int64_t* counts, int64_t n_bins, int64_t m);
 double orc_neumaier(const double* v, int64_t n);
+int orc_ce_interval(const double* grid, int n, double e);
+void orc_ce_macro(const orc_ce* ce, int m, double e, double out[3]);
+double orc_watt_attempt(double a, double b, double xi1, double xi2, double xi3, double xi4);
+double orc_elastic(double awr, double e, double xi_mu, double* mu_lab);
+void orc_rotate(double mu, double xi_phi, double dir[3]);
 
 #ifdef __cplusplus
 }

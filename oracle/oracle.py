@@ -17,8 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "oracle.c")
 
-COUNT_NAMES = ["seg", "col", "cross", "refl", "leak", "abs", "killed", "sites", "scat"]
-FATE = {"alive": 0, "absorbed": 1, "leaked": 2, "killed": 3}
+COUNT_NAMES = ["seg", "col", "cross", "refl", "leak", "abs", "killed", "sites", "scat", "cutoff"]
+FATE = {"alive": 0, "absorbed": 1, "leaked": 2, "killed": 3, "cutoff": 4}
 TAG_SRC, TAG_TRANSPORT, TAG_RESAMPLE = 1, 2, 3
 
 
@@ -51,6 +51,19 @@ class _Problem(C.Structure):
         ("ent_nx", C.c_int32), ("ent_ny", C.c_int32),
         ("max_events", C.c_int64), ("n_threads", C.c_int32),
         ("ext_state", C.c_void_p),
+        ("ce", C.c_void_p),
+    ]
+
+
+class _CE(C.Structure):
+    _fields_ = [
+        ("n_nuc", C.c_int32), ("n_pts", C.c_int32),
+        ("e_grid", C.c_void_p), ("sig_t", C.c_void_p), ("sig_s", C.c_void_p),
+        ("sig_f", C.c_void_p), ("awr", C.c_void_p), ("nu", C.c_double),
+        ("max_nuc", C.c_int32), ("mat_n", C.c_void_p), ("mat_nuc", C.c_void_p),
+        ("mat_dens", C.c_void_p), ("watt_a", C.c_double), ("watt_b", C.c_double),
+        ("e_max", C.c_double), ("e_cut", C.c_double), ("n_ebins", C.c_int32),
+        ("e_edges", C.c_void_p),
     ]
 
 
@@ -58,6 +71,7 @@ RECORD_DTYPE = np.dtype([
     ("n_seg", "<i4"), ("n_col", "<i4"), ("n_cross", "<i4"), ("n_refl", "<i4"),
     ("fate", "<i4"), ("n_sites", "<i4"), ("g_final", "<i4"), ("ctr_final", "<u4"),
     ("tl_sum", "<f8"), ("kcol_sum", "<f8"), ("x_final", "<f8"), ("y_final", "<f8"),
+    ("e_final", "<f8"),
 ])
 
 
@@ -65,7 +79,7 @@ class _Record(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("n_seg", "n_col", "n_cross", "n_refl", "fate",
                                           "n_sites", "g_final")] + [
         ("ctr_final", C.c_uint32), ("tl_sum", C.c_double), ("kcol_sum", C.c_double),
-        ("x_final", C.c_double), ("y_final", C.c_double)]
+        ("x_final", C.c_double), ("y_final", C.c_double), ("e_final", C.c_double)]
 
 
 class _Output(C.Structure):
@@ -81,7 +95,7 @@ class _Output(C.Structure):
     ]
 
 
-assert C.sizeof(_Record) == RECORD_DTYPE.itemsize == 64
+assert C.sizeof(_Record) == RECORD_DTYPE.itemsize == 72
 
 _lib = None
 
@@ -121,6 +135,16 @@ def lib():
         L.orc_entropy.restype = C.c_double
         L.orc_neumaier.argtypes = [C.POINTER(C.c_double), C.c_int64]
         L.orc_neumaier.restype = C.c_double
+        L.orc_ce_interval.argtypes = [C.POINTER(C.c_double), C.c_int, C.c_double]
+        L.orc_ce_interval.restype = C.c_int
+        L.orc_ce_macro.argtypes = [C.POINTER(_CE), C.c_int, C.c_double, C.POINTER(C.c_double)]
+        L.orc_ce_macro.restype = None
+        L.orc_watt_attempt.argtypes = [C.c_double] * 6
+        L.orc_watt_attempt.restype = C.c_double
+        L.orc_elastic.argtypes = [C.c_double] * 3 + [C.POINTER(C.c_double)]
+        L.orc_elastic.restype = C.c_double
+        L.orc_rotate.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_double)]
+        L.orc_rotate.restype = None
         _lib = L
     return _lib
 
@@ -190,6 +214,64 @@ def neumaier(values):
     return lib().orc_neumaier(v.ctypes.data_as(C.POINTER(C.c_double)), len(v))
 
 
+def ce_interval(grid, e):
+    g = np.ascontiguousarray(grid, dtype=np.float64)
+    return lib().orc_ce_interval(g.ctypes.data_as(C.POINTER(C.c_double)), len(g), float(e))
+
+
+def ce_macro(ce, m, e):
+    """(Sigma_t, Sigma_s, Sigma_f) of material m at energy e."""
+    keep = []
+    S = _ce_struct(ce, keep)
+    o = (C.c_double * 3)()
+    lib().orc_ce_macro(C.byref(S), int(m), float(e), o)
+    return tuple(o)
+
+
+def watt_attempt(a, b, x1, x2, x3, x4):
+    return lib().orc_watt_attempt(a, b, x1, x2, x3, x4)
+
+
+def elastic(awr, e, xi_mu):
+    mu = C.c_double()
+    e_out = lib().orc_elastic(awr, e, xi_mu, C.byref(mu))
+    return e_out, mu.value
+
+
+def rotate(mu, xi_phi, direction):
+    d = (C.c_double * 3)(*[float(v) for v in direction])
+    lib().orc_rotate(mu, xi_phi, d)
+    return tuple(d)
+
+
+def _ce_struct(ce, keep):
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data
+
+    S = _CE()
+    sig_t = np.asarray(ce["sig_t"])
+    S.n_nuc, S.n_pts = sig_t.shape
+    S.e_grid = arr(ce["e_grid"], np.float64)
+    S.sig_t = arr(ce["sig_t"], np.float64)
+    S.sig_s = arr(ce["sig_s"], np.float64)
+    S.sig_f = arr(ce["sig_f"], np.float64)
+    S.awr = arr(ce["awr"], np.float64)
+    S.nu = ce["nu"]
+    mat_nuc = np.asarray(ce["mat_nuc"])
+    S.max_nuc = mat_nuc.shape[1]
+    S.mat_n = arr(ce["mat_n"], np.int32)
+    S.mat_nuc = arr(mat_nuc, np.int32)
+    S.mat_dens = arr(ce["mat_dens"], np.float64)
+    S.watt_a, S.watt_b = ce["watt_a"], ce["watt_b"]
+    S.e_max, S.e_cut = ce["e_max"], ce["e_cut"]
+    edges = np.asarray(ce["e_edges"])
+    S.n_ebins = len(edges) - 1
+    S.e_edges = arr(edges, np.float64)
+    return S
+
+
 # ---------------------------------------------------------------------------
 # full runs
 # ---------------------------------------------------------------------------
@@ -207,7 +289,8 @@ def _ptr(a):
 def run(problem, n_threads=None, records=False, per_gen_tallies=False, bank_cap=0,
         ext_state=None):
     """Run the oracle on a problem dict; returns a dict of numpy arrays."""
-    geo, xs, rp = problem["geometry"], problem["xs"], problem["run"]
+    geo, rp = problem["geometry"], problem["run"]
+    ce = problem.get("ce")
     keep = []
 
     def arr(a, dt):
@@ -219,12 +302,18 @@ def run(problem, n_threads=None, records=False, per_gen_tallies=False, bank_cap=
     radii = arr(geo["radii"], np.float64)
     mats = arr(geo["mats"], np.int32)
     pin_map = arr(geo["pin_map"], np.int32)
-    sig_t = arr(xs["sig_t"], np.float64)
-    sig_s = arr(xs["sig_s"], np.float64)
-    nusf = arr(xs["nu_sig_f"], np.float64)
-    chi = arr(xs["chi"], np.float64)
-    n_mat, n_grp = sig_t.shape
-    assert sig_s.shape == (n_mat, n_grp, n_grp)
+    if ce is None:
+        xs = problem["xs"]
+        sig_t = arr(xs["sig_t"], np.float64)
+        sig_s = arr(xs["sig_s"], np.float64)
+        nusf = arr(xs["nu_sig_f"], np.float64)
+        chi = arr(xs["chi"], np.float64)
+        n_mat, n_grp = sig_t.shape
+        assert sig_s.shape == (n_mat, n_grp, n_grp)
+    else:
+        sig_t = sig_s = nusf = chi = None
+        n_mat, n_grp = len(ce["mat_n"]), 0
+        ce_s = _ce_struct(ce, keep)
     ext = None if ext_state is None else arr(ext_state, np.float64)
     if ext is not None:
         assert ext.shape == (rp["n_per_gen"], 6)
@@ -248,6 +337,7 @@ def run(problem, n_threads=None, records=False, per_gen_tallies=False, bank_cap=
     P.max_events = rp["max_events"]
     P.n_threads = n_threads if n_threads else (os.cpu_count() or 1)
     P.ext_state = _ptr(ext)
+    P.ce = None if ce is None else C.addressof(ce_s)
 
     L = lib()
     nb = L.orc_n_bins(C.byref(P))

@@ -232,6 +232,116 @@ def slab(thickness, sig_t, n_per_gen, seed):
                         run_params(seed, n_per_gen, 1, 0, fixed_source=True, ent=(1, 1)))
 
 
+# ---------------------------------------------------------------------------
+# continuous-energy data (input tables only: pointwise values on a grid)
+# ---------------------------------------------------------------------------
+
+CE_E_MIN, CE_E_MAX = 1e-5, 2e7     # eV
+WATT_A, WATT_B = 0.988e6, 2.249e-6  # eV, 1/eV
+NU_CE = 2.43
+
+
+def _resonances(rng, e, n_res, channels):
+    """Sum of n_res single-level resonance shapes
+    s0 (G/2)^2 / ((E - Er)^2 + (G/2)^2) sqrt(Er / E), each split over the
+    channels by Dirichlet fractions; returns [channels][len(e)]."""
+    out = np.zeros((channels, len(e)))
+    er = np.exp(rng.uniform(math.log(1.0), math.log(1e5), n_res))
+    gam = np.exp(rng.uniform(math.log(1e-2), math.log(1.0), n_res))
+    s0 = np.exp(rng.uniform(math.log(10.0), math.log(1e4), n_res))
+    frac = rng.dirichlet(np.ones(channels), n_res)
+    for k in range(n_res):
+        h = 0.5 * gam[k]
+        shape = s0[k] * h * h / ((e - er[k]) ** 2 + h * h) * np.sqrt(er[k] / e)
+        out += frac[k][:, None] * shape[None, :]
+    return out
+
+
+def _ce_tables(seed, n_nuc, n_pts, n_res):
+    rng = np.random.default_rng(seed)
+    e = np.geomspace(CE_E_MIN, CE_E_MAX, n_pts)
+    awr = np.sort(rng.uniform(1.0, 240.0, n_nuc))
+    n_fissile = 2
+    sig_s = np.zeros((n_nuc, n_pts))
+    sig_c = np.zeros((n_nuc, n_pts))
+    sig_f = np.zeros((n_nuc, n_pts))
+    inv_v = np.sqrt(0.0253 / e)
+    for n in range(n_nuc):
+        fissile = n >= n_nuc - n_fissile
+        sig_s[n] = rng.uniform(2.0, 20.0)
+        if fissile:
+            sig_c[n] = rng.uniform(20.0, 100.0) * inv_v
+            sig_f[n] = rng.uniform(200.0, 600.0) * inv_v
+            res = _resonances(rng, e, n_res, 3)
+            sig_s[n] += res[0]
+            sig_c[n] += res[1]
+            sig_f[n] += res[2]
+        else:
+            sig_c[n] = rng.uniform(0.1, 5.0) * inv_v
+            res = _resonances(rng, e, n_res, 2)
+            sig_s[n] += res[0]
+            sig_c[n] += res[1]
+    sig_t = sig_s + sig_c + sig_f
+    return e, awr, sig_t, sig_s, sig_f
+
+
+_CE_CACHE = {}
+
+
+def ce_data(seed=4001, n_nuc=10, n_pts=50_000, n_res=200, n_ebins=100):
+    """10 synthetic nuclides on a 50,000-point log grid, 1e-5 eV .. 20 MeV:
+    1/v capture and fission backgrounds plus 200 seeded resonances each,
+    constant potential scattering; target masses A ~ U[1, 240] sorted, the
+    five lightest make the moderator, the five heaviest the fuel, whose two
+    heaviest are fissile.  Material 0 = fuel, 1 = moderator."""
+    key = (seed, n_nuc, n_pts, n_res, n_ebins)
+    if key not in _CE_CACHE:
+        e, awr, sig_t, sig_s, sig_f = _ce_tables(seed, n_nuc, n_pts, n_res)
+        rng = np.random.default_rng(seed + 1)
+        half = n_nuc // 2
+        fuel = np.arange(half, n_nuc)
+        mod = np.arange(0, half)
+        mat_nuc = np.stack([fuel, mod]).astype(np.int32)
+        mat_dens = np.stack([rng.uniform(1e-3, 2e-2, len(fuel)),
+                             rng.uniform(1e-2, 5e-2, len(mod))])
+        _CE_CACHE[key] = dict(
+            e_grid=e, sig_t=sig_t, sig_s=sig_s, sig_f=sig_f, awr=awr, nu=NU_CE,
+            mat_n=np.array([len(fuel), len(mod)], np.int32), mat_nuc=mat_nuc,
+            mat_dens=mat_dens, watt_a=WATT_A, watt_b=WATT_B, e_max=CE_E_MAX,
+            e_cut=CE_E_MIN, e_edges=np.geomspace(CE_E_MIN, CE_E_MAX, n_ebins + 1))
+    return _CE_CACHE[key]
+
+
+def ce_pin_cell(n_per_gen=1_000_000, n_gen=50, n_inactive=10, seed=5, data=None):
+    """Continuous-energy pin cell (r = 0.54 cm in a 1.26 cm reflective
+    square: an infinite lattice), flux tallied per region on 100 log bins."""
+    ce = ce_data() if data is None else data
+    geo = lattice_geometry(1, 1, PIN_PITCH, [([PIN_RADIUS], [0, 1])], [[0]], [REFLECT] * 4)
+    return dict(name="ce_pin_cell", geometry=geo, ce=ce,
+                run=run_params(seed, n_per_gen, n_gen, n_inactive, ent=(8, 8)))
+
+
+def ce_flat(sig_s, sig_c, sig_f, awr, dens=1.0, n_pts=2, n_ebins=10, e_cut=CE_E_MIN):
+    """One nuclide with energy-independent cross sections (barns) in one
+    material: the continuous-energy code path with closed-form answers."""
+    e = np.array([CE_E_MIN, CE_E_MAX]) if n_pts == 2 else np.geomspace(CE_E_MIN, CE_E_MAX, n_pts)
+    row = np.ones(len(e))
+    return dict(e_grid=e, sig_t=((sig_s + sig_c + sig_f) * row)[None, :],
+                sig_s=(sig_s * row)[None, :], sig_f=(sig_f * row)[None, :],
+                awr=np.array([float(awr)]), nu=NU_CE, mat_n=np.array([1], np.int32),
+                mat_nuc=np.array([[0]], np.int32), mat_dens=np.array([[float(dens)]]),
+                watt_a=WATT_A, watt_b=WATT_B, e_max=CE_E_MAX, e_cut=e_cut,
+                e_edges=np.geomspace(CE_E_MIN, CE_E_MAX, n_ebins + 1))
+
+
+def ce_homogeneous(ce, n_per_gen, n_gen, n_inactive, seed, fixed_source=False, pitch=2.0):
+    """Infinite medium of continuous-energy material 0."""
+    geo = lattice_geometry(1, 1, pitch, [([], [0])], [[0]], [REFLECT] * 4)
+    return dict(name="ce_homogeneous", geometry=geo, ce=ce,
+                run=run_params(seed, n_per_gen, n_gen, n_inactive, fixed_source=fixed_source,
+                               ent=(4, 4)))
+
+
 def with_run(problem, **kw):
     """Copy of a problem with some run parameters replaced."""
     p = dict(problem)
@@ -241,14 +351,18 @@ def with_run(problem, **kw):
 
 
 def n_bins(problem):
-    geo, xs = problem["geometry"], problem["xs"]
-    return geo["nx"] * geo["ny"] * (geo["radii"].shape[1] + 1) * xs["sig_t"].shape[1]
+    geo = problem["geometry"]
+    per = (len(problem["ce"]["e_edges"]) - 1 if "ce" in problem
+           else problem["xs"]["sig_t"].shape[1])
+    return geo["nx"] * geo["ny"] * (geo["radii"].shape[1] + 1) * per
 
 
 def digest(problem):
     """sha256 over every array and scalar of a problem (records the inputs)."""
     h = hashlib.sha256()
-    for part in ("geometry", "xs", "run"):
+    for part in ("geometry", "xs", "ce", "run"):
+        if part not in problem:
+            continue
         d = problem[part]
         for k in sorted(d):
             v = d[k]
