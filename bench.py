@@ -70,6 +70,7 @@ def parse():
                     help="skip the 1e7-history FP64 / FP32-mixed comparison")
     ap.add_argument("--n-fp32", type=int, default=10_000_000)
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-problem batch")
+    ap.add_argument("--no-ce", action="store_true", help="skip the continuous-energy pin cell")
     ap.add_argument("--no-persistent", action="store_true",
                     help="skip the lattice on the persistent engine")
     ap.add_argument("--tune-cache", default=None,
@@ -170,6 +171,48 @@ def batch_comparison(P, mcx, tune_cache, steps):
             "speedup_over_one_at_a_time": round(base / sec, 3),
             "tuned": {kk: tune[kk] for kk in ("block", "slots", "grid", "tau")},
             "killed": int(cnt[:, 6].sum())}
+
+
+def ce_measurement(P, mcx, steps):
+    """Continuous-energy pin cell, 1e6 histories x 50 generations (10
+    inactive), event engine, FP64 and FP32-mixed."""
+    import math
+    import torch
+    prob = P.ce_pin_cell()
+    n = prob["run"]["n_per_gen"] * prob["run"]["n_gen"]
+    ni = prob["run"]["n_inactive"]
+    out, gk = {}, {}
+    for prec in ("fp64", "fp32"):
+        ctx = mcx.Context(prob, time_kernels=True, precision=prec)
+        ctx.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.run()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        t = ctx.timing()
+        km, ks, pg = ctx.keff()
+        _, c = ctx.generation_stats()
+        ctx.close()
+        gk[prec] = (km, ks, pg)
+        out[prec] = {"histories_per_s": round(n / sec, 1),
+                     "events_per_s": round(float(c[:, 0].sum()) / sec, 1),
+                     "ms_per_step": round(sec * 1e3, 2),
+                     "segments_per_history": round(float(c[:, 0].sum()) / n, 3),
+                     "k_col": round(float(km[0]), 7), "sigma": round(float(ks[0]), 7),
+                     "kernel_ms_per_step": {"advance": round(t["advance_ms"], 2),
+                                            "collide": round(t["collide_ms"], 2),
+                                            "tail": round(t["tail_ms"], 2)}}
+    d = gk["fp32"][2][ni:, 0] - gk["fp64"][2][ni:, 0]
+    out["dk_pcm"] = round(float(gk["fp32"][0][0] - gk["fp64"][0][0]) * 1e5, 3)
+    out["sigma_pcm"] = round(math.hypot(gk["fp32"][1][0], gk["fp64"][1][0]) * 1e5, 3)
+    out["paired_sigma_pcm"] = round(float(d.std(ddof=1) / math.sqrt(len(d))) * 1e5, 3)
+    out["speedup_fp32_over_fp64"] = round(out["fp32"]["histories_per_s"] /
+                                          out["fp64"]["histories_per_s"], 3)
+    out["workload"] = ("continuous-energy pin cell: 10 nuclides x 50,000-point grid, "
+                       "1e6 histories/gen x 50 gens (10 inactive), event engine")
+    return out
 
 
 def main():
@@ -274,6 +317,11 @@ def main():
         print("[bench] 512-problem batch", file=sys.stderr, flush=True)
         batch = batch_comparison(P, mcx, tune_cache, a.steps)
 
+    ce = None
+    if not a.no_ce:
+        print("[bench] continuous-energy pin cell", file=sys.stderr, flush=True)
+        ce = ce_measurement(P, mcx, 1)
+
     extra = None
     if not a.no_fp32:
         print(f"[bench] FP64 vs FP32-mixed at {a.n_fp32} histories/gen", file=sys.stderr, flush=True)
@@ -306,6 +354,7 @@ def main():
         "persistent_engine": pers,
         "fp32_mixed": extra,
         "batch": batch,
+        "continuous_energy": ce,
     }
     print(json.dumps(out), flush=True)
 

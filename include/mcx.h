@@ -55,7 +55,7 @@ enum mcx_status {
 enum { MCX_FP64 = 0, MCX_FP32_MIXED = 1 };
 enum { MCX_ENGINE_EVENT = 0, MCX_ENGINE_PERSISTENT = 1 };
 enum { MCX_VACUUM = 0, MCX_REFLECT = 1 };
-enum { MCX_FATE_ABSORBED = 1, MCX_FATE_LEAKED = 2, MCX_FATE_KILLED = 3 };
+enum { MCX_FATE_ABSORBED = 1, MCX_FATE_LEAKED = 2, MCX_FATE_KILLED = 3, MCX_FATE_CUTOFF = 4 };
 
 /* Per-generation counters, in this order (mcx_get_generation_stats). */
 enum {
@@ -68,7 +68,8 @@ enum {
   MCX_CNT_KILLED = 6, /* histories ended by the event guard */
   MCX_CNT_SITES = 7,  /* fission sites banked */
   MCX_CNT_SCAT = 8,   /* scatters */
-  MCX_N_CNT = 9
+  MCX_CNT_CUTOFF = 9, /* histories ended below the energy cutoff (continuous energy) */
+  MCX_N_CNT = 10
 };
 
 typedef struct {
@@ -149,6 +150,7 @@ typedef struct {
   double tl_sum;            /* total track length */
   double kcol_sum;          /* sum of nu_sig_f / sig_t over collisions */
   double x_final, y_final;
+  double e_final;           /* final energy (continuous energy), else 0 */
 } mcx_record;
 
 /* Timing of the last mcx_run_generations or mcx_run_batch.  The *_ms kernel sums are filled
@@ -206,6 +208,43 @@ int mcx_load_geometry(mcx_ctx* ctx, const mcx_geometry* geo);
 int mcx_load_mg_xs(mcx_ctx* ctx, int32_t n_mat, int32_t n_grp, const double* sig_t,
                    const double* sig_s, const double* nu_sig_f, const double* chi);
 
+/* Continuous-energy data (paper Sec. 1: continuous-energy physics; Sec. 4:
+   continuous-energy pin cell).  Pointwise microscopic cross sections on one
+   shared, strictly increasing energy grid, interpolated linearly in energy
+   (the interval is the largest i with e_grid[i] <= E, within [0, n_pts-2];
+   the fraction is clipped to [0, 1]); a material's macroscopic value is the
+   density-weighted sum over its nuclides in the listed order.  A collision
+   banks floor(nu Sigma_f / (Sigma_t k) + xi) sites with Watt energies,
+   picks the nuclide by its share of Sigma_t, then scatters elastically off
+   it (target at rest, isotropic in the centre-of-mass frame, direction
+   turned about itself) or absorbs; a scatter below e_cut ends the history
+   (MCX_FATE_CUTOFF).  The flux is tallied per (cell, region, energy bin)
+   with n_ebins bins between e_edges; the production tally is not kept
+   (reads zero) and the track-length k estimator is summed directly.
+   Event engine, FP64 only. */
+typedef struct {
+  int32_t n_nuc, n_pts;
+  const double* e_grid;     /* [n_pts] eV */
+  const double* sig_t;      /* [n_nuc][n_pts] barns; sig_t >= sig_s */
+  const double* sig_s;      /* [n_nuc][n_pts] elastic scattering */
+  const double* sig_f;      /* [n_nuc][n_pts] fission */
+  const double* awr;        /* [n_nuc] target mass / neutron mass, > 0 */
+  double nu;                /* neutrons per fission */
+  int32_t n_mat, max_nuc;
+  const int32_t* mat_n;     /* [n_mat] nuclides per material, 1..max_nuc */
+  const int32_t* mat_nuc;   /* [n_mat][max_nuc] */
+  const double* mat_dens;   /* [n_mat][max_nuc] atoms per barn-cm, >= 0 */
+  double watt_a, watt_b;    /* Watt spectrum, eV and 1/eV: E = W + a^2 b/4 +
+                               (2 xi - 1) sqrt(a^2 b W), W Maxwellian of temperature a */
+  double e_max;             /* Watt energies above e_max are drawn again */
+  double e_cut;             /* energy cutoff, eV */
+  int32_t n_ebins;
+  const double* e_edges;    /* [n_ebins + 1] strictly increasing, eV */
+} mcx_ce_data;
+
+/* Copy and validate continuous-energy data; replaces multigroup data. */
+int mcx_load_ce_xs(mcx_ctx* ctx, const mcx_ce_data* ce);
+
 int mcx_seed_source(mcx_ctx* ctx, const mcx_source* src);
 
 /* Bytes of device workspace needed to run up to n_gen_max generations. */
@@ -246,7 +285,8 @@ int mcx_get_generation_tallies(mcx_ctx* ctx, int32_t gen, double* flux, double* 
 int mcx_get_records(mcx_ctx* ctx, int32_t gen, mcx_record* out, int64_t n);
 
 /* Canonical fission bank of the last k-eigenvalue generation, ordered by
-   (parent history, banking order): xyg[k][3] = x, y, group; *len receives
+   (parent history, banking order): xyg[k][3] = x, y, group (energy in eV for
+   continuous energy); *len receives
    the bank size (entries beyond cap are not written). */
 int mcx_get_bank(mcx_ctx* ctx, double* xyg, int64_t cap, int64_t* len);
 

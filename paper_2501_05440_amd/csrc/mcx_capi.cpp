@@ -50,6 +50,50 @@ double fixed_point_scale(double max_term) {
   return std::ldexp(1.0, 61 - e);
 }
 
+// Largest i with grid[i] <= e within [0, n - 2] (the device's bisection).
+template <class R>
+int host_interval(const R* grid, int n, R e) {
+  int lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    const int mid = lo + (hi - lo) / 2;
+    if (grid[mid] <= e)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Bucket start points of the interval search over a positive increasing
+// grid: bucket b covers the bit patterns base + (b << shift) ... base +
+// ((b + 1) << shift) - 1; hash[b] is the interval of the bucket's smallest
+// value, hash[n_hash] that of the grid's end.  About two buckets per point.
+template <class R, class U>
+void build_hash(const std::vector<R>& grid, std::vector<int>* hash, int* shift, U* base) {
+  const int n = (int)grid.size();
+  U b0, b1;
+  std::memcpy(&b0, &grid[0], sizeof(U));
+  std::memcpy(&b1, &grid[n - 1], sizeof(U));
+  const uint64_t span = (uint64_t)(b1 - b0);
+  int s = 0;
+  while ((span >> s) + 1 > (uint64_t)2 * (uint64_t)n) ++s;
+  const uint64_t nb = (span >> s) + 1;
+  hash->assign(nb + 1, 0);
+  for (uint64_t b = 0; b <= nb; ++b) {
+    const uint64_t key = b << s;
+    R e;
+    if (key > span) {
+      e = grid[n - 1];
+    } else {
+      const U bits = (U)(b0 + key);
+      std::memcpy(&e, &bits, sizeof(U));
+    }
+    (*hash)[b] = host_interval<R>(grid.data(), n, e);
+  }
+  *shift = s;
+  *base = b0;
+}
+
 }  // namespace
 
 // Device layout carved from the caller's workspace.
@@ -61,9 +105,9 @@ struct Dev {
   Bank bank[3]{};
   Records R{};
   Accum A{};
-  double *src_x = nullptr, *src_y = nullptr;
+  double *src_x = nullptr, *src_y = nullptr, *src_e = nullptr;
   int32_t* src_g = nullptr;
-  double *can_x = nullptr, *can_y = nullptr;
+  double *can_x = nullptr, *can_y = nullptr, *can_e = nullptr;
   int32_t* can_g = nullptr;
   uint32_t *offs = nullptr, *chunk_sum = nullptr, *scan_total = nullptr;
   uint32_t *cnt_live = nullptr, *cnt_col = nullptr;
@@ -110,6 +154,19 @@ struct mcx_ctx {
   std::vector<float> sig_t_f, nusf_f, sst_f, cum_s_f, cum_chi_f;  // FP32-mixed tables
   std::vector<int> last_s, last_chi, fissile;
   mcx_source src{};
+
+  // continuous-energy data (ce = true replaces the multigroup tables)
+  bool ce = false;
+  int ce_n_nuc = 0, ce_n_pts = 0, ce_max_nuc = 0, ce_n_ebins = 0;
+  std::vector<double> ce_grid, ce_xs, ce_awr, ce_dens, ce_edges;
+  std::vector<int> ce_mat_n, ce_mat_nuc;
+  double ce_nu = 0, ce_watt_a = 0, ce_watt_b = 0, ce_e_max = 0, ce_e_cut = 0;
+  double ce_sigt_min = 0;
+  std::vector<float> ce_f32[5];  // binary32 grid, tables, masses, densities, edges
+  std::vector<int> ce_hash, ce_hash_f;
+  int ce_hash_shift = 0, ce_hash_shift_f = 0;
+  uint64_t ce_hash_base = 0;
+  uint32_t ce_hash_base_f = 0;
 
   // workspace
   char* ws = nullptr;
@@ -397,6 +454,120 @@ int mcx_load_mg_xs(mcx_ctx* c, int32_t n_mat, int32_t n_grp, const double* sig_t
   c->last_chi = std::move(last_chi);
   c->fissile = std::move(fis);
   c->has_xs = true;
+  c->ce = false;
+  c->bound = false;
+  return MCX_OK;
+}
+
+int mcx_load_ce_xs(mcx_ctx* c, const mcx_ce_data* d) {
+  if (!c || !d) return MCX_EINVAL;
+  if (d->n_nuc < 1 || d->n_pts < 2 || d->n_mat < 1 || d->max_nuc < 1 || d->n_ebins < 1 ||
+      (int64_t)d->n_nuc * d->n_pts > (int64_t(1) << 28) || !d->e_grid || !d->sig_t ||
+      !d->sig_s || !d->sig_f || !d->awr || !d->mat_n || !d->mat_nuc || !d->mat_dens ||
+      !d->e_edges)
+    return fail(c, MCX_EINVAL, "continuous-energy sizes");
+  if (!(d->nu >= 0.0) || !std::isfinite(d->nu) || !(d->watt_a > 0.0) || !(d->watt_b >= 0.0) ||
+      !(d->e_max > 0.0) || !(d->e_cut >= 0.0) || !std::isfinite(d->e_max))
+    return fail(c, MCX_EINVAL, "continuous-energy constants");
+  for (int k = 0; k + 1 < d->n_pts; ++k)
+    if (!(d->e_grid[k] < d->e_grid[k + 1]) || !std::isfinite(d->e_grid[k + 1]) ||
+        !(d->e_grid[0] > 0.0))
+      return fail(c, MCX_EINVAL, "energy grid must increase");
+  for (int k = 0; k < d->n_ebins; ++k)
+    if (!(d->e_edges[k] < d->e_edges[k + 1])) return fail(c, MCX_EINVAL, "tally edges must increase");
+  const size_t NP = (size_t)d->n_nuc * d->n_pts;
+  for (size_t k = 0; k < NP; ++k)
+    if (!(d->sig_s[k] >= 0.0) || !(d->sig_f[k] >= 0.0) || !(d->sig_t[k] >= d->sig_s[k]) ||
+        !std::isfinite(d->sig_t[k]))
+      return fail(c, MCX_EINVAL, "pointwise cross sections (need 0 <= sig_s <= sig_t, sig_f >= 0)");
+  for (int n = 0; n < d->n_nuc; ++n)
+    if (!(d->awr[n] > 0.0) || !std::isfinite(d->awr[n])) return fail(c, MCX_EINVAL, "target mass");
+  std::vector<int> fis(d->n_mat, 0);
+  double sigt_min = 1e300;
+  for (int m = 0; m < d->n_mat; ++m) {
+    if (d->mat_n[m] < 1 || d->mat_n[m] > d->max_nuc) return fail(c, MCX_EINVAL, "material size");
+    for (int k = 0; k < d->mat_n[m]; ++k) {
+      const int n = d->mat_nuc[m * d->max_nuc + k];
+      const double dens = d->mat_dens[m * d->max_nuc + k];
+      if (n < 0 || n >= d->n_nuc || !(dens >= 0.0) || !std::isfinite(dens))
+        return fail(c, MCX_EINVAL, "material nuclide or density");
+      if (dens > 0.0 && d->nu > 0.0)
+        for (int q = 0; q < d->n_pts; ++q)
+          if (d->sig_f[(size_t)n * d->n_pts + q] > 0.0) {
+            fis[m] = 1;
+            break;
+          }
+    }
+    // the macroscopic total is piecewise linear in energy: its minimum is at
+    // a grid point
+    for (int q = 0; q < d->n_pts; ++q) {
+      double st = 0.0;
+      for (int k = 0; k < d->mat_n[m]; ++k)
+        st += d->mat_dens[m * d->max_nuc + k] *
+              d->sig_t[(size_t)d->mat_nuc[m * d->max_nuc + k] * d->n_pts + q];
+      sigt_min = std::min(sigt_min, st);
+    }
+  }
+  if (!(sigt_min > 0.0)) return fail(c, MCX_EINVAL, "a material has zero total cross section");
+  // interleave (t, s, f, 0) per point so one interval of one nuclide is 64 contiguous bytes
+  std::vector<double> xs(NP * 4);
+  for (size_t k = 0; k < NP; ++k) {
+    xs[4 * k + 0] = d->sig_t[k];
+    xs[4 * k + 1] = d->sig_s[k];
+    xs[4 * k + 2] = d->sig_f[k];
+    xs[4 * k + 3] = 0.0;
+  }
+  if (c->batch) {
+    c->has_geo = false;
+    c->batch = false;
+  }
+  c->ce_xs = std::move(xs);
+  c->ce_grid.assign(d->e_grid, d->e_grid + d->n_pts);
+  c->ce_awr.assign(d->awr, d->awr + d->n_nuc);
+  c->ce_mat_n.assign(d->mat_n, d->mat_n + d->n_mat);
+  c->ce_mat_nuc.assign(d->mat_nuc, d->mat_nuc + (size_t)d->n_mat * d->max_nuc);
+  c->ce_dens.assign(d->mat_dens, d->mat_dens + (size_t)d->n_mat * d->max_nuc);
+  c->ce_edges.assign(d->e_edges, d->e_edges + d->n_ebins + 1);
+  c->ce_n_nuc = d->n_nuc;
+  c->ce_n_pts = d->n_pts;
+  c->ce_max_nuc = d->max_nuc;
+  c->ce_n_ebins = d->n_ebins;
+  c->ce_nu = d->nu;
+  c->ce_watt_a = d->watt_a;
+  c->ce_watt_b = d->watt_b;
+  c->ce_e_max = d->e_max;
+  c->ce_e_cut = d->e_cut;
+  c->ce_sigt_min = sigt_min;
+  build_hash<double, uint64_t>(c->ce_grid, &c->ce_hash, &c->ce_hash_shift, &c->ce_hash_base);
+  {
+    std::vector<float> gf(c->ce_grid.size());
+    for (size_t k = 0; k < gf.size(); ++k) gf[k] = (float)c->ce_grid[k];
+    bool inc = true;
+    for (size_t k = 1; k < gf.size(); ++k) inc = inc && gf[k - 1] < gf[k] && gf[k - 1] > 0.0f;
+    if (inc) {
+      build_hash<float, uint32_t>(gf, &c->ce_hash_f, &c->ce_hash_shift_f, &c->ce_hash_base_f);
+    } else {
+      c->ce_hash_f.clear();
+    }
+  }
+  c->fissile = std::move(fis);
+  c->n_mat = d->n_mat;
+  c->G = d->n_ebins;
+  // the multigroup tables are not used
+  c->sig_t.clear();
+  c->nusf.clear();
+  c->sst.clear();
+  c->cum_s.clear();
+  c->cum_chi.clear();
+  c->last_s.clear();
+  c->last_chi.clear();
+  c->sig_t_f.clear();
+  c->nusf_f.clear();
+  c->sst_f.clear();
+  c->cum_s_f.clear();
+  c->cum_chi_f.clear();
+  c->ce = true;
+  c->has_xs = true;
   c->bound = false;
   return MCX_OK;
 }
@@ -437,20 +608,38 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   T.geo.n_rings = cv.take<int>(c->n_rings.size());
   T.geo.radii = cv.take<double>(c->radii.size());
   T.geo.mats = cv.take<int>(c->mats.size());
-  T.sig_t = cv.take<double>(MG);
-  T.nusf = cv.take<double>(MG);
-  T.sst = cv.take<double>(MG);
-  T.cum_s = cv.take<double>(MG * c->G);
-  T.last_s = cv.take<int>(MG);
-  T.cum_chi = cv.take<double>(MG);
-  T.last_chi = cv.take<int>(c->n_mat);
+  (void)MG;
+  T.sig_t = cv.take<double>(c->sig_t.size());
+  T.nusf = cv.take<double>(c->nusf.size());
+  T.sst = cv.take<double>(c->sst.size());
+  T.cum_s = cv.take<double>(c->cum_s.size());
+  T.last_s = cv.take<int>(c->last_s.size());
+  T.cum_chi = cv.take<double>(c->cum_chi.size());
+  T.last_chi = cv.take<int>(c->last_chi.size());
   T.fissile = cv.take<int>(c->n_mat);
-  T.sig_t_f = cv.take<float>(MG);
-  T.nusf_f = cv.take<float>(MG);
-  T.sst_f = cv.take<float>(MG);
-  T.cum_s_f = cv.take<float>(MG * c->G);
-  T.cum_chi_f = cv.take<float>(MG);
+  T.sig_t_f = cv.take<float>(c->sig_t_f.size());
+  T.nusf_f = cv.take<float>(c->nusf_f.size());
+  T.sst_f = cv.take<float>(c->sst_f.size());
+  T.cum_s_f = cv.take<float>(c->cum_s_f.size());
+  T.cum_chi_f = cv.take<float>(c->cum_chi_f.size());
+  const bool ce = c->ce;
+  T.ce = ce ? 1 : 0;
+  T.e_grid = cv.take<double>(c->ce_grid.size());
+  T.ce_xs = cv.take<double>(c->ce_xs.size());
+  T.awr = cv.take<double>(c->ce_awr.size());
+  T.mat_n = cv.take<int>(c->ce_mat_n.size());
+  T.mat_nuc = cv.take<int>(c->ce_mat_nuc.size());
+  T.mat_dens = cv.take<double>(c->ce_dens.size());
+  T.e_edges = cv.take<double>(c->ce_edges.size());
   const bool fp32 = c->opt.precision == MCX_FP32_MIXED;
+  const bool ce32 = ce && fp32;
+  T.e_grid_f = cv.take<float>(ce32 ? c->ce_grid.size() : 0);
+  T.ce_xs_f = cv.take<float>(ce32 ? c->ce_xs.size() : 0);
+  T.awr_f = cv.take<float>(ce32 ? c->ce_awr.size() : 0);
+  T.mat_dens_f = cv.take<float>(ce32 ? c->ce_dens.size() : 0);
+  T.e_edges_f = cv.take<float>(ce32 ? c->ce_edges.size() : 0);
+  T.e_hash = cv.take<int>(c->ce_hash.size());
+  T.e_hash_f = cv.take<int>(ce32 ? c->ce_hash_f.size() : 0);
   for (int b = 0; b < 3; ++b) {
     Bank& k = d.bank[b];
     k.x = cv.take<double>(N);
@@ -467,20 +656,30 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
     k.ctr = cv.take<uint32_t>(N);
     k.id = cv.take<uint32_t>(N);
     k.nseg = cv.take<uint32_t>(N);
+    if (fp32) {
+      k.w = cv.take<float>(ce ? N : 0);
+      k.e = cv.take<float>(ce ? N : 0);
+    } else {
+      k.w = cv.take<double>(ce ? N : 0);
+      k.e = cv.take<double>(ce ? N : 0);
+    }
   }
   d.src_x = cv.take<double>(N);
   d.src_y = cv.take<double>(N);
   d.src_g = cv.take<int32_t>(N);
+  d.src_e = ce ? cv.take<double>(N) : nullptr;
   Accum& A = d.A;
   A.fis.x = cv.take<double>(fis_cap);
   A.fis.y = cv.take<double>(fis_cap);
   A.fis.g = cv.take<int32_t>(fis_cap);
   A.fis.parent = cv.take<uint32_t>(fis_cap);
   A.fis.seq = cv.take<uint32_t>(fis_cap);
+  A.fis.e = ce ? cv.take<double>(fis_cap) : nullptr;
   A.fis_cap = fis_cap;
   d.can_x = cv.take<double>(fis_cap);
   d.can_y = cv.take<double>(fis_cap);
   d.can_g = cv.take<int32_t>(fis_cap);
+  d.can_e = ce ? cv.take<double>(fis_cap) : nullptr;
   A.nsite_id = cv.take<uint32_t>(std::max<size_t>(N, n_hist));
   if (persistent) {
     d.h_kcol = cv.take<unsigned long long>(2 * n_hist);
@@ -554,6 +753,7 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
       R.kcol_sum = rc.take<double>(N);
       R.x_final = rc.take<double>(N);
       R.y_final = rc.take<double>(N);
+      R.e_final = rc.take<double>(N);
       if (pass == 0) {
         d.rec_words = (rc.off + 7) / 8;
         d.rec_base = cv.take<unsigned long long>(d.rec_words);
@@ -600,6 +800,10 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
   }
   if (!loaded(c)) return fail(c, MCX_ESTATE, "load and seed first");
   if ((uintptr_t)ptr % 256) return fail(c, MCX_EINVAL, "workspace must be 256-byte aligned");
+  if (c->ce && c->opt.engine != MCX_ENGINE_EVENT)
+    return fail(c, MCX_EINVAL, "continuous energy runs on the event engine");
+  if (c->ce && c->opt.precision == MCX_FP32_MIXED && c->ce_hash_f.empty())
+    return fail(c, MCX_EINVAL, "the energy grid is not strictly increasing in binary32");
   // materials referenced by the geometry must exist (batches: checked per problem)
   if (!c->batch)
     for (int u = 0; u < c->n_univ; ++u)
@@ -623,6 +827,15 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
     d_max = std::max(d_max, d);
     kc_max = std::max(kc_max, c->nusf[mg] / c->sig_t[mg]);
     if (c->nusf[mg] > 0.0) ka_max = std::max(ka_max, c->nusf[mg] / (c->sig_t[mg] - c->sst[mg]));
+  }
+  double ktl_max = 0.0;
+  if (c->ce) {
+    // nu Sigma_f <= nu Sigma_t and nu Sigma_f <= nu Sigma_a (sigma_t = sigma_s +
+    // capture + fission pointwise), so every k term is at most nu and a
+    // track-length term d nu Sigma_f at most ln_max nu
+    d_max = ln_max / c->ce_sigt_min;
+    kc_max = ka_max = c->ce_nu;
+    ktl_max = ln_max * c->ce_nu;
   }
   Tables& T = c->d.T;
   T.geo.nx = c->nx;
@@ -693,10 +906,26 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
   T.q_flux = fixed_point_scale(d_max);
   T.q_kcol = fixed_point_scale(kc_max);
   T.q_kabs = fixed_point_scale(ka_max);
+  T.q_ktl = fixed_point_scale(ktl_max * 1.01);
   T.max_events = c->opt.max_events;
+  T.n_pts = c->ce_n_pts;
+  T.max_nuc = c->ce_max_nuc;
+  T.n_ebins = c->ce_n_ebins;
+  T.nu = c->ce_nu;
+  T.watt_a = c->ce_watt_a;
+  T.watt_b = c->ce_watt_b;
+  T.e_max = c->ce_e_max;
+  T.e_cut = c->ce_e_cut;
+  T.n_hash = c->ce_hash.empty() ? 0 : (int)c->ce_hash.size() - 1;
+  T.hash_shift = c->ce_hash_shift;
+  T.hash_base = c->ce_hash_base;
+  T.n_hash_f = c->ce_hash_f.empty() ? 0 : (int)c->ce_hash_f.size() - 1;
+  T.hash_shift_f = c->ce_hash_shift_f;
+  T.hash_base_f = c->ce_hash_base_f;
 
   hipStream_t s = c->stream;
   auto up = [&](const void* dst, const void* srcp, size_t n) {
+    if (n == 0) return hipSuccess;
     return hipMemcpyAsync(const_cast<void*>(dst), srcp, n, hipMemcpyHostToDevice, s);
   };
   HIP_TRY(c, up(T.geo.pin_map, c->pin_map.data(), c->pin_map.size() * sizeof(int)));
@@ -717,6 +946,33 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
   HIP_TRY(c, up(T.cum_s_f, c->cum_s_f.data(), c->cum_s_f.size() * sizeof(float)));
   HIP_TRY(c, up(T.cum_chi_f, c->cum_chi_f.data(), c->cum_chi_f.size() * sizeof(float)));
   if (c->batch) HIP_TRY(c, up(c->d.probs, pd.data(), pd.size() * sizeof(ProbDesc)));
+  if (c->ce) {
+    HIP_TRY(c, up(T.e_grid, c->ce_grid.data(), c->ce_grid.size() * sizeof(double)));
+    HIP_TRY(c, up(T.ce_xs, c->ce_xs.data(), c->ce_xs.size() * sizeof(double)));
+    HIP_TRY(c, up(T.awr, c->ce_awr.data(), c->ce_awr.size() * sizeof(double)));
+    HIP_TRY(c, up(T.mat_n, c->ce_mat_n.data(), c->ce_mat_n.size() * sizeof(int)));
+    HIP_TRY(c, up(T.mat_nuc, c->ce_mat_nuc.data(), c->ce_mat_nuc.size() * sizeof(int)));
+    HIP_TRY(c, up(T.mat_dens, c->ce_dens.data(), c->ce_dens.size() * sizeof(double)));
+    HIP_TRY(c, up(T.e_edges, c->ce_edges.data(), c->ce_edges.size() * sizeof(double)));
+    HIP_TRY(c, up(T.e_hash, c->ce_hash.data(), c->ce_hash.size() * sizeof(int)));
+    if (c->opt.precision == MCX_FP32_MIXED) {
+      HIP_TRY(c, up(T.e_hash_f, c->ce_hash_f.data(), c->ce_hash_f.size() * sizeof(int)));
+      // binary32 copies, each value rounded once
+      auto to_f = [](const std::vector<double>& v) {
+        std::vector<float> f(v.size());
+        for (size_t k = 0; k < v.size(); ++k) f[k] = (float)v[k];
+        return f;
+      };
+      c->ce_f32[0] = to_f(c->ce_grid);
+      c->ce_f32[1] = to_f(c->ce_xs);
+      c->ce_f32[2] = to_f(c->ce_awr);
+      c->ce_f32[3] = to_f(c->ce_dens);
+      c->ce_f32[4] = to_f(c->ce_edges);
+      const float* dst[5] = {T.e_grid_f, T.ce_xs_f, T.awr_f, T.mat_dens_f, T.e_edges_f};
+      for (int k = 0; k < 5; ++k)
+        HIP_TRY(c, up(dst[k], c->ce_f32[k].data(), c->ce_f32[k].size() * sizeof(float)));
+    }
+  }
   const double one = 1.0;
   HIP_TRY(c, up(c->d.k_used, &one, sizeof(double)));
   HIP_TRY(c, hipStreamSynchronize(s));
@@ -789,11 +1045,19 @@ static int run_generation(mcx_ctx* c, int gen) {
                                   s));
     return generation_end(c, gen);
   }
-  if (gen == 0 || T.fixed_source)
-    HIP_TRY(c, launch_source(T, gen, N, c->d.src_x, c->d.src_y, c->d.src_g, A.status, s));
-  HIP_TRY(c, launch_birth(prec, T, gen, N, c->d.src_x, c->d.src_y, c->d.src_g, c->d.bank[0], c->d.cnt_live,
-                          c->d.cnt_col, gen > 0 ? c->d.gen_status + gen - 1 : nullptr, A.status,
-                          s));
+  const bool ce = T.ce != 0;
+  const uint32_t* prev_st = gen > 0 ? c->d.gen_status + gen - 1 : nullptr;
+  if (ce) {
+    if (gen == 0 || T.fixed_source)
+      HIP_TRY(c, launch_ce_source(prec, T, gen, N, c->d.src_x, c->d.src_y, c->d.src_e, A.status, s));
+    HIP_TRY(c, launch_ce_birth(prec, T, gen, N, c->d.src_x, c->d.src_y, c->d.src_e, c->d.bank[0],
+                               c->d.cnt_live, c->d.cnt_col, prev_st, A.status, s));
+  } else {
+    if (gen == 0 || T.fixed_source)
+      HIP_TRY(c, launch_source(T, gen, N, c->d.src_x, c->d.src_y, c->d.src_g, A.status, s));
+    HIP_TRY(c, launch_birth(prec, T, gen, N, c->d.src_x, c->d.src_y, c->d.src_g, c->d.bank[0],
+                            c->d.cnt_live, c->d.cnt_col, prev_st, A.status, s));
+  }
 
   // event iterations; `bound` is the live count of iteration `known`, an
   // upper bound for every later iteration
@@ -813,21 +1077,38 @@ static int run_generation(mcx_ctx* c, int gen) {
     if ((size_t)it + 3 >= c->d.n_cnt_slots) return fail(c, MCX_EDEVICE, "iteration slots exhausted");
     if (tail > 0 && bound <= (uint32_t)tail) {
       HIP_TRY(c, time_mark(c, 2, true));
-      HIP_TRY(c, launch_tail(prec, rec, T, gen, c->d.bank[cur], c->d.cnt_live + it, A, c->d.R,
-                             bound, s));
+      if (ce)
+        HIP_TRY(c, launch_ce_tail(prec, rec, T, gen, c->d.bank[cur], c->d.cnt_live + it, A, c->d.R,
+                                  bound, s));
+      else
+        HIP_TRY(c, launch_tail(prec, rec, T, gen, c->d.bank[cur], c->d.cnt_live + it, A, c->d.R,
+                               bound, s));
       HIP_TRY(c, time_mark(c, 2, false));
       c->timing.n_tail_launches += 1;
       break;
     }
     HIP_TRY(c, time_mark(c, 0, true));
-    HIP_TRY(c, launch_advance(prec, rec, T, gen, (uint32_t)c->opt.flights, c->d.bank[cur], c->d.cnt_live + it,
-                              c->d.bank[1 - cur], c->d.cnt_live + it + 1, c->d.bank[2],
-                              c->d.cnt_col + it, A, c->d.R, c->d.cnt_live + it + 2, c->d.cnt_col + it + 1,
-                              bound, block, s));
+    const uint32_t fl = (uint32_t)c->opt.flights;
+    if (ce)
+      HIP_TRY(c, launch_ce_advance(prec, rec, T, gen, fl, c->d.bank[cur], c->d.cnt_live + it,
+                                   c->d.bank[1 - cur], c->d.cnt_live + it + 1, c->d.bank[2],
+                                   c->d.cnt_col + it, A, c->d.R, c->d.cnt_live + it + 2,
+                                   c->d.cnt_col + it + 1, bound, block, s));
+    else
+      HIP_TRY(c, launch_advance(prec, rec, T, gen, fl, c->d.bank[cur], c->d.cnt_live + it,
+                                c->d.bank[1 - cur], c->d.cnt_live + it + 1, c->d.bank[2],
+                                c->d.cnt_col + it, A, c->d.R, c->d.cnt_live + it + 2,
+                                c->d.cnt_col + it + 1, bound, block, s));
     HIP_TRY(c, time_mark(c, 0, false));
     HIP_TRY(c, time_mark(c, 1, true));
-    HIP_TRY(c, launch_collide(prec, rec, T, gen, c->d.bank[2], c->d.cnt_col + it, c->d.bank[1 - cur],
-                              c->d.cnt_live + it + 1, A, c->d.R, bound, block, s));
+    if (ce)
+      HIP_TRY(c, launch_ce_collide(prec, rec, T, gen, c->d.bank[2], c->d.cnt_col + it,
+                                   c->d.bank[1 - cur], c->d.cnt_live + it + 1, A, c->d.R, bound,
+                                   block, s));
+    else
+      HIP_TRY(c, launch_collide(prec, rec, T, gen, c->d.bank[2], c->d.cnt_col + it,
+                                c->d.bank[1 - cur], c->d.cnt_live + it + 1, A, c->d.R, bound,
+                                block, s));
     HIP_TRY(c, time_mark(c, 1, false));
     cur = 1 - cur;
     ++it;
@@ -864,12 +1145,13 @@ static int generation_end(mcx_ctx* c, int gen) {
   if (!T.fixed_source) {
     HIP_TRY(c, launch_scan(A.nsite_id, N, c->d.chunk_sum, c->d.offs, c->d.scan_total, s));
     HIP_TRY(c, launch_gen_check(T, A.n_fis, c->d.scan_total, A.status, s));
-    HIP_TRY(c, launch_canon(A.fis, A.n_fis, c->d.offs, A.nsite_id, c->d.fis_cap, c->d.can_x, c->d.can_y,
-                            c->d.can_g, A.status, c->d.fis_cap, s));
+    HIP_TRY(c, launch_canon(A.fis, A.n_fis, c->d.offs, A.nsite_id, c->d.fis_cap, c->d.can_x,
+                            c->d.can_y, c->d.can_g, c->d.can_e, A.status, c->d.fis_cap, s));
     HIP_TRY(c, launch_entropy(T, gen, c->d.can_x, c->d.can_y, A.n_fis, c->d.fis_cap, c->d.ent_hist,
                               c->d.ent_term, c->d.gen_h, c->d.fis_cap, s));
-    HIP_TRY(c, launch_comb(N, A.n_fis, c->d.fis_cap, c->d.xi0, c->d.can_x, c->d.can_y, c->d.can_g, c->d.src_x, c->d.src_y,
-                           c->d.src_g, s));
+    HIP_TRY(c, launch_comb(N, A.n_fis, c->d.fis_cap, c->d.xi0, c->d.can_x, c->d.can_y,
+                           c->d.can_g, c->d.can_e, c->d.src_x, c->d.src_y, c->d.src_g,
+                           c->d.src_e, s));
   } else {
     HIP_TRY(c, launch_fill_u64(reinterpret_cast<unsigned long long*>(c->d.gen_h + gen), 1, 0ull, s));
   }
@@ -893,10 +1175,11 @@ static int generation_end(mcx_ctx* c, int gen) {
     double* kc = rc.take<double>(N);
     double* xf = rc.take<double>(N);
     double* yf = rc.take<double>(N);
+    double* ef = rc.take<double>(N);
     mcx_record* out = c->h_rec.data() + (size_t)gen * N;
     for (uint32_t i = 0; i < N; ++i) {
       out[i] = mcx_record{n_seg[i], n_col[i], n_cross[i], n_refl[i], fate[i], (int32_t)ns[i],
-                          g_final[i], ctr[i], tl[i], kc[i], xf[i], yf[i]};
+                          g_final[i], ctr[i], tl[i], kc[i], xf[i], yf[i], ef[i]};
     }
   }
   return MCX_OK;
@@ -1051,15 +1334,16 @@ int mcx_get_bank(mcx_ctx* c, double* xyg, int64_t cap, int64_t* len) {
   *len = m;
   const size_t n = (size_t)std::min<int64_t>(cap, m);
   if (!xyg || n == 0) return MCX_OK;
-  std::vector<double> x(n), y(n);
+  std::vector<double> x(n), y(n), e(c->d.can_e ? n : 0);
   std::vector<int32_t> g(n);
   HIP_TRY(c, hipMemcpy(x.data(), c->d.can_x, n * 8, hipMemcpyDeviceToHost));
   HIP_TRY(c, hipMemcpy(y.data(), c->d.can_y, n * 8, hipMemcpyDeviceToHost));
   HIP_TRY(c, hipMemcpy(g.data(), c->d.can_g, n * 4, hipMemcpyDeviceToHost));
+  if (c->d.can_e) HIP_TRY(c, hipMemcpy(e.data(), c->d.can_e, n * 8, hipMemcpyDeviceToHost));
   for (size_t k = 0; k < n; ++k) {
     xyg[3 * k] = x[k];
     xyg[3 * k + 1] = y[k];
-    xyg[3 * k + 2] = (double)g[k];
+    xyg[3 * k + 2] = c->d.can_e ? e[k] : (double)g[k];
   }
   return MCX_OK;
 }

@@ -22,7 +22,7 @@
 namespace mcx {
 
 enum : int { BC_VACUUM = 0, BC_REFLECT = 1 };
-enum : int { FATE_ALIVE = 0, FATE_ABSORBED = 1, FATE_LEAKED = 2, FATE_KILLED = 3 };
+enum : int { FATE_ALIVE = 0, FATE_ABSORBED = 1, FATE_LEAKED = 2, FATE_KILLED = 3, FATE_CUTOFF = 4 };
 enum : int {
   CNT_SEG = 0,
   CNT_COL = 1,
@@ -33,11 +33,12 @@ enum : int {
   CNT_KILLED = 6,
   CNT_SITES = 7,
   CNT_SCAT = 8,
-  N_CNT = 9,
-  CNT_ADV_ITEMS = 9,   // lanes processed by advance kernels
-  CNT_COL_ITEMS = 10,  // lanes processed by collide kernels
-  CNT_ADV_SEGS = 11,   // flights made inside advance kernels
-  N_CNT_ALL = 12
+  CNT_CUTOFF = 9,      // histories ended below the energy cutoff (continuous energy)
+  N_CNT = 10,          // counters reported per generation
+  CNT_ADV_ITEMS = 10,  // lanes processed by advance kernels
+  CNT_COL_ITEMS = 11,  // lanes processed by collide kernels
+  CNT_ADV_SEGS = 12,   // flights made inside advance kernels
+  N_CNT_ALL = 13
 };
 enum : int { K_COL = 0, K_TL = 1, K_ABS = 2 };
 constexpr int STRIPES = 64;  // copies of each global accumulator (atomic contention)
@@ -103,6 +104,31 @@ struct Tables {
   int tally_stripes;   // copies of the tally accumulators
   double q_flux, q_kcol, q_kabs;  // fixed-point scales 2^s
   int64_t max_events;
+  // continuous energy (ce != 0; then G counts the flux tally's energy bins)
+  int ce;
+  int n_pts, max_nuc, n_ebins;
+  const double* e_grid;    // [n_pts] increasing, eV
+  const double* ce_xs;     // [n_nuc][n_pts][4]: sig_t, sig_s, sig_f, 0 (barns)
+  const double* awr;       // [n_nuc]
+  const int* mat_n;        // [n_mat]
+  const int* mat_nuc;      // [n_mat][max_nuc]
+  const double* mat_dens;  // [n_mat][max_nuc]
+  const double* e_edges;   // [n_ebins + 1]
+  // binary32 copies for the FP32-mixed mode
+  const float* e_grid_f;
+  const float* ce_xs_f;    // [n_nuc][n_pts][4]
+  const float* awr_f;
+  const float* mat_dens_f;
+  const float* e_edges_f;
+  // interval search start points: bucket b of the bit patterns of E above
+  // the first grid point holds the intervals hash[b] .. hash[b + 1]
+  const int* e_hash;       // [n_hash + 1]
+  const int* e_hash_f;     // [n_hash_f + 1]
+  int n_hash, n_hash_f, hash_shift, hash_shift_f;
+  uint64_t hash_base;
+  uint32_t hash_base_f;
+  double nu, watt_a, watt_b, e_max, e_cut;
+  double q_ktl;            // fixed-point scale of the track-length k terms
 };
 
 // Particle bank in structure-of-arrays form.
@@ -116,6 +142,8 @@ struct Bank {
   uint32_t* ctr;  // transport-stream draws consumed
   uint32_t* id;   // source index of the history
   uint32_t* nseg; // flights made so far (event guard)
+  void* w;        // continuous energy: z direction cosine (working precision)
+  void* e;        // continuous energy: energy, eV (working precision)
 };
 
 // Fission sites as banked (unordered) and in canonical (parent, seq) order.
@@ -125,6 +153,7 @@ struct Sites {
   int32_t* g;
   uint32_t* parent;
   uint32_t* seq;
+  double* e;  // continuous energy: site energies
 };
 
 // Per-history debug records, indexed by history id.
@@ -140,6 +169,7 @@ struct Records {
   double* kcol_sum;
   double* x_final;
   double* y_final;
+  double* e_final;
 };
 
 // Per-generation accumulators (zeroed at the start of every generation).

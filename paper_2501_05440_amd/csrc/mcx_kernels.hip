@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_chunk(const uint32_t* in,
 // Canonical bank: site s of history parent goes to offset[parent] + seq.
 __global__ void k_canon(Sites fis, const uint32_t* n_fis_p, const uint32_t* offs,
                         const uint32_t* nsite_id, uint32_t cap, double* cx, double* cy,
-                        int32_t* cg, uint32_t* status) {
+                        int32_t* cg, double* ce, uint32_t* status) {
   const uint32_t n = min(*n_fis_p, cap);
   for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
     const uint32_t par = fis.parent[s];
@@ -328,6 +328,7 @@ __global__ void k_canon(Sites fis, const uint32_t* n_fis_p, const uint32_t* offs
     cx[pos] = fis.x[s];
     cy[pos] = fis.y[s];
     cg[pos] = fis.g[s];
+    if (ce) ce[pos] = fis.e[s];
   }
 }
 
@@ -336,8 +337,9 @@ __global__ void k_gen_totals(Tables T, uint32_t gen, uint32_t n, Accum A, double
                              unsigned long long* gen_cnt, uint32_t* gen_m, double* k_used,
                              double* xi0) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  const double inv_q[3] = {1.0 / T.q_kcol, 0.0, 1.0 / T.q_kabs};
-  for (int e = 0; e < 3; e += 2) {
+  // multigroup: the track-length estimator follows from the flux tallies
+  const double inv_q[3] = {1.0 / T.q_kcol, T.ce ? 1.0 / T.q_ktl : 0.0, 1.0 / T.q_kabs};
+  for (int e = 0; e < 3; e += T.ce ? 1 : 2) {
     const double v = stripes_to_double(A.k + (size_t)e * STRIPES * 2, STRIPES, 2) * inv_q[e];
     gen_k[3 * gen + e] = v / (double)n;
   }
@@ -369,7 +371,8 @@ __global__ void __launch_bounds__(1024) k_gen_tallies(Tables T, uint32_t gen, ui
     const int r = (b / T.G) % T.geo.mr1;
     const int g = b % T.G;
     const int m = T.geo.mats[T.geo.pin_map[cell] * T.geo.mr1 + r];
-    const double prod = T.nusf[m * T.G + g] * flux;
+    // continuous energy: nu_sig_f varies inside a bin; no production tally
+    const double prod = T.ce ? 0.0 : T.nusf[m * T.G + g] * flux;
     gen_tal[(size_t)gen * 2 * nb + b] = flux / (double)n;
     gen_tal[(size_t)gen * 2 * nb + nb + b] = prod / (double)n;
     const double t = s + prod;
@@ -379,7 +382,7 @@ __global__ void __launch_bounds__(1024) k_gen_tallies(Tables T, uint32_t gen, ui
   ps[threadIdx.x] = s;
   pc[threadIdx.x] = cmp;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && !T.ce) {
     double a = 0.0, ac = 0.0;
     for (unsigned k = 0; k < blockDim.x; ++k) {
       const double parts[2] = {ps[k], pc[k]};
@@ -462,8 +465,8 @@ __global__ void k_gen_check(Tables T, const uint32_t* n_fis, const uint32_t* sca
 // Combing: source site i of the next generation is canonical entry
 // floor((i + xi0) M / N), capped at M - 1.
 __global__ void k_comb(uint32_t n, const uint32_t* m_p, uint32_t cap, const double* xi0_p,
-                       const double* cx, const double* cy, const int32_t* cg, double* sx,
-                       double* sy, int32_t* sg) {
+                       const double* cx, const double* cy, const int32_t* cg, const double* ce,
+                       double* sx, double* sy, int32_t* sg, double* se) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t m = min(*m_p, cap);  // m > cap only after an overflow
@@ -474,6 +477,7 @@ __global__ void k_comb(uint32_t n, const uint32_t* m_p, uint32_t cap, const doub
   sx[i] = cx[k];
   sy[i] = cy[k];
   sg[i] = cg[k];
+  if (se) se[i] = ce[k];
 }
 
 // Active-generation mean and standard deviation of the mean, per bin, and
@@ -661,10 +665,11 @@ hipError_t launch_gen_check(const Tables& T, const uint32_t* n_fis, const uint32
 
 hipError_t launch_canon(const Sites& fis, const uint32_t* n_fis, const uint32_t* offs,
                         const uint32_t* nsite_id, uint32_t cap, double* cx, double* cy,
-                        int32_t* cg, uint32_t* status, uint32_t bound, hipStream_t s) {
+                        int32_t* cg, double* ce, uint32_t* status, uint32_t bound,
+                        hipStream_t s) {
   const unsigned g = std::max(1u, std::min(nblk(bound, 256), 8192u));
   hipLaunchKernelGGL(k_canon, dim3(g), dim3(256), 0, s, fis, n_fis, offs, nsite_id, cap, cx, cy,
-                     cg, status);
+                     cg, ce, status);
   return hipGetLastError();
 }
 
@@ -692,10 +697,10 @@ hipError_t launch_entropy(const Tables& T, uint32_t gen, const double* cx, const
 }
 
 hipError_t launch_comb(uint32_t n, const uint32_t* m_p, uint32_t cap, const double* xi0,
-                       const double* cx, const double* cy, const int32_t* cg, double* sx,
-                       double* sy, int32_t* sg, hipStream_t s) {
+                       const double* cx, const double* cy, const int32_t* cg, const double* ce,
+                       double* sx, double* sy, int32_t* sg, double* se, hipStream_t s) {
   hipLaunchKernelGGL(k_comb, dim3(nblk(n, 256)), dim3(256), 0, s, n, m_p, cap, xi0, cx, cy, cg,
-                     sx, sy, sg);
+                     ce, sx, sy, sg, se);
   return hipGetLastError();
 }
 

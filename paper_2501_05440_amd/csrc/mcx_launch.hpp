@@ -36,7 +36,8 @@ hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* chunk_sum, uint
                        uint32_t* total, hipStream_t s);
 hipError_t launch_canon(const Sites& fis, const uint32_t* n_fis, const uint32_t* offs,
                         const uint32_t* nsite_id, uint32_t cap, double* cx, double* cy,
-                        int32_t* cg, uint32_t* status, uint32_t bound, hipStream_t s);
+                        int32_t* cg, double* ce, uint32_t* status, uint32_t bound,
+                        hipStream_t s);
 hipError_t launch_gen_totals(const Tables& T, uint32_t gen, uint32_t n, const Accum& A,
                              double* gen_k, unsigned long long* gen_cnt, uint32_t* gen_m,
                              double* k_used, double* xi0, hipStream_t s);
@@ -46,8 +47,8 @@ hipError_t launch_entropy(const Tables& T, uint32_t gen, const double* cx, const
                           const uint32_t* n_p, uint32_t cap, uint32_t* hist, double* term,
                           double* gen_h, uint32_t bound, hipStream_t s);
 hipError_t launch_comb(uint32_t n, const uint32_t* m_p, uint32_t cap, const double* xi0,
-                       const double* cx, const double* cy, const int32_t* cg, double* sx,
-                       double* sy, int32_t* sg, hipStream_t s);
+                       const double* cx, const double* cy, const int32_t* cg, const double* ce,
+                       double* sx, double* sy, int32_t* sg, double* se, hipStream_t s);
 hipError_t launch_stats(int n_bins2, int n_gen, int n_inactive, const double* gen_tal,
                         double* tal_mean, double* tal_sigma, const double* gen_k, double* k_stat,
                         hipStream_t s);
@@ -74,6 +75,25 @@ hipError_t launch_hist_reduce(const Tables& T, int n_probs, unsigned long long* 
 hipError_t launch_batch_results(const Tables& T, int n_probs, const Accum& A,
                                 const unsigned long long* prob_k, double* flux, double* prod,
                                 double* k_out, hipStream_t s);
+// continuous energy (event engine; prec 0 = FP64, 1 = FP32-mixed)
+hipError_t launch_ce_source(int prec, const Tables& T, uint32_t gen, uint32_t n, double* sx, double* sy,
+                            double* se, uint32_t* status, hipStream_t s);
+hipError_t launch_ce_birth(int prec, const Tables& T, uint32_t gen, uint32_t n, const double* sx,
+                           const double* sy, const double* se, const Bank& out,
+                           uint32_t* cnt_live, uint32_t* cnt_col, const uint32_t* prev_status,
+                           uint32_t* status, hipStream_t s);
+hipError_t launch_ce_advance(int prec, bool rec, const Tables& T, uint32_t gen, uint32_t flights,
+                             const Bank& in, const uint32_t* n_in, const Bank& live,
+                             uint32_t* n_live, const Bank& col, uint32_t* n_col, const Accum& A,
+                             const Records& Rc, uint32_t* clr_live, uint32_t* clr_col,
+                             uint32_t bound, int block, hipStream_t s);
+hipError_t launch_ce_collide(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in,
+                             const uint32_t* n_in, const Bank& live, uint32_t* n_live,
+                             const Accum& A, const Records& Rc, uint32_t bound, int block,
+                             hipStream_t s);
+hipError_t launch_ce_tail(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in,
+                          const uint32_t* n_in, const Accum& A, const Records& Rc, uint32_t bound,
+                          hipStream_t s);
 hipError_t launch_diag_math(int which, const double* in, double* out, int64_t n, hipStream_t s);
 hipError_t launch_diag_philox(const uint64_t* in, uint64_t* out, int64_t n, hipStream_t s);
 void host_math(int which, const double* in, double* out, int64_t n);

@@ -316,6 +316,7 @@ __global__ void __launch_bounds__(256) k_hist_reduce(Tables T, HistOut H, Accum 
     v[CNT_LEAK] += q[HO_FATE] == FATE_LEAKED;
     v[CNT_ABS] += q[HO_FATE] == FATE_ABSORBED;
     v[CNT_KILLED] += q[HO_FATE] == FATE_KILLED;
+    v[CNT_CUTOFF] += q[HO_FATE] == FATE_CUTOFF;
     v[N_CNT + 0] += H.kcol[2 * h + 0];
     v[N_CNT + 1] += H.kcol[2 * h + 1];
     v[N_CNT + 2] += H.kabs[h] & 0xFFFFFFFFull;

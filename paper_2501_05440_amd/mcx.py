@@ -18,8 +18,8 @@ OK, EINVAL, ESTATE, ENOMEM, EDEVICE, ELOST, EGUARD, EEXTINCT, EOVERFLOW = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 FP64, FP32_MIXED = 0, 1
 ENGINE_EVENT, ENGINE_PERSISTENT = 0, 1
-N_CNT = 9
-COUNT_NAMES = ["seg", "col", "cross", "refl", "leak", "abs", "killed", "sites", "scat"]
+N_CNT = 10
+COUNT_NAMES = ["seg", "col", "cross", "refl", "leak", "abs", "killed", "sites", "scat", "cutoff"]
 
 # every function the header declares
 EXPORTS = [
@@ -28,7 +28,7 @@ EXPORTS = [
     "mcx_get_generation_stats", "mcx_get_tallies", "mcx_get_generation_tallies",
     "mcx_get_records", "mcx_get_bank", "mcx_get_timing", "mcx_diag_math", "mcx_host_math",
     "mcx_diag_philox", "mcx_last_error", "mcx_destroy", "mcx_load_batch", "mcx_run_batch",
-    "mcx_get_batch_results", "mcx_get_batch_tallies", "mcx_autotune",
+    "mcx_get_batch_results", "mcx_get_batch_tallies", "mcx_autotune", "mcx_load_ce_xs",
 ]
 
 
@@ -69,6 +69,16 @@ class Timing(C.Structure):
                 ("advance_segments", C.c_int64)]
 
 
+class CEData(C.Structure):
+    _fields_ = [("n_nuc", C.c_int32), ("n_pts", C.c_int32), ("e_grid", C.c_void_p),
+                ("sig_t", C.c_void_p), ("sig_s", C.c_void_p), ("sig_f", C.c_void_p),
+                ("awr", C.c_void_p), ("nu", C.c_double), ("n_mat", C.c_int32),
+                ("max_nuc", C.c_int32), ("mat_n", C.c_void_p), ("mat_nuc", C.c_void_p),
+                ("mat_dens", C.c_void_p), ("watt_a", C.c_double), ("watt_b", C.c_double),
+                ("e_max", C.c_double), ("e_cut", C.c_double), ("n_ebins", C.c_int32),
+                ("e_edges", C.c_void_p)]
+
+
 class Problem(C.Structure):
     _fields_ = [("geo", Geometry), ("n_mat", C.c_int32), ("n_grp", C.c_int32),
                 ("sig_t", C.c_void_p), ("sig_s", C.c_void_p), ("nu_sig_f", C.c_void_p),
@@ -85,6 +95,7 @@ RECORD_DTYPE = np.dtype([
     ("n_seg", "<i4"), ("n_col", "<i4"), ("n_cross", "<i4"), ("n_refl", "<i4"),
     ("fate", "<i4"), ("n_sites", "<i4"), ("g_final", "<i4"), ("ctr_final", "<u4"),
     ("tl_sum", "<f8"), ("kcol_sum", "<f8"), ("x_final", "<f8"), ("y_final", "<f8"),
+    ("e_final", "<f8"),
 ])
 
 _lib = None
@@ -124,6 +135,7 @@ def lib():
         "mcx_get_batch_results": ([vp, dp, dp], C.c_int),
         "mcx_get_batch_tallies": ([vp, i32, dp, dp, i64], C.c_int),
         "mcx_autotune": ([vp, C.c_char_p, C.POINTER(Tune)], C.c_int),
+        "mcx_load_ce_xs": ([vp, C.POINTER(CEData)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -162,6 +174,29 @@ def _geometry(geo, keep):
     g.n_rings, g.radii = n_rings.ctypes.data, radii.ctypes.data
     g.mats, g.pin_map = mats.ctypes.data, pin_map.ctypes.data
     return g
+
+
+def _ce(ce, keep):
+    d = CEData()
+    sig_t = _arr(ce["sig_t"], np.float64, keep)
+    d.n_nuc, d.n_pts = sig_t.shape
+    d.e_grid = _arr(ce["e_grid"], np.float64, keep).ctypes.data
+    d.sig_t = sig_t.ctypes.data
+    d.sig_s = _arr(ce["sig_s"], np.float64, keep).ctypes.data
+    d.sig_f = _arr(ce["sig_f"], np.float64, keep).ctypes.data
+    d.awr = _arr(ce["awr"], np.float64, keep).ctypes.data
+    d.nu = ce["nu"]
+    mat_nuc = _arr(ce["mat_nuc"], np.int32, keep)
+    d.n_mat, d.max_nuc = mat_nuc.shape
+    d.mat_n = _arr(ce["mat_n"], np.int32, keep).ctypes.data
+    d.mat_nuc = mat_nuc.ctypes.data
+    d.mat_dens = _arr(ce["mat_dens"], np.float64, keep).ctypes.data
+    d.watt_a, d.watt_b = ce["watt_a"], ce["watt_b"]
+    d.e_max, d.e_cut = ce["e_max"], ce["e_cut"]
+    edges = _arr(ce["e_edges"], np.float64, keep)
+    d.n_ebins = len(edges) - 1
+    d.e_edges = edges.ctypes.data
+    return d
 
 
 def _xs(xs, keep):
@@ -213,12 +248,17 @@ class Context:
         h = C.c_void_p()
         self._check(L.mcx_create(C.byref(h), C.byref(o)), None)
         self.h = h
-        geo, xs = problem["geometry"], problem["xs"]
+        geo = problem["geometry"]
         k = self._keep
         g = _geometry(geo, k)
         self._check(L.mcx_load_geometry(h, C.byref(g)))
-        (n_mat, n_grp), ptrs = _xs(xs, k)
-        self._check(L.mcx_load_mg_xs(h, n_mat, n_grp, *ptrs))
+        if "ce" in problem:
+            d = _ce(problem["ce"], k)
+            self._check(L.mcx_load_ce_xs(h, C.byref(d)))
+            n_grp = d.n_ebins
+        else:
+            (n_mat, n_grp), ptrs = _xs(problem["xs"], k)
+            self._check(L.mcx_load_mg_xs(h, n_mat, n_grp, *ptrs))
         s = Source()
         s.seed, s.n_per_gen = rp["seed"], rp["n_per_gen"]
         s.fixed_source, s.problem_id = int(rp["fixed_source"]), rp["problem_id"]
