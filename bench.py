@@ -97,13 +97,24 @@ def fp32_mixed_comparison(P, mcx, n, n_gen, n_inactive):
     out = {}
     res = {}
     for prec in ("fp64", "fp32"):
-        ctx = mcx.Context(prob, precision=prec)
+        ctx = mcx.Context(prob, precision=prec, time_kernels=True)
         sec = timed_runs(ctx, 1)
         km, ks, pg = ctx.keff()
+        t = ctx.timing()
         res[prec] = (km, ks, pg)
         ctx.close()
         out[prec] = {"histories_per_s": round(n * n_gen / sec, 1), "ms_per_step": round(sec * 1e3, 2),
                      "k_col": round(float(km[0]), 7), "sigma": round(float(ks[0]), 7)}
+        # the advance kernel at this size (direction cosines are binary32 in FP32-mixed)
+        state = STATE_BYTES if prec == "fp64" else STATE_BYTES - 8
+        items = t["advance_items"] / max(1, t["n_advance"])
+        fl = t["advance_segments"] / max(1, t["advance_items"])
+        avg_ms = t["advance_ms"] / max(1, t["n_advance"])
+        ach = items * (2 * state + TALLY_BYTES_ADV * fl) / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+        out[prec]["k_advance_roofline"] = {"achieved_GBps": round(ach, 1),
+                                           "frac": round(ach / HBM_PEAK_GBS, 4),
+                                           "items_per_launch": round(items, 1),
+                                           "avg_launch_us": round(avg_ms * 1e3, 2)}
     dk = res["fp32"][0][0] - res["fp64"][0][0]
     sig = math.hypot(res["fp32"][1][0], res["fp64"][1][0])
     d = res["fp32"][2][n_inactive:, 0] - res["fp64"][2][n_inactive:, 0]

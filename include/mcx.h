@@ -260,6 +260,26 @@ int mcx_bind_workspace(mcx_ctx* ctx, void* device_ptr, size_t bytes, int32_t n_g
    MCX_EGUARD (results are still readable) or MCX_EDEVICE on failure. */
 int mcx_run_generations(mcx_ctx* ctx, int32_t n_gen, int32_t n_inactive);
 
+/* Continue the last completed run (or a restored checkpoint) by n_more
+   generations: the next generation starts from the source and k_used the
+   previous one left, with the same random streams, so a run continued in
+   pieces equals one uninterrupted run of the total length.  Statistics
+   cover every generation so far with the first run's n_inactive.  The total
+   must stay within n_gen_max. */
+int mcx_continue_generations(mcx_ctx* ctx, int32_t n_more);
+
+/* Serialize the state a continued run needs after a completed run: the next
+   source, k_used and every generation's results so far (not the per-history
+   records), tied to the problem, precision and event guard by a
+   fingerprint.  buf = NULL: *len receives the size in bytes.  MCX_ENOMEM if
+   *len is too small (then *len receives the size). */
+int mcx_checkpoint(mcx_ctx* ctx, void* buf, size_t* len);
+
+/* Load a checkpoint into a context bound to the same problem (MCX_EINVAL
+   otherwise); the results read back as after the checkpointed run, and
+   mcx_continue_generations proceeds from it. */
+int mcx_restore(mcx_ctx* ctx, const void* buf, size_t len);
+
 /* Active-generation mean and standard deviation of the mean of the
    collision, track-length and absorption k estimators (mean3, sigma3), and
    optionally the per-generation values per_gen[n_gen][3] (may be NULL). */
@@ -268,6 +288,26 @@ int mcx_get_keff(mcx_ctx* ctx, double* mean3, double* sigma3, double* per_gen);
 /* Per-generation Shannon entropy of the fission bank entropy[n_gen] and
    counters counts[n_gen][MCX_N_CNT]; either may be NULL. */
 int mcx_get_generation_stats(mcx_ctx* ctx, double* entropy, int64_t* counts);
+
+/* Continue the last completed run (or a restored checkpoint) by n_more
+   generations: the next generation starts from the source and k_used the
+   previous one left, with the same random streams, so a run continued in
+   pieces equals one uninterrupted run of the total length.  Statistics
+   cover every generation so far with the first run's n_inactive.  The total
+   must stay within n_gen_max. */
+int mcx_continue_generations(mcx_ctx* ctx, int32_t n_more);
+
+/* Serialize the state a continued run needs after a completed run: the next
+   source, k_used and every generation's results so far (not the per-history
+   records), tied to the problem, precision and event guard by a
+   fingerprint.  buf = NULL: *len receives the size in bytes.  MCX_ENOMEM if
+   *len is too small (then *len receives the size). */
+int mcx_checkpoint(mcx_ctx* ctx, void* buf, size_t* len);
+
+/* Load a checkpoint into a context bound to the same problem (MCX_EINVAL
+   otherwise); the results read back as after the checkpointed run, and
+   mcx_continue_generations proceeds from it. */
+int mcx_restore(mcx_ctx* ctx, const void* buf, size_t len);
 
 /* Active-generation mean and standard deviation of the mean of the
    track-length flux and nu-fission production per source particle, bin

@@ -175,8 +175,8 @@ struct mcx_ctx {
   Dev d;
 
   // results of the last run
-  int last_n_gen = 0, last_n_inactive = 0;
-  bool ran = false;
+  int last_n_gen = 0, last_n_inactive = 0, req_n_inactive = 0;
+  bool ran = false, can_continue = false;
   std::vector<double> h_gen_k, h_gen_h, h_kstat;
   std::vector<unsigned long long> h_gen_cnt;
   std::vector<uint32_t> h_gen_m;
@@ -789,6 +789,7 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
   if (!c || !ptr || n_gen_max < 1) return MCX_EINVAL;
   c->bound = false;
   c->ran = false;
+  c->can_continue = false;
   c->batch_ran = false;
   if (c->graph_exec) {
     (void)hipGraphExecDestroy(c->graph_exec);
@@ -1193,56 +1194,12 @@ static int status_error(mcx_ctx* c, uint32_t st) {
   return fail(c, MCX_EDEVICE, "generation skipped");
 }
 
-int mcx_run_generations(mcx_ctx* c, int32_t n_gen, int32_t n_inactive) {
-  if (!c) return MCX_EINVAL;
-  if (!c->bound) return fail(c, MCX_ESTATE, "bind a workspace first");
-  if (c->batch) return fail(c, MCX_ESTATE, "a batch is loaded: use mcx_run_batch");
-  if (n_gen < 1 || n_gen > c->n_gen_max || n_inactive < 0 || n_inactive >= n_gen)
-    return fail(c, MCX_EINVAL, "generation counts");
-  HIP_TRY(c, hipSetDevice(c->opt.device));
+// Statistics over the completed generations [0, ng) and their host copies.
+static int finish_results(mcx_ctx* c, int ng, int n_inactive) {
   hipStream_t s = c->stream;
-  c->timing = mcx_timing{};
-  c->ran = false;
-  c->last_n_gen = n_gen;
-  c->last_n_inactive = n_inactive;
-  if (c->opt.record_histories) c->h_rec.assign((size_t)n_gen * c->d.N, mcx_record{});
-  const double one = 1.0;
-  HIP_TRY(c, hipMemcpyAsync(c->d.k_used, &one, sizeof(double), hipMemcpyHostToDevice, s));
-  HIP_TRY(c, launch_fill_u64(reinterpret_cast<unsigned long long*>(c->d.gen_status),
-                             ((size_t)n_gen + 1) / 2, 0ull, s));
-  HIP_TRY(c, hipEventRecord(c->ev_start, s));
-  // generations are enqueued back to back; each one's status is checked
-  // once the run has finished (a failed generation makes the later ones run
-  // empty)
-  int rc = MCX_OK;
-  for (int g = 0; g < n_gen; ++g) {
-    rc = run_generation(c, g);
-    if (rc != MCX_OK) break;
-  }
-  HIP_TRY(c, hipEventRecord(c->ev_stop, s));
-  HIP_TRY(c, hipStreamSynchronize(s));
-  if (rc != MCX_OK) return rc;
-  float ms = 0.f;
-  HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_start, c->ev_stop));
-  c->timing.run_ms = ms;
-  if (c->opt.time_kernels) {
-    int trc = collect_kernel_times(c);
-    if (trc) return trc;
-  }
-  std::vector<uint32_t> st(n_gen);
-  HIP_TRY(c, hipMemcpy(st.data(), c->d.gen_status, n_gen * sizeof(uint32_t), hipMemcpyDeviceToHost));
-  int done = n_gen;
-  for (int g = 0; g < n_gen; ++g)
-    if (st[g]) {
-      rc = status_error(c, st[g]);
-      done = g;
-      break;
-    }
-  if (done == 0) return rc;
-  const int ng = done;
   const int ni = std::min(n_inactive, ng - 1);
-  HIP_TRY(c, launch_stats(2 * c->d.n_bins, ng, ni, c->d.gen_tal, c->d.tal_stat, c->d.tal_stat + 2 * c->d.n_bins,
-                          c->d.gen_k, c->d.k_stat, s));
+  HIP_TRY(c, launch_stats(2 * c->d.n_bins, ng, ni, c->d.gen_tal, c->d.tal_stat,
+                          c->d.tal_stat + 2 * c->d.n_bins, c->d.gen_k, c->d.k_stat, s));
   c->h_gen_k.resize((size_t)3 * ng);
   c->h_gen_h.resize(ng);
   c->h_gen_cnt.resize((size_t)N_CNT_ALL * ng);
@@ -1258,15 +1215,247 @@ int mcx_run_generations(mcx_ctx* c, int32_t n_gen, int32_t n_inactive) {
   c->last_n_gen = ng;
   c->last_n_inactive = ni;
   c->ran = true;
-  for (int g = 0; g < ng; ++g) {
+  return MCX_OK;
+}
+
+// Generations [g0, g1) of the power iteration (g0 = 0 starts it, g0 > 0
+// continues from the source and k_used the previous generation left).
+static int run_range(mcx_ctx* c, int g0, int g1, int n_inactive) {
+  HIP_TRY(c, hipSetDevice(c->opt.device));
+  hipStream_t s = c->stream;
+  c->timing = mcx_timing{};
+  c->ran = false;
+  c->can_continue = false;
+  c->req_n_inactive = n_inactive;
+  if (c->opt.record_histories) c->h_rec.resize((size_t)g1 * c->d.N, mcx_record{});
+  if (g0 == 0) {
+    const double one = 1.0;
+    HIP_TRY(c, hipMemcpyAsync(c->d.k_used, &one, sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  // the status words of the earlier generations are zero (only a fully
+  // successful run can be continued)
+  HIP_TRY(c, launch_fill_u64(reinterpret_cast<unsigned long long*>(c->d.gen_status),
+                             ((size_t)g1 + 1) / 2, 0ull, s));
+  HIP_TRY(c, hipEventRecord(c->ev_start, s));
+  // generations are enqueued back to back; each one's status is checked
+  // once the run has finished (a failed generation makes the later ones run
+  // empty)
+  int rc = MCX_OK;
+  for (int g = g0; g < g1; ++g) {
+    rc = run_generation(c, g);
+    if (rc != MCX_OK) break;
+  }
+  HIP_TRY(c, hipEventRecord(c->ev_stop, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (rc != MCX_OK) return rc;
+  float ms = 0.f;
+  HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_start, c->ev_stop));
+  c->timing.run_ms = ms;
+  if (c->opt.time_kernels) {
+    int trc = collect_kernel_times(c);
+    if (trc) return trc;
+  }
+  std::vector<uint32_t> st(g1);
+  HIP_TRY(c, hipMemcpy(st.data(), c->d.gen_status, g1 * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  int done = g1;
+  for (int g = g0; g < g1; ++g)
+    if (st[g]) {
+      rc = status_error(c, st[g]);
+      done = g;
+      break;
+    }
+  if (done == 0) return rc;
+  const int frc = finish_results(c, done, n_inactive);
+  if (frc != MCX_OK) return frc;
+  for (int g = g0; g < done; ++g) {
     c->timing.advance_items += (int64_t)c->h_gen_cnt[(size_t)g * N_CNT_ALL + CNT_ADV_ITEMS];
     c->timing.collide_items += (int64_t)c->h_gen_cnt[(size_t)g * N_CNT_ALL + CNT_COL_ITEMS];
     c->timing.advance_segments += (int64_t)c->h_gen_cnt[(size_t)g * N_CNT_ALL + CNT_ADV_SEGS];
   }
   if (rc != MCX_OK) return rc;
-  for (int g = 0; g < ng; ++g)
+  c->can_continue = true;
+  for (int g = g0; g < done; ++g)
     if (c->h_gen_cnt[(size_t)g * N_CNT_ALL + CNT_KILLED] > 0)
       return fail(c, MCX_EGUARD, "histories reached the event guard");
+  return MCX_OK;
+}
+
+int mcx_run_generations(mcx_ctx* c, int32_t n_gen, int32_t n_inactive) {
+  if (!c) return MCX_EINVAL;
+  if (!c->bound) return fail(c, MCX_ESTATE, "bind a workspace first");
+  if (c->batch) return fail(c, MCX_ESTATE, "a batch is loaded: use mcx_run_batch");
+  if (n_gen < 1 || n_gen > c->n_gen_max || n_inactive < 0 || n_inactive >= n_gen)
+    return fail(c, MCX_EINVAL, "generation counts");
+  return run_range(c, 0, n_gen, n_inactive);
+}
+
+int mcx_continue_generations(mcx_ctx* c, int32_t n_more) {
+  if (!c) return MCX_EINVAL;
+  if (!c->bound || !c->can_continue)
+    return fail(c, MCX_ESTATE, "no completed run (or restored checkpoint) to continue");
+  if (n_more < 1 || (int64_t)c->last_n_gen + n_more > c->n_gen_max)
+    return fail(c, MCX_EINVAL, "generation count beyond n_gen_max");
+  return run_range(c, c->last_n_gen, c->last_n_gen + n_more, c->req_n_inactive);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// checkpoints: the state a continued run needs (next source, k_used) and the
+// per-generation results so far, tied to the problem by a fingerprint
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct CkptHeader {
+  char magic[8];
+  uint32_t version, ce;
+  int32_t precision;
+  uint32_t n;
+  int32_t n_bins, n_gen, n_inactive, n_cnt;
+  uint64_t fingerprint;
+};
+
+template <class T>
+void fnv(uint64_t* h, const T* p, size_t n) {
+  const unsigned char* b = reinterpret_cast<const unsigned char*>(p);
+  for (size_t k = 0; k < n * sizeof(T); ++k) {
+    *h ^= b[k];
+    *h *= 1099511628211ull;
+  }
+}
+
+uint64_t fingerprint(const mcx_ctx* c) {
+  uint64_t h = 1469598103934665603ull;
+  const int32_t ints[] = {c->nx, c->ny, c->n_univ, c->max_rings, c->bc[0], c->bc[1], c->bc[2],
+                          c->bc[3], c->n_mat, c->G, c->opt.precision, c->ce ? 1 : 0};
+  fnv(&h, ints, sizeof(ints) / sizeof(ints[0]));
+  const double dbl[] = {c->pitch, c->x0, c->y0, (double)c->opt.max_events};
+  fnv(&h, dbl, 4);
+  fnv(&h, c->pin_map.data(), c->pin_map.size());
+  fnv(&h, c->n_rings.data(), c->n_rings.size());
+  fnv(&h, c->radii.data(), c->radii.size());
+  fnv(&h, c->mats.data(), c->mats.size());
+  fnv(&h, c->sig_t.data(), c->sig_t.size());
+  fnv(&h, c->nusf.data(), c->nusf.size());
+  fnv(&h, c->cum_s.data(), c->cum_s.size());
+  fnv(&h, c->cum_chi.data(), c->cum_chi.size());
+  fnv(&h, c->ce_grid.data(), c->ce_grid.size());
+  fnv(&h, c->ce_xs.data(), c->ce_xs.size());
+  fnv(&h, c->ce_awr.data(), c->ce_awr.size());
+  fnv(&h, c->ce_dens.data(), c->ce_dens.size());
+  fnv(&h, c->ce_mat_nuc.data(), c->ce_mat_nuc.size());
+  fnv(&h, c->ce_edges.data(), c->ce_edges.size());
+  const uint64_t src[] = {c->src.seed, (uint64_t)c->src.n_per_gen, (uint64_t)c->src.fixed_source,
+                          c->src.problem_id, (uint64_t)c->src.ent_nx, (uint64_t)c->src.ent_ny};
+  fnv(&h, src, 6);
+  return h;
+}
+
+// Byte layout of a checkpoint: header, k_used, source (x, y, g[, e]), then
+// per generation k, entropy, counters, bank size and tallies.
+size_t ckpt_size(const mcx_ctx* c, int ng) {
+  const size_t N = c->d.N, nb = (size_t)c->d.n_bins;
+  size_t b = sizeof(CkptHeader) + 8 + N * (8 + 8 + 4) + (c->ce ? N * 8 : 0);
+  b += (size_t)ng * (3 * 8 + 8 + N_CNT_ALL * 8 + 4 + 2 * nb * 8);
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mcx_checkpoint(mcx_ctx* c, void* buf, size_t* len) {
+  if (!c || !len) return MCX_EINVAL;
+  if (!c->bound || !c->can_continue || c->batch)
+    return fail(c, MCX_ESTATE, "no completed run to checkpoint");
+  const int ng = c->last_n_gen;
+  const size_t need = ckpt_size(c, ng);
+  if (!buf) {
+    *len = need;
+    return MCX_OK;
+  }
+  if (*len < need) {
+    *len = need;
+    return fail(c, MCX_ENOMEM, "checkpoint buffer too small");
+  }
+  HIP_TRY(c, hipSetDevice(c->opt.device));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  char* p = static_cast<char*>(buf);
+  CkptHeader hd{};
+  std::memcpy(hd.magic, "MCXCKPT1", 8);
+  hd.version = 1;
+  hd.ce = c->ce ? 1u : 0u;
+  hd.precision = c->opt.precision;
+  hd.n = c->d.N;
+  hd.n_bins = c->d.n_bins;
+  hd.n_gen = ng;
+  hd.n_inactive = c->req_n_inactive;
+  hd.n_cnt = N_CNT_ALL;
+  hd.fingerprint = fingerprint(c);
+  std::memcpy(p, &hd, sizeof hd);
+  p += sizeof hd;
+  const size_t N = c->d.N, nb = (size_t)c->d.n_bins;
+  auto down = [&](const void* d, size_t n) {
+    hipError_t e = hipMemcpy(p, d, n, hipMemcpyDeviceToHost);
+    p += n;
+    return e;
+  };
+  HIP_TRY(c, down(c->d.k_used, 8));
+  HIP_TRY(c, down(c->d.src_x, N * 8));
+  HIP_TRY(c, down(c->d.src_y, N * 8));
+  HIP_TRY(c, down(c->d.src_g, N * 4));
+  if (c->ce) HIP_TRY(c, down(c->d.src_e, N * 8));
+  HIP_TRY(c, down(c->d.gen_k, (size_t)3 * ng * 8));
+  HIP_TRY(c, down(c->d.gen_h, (size_t)ng * 8));
+  HIP_TRY(c, down(c->d.gen_cnt, (size_t)N_CNT_ALL * ng * 8));
+  HIP_TRY(c, down(c->d.gen_m, (size_t)ng * 4));
+  HIP_TRY(c, down(c->d.gen_tal, (size_t)2 * nb * ng * 8));
+  *len = need;
+  return MCX_OK;
+}
+
+int mcx_restore(mcx_ctx* c, const void* buf, size_t len) {
+  if (!c || !buf) return MCX_EINVAL;
+  if (!c->bound || c->batch) return fail(c, MCX_ESTATE, "bind a workspace for the problem first");
+  CkptHeader hd{};
+  if (len < sizeof hd) return fail(c, MCX_EINVAL, "checkpoint too short");
+  std::memcpy(&hd, buf, sizeof hd);
+  if (std::memcmp(hd.magic, "MCXCKPT1", 8) != 0 || hd.version != 1 || hd.n_cnt != N_CNT_ALL)
+    return fail(c, MCX_EINVAL, "not a checkpoint of this library");
+  if (hd.fingerprint != fingerprint(c) || hd.n != c->d.N || hd.n_bins != c->d.n_bins ||
+      hd.ce != (c->ce ? 1u : 0u) || hd.precision != c->opt.precision)
+    return fail(c, MCX_EINVAL, "checkpoint of a different problem or precision");
+  if (hd.n_gen < 1 || hd.n_gen > c->n_gen_max || hd.n_inactive < 0)
+    return fail(c, MCX_EINVAL, "checkpoint generation count beyond n_gen_max");
+  if (len < ckpt_size(c, hd.n_gen)) return fail(c, MCX_EINVAL, "checkpoint truncated");
+  HIP_TRY(c, hipSetDevice(c->opt.device));
+  const int ng = hd.n_gen;
+  const char* p = static_cast<const char*>(buf) + sizeof hd;
+  const size_t N = c->d.N, nb = (size_t)c->d.n_bins;
+  auto up = [&](void* d, size_t n) {
+    hipError_t e = hipMemcpy(d, p, n, hipMemcpyHostToDevice);
+    p += n;
+    return e;
+  };
+  HIP_TRY(c, up(c->d.k_used, 8));
+  HIP_TRY(c, up(c->d.src_x, N * 8));
+  HIP_TRY(c, up(c->d.src_y, N * 8));
+  HIP_TRY(c, up(c->d.src_g, N * 4));
+  if (c->ce) HIP_TRY(c, up(c->d.src_e, N * 8));
+  HIP_TRY(c, up(c->d.gen_k, (size_t)3 * ng * 8));
+  HIP_TRY(c, up(c->d.gen_h, (size_t)ng * 8));
+  HIP_TRY(c, up(c->d.gen_cnt, (size_t)N_CNT_ALL * ng * 8));
+  HIP_TRY(c, up(c->d.gen_m, (size_t)ng * 4));
+  HIP_TRY(c, up(c->d.gen_tal, (size_t)2 * nb * ng * 8));
+  std::vector<uint32_t> zero((size_t)ng + 1, 0u);
+  HIP_TRY(c, hipMemcpy(c->d.gen_status, zero.data(), zero.size() * 4, hipMemcpyHostToDevice));
+  c->timing = mcx_timing{};
+  if (c->opt.record_histories) c->h_rec.assign((size_t)ng * c->d.N, mcx_record{});
+  const int frc = finish_results(c, ng, hd.n_inactive);
+  if (frc != MCX_OK) return frc;
+  c->req_n_inactive = hd.n_inactive;
+  c->can_continue = true;
   return MCX_OK;
 }
 

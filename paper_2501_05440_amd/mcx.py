@@ -29,6 +29,7 @@ EXPORTS = [
     "mcx_get_records", "mcx_get_bank", "mcx_get_timing", "mcx_diag_math", "mcx_host_math",
     "mcx_diag_philox", "mcx_last_error", "mcx_destroy", "mcx_load_batch", "mcx_run_batch",
     "mcx_get_batch_results", "mcx_get_batch_tallies", "mcx_autotune", "mcx_load_ce_xs",
+    "mcx_continue_generations", "mcx_checkpoint", "mcx_restore",
 ]
 
 
@@ -136,6 +137,9 @@ def lib():
         "mcx_get_batch_tallies": ([vp, i32, dp, dp, i64], C.c_int),
         "mcx_autotune": ([vp, C.c_char_p, C.POINTER(Tune)], C.c_int),
         "mcx_load_ce_xs": ([vp, C.POINTER(CEData)], C.c_int),
+        "mcx_continue_generations": ([vp, i32], C.c_int),
+        "mcx_checkpoint": ([vp, vp, C.POINTER(C.c_size_t)], C.c_int),
+        "mcx_restore": ([vp, vp, C.c_size_t], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -288,6 +292,27 @@ class Context:
         if check:
             self._check(rc)
         return rc
+
+    def continue_run(self, n_more, check=True):
+        rc = self.L.mcx_continue_generations(self.h, n_more)
+        if rc in (OK, EGUARD):
+            self.n_gen = (self.n_gen or 0) + n_more
+        if check:
+            self._check(rc)
+        return rc
+
+    def checkpoint(self):
+        """Bytes of a checkpoint of the last completed run."""
+        n = C.c_size_t()
+        self._check(self.L.mcx_checkpoint(self.h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._check(self.L.mcx_checkpoint(self.h, buf, C.byref(n)))
+        return buf.raw[: n.value]
+
+    def restore(self, data, n_gen):
+        buf = C.create_string_buffer(bytes(data), len(data))
+        self._check(self.L.mcx_restore(self.h, buf, len(data)))
+        self.n_gen = n_gen
 
     def keff(self):
         m, s = np.zeros(3), np.zeros(3)

@@ -1,0 +1,98 @@
+"""GPU: continued runs and checkpoints.
+
+Generation g draws from streams keyed by g and starts from the source and
+k_used generation g - 1 left, so a power iteration run in pieces, or
+checkpointed and restored into a fresh context, equals the uninterrupted
+run bit for bit (the sums are exact)."""
+import numpy as np
+import pytest
+
+from paper_2501_05440_amd import mcx
+from paper_2501_05440_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("k_mean", "k_sigma", "flux_mean", "flux_sigma", "prod_mean", "prod_sigma")
+
+
+def banner(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+def results(ctx):
+    m, s, pg = ctx.keff()
+    h, c = ctx.generation_stats()
+    out = dict(k_mean=m, k_sigma=s, gen_k=pg, gen_entropy=h, gen_counts=c)
+    out.update(ctx.tallies())
+    return out
+
+
+def same(a, b):
+    for k in ("gen_k", "gen_entropy", "gen_counts") + KEYS:
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("kind", ["mg", "ce", "mg_fp32", "mg_persistent"])
+def test_continue_and_restore_equal_one_run(kind):
+    banner(f"continue / checkpoint / restore ({kind})")
+    kw = {}
+    if kind.startswith("mg"):
+        prob = P.lattice_17x17(n_per_gen=5000, n_gen=10, n_inactive=3)
+    else:
+        prob = P.ce_pin_cell(n_per_gen=2000, n_gen=10, n_inactive=3)
+    if kind == "mg_fp32":
+        kw["precision"] = "fp32"
+    if kind == "mg_persistent":
+        kw["engine"] = "persistent"
+    ref = mcx.Context(prob, **kw)
+    ref.run()
+    want = results(ref)
+    ref.close()
+
+    a = mcx.Context(prob, **kw)
+    a.run(n_gen=6, n_inactive=3)
+    blob = a.checkpoint()
+    a.continue_run(4)
+    same(results(a), want)
+    a.close()
+
+    b = mcx.Context(prob, **kw)
+    b.restore(blob, 6)
+    b.continue_run(2)
+    b.continue_run(2)
+    same(results(b), want)
+    b.close()
+
+
+def test_checkpoint_errors():
+    banner("checkpoint errors")
+    prob = P.lattice_17x17(n_per_gen=2000, n_gen=4, n_inactive=1)
+    a = mcx.Context(prob)
+    try:
+        with pytest.raises(mcx.MCXError) as e:
+            a.checkpoint()
+        assert e.value.code == mcx.ESTATE
+        assert a.continue_run(1, check=False) == mcx.ESTATE
+        a.run(n_gen=2, n_inactive=1)
+        assert a.continue_run(3, check=False) == mcx.EINVAL  # beyond n_gen_max = 4
+        blob = a.checkpoint()
+    finally:
+        a.close()
+    other = P.lattice_17x17(n_per_gen=2000, n_gen=4, n_inactive=1, seed=99)
+    b = mcx.Context(other)
+    try:
+        with pytest.raises(mcx.MCXError) as e:
+            b.restore(blob, 2)
+        assert e.value.code == mcx.EINVAL
+        with pytest.raises(mcx.MCXError) as e:
+            b.restore(blob[:100], 2)
+        assert e.value.code == mcx.EINVAL
+    finally:
+        b.close()
+    c32 = mcx.Context(prob, precision="fp32")
+    try:
+        with pytest.raises(mcx.MCXError) as e:
+            c32.restore(blob, 2)
+        assert e.value.code == mcx.EINVAL
+    finally:
+        c32.close()
