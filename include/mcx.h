@@ -106,6 +106,9 @@ typedef struct {
                                the paper's decomposition; larger values keep a particle in
                                the kernel across surface crossings.  Results are identical
                                for every value.  0 = default (8); at most 65536 */
+  int32_t event_log;        /* > 0 (with record_histories = 1): keep the first event_log
+                               flights of every history in every generation as mcx_event
+                               entries (mcx_get_event_log); at most 65536 */
 } mcx_options;
 
 /* Lattice of pin universes (paper Sec. 1: CSG geometry).  Cell (i, j),
@@ -152,6 +155,15 @@ typedef struct {
   double x_final, y_final;
   double e_final;           /* final energy (continuous energy), else 0 */
 } mcx_record;
+
+/* One logged flight (event_log > 0): position after it, its length, the
+   energy it flew at (continuous energy, else 0), the lattice cell
+   (j * nx + i), ring region and group or energy bin it flew in, and how it
+   ended: 1 collision, 2 surface crossing, 3 leak.  Unused entries are 0. */
+typedef struct {
+  double x, y, d, e;
+  int32_t cell, region, group, type;
+} mcx_event;
 
 /* Timing of the last mcx_run_generations or mcx_run_batch.  The *_ms kernel sums are filled
    when time_kernels = 1 (events recorded on the stream around each launch);
@@ -323,6 +335,10 @@ int mcx_get_generation_tallies(mcx_ctx* ctx, int32_t gen, double* flux, double* 
 /* Per-history records of generation gen (record_histories = 1), n_per_gen
    entries indexed by history id. */
 int mcx_get_records(mcx_ctx* ctx, int32_t gen, mcx_record* out, int64_t n);
+
+/* Event log of generation gen: n = n_per_gen * event_log entries, history
+   id major. */
+int mcx_get_event_log(mcx_ctx* ctx, int32_t gen, mcx_event* out, int64_t n);
 
 /* Canonical fission bank of the last k-eigenvalue generation, ordered by
    (parent history, banking order): xyg[k][3] = x, y, group (energy in eV for

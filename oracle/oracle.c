@@ -469,7 +469,23 @@ typedef struct {
   int64_t n_chunks, chunk_size;
   atomic_long next_chunk;
   orc_record* records;         /* this generation's records or NULL */
+  orc_event* events;           /* this generation's event log or NULL */
+  int32_t event_cap;
 } ctx_t;
+
+static void log_flight(const ctx_t* C, int64_t id, int32_t k, double x, double y, double d,
+                       double e, int cell, int region, int group, int type) {
+  if (!C->events || k >= C->event_cap) return;
+  orc_event* ev = &C->events[id * C->event_cap + k];
+  ev->x = x;
+  ev->y = y;
+  ev->d = d;
+  ev->e = e;
+  ev->cell = cell;
+  ev->region = region;
+  ev->group = group;
+  ev->type = type;
+}
 
 static void locate(const orc_problem* p, double x, double y, int* ci, int* cj, int* cr) {
   int i = (int)floor((x - p->x0) / p->pitch);
@@ -623,8 +639,10 @@ static void run_history(ctx_t* C, int64_t id, chunk_t* ch) {
     nadd(&ch->prod[bin], d * nusf);
     nadd(&ch->k[1], d * nusf);
     tl_sum += d;
+    const int r_flight = r;
 
     if (collide) {
+      log_flight(C, id, n_seg - 1, x, y, d, 0.0, c, r_flight, g, 1);
       n_col += 1;
       double kc = nusf / st;
       kcol_sum += kc;
@@ -670,9 +688,11 @@ static void run_history(ctx_t* C, int64_t id, chunk_t* ch) {
         int side_x = u > 0.0 ? 1 : 0;
         int side_y = v > 0.0 ? 3 : 2;
         if ((out_x && p->bc[side_x] == ORC_VACUUM) || (out_y && p->bc[side_y] == ORC_VACUUM)) {
+          log_flight(C, id, n_seg - 1, x, y, d, 0.0, c, r_flight, g, 3);
           fate = ORC_LEAKED;
           break;
         }
+        log_flight(C, id, n_seg - 1, x, y, d, 0.0, c, r_flight, g, 2);
         int refl = 0;
         if (hit_x) {
           if (out_x) {
@@ -694,8 +714,10 @@ static void run_history(ctx_t* C, int64_t id, chunk_t* ch) {
         /* a lattice face lies outside every ring */
         r = p->n_rings[p->pin_map[j * p->nx + i]];
       } else if (t_out == d_bnd) {
+        log_flight(C, id, n_seg - 1, x, y, d, 0.0, c, r_flight, g, 2);
         r += 1;
       } else {
+        log_flight(C, id, n_seg - 1, x, y, d, 0.0, c, r_flight, g, 2);
         r -= 1;
       }
     }
@@ -805,8 +827,10 @@ static void run_history_ce(ctx_t* C, int64_t id, chunk_t* ch) {
     nadd(&ch->flux[bin], d);
     nadd(&ch->k[1], d * nusf);
     tl_sum += d;
+    const int r_flight = r;
 
     if (collide) {
+      log_flight(C, id, n_seg - 1, x, y, d, e, c, r_flight, b, 1);
       n_col += 1;
       double kc = nusf / st;
       kcol_sum += kc;
@@ -868,9 +892,11 @@ static void run_history_ce(ctx_t* C, int64_t id, chunk_t* ch) {
         int side_x = u > 0.0 ? 1 : 0;
         int side_y = v > 0.0 ? 3 : 2;
         if ((out_x && p->bc[side_x] == ORC_VACUUM) || (out_y && p->bc[side_y] == ORC_VACUUM)) {
+          log_flight(C, id, n_seg - 1, x, y, d, e, c, r_flight, b, 3);
           fate = ORC_LEAKED;
           break;
         }
+        log_flight(C, id, n_seg - 1, x, y, d, e, c, r_flight, b, 2);
         int refl = 0;
         if (hit_x) {
           if (out_x) {
@@ -891,8 +917,10 @@ static void run_history_ce(ctx_t* C, int64_t id, chunk_t* ch) {
         if (refl) n_refl += 1;
         r = p->n_rings[p->pin_map[j * p->nx + i]];
       } else if (t_out == d_bnd) {
+        log_flight(C, id, n_seg - 1, x, y, d, e, c, r_flight, b, 2);
         r += 1;
       } else {
+        log_flight(C, id, n_seg - 1, x, y, d, e, c, r_flight, b, 2);
         r -= 1;
       }
     }
@@ -1119,6 +1147,9 @@ int orc_run(const orc_problem* p, orc_output* out) {
     C.src_e = src_e;
     C.src_dir = src_dir;
     C.records = out->records ? out->records + (int64_t)gen * N : NULL;
+    C.events = out->events && out->event_cap > 0 ? out->events + (int64_t)gen * N * out->event_cap
+                                                 : NULL;
+    C.event_cap = out->event_cap;
     for (int64_t k = 0; k < C.n_chunks; ++k) chunk_reset(&C.chunks[k], C.n_bins);
     atomic_store(&C.next_chunk, 0);
     if (n_threads == 1) {

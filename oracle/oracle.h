@@ -119,6 +119,16 @@ typedef struct {
   double e_final;                /* final energy (continuous energy), else 0 */
 } orc_record;
 
+/* One flight of a history (event log): where it ended, its length, and the
+   state it flew in. */
+typedef struct {
+  double x, y;                   /* position after the flight */
+  double d;                      /* flight length */
+  double e;                      /* energy (continuous energy), else 0 */
+  int32_t cell, region, group;   /* lattice cell j * nx + i, ring region, group or energy bin */
+  int32_t type;                  /* 1 collision, 2 surface crossing, 3 leak */
+} orc_event;
+
 typedef struct {
   double* gen_k;                 /* [n_gen][3]: k_col, k_tl, k_abs (required) */
   double* gen_entropy;           /* [n_gen] (required) */
@@ -134,6 +144,8 @@ typedef struct {
   double* bank;                  /* last canonical bank [bank_cap][3] = x, y, g or NULL */
   int64_t bank_cap;
   int64_t bank_len;              /* out */
+  orc_event* events;             /* [n_gen][n_per_gen][event_cap] flights, or NULL */
+  int32_t event_cap;             /* flights logged per history (later ones are not) */
   char errmsg[256];
 } orc_output;
 

@@ -82,6 +82,12 @@ class _Record(C.Structure):
         ("x_final", C.c_double), ("y_final", C.c_double), ("e_final", C.c_double)]
 
 
+EVENT_DTYPE = np.dtype([
+    ("x", "<f8"), ("y", "<f8"), ("d", "<f8"), ("e", "<f8"),
+    ("cell", "<i4"), ("region", "<i4"), ("group", "<i4"), ("type", "<i4"),
+])
+
+
 class _Output(C.Structure):
     _fields_ = [
         ("gen_k", C.c_void_p), ("gen_entropy", C.c_void_p), ("gen_counts", C.c_void_p),
@@ -91,6 +97,7 @@ class _Output(C.Structure):
         ("gen_flux", C.c_void_p), ("gen_prod", C.c_void_p),
         ("records", C.c_void_p),
         ("bank", C.c_void_p), ("bank_cap", C.c_int64), ("bank_len", C.c_int64),
+        ("events", C.c_void_p), ("event_cap", C.c_int32),
         ("errmsg", C.c_char * 256),
     ]
 
@@ -287,7 +294,7 @@ def _ptr(a):
 
 
 def run(problem, n_threads=None, records=False, per_gen_tallies=False, bank_cap=0,
-        ext_state=None):
+        ext_state=None, events=0):
     """Run the oracle on a problem dict; returns a dict of numpy arrays."""
     geo, rp = problem["geometry"], problem["run"]
     ce = problem.get("ce")
@@ -364,6 +371,10 @@ def run(problem, n_threads=None, records=False, per_gen_tallies=False, bank_cap=
         res["bank"] = np.zeros((bank_cap, 3))
         O.bank = _ptr(res["bank"])
         O.bank_cap = bank_cap
+    if events:
+        res["events"] = np.zeros((G, N, events), EVENT_DTYPE)
+        O.events = _ptr(res["events"])
+        O.event_cap = events
     rc = L.orc_run(C.byref(P), C.byref(O))
     if rc != 0:
         raise OracleError(rc, O.errmsg.decode())

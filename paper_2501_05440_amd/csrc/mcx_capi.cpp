@@ -181,6 +181,7 @@ struct mcx_ctx {
   std::vector<unsigned long long> h_gen_cnt;
   std::vector<uint32_t> h_gen_m;
   std::vector<mcx_record> h_rec;
+  std::vector<mcx_event> h_ev;
   mcx_timing timing{};
 
   // batches of fixed-source problems (persistent engine)
@@ -258,6 +259,11 @@ int mcx_create(mcx_ctx** out, const mcx_options* opt) {
     return MCX_EINVAL;
   }
   if (c->opt.engine == MCX_ENGINE_PERSISTENT && c->opt.record_histories) {
+    delete c;
+    return MCX_EINVAL;
+  }
+  if (c->opt.event_log < 0 || c->opt.event_log > 65536 ||
+      (c->opt.event_log > 0 && !c->opt.record_histories)) {
     delete c;
     return MCX_EINVAL;
   }
@@ -754,6 +760,8 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
       R.x_final = rc.take<double>(N);
       R.y_final = rc.take<double>(N);
       R.e_final = rc.take<double>(N);
+      R.ev_cap = c->opt.event_log;
+      R.ev = c->opt.event_log > 0 ? rc.take<EvEntry>(N * (size_t)c->opt.event_log) : nullptr;
       if (pass == 0) {
         d.rec_words = (rc.off + 7) / 8;
         d.rec_base = cv.take<unsigned long long>(d.rec_words);
@@ -1182,6 +1190,12 @@ static int generation_end(mcx_ctx* c, int gen) {
       out[i] = mcx_record{n_seg[i], n_col[i], n_cross[i], n_refl[i], fate[i], (int32_t)ns[i],
                           g_final[i], ctr[i], tl[i], kc[i], xf[i], yf[i], ef[i]};
     }
+    if (c->opt.event_log > 0) {
+      const size_t ne = (size_t)N * c->opt.event_log;
+      EvEntry* ev = rc.take<EvEntry>(ne);
+      static_assert(sizeof(EvEntry) == sizeof(mcx_event), "event layout");
+      std::memcpy(c->h_ev.data() + (size_t)gen * ne, ev, ne * sizeof(EvEntry));
+    }
   }
   return MCX_OK;
 }
@@ -1228,6 +1242,7 @@ static int run_range(mcx_ctx* c, int g0, int g1, int n_inactive) {
   c->can_continue = false;
   c->req_n_inactive = n_inactive;
   if (c->opt.record_histories) c->h_rec.resize((size_t)g1 * c->d.N, mcx_record{});
+  if (c->opt.event_log > 0) c->h_ev.resize((size_t)g1 * c->d.N * c->opt.event_log, mcx_event{});
   if (g0 == 0) {
     const double one = 1.0;
     HIP_TRY(c, hipMemcpyAsync(c->d.k_used, &one, sizeof(double), hipMemcpyHostToDevice, s));
@@ -1513,6 +1528,17 @@ int mcx_get_records(mcx_ctx* c, int32_t gen, mcx_record* out, int64_t n) {
   if (gen < 0 || gen >= c->last_n_gen || n != (int64_t)c->d.N)
     return fail(c, MCX_EINVAL, "generation index or length");
   std::memcpy(out, c->h_rec.data() + (size_t)gen * c->d.N, (size_t)n * sizeof(mcx_record));
+  return MCX_OK;
+}
+
+int mcx_get_event_log(mcx_ctx* c, int32_t gen, mcx_event* out, int64_t n) {
+  if (!c || !out) return MCX_EINVAL;
+  if (!c->ran) return fail(c, MCX_ESTATE, "no completed run");
+  if (c->opt.event_log <= 0) return fail(c, MCX_ESTATE, "no event log was kept");
+  const size_t ne = (size_t)c->d.N * c->opt.event_log;
+  if (gen < 0 || gen >= c->last_n_gen || n != (int64_t)ne)
+    return fail(c, MCX_EINVAL, "generation index or length");
+  std::memcpy(out, c->h_ev.data() + (size_t)gen * ne, ne * sizeof(mcx_event));
   return MCX_OK;
 }
 

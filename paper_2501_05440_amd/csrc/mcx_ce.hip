@@ -378,12 +378,17 @@ __device__ __forceinline__ int segment_ce(const Tables& T, const Geo& L, PartCE<
     acc_add(tb + 2 * bin, qf);
   }
   *q_tl = quantize(d * (double)nusf, T.q_ktl);
+  int k_ev = 0;
   if (REC) {
+    k_ev = Rc.n_seg[p.id];
     Rc.n_seg[p.id] += 1;
     Rc.tl_sum[p.id] += d;
   }
   *refl_out = false;
-  if (collide) return EV_COLLIDE;
+  if (collide) {
+    if (REC) log_flight(Rc, p.id, k_ev, p.x, p.y, d, (double)p.e, c, p.r, b, 1);
+    return EV_COLLIDE;
+  }
 
   if (REC) Rc.n_cross[p.id] += 1;
   const bool hit_x = (double)tx == d_bnd;
@@ -393,8 +398,11 @@ __device__ __forceinline__ int segment_ce(const Tables& T, const Geo& L, PartCE<
     const bool out_y = hit_y && (p.v > R(0) ? p.j == L.ny - 1 : p.j == 0);
     const int side_x = p.u > R(0) ? 1 : 0;
     const int side_y = p.v > R(0) ? 3 : 2;
-    if ((out_x && L.bc[side_x] == BC_VACUUM) || (out_y && L.bc[side_y] == BC_VACUUM))
+    if ((out_x && L.bc[side_x] == BC_VACUUM) || (out_y && L.bc[side_y] == BC_VACUUM)) {
+      if (REC) log_flight(Rc, p.id, k_ev, p.x, p.y, d, (double)p.e, c, p.r, b, 3);
       return EV_LEAK;
+    }
+    if (REC) log_flight(Rc, p.id, k_ev, p.x, p.y, d, (double)p.e, c, p.r, b, 2);
     bool refl = false;
     if (hit_x) {
       if (out_x) {
@@ -415,10 +423,9 @@ __device__ __forceinline__ int segment_ce(const Tables& T, const Geo& L, PartCE<
     if (REC && refl) Rc.n_refl[p.id] += 1;
     *refl_out = refl;
     p.r = L.n_rings[L.pin_map[p.j * L.nx + p.i]];
-  } else if (t_out == d_bnd) {
-    p.r += 1;
   } else {
-    p.r -= 1;
+    if (REC) log_flight(Rc, p.id, k_ev, p.x, p.y, d, (double)p.e, c, p.r, b, 2);
+    p.r += t_out == d_bnd ? 1 : -1;
   }
   return EV_CROSS;
 }

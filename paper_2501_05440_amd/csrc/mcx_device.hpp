@@ -156,6 +156,14 @@ struct Sites {
   double* e;  // continuous energy: site energies
 };
 
+// One logged flight: position after it, its length and energy, the cell,
+// region and group (or energy bin) it flew in, and how it ended
+// (1 collision, 2 surface crossing, 3 leak).
+struct EvEntry {
+  double x, y, d, e;
+  int cell, region, group, type;
+};
+
 // Per-history debug records, indexed by history id.
 struct Records {
   int32_t* n_seg;
@@ -170,7 +178,25 @@ struct Records {
   double* x_final;
   double* y_final;
   double* e_final;
+  EvEntry* ev;  // [history][ev_cap] flights, or null
+  int ev_cap;
 };
+
+// Record flight k of history id (debug event log).
+MCX_HD void log_flight(const Records& Rc, uint32_t id, int k, double x, double y, double d,
+                       double e, int cell, int region, int group, int type) {
+  if (Rc.ev && k < Rc.ev_cap) {
+    EvEntry& v = Rc.ev[(size_t)id * (size_t)Rc.ev_cap + (size_t)k];
+    v.x = x;
+    v.y = y;
+    v.d = d;
+    v.e = e;
+    v.cell = cell;
+    v.region = region;
+    v.group = group;
+    v.type = type;
+  }
+}
 
 // Per-generation accumulators (zeroed at the start of every generation).
 struct Accum {

@@ -207,12 +207,17 @@ __device__ __forceinline__ int segment(const Tables& T, const Geo& L, Part<R>& p
         A.tally + (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
     acc_add(tb + 2 * bin, qf);
   }
+  int k_ev = 0;
   if (REC) {
+    k_ev = Rc.n_seg[p.id];
     Rc.n_seg[p.id] += 1;
     Rc.tl_sum[p.id] += d;
   }
   *refl_out = false;
-  if (collide) return EV_COLLIDE;
+  if (collide) {
+    if (REC) log_flight(Rc, p.id, k_ev, p.x, p.y, d, 0.0, c, p.r, p.g, 1);
+    return EV_COLLIDE;
+  }
 
   if (REC) Rc.n_cross[p.id] += 1;
   const bool hit_x = (double)tx == d_bnd;
@@ -222,8 +227,11 @@ __device__ __forceinline__ int segment(const Tables& T, const Geo& L, Part<R>& p
     const bool out_y = hit_y && (p.v > R(0) ? p.j == L.ny - 1 : p.j == 0);
     const int side_x = p.u > R(0) ? 1 : 0;
     const int side_y = p.v > R(0) ? 3 : 2;
-    if ((out_x && L.bc[side_x] == BC_VACUUM) || (out_y && L.bc[side_y] == BC_VACUUM))
+    if ((out_x && L.bc[side_x] == BC_VACUUM) || (out_y && L.bc[side_y] == BC_VACUUM)) {
+      if (REC) log_flight(Rc, p.id, k_ev, p.x, p.y, d, 0.0, c, p.r, p.g, 3);
       return EV_LEAK;
+    }
+    if (REC) log_flight(Rc, p.id, k_ev, p.x, p.y, d, 0.0, c, p.r, p.g, 2);
     bool refl = false;
     if (hit_x) {
       if (out_x) {
@@ -245,10 +253,9 @@ __device__ __forceinline__ int segment(const Tables& T, const Geo& L, Part<R>& p
     *refl_out = refl;
     // a lattice face lies outside every ring
     p.r = L.n_rings[L.pin_map[p.j * L.nx + p.i]];
-  } else if (t_out == d_bnd) {
-    p.r += 1;
   } else {
-    p.r -= 1;
+    if (REC) log_flight(Rc, p.id, k_ev, p.x, p.y, d, 0.0, c, p.r, p.g, 2);
+    p.r += t_out == d_bnd ? 1 : -1;
   }
   return EV_CROSS;
 }

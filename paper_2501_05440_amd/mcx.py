@@ -29,7 +29,7 @@ EXPORTS = [
     "mcx_get_records", "mcx_get_bank", "mcx_get_timing", "mcx_diag_math", "mcx_host_math",
     "mcx_diag_philox", "mcx_last_error", "mcx_destroy", "mcx_load_batch", "mcx_run_batch",
     "mcx_get_batch_results", "mcx_get_batch_tallies", "mcx_autotune", "mcx_load_ce_xs",
-    "mcx_continue_generations", "mcx_checkpoint", "mcx_restore",
+    "mcx_continue_generations", "mcx_checkpoint", "mcx_restore", "mcx_get_event_log",
 ]
 
 
@@ -45,7 +45,8 @@ class Options(C.Structure):
                 ("lookahead", C.c_int32), ("max_events", C.c_int64),
                 ("record_histories", C.c_int32), ("time_kernels", C.c_int32),
                 ("engine", C.c_int32), ("p_block", C.c_int32), ("p_slots", C.c_int32),
-                ("p_grid", C.c_int32), ("p_tau", C.c_double), ("flights", C.c_int32)]
+                ("p_grid", C.c_int32), ("p_tau", C.c_double), ("flights", C.c_int32),
+                ("event_log", C.c_int32)]
 
 
 class Geometry(C.Structure):
@@ -91,6 +92,11 @@ class Tune(C.Structure):
     _fields_ = [("block", C.c_int32), ("slots", C.c_int32), ("grid", C.c_int32),
                 ("tau", C.c_double), ("ms", C.c_double)]
 
+
+EVENT_DTYPE = np.dtype([
+    ("x", "<f8"), ("y", "<f8"), ("d", "<f8"), ("e", "<f8"),
+    ("cell", "<i4"), ("region", "<i4"), ("group", "<i4"), ("type", "<i4"),
+])
 
 RECORD_DTYPE = np.dtype([
     ("n_seg", "<i4"), ("n_col", "<i4"), ("n_cross", "<i4"), ("n_refl", "<i4"),
@@ -140,6 +146,7 @@ def lib():
         "mcx_continue_generations": ([vp, i32], C.c_int),
         "mcx_checkpoint": ([vp, vp, C.POINTER(C.c_size_t)], C.c_int),
         "mcx_restore": ([vp, vp, C.c_size_t], C.c_int),
+        "mcx_get_event_log": ([vp, i32, dp, i64], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -229,7 +236,8 @@ class Context:
 
     def __init__(self, problem, device=0, record=False, block_size=0, tail_threshold=0,
                  lookahead=0, max_events=None, time_kernels=False, n_gen_max=None,
-                 stream=None, precision="fp64", engine="event", persistent=None, flights=0):
+                 stream=None, precision="fp64", engine="event", persistent=None, flights=0,
+                 event_log=0):
         import torch
 
         self.problem = problem
@@ -248,6 +256,8 @@ class Context:
         o.max_events = rp["max_events"] if max_events is None else max_events
         o.record_histories = int(bool(record))
         o.flights = flights
+        o.event_log = event_log
+        self.event_log = event_log
         o.time_kernels = int(bool(time_kernels))
         h = C.c_void_p()
         self._check(L.mcx_create(C.byref(h), C.byref(o)), None)
@@ -346,6 +356,12 @@ class Context:
         self._check(self.L.mcx_get_records(self.h, gen, r.ctypes.data, self.n_per_gen))
         return r
 
+    def events(self, gen):
+        n = self.n_per_gen * self.event_log
+        e = np.zeros(n, EVENT_DTYPE)
+        self._check(self.L.mcx_get_event_log(self.h, gen, e.ctypes.data, n))
+        return e.reshape(self.n_per_gen, self.event_log)
+
     def bank(self, cap=None):
         n = C.c_int64()
         self._check(self.L.mcx_get_bank(self.h, None, 0, C.byref(n)))
@@ -418,6 +434,8 @@ def run(problem, device=0, record=False, per_gen_tallies=False, bank=False, **kw
                 res["gen_flux"][g], res["gen_prod"][g] = ctx.generation_tallies(g)
         if record:
             res["records"] = np.stack([ctx.records(g) for g in range(G)])
+        if kw.get("event_log"):
+            res["events"] = np.stack([ctx.events(g) for g in range(G)])
         if bank:
             res["bank"] = ctx.bank()
         return res

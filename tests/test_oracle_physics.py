@@ -287,3 +287,32 @@ def test_fission_bank_size_follows_k_used(oracle):
     expect = n * r["gen_k"][:, 0] / k_used
     bound = 4 * np.sqrt(r["gen_counts"][:, 1] / 4.0)
     assert np.all(np.abs(m - expect) < bound), (m, expect, bound)
+
+
+def test_event_log_is_consistent_with_records(oracle):
+    """The per-flight event log of the oracle: as many flights as the record
+    counts, flight lengths summing to the track length, one collision entry
+    per collision, the last entry at the final position, leaks only last,
+    and consecutive flights in the same or a neighbouring lattice cell."""
+    for prob in (P.lattice_17x17(n_per_gen=300, n_gen=2, n_inactive=1),
+                 P.ce_pin_cell(n_per_gen=200, n_gen=2, n_inactive=1)):
+        cap = 4096
+        r = oracle.run(prob, records=True, events=cap)
+        ev, rec = r["events"], r["records"]
+        nx = prob["geometry"]["nx"]
+        for g in range(ev.shape[0]):
+            for h in range(ev.shape[1]):
+                rh = rec[g, h]
+                n = int(rh["n_seg"])
+                assert n <= cap
+                e = ev[g, h, :n]
+                assert np.all(ev[g, h, n:]["type"] == 0)
+                assert np.all(e["type"] > 0)
+                assert abs(e["d"].sum() - rh["tl_sum"]) <= 1e-12 * rh["tl_sum"]
+                assert int((e["type"] == 1).sum()) == rh["n_col"]
+                assert int((e["type"] != 1).sum()) == rh["n_cross"]
+                assert e[-1]["x"] == rh["x_final"] and e[-1]["y"] == rh["y_final"]
+                assert np.all(e[:-1]["type"] != 3)
+                assert (e[-1]["type"] == 3) == (rh["fate"] == 2)
+                ci, cj = e["cell"] % nx, e["cell"] // nx
+                assert np.all(np.abs(np.diff(ci)) <= 1) and np.all(np.abs(np.diff(cj)) <= 1)
