@@ -137,7 +137,7 @@ def persistent_comparison(P, mcx, prob, event_hps, tune_cache):
     return {"histories_per_s": round(n / sec, 1), "ms_per_step": round(sec * 1e3, 2),
             "speedup_over_event_engine": round(n / sec / event_hps, 3),
             "k_col": round(float(km[0]), 7),
-            "tuned": {k: tune[k] for k in ("block", "slots", "grid", "tau")}}
+            "tuned": {k: tune[k] for k in ("block", "slots", "grid", "tau", "sort")}}
 
 
 def batch_comparison(P, mcx, tune_cache, steps):
@@ -180,7 +180,7 @@ def batch_comparison(P, mcx, tune_cache, steps):
             "one_at_a_time_event_fp64": {"histories_per_s": round(n.sum() / base, 1),
                                          "ms": round(base * 1e3, 1)},
             "speedup_over_one_at_a_time": round(base / sec, 3),
-            "tuned": {kk: tune[kk] for kk in ("block", "slots", "grid", "tau")},
+            "tuned": {kk: tune[kk] for kk in ("block", "slots", "grid", "tau", "sort")},
             "killed": int(cnt[:, 6].sum())}
 
 

@@ -100,6 +100,8 @@ typedef struct {
   int32_t p_grid;           /* persistent: workgroups; 0 = 2 per compute unit */
   double p_tau;             /* persistent: refill when fewer than p_tau * p_slots particles
                                of a block are live, 0 < p_tau <= 1; 0 = 0.75 */
+  int32_t p_sort;           /* persistent: 1 = order each collide list by material class
+                               (fissile first) so fission sampling runs in the same waves */
   int32_t flights;          /* event engine: flights one advance launch makes per particle
                                before it returns to the live bank (it stops earlier at a
                                collision, a leak or the guard).  1 = one event per launch,
@@ -205,6 +207,7 @@ typedef struct {
   int32_t block, slots, grid;
   double tau;
   double ms;                /* measured stream time of one batch (or generation) */
+  int32_t sort;             /* collide lists ordered by material class */
 } mcx_tune;
 
 /* Create a context on opt->device (NULL opt = defaults). */
@@ -373,9 +376,10 @@ int mcx_get_batch_results(mcx_ctx* ctx, double* k, int64_t* counts);
    n_bins = nx * ny * (max_rings + 1) * n_grp of problem p. */
 int mcx_get_batch_tallies(mcx_ctx* ctx, int32_t p, double* flux, double* prod, int64_t n_bins);
 
-/* Pick the persistent-engine configuration (block, slots, grid, tau) with
-   the shortest measured run of the bound problem or batch by timing a sweep
-   of candidates on ctx's stream, and use it from then on.  A non-NULL
+/* Pick the persistent-engine configuration (block, slots, grid, tau, then
+   the collide-list ordering) with the shortest measured run of the bound
+   problem or batch by timing a sweep of candidates on ctx's stream, and use
+   it from then on.  A non-NULL
    cache_path names a text file of earlier results keyed by the workload's
    shape and the device: a hit skips the sweep, a miss appends the winner.
    Results do not depend on the configuration.  Overwrites the results of

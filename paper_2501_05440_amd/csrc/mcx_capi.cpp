@@ -275,6 +275,11 @@ int mcx_create(mcx_ctx** out, const mcx_options* opt) {
     c->pcfg.slots = c->opt.p_slots ? c->opt.p_slots : 512;
     c->pcfg.grid = c->opt.p_grid ? c->opt.p_grid : 2 * dev_cus;
     c->pcfg.tau = c->opt.p_tau > 0.0 ? c->opt.p_tau : 0.75;
+    c->pcfg.sort = c->opt.p_sort;
+    if (c->opt.p_sort != 0 && c->opt.p_sort != 1) {
+      delete c;
+      return MCX_EINVAL;
+    }
     if (!persistent_config_valid(c->pcfg.block, c->pcfg.slots) || c->pcfg.tau > 1.0 ||
         c->opt.p_grid < 0 || c->opt.p_grid > (1 << 20)) {
       delete c;
@@ -1848,9 +1853,10 @@ static bool tune_lookup(const char* path, const std::string& key, mcx_tune* t) {
     const char* bar = std::strstr(line, " | ");
     if (!bar || std::string(line, bar - line) != key) continue;
     mcx_tune v{};
-    if (std::sscanf(bar + 3, "block=%d slots=%d grid=%d tau=%lf ms=%lf", &v.block, &v.slots,
-                    &v.grid, &v.tau, &v.ms) == 5 &&
-        persistent_config_valid(v.block, v.slots) && v.grid >= 1 && v.tau > 0.0 && v.tau <= 1.0) {
+    if (std::sscanf(bar + 3, "block=%d slots=%d grid=%d tau=%lf sort=%d ms=%lf", &v.block,
+                    &v.slots, &v.grid, &v.tau, &v.sort, &v.ms) == 6 &&
+        persistent_config_valid(v.block, v.slots) && v.grid >= 1 && v.tau > 0.0 && v.tau <= 1.0 &&
+        (v.sort == 0 || v.sort == 1)) {
       *t = v;  // the last matching line wins
       hit = true;
     }
@@ -1884,7 +1890,7 @@ int mcx_autotune(mcx_ctx* c, const char* cache_path, mcx_tune* best) {
   const std::string key = tune_key(c);
   mcx_tune t{};
   if (cache_path && tune_lookup(cache_path, key, &t)) {
-    c->pcfg = PersistentCfg{t.block, t.slots, t.grid, t.tau};
+    c->pcfg = PersistentCfg{t.block, t.slots, t.grid, t.tau, t.sort};
     drop_graph(c);
     if (best) *best = t;
     return MCX_OK;
@@ -1903,7 +1909,7 @@ int mcx_autotune(mcx_ctx* c, const char* cache_path, mcx_tune* best) {
     for (int sl : slots)
       for (int m : per_cu)
         for (double tau : taus) {
-          PersistentCfg cfg{b, sl, m * cus, tau};
+          PersistentCfg cfg{b, sl, m * cus, tau, 0};
           double ms = 0;
           const int rc = tune_trial(c, cfg, &ms);
           if (rc != MCX_OK) {
@@ -1916,14 +1922,30 @@ int mcx_autotune(mcx_ctx* c, const char* cache_path, mcx_tune* best) {
             win = cfg;
           }
         }
+  // then the collide-list ordering at the winning launch shape
+  {
+    PersistentCfg cfg = win;
+    cfg.sort = 1;
+    double ms = 0;
+    const int rc = tune_trial(c, cfg, &ms);
+    if (rc != MCX_OK) {
+      c->pcfg = keep;
+      drop_graph(c);
+      return rc;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      win = cfg;
+    }
+  }
   c->pcfg = win;
   drop_graph(c);
-  t = mcx_tune{win.block, win.slots, win.grid, win.tau, best_ms};
+  t = mcx_tune{win.block, win.slots, win.grid, win.tau, best_ms, win.sort};
   if (cache_path) {
     FILE* f = std::fopen(cache_path, "a");
     if (f) {
-      std::fprintf(f, "%s | block=%d slots=%d grid=%d tau=%.4f ms=%.4f\n", key.c_str(), t.block,
-                   t.slots, t.grid, t.tau, t.ms);
+      std::fprintf(f, "%s | block=%d slots=%d grid=%d tau=%.4f sort=%d ms=%.4f\n", key.c_str(),
+                   t.block, t.slots, t.grid, t.tau, t.sort, t.ms);
       std::fclose(f);
     }
   }

@@ -60,6 +60,7 @@ struct PersistentCfg {
   int slots = 512;
   int grid = 512;
   double tau = 0.75;
+  int sort = 0;  // 1: collisions in fissile material first in the collide list
 };
 bool persistent_config_valid(int block, int slots);
 size_t persistent_lds_bytes(int prec, int block, int slots);

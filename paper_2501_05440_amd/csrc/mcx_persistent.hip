@@ -25,7 +25,10 @@
 
 namespace mcx {
 
-enum : uint8_t { SL_FREE = 0, SL_LIVE = 1, SL_COL = 2 };
+// slot states; a collision in fissile material is SL_COLF when the collide
+// list is sorted (fissile collisions first, so the fission-site loop runs in
+// the same waves), else SL_COL
+enum : uint8_t { SL_FREE = 0, SL_LIVE = 1, SL_COL = 2, SL_COLF = 3 };
 
 template <class R, int S>
 struct SlotMem {
@@ -74,23 +77,30 @@ __device__ __forceinline__ void slot_store(SlotMem<R, S>& M, int s, const Part<R
   M.ctr[s] = p.ctr;
 }
 
-// List (in slot order) of the slots whose state equals `want`; each thread
-// owns S / PB consecutive slots.  Returns the count (also in M.n_list).
+// List (in slot order) of the slots whose state is in the bit set `want`
+// (bit k = state k), written from M.list[base]; each thread owns S / PB
+// consecutive slots.  Returns the count.
 template <class R, int PB, int S>
-__device__ __forceinline__ uint32_t build_list(SlotMem<R, S>& M, uint8_t want) {
+__device__ __forceinline__ uint32_t build_list_set(SlotMem<R, S>& M, uint32_t want,
+                                                   uint32_t base) {
   constexpr int K = S / PB;
   const int s0 = threadIdx.x * K;
   uint32_t n = 0;
 #pragma unroll
-  for (int e = 0; e < K; ++e) n += M.state[s0 + e] == want ? 1u : 0u;
+  for (int e = 0; e < K; ++e) n += (want >> M.state[s0 + e]) & 1u;
   uint32_t total;
-  uint32_t off = block_excl_scan(n, M.scan, &total);
+  uint32_t off = base + block_excl_scan(n, M.scan, &total);
 #pragma unroll
   for (int e = 0; e < K; ++e)
-    if (M.state[s0 + e] == want) M.list[off++] = (uint16_t)(s0 + e);
-  if (threadIdx.x == 0) M.n_list = total;
+    if ((want >> M.state[s0 + e]) & 1u) M.list[off++] = (uint16_t)(s0 + e);
+  if (threadIdx.x == 0) M.n_list = base + total;
   __syncthreads();
   return total;
+}
+
+template <class R, int PB, int S>
+__device__ __forceinline__ uint32_t build_list(SlotMem<R, S>& M, uint8_t want) {
+  return build_list_set<R, PB, S>(M, 1u << want, 0);
 }
 
 // The problem of global history index h (binary search of the batch).
@@ -137,7 +147,7 @@ __global__ void __launch_bounds__(PB) k_persistent(Tables T, uint32_t gen, Accum
                                                    uint32_t* work, uint32_t tau,
                                                    const double* sx, const double* sy,
                                                    const int32_t* sg,
-                                                   const uint32_t* prev_status) {
+                                                   const uint32_t* prev_status, int sort) {
   extern __shared__ unsigned char lds_raw[];
   SlotMem<R, S>& M = *reinterpret_cast<SlotMem<R, S>*>(lds_raw);
   const ProbDesc* P = T.probs;
@@ -241,15 +251,29 @@ __global__ void __launch_bounds__(PB) k_persistent(Tables T, uint32_t gen, Accum
       if (ev != EV_COLLIDE) M.ncross[s] += 1;
       if (refl) M.nrefl[s] += 1;
       slot_store(M, s, p);
-      if (ev == EV_LEAK)
+      if (ev == EV_LEAK) {
         slot_death(M, s, p, FATE_LEAKED, 0, A, H);
-      else
-        M.state[s] = ev == EV_COLLIDE ? SL_COL : SL_LIVE;
+      } else if (ev == EV_COLLIDE) {
+        uint8_t st = SL_COL;
+        if (sort) {
+          const int m = L.mats[L.pin_map[p.j * L.nx + p.i] * L.mr1 + p.r];
+          if (T.fissile[m]) st = SL_COLF;
+        }
+        M.state[s] = st;
+      } else {
+        M.state[s] = SL_LIVE;
+      }
     }
     __syncthreads();
 
     // ---------------- collide ----------------
-    const uint32_t n_col = build_list<R, PB, S>(M, SL_COL);
+    uint32_t n_col;
+    if (sort) {
+      const uint32_t nf = build_list_set<R, PB, S>(M, 1u << SL_COLF, 0);
+      n_col = nf + build_list_set<R, PB, S>(M, 1u << SL_COL, nf);
+    } else {
+      n_col = build_list_set<R, PB, S>(M, (1u << SL_COL) | (1u << SL_COLF), 0);
+    }
     for (uint32_t t0 = 0; t0 < n_col; t0 += PB) {
       const uint32_t t = t0 + threadIdx.x;
       const bool valid = t < n_col;
@@ -414,10 +438,10 @@ template <class R, int PB, int S>
 static hipError_t launch_p(unsigned grid, const Tables& T, uint32_t gen, const Accum& A,
                            const HistOut& H, uint32_t* work, uint32_t tau, const double* sx,
                            const double* sy, const int32_t* sg, const uint32_t* prev_status,
-                           hipStream_t s) {
+                           int sort, hipStream_t s) {
   const size_t lds = sizeof(SlotMem<R, S>);
   hipLaunchKernelGGL((k_persistent<R, PB, S>), dim3(grid), dim3(PB), lds, s, T, gen, A, H, work,
-                     tau, sx, sy, sg, prev_status);
+                     tau, sx, sy, sg, prev_status, sort);
   return hipGetLastError();
 }
 
@@ -432,7 +456,7 @@ hipError_t launch_persistent(int prec, const PersistentCfg& cfg, const Tables& T
   const uint32_t tau = (uint32_t)std::max(1, (int)(cfg.tau * (double)S));
 #define MCX_P(RT, PBV, SV)                                                                   \
   if (cfg.block == PBV && S == SV)                                                           \
-    return launch_p<RT, PBV, SV>(grid, T, gen, A, H, work, tau, sx, sy, sg, prev_status, s);
+    return launch_p<RT, PBV, SV>(grid, T, gen, A, H, work, tau, sx, sy, sg, prev_status, cfg.sort, s);
   if (prec == 0) {
     MCX_P(double, 128, 256)
     MCX_P(double, 128, 512)

@@ -45,8 +45,8 @@ class Options(C.Structure):
                 ("lookahead", C.c_int32), ("max_events", C.c_int64),
                 ("record_histories", C.c_int32), ("time_kernels", C.c_int32),
                 ("engine", C.c_int32), ("p_block", C.c_int32), ("p_slots", C.c_int32),
-                ("p_grid", C.c_int32), ("p_tau", C.c_double), ("flights", C.c_int32),
-                ("event_log", C.c_int32)]
+                ("p_grid", C.c_int32), ("p_tau", C.c_double), ("p_sort", C.c_int32),
+                ("flights", C.c_int32), ("event_log", C.c_int32)]
 
 
 class Geometry(C.Structure):
@@ -90,7 +90,7 @@ class Problem(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("block", C.c_int32), ("slots", C.c_int32), ("grid", C.c_int32),
-                ("tau", C.c_double), ("ms", C.c_double)]
+                ("tau", C.c_double), ("ms", C.c_double), ("sort", C.c_int32)]
 
 
 EVENT_DTYPE = np.dtype([
@@ -229,6 +229,7 @@ def _options(o, precision, device, stream, engine, persistent):
     o.p_slots = p.get("slots", 0)
     o.p_grid = p.get("grid", 0)
     o.p_tau = p.get("tau", 0.0)
+    o.p_sort = p.get("sort", 0)
 
 
 class Context:

@@ -66,9 +66,9 @@ def test_persistent_engine_matches_oracle_lattice(oracle):
 
 
 @pytest.mark.parametrize("cfg", [dict(block=128, slots=256, grid=1, tau=1.0),
-                                 dict(block=128, slots=512, grid=37, tau=0.5),
+                                 dict(block=128, slots=512, grid=37, tau=0.5, sort=1),
                                  dict(block=256, slots=256, grid=256, tau=0.9),
-                                 dict(block=256, slots=512, grid=1024, tau=0.25)])
+                                 dict(block=256, slots=512, grid=1024, tau=0.25, sort=1)])
 def test_persistent_configuration_does_not_change_results(cfg):
     banner(f"persistent configuration {cfg}")
     prob = P.lattice_17x17(n_per_gen=5000, n_gen=3, n_inactive=1)
@@ -156,6 +156,21 @@ def test_batch_equals_single_runs_and_oracle(oracle):
         b.close()
 
 
+def test_batch_sorted_collide_lists_equal_unsorted():
+    banner("batch with sorted collide lists")
+    probs = small_batch(n=12, cap=6000)
+    out = []
+    for sort in (0, 1):
+        b = mcx.Batch(probs, persistent=dict(sort=sort))
+        try:
+            b.run()
+            out.append(b.results())
+        finally:
+            b.close()
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][0], out[1][0])
+
+
 def test_batch_fp32_mixed_equals_single_fp32_runs():
     banner("batch FP32-mixed vs single FP32-mixed runs")
     probs = small_batch(n=6, cap=8000)
@@ -207,8 +222,10 @@ def test_autotune_picks_a_valid_configuration_and_caches(tmp_path):
         t = b.autotune(cache)
         assert t["block"] in (128, 256) and t["slots"] in (256, 512)
         assert t["grid"] >= 1 and 0 < t["tau"] <= 1 and t["ms"] > 0
+        assert t["sort"] in (0, 1)
         t2 = b.autotune(cache)  # cache hit
-        assert (t2["block"], t2["slots"], t2["grid"]) == (t["block"], t["slots"], t["grid"])
+        assert (t2["block"], t2["slots"], t2["grid"], t2["sort"]) == (t["block"], t["slots"],
+                                                                      t["grid"], t["sort"])
         b.run()
         k1, c1 = b.results()
         assert np.array_equal(c0, c1)
