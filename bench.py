@@ -140,6 +140,18 @@ def persistent_comparison(P, mcx, prob, event_hps, tune_cache):
             "tuned": {k: tune[k] for k in ("block", "slots", "grid", "tau", "sort")}}
 
 
+def monolithic_comparison(P, mcx, prob, event_hps):
+    """The paper's monolithic form for comparison: every history of a
+    generation run by one history-based kernel (the tail kernel from the
+    first flight)."""
+    ctx = mcx.Context(prob, tail_threshold=1 << 30)
+    sec = timed_runs(ctx, 1)
+    ctx.close()
+    n = prob["run"]["n_per_gen"] * prob["run"]["n_gen"]
+    return {"histories_per_s": round(n / sec, 1), "ms_per_step": round(sec * 1e3, 2),
+            "event_engine_speedup": round(event_hps / (n / sec), 3)}
+
+
 def batch_comparison(P, mcx, tune_cache, steps):
     """512 fixed-source pin cells in one persistent launch (autotuned) against
     the same problems run one at a time with the FP64 event engine."""
@@ -323,6 +335,11 @@ def main():
     if not a.no_persistent:
         print("[bench] lattice on the persistent engine", file=sys.stderr, flush=True)
         pers = persistent_comparison(P, mcx, prob, value, tune_cache)
+    mono = None
+    if not a.no_persistent:
+        print("[bench] lattice as one history-based kernel per generation", file=sys.stderr,
+              flush=True)
+        mono = monolithic_comparison(P, mcx, prob, value)
     batch = None
     if not a.no_batch:
         print("[bench] 512-problem batch", file=sys.stderr, flush=True)
@@ -363,6 +380,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "persistent_engine": pers,
+        "monolithic_history_kernel": mono,
         "fp32_mixed": extra,
         "batch": batch,
         "continuous_energy": ce,
