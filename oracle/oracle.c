@@ -589,6 +589,10 @@ static void run_history(ctx_t* C, int64_t id, chunk_t* ch) {
   }
   double u = dir[0], v = dir[1], w = dir[2];
   (void)w; /* z-invariant geometry: w only fixes the in-plane speed sqrt(1-w^2) */
+  const orc_time* tm = p->time;
+  const int NT = tm ? tm->n_tbins : 1;
+  const double t_max = tm ? tm->t_edges[NT] : 0.0;
+  double t = 0.0;  /* time since the source pulse */
 
   int32_t n_seg = 0, n_col = 0, n_cross = 0, n_refl = 0, n_sites = 0;
   int fate = ORC_ALIVE;
@@ -630,16 +634,51 @@ static void run_history(ctx_t* C, int64_t id, chunk_t* ch) {
     n_seg += 1;
     int collide = d_col < d_bnd;
     double d = collide ? d_col : d_bnd;
+    /* time-dependent: the flight stops at the end of the time grid if that
+       comes first (census) */
+    int census = 0;
+    double vg = 0.0;
+    if (tm) {
+      vg = tm->speed[g];
+      double d_cen = (t_max - t) * vg;
+      if (d_cen < d) {
+        d = d_cen;
+        census = 1;
+        collide = 0;
+      }
+    }
     x = x + d * u;
     y = y + d * v;
 
-    /* track-length tallies: flux and nu-fission production per bin */
+    /* track-length tallies: flux and nu-fission production per bin (per
+       time bin by the time the flight spends in it) */
     int64_t bin = ((int64_t)c * C->mr1 + r) * G + g;
-    nadd(&ch->flux[bin], d);
-    nadd(&ch->prod[bin], d * nusf);
+    if (tm) {
+      double t1 = census ? t_max : t + d / vg;
+      if (t1 > t_max) t1 = t_max;
+      for (int b = orc_ce_interval(tm->t_edges, NT + 1, t); b < NT; ++b) {
+        double lo = tm->t_edges[b] > t ? tm->t_edges[b] : t;
+        double hi = tm->t_edges[b + 1] < t1 ? tm->t_edges[b + 1] : t1;
+        if (hi > lo) {
+          double ell = (hi - lo) * vg;
+          nadd(&ch->flux[bin * NT + b], ell);
+          nadd(&ch->prod[bin * NT + b], ell * nusf);
+        }
+        if (tm->t_edges[b + 1] >= t1) break;
+      }
+      t = t1;
+    } else {
+      nadd(&ch->flux[bin], d);
+      nadd(&ch->prod[bin], d * nusf);
+    }
     nadd(&ch->k[1], d * nusf);
     tl_sum += d;
     const int r_flight = r;
+    if (census) {
+      log_flight(C, id, n_seg - 1, x, y, d, 0.0, c, r_flight, g, 4);
+      fate = ORC_CENSUS;
+      break;
+    }
 
     if (collide) {
       log_flight(C, id, n_seg - 1, x, y, d, 0.0, c, r_flight, g, 1);
@@ -731,8 +770,10 @@ static void run_history(ctx_t* C, int64_t id, chunk_t* ch) {
   if (fate == ORC_LEAKED) ch->counts[ORC_C_LEAK] += 1;
   if (fate == ORC_ABSORBED) ch->counts[ORC_C_ABS] += 1;
   if (fate == ORC_KILLED) ch->counts[ORC_C_KILLED] += 1;
+  if (fate == ORC_CENSUS) ch->counts[ORC_C_CENSUS] += 1;
   if (C->records) {
     orc_record* rec = &C->records[id];
+    rec->t_final = t;
     rec->n_seg = n_seg;
     rec->n_col = n_col;
     rec->n_cross = n_cross;
@@ -981,7 +1022,8 @@ static void chunk_reset(chunk_t* ch, int64_t n_bins) {
 }
 
 int64_t orc_n_bins(const orc_problem* p) {
-  return (int64_t)p->nx * p->ny * (p->max_rings + 1) * (p->ce ? p->ce->n_ebins : p->n_grp);
+  return (int64_t)p->nx * p->ny * (p->max_rings + 1) * (p->ce ? p->ce->n_ebins : p->n_grp) *
+         (p->time ? p->time->n_tbins : 1);
 }
 
 static int fail(orc_output* out, int code, const char* msg) {
@@ -1010,6 +1052,17 @@ static int validate(const orc_problem* p, orc_output* out) {
       if (!(rad > prev) || !(rad < 0.5 * p->pitch)) return fail(out, ORC_EINVAL, "ring radius");
       prev = rad;
     }
+  }
+  if (p->time) {
+    const orc_time* tm = p->time;
+    if (p->ce || !p->fixed_source || tm->n_tbins < 1 || !(tm->t_edges[0] == 0.0))
+      return fail(out, ORC_EINVAL, "time-dependent mode: multigroup fixed source, edges from 0");
+    for (int k = 0; k < tm->n_tbins; ++k)
+      if (!(tm->t_edges[k] < tm->t_edges[k + 1]) || !isfinite(tm->t_edges[k + 1]))
+        return fail(out, ORC_EINVAL, "time edges must increase");
+    for (int g = 0; g < p->n_grp; ++g)
+      if (!(tm->speed[g] > 0.0) || !isfinite(tm->speed[g]))
+        return fail(out, ORC_EINVAL, "group speeds must be positive");
   }
   if (p->ce) {
     const orc_ce* ce = p->ce;

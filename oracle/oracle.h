@@ -33,7 +33,8 @@ enum {
 
 enum { ORC_VACUUM = 0, ORC_REFLECT = 1 };
 enum { ORC_TAG_SRC = 1, ORC_TAG_TRANSPORT = 2, ORC_TAG_RESAMPLE = 3 };
-enum { ORC_ALIVE = 0, ORC_ABSORBED = 1, ORC_LEAKED = 2, ORC_KILLED = 3, ORC_CUTOFF = 4 };
+enum { ORC_ALIVE = 0, ORC_ABSORBED = 1, ORC_LEAKED = 2, ORC_KILLED = 3, ORC_CUTOFF = 4,
+       ORC_CENSUS = 5 };
 
 /* per-generation counters (gen_counts[g * ORC_NCOUNT + k]) */
 enum {
@@ -47,8 +48,19 @@ enum {
   ORC_C_SITES = 7,   /* fission sites banked (M) */
   ORC_C_SCAT = 8,    /* scatters */
   ORC_C_CUTOFF = 9,  /* histories ended below the energy cutoff (continuous energy) */
-  ORC_NCOUNT = 10
+  ORC_C_CENSUS = 10, /* histories that reached the end of the time grid (time-dependent) */
+  ORC_NCOUNT = 11
 };
+
+/* Time-dependent fixed source (Sec. 1: MC/DC's time-dependent mode): every
+   history starts at t = 0, a flight of length d in group g lasts d / v_g,
+   the flux is tallied per time bin by the time the flight spends in it, and
+   a history still flying at the last edge stops there (census). */
+typedef struct {
+  int32_t n_tbins;
+  const double* t_edges;         /* [n_tbins + 1] increasing, t_edges[0] = 0, s */
+  const double* speed;           /* [n_grp] group speeds, cm/s */
+} orc_time;
 
 /* Continuous-energy data (Sec. 1 lists continuous-energy physics among the
    method's capabilities; Sec. 4 runs a continuous-energy pin cell).
@@ -107,6 +119,8 @@ typedef struct {
      (n_mat still counts the materials; n_grp, sig_t, sig_s, nu_sig_f and
      chi are unused); NULL = multigroup */
   const orc_ce* ce;
+  /* time-dependent fixed source (multigroup, fixed_source = 1), or NULL */
+  const orc_time* time;
 } orc_problem;
 
 typedef struct {
@@ -117,6 +131,7 @@ typedef struct {
   double kcol_sum;               /* sum of nu_sig_f / sig_t over collisions */
   double x_final, y_final;
   double e_final;                /* final energy (continuous energy), else 0 */
+  double t_final;                /* final time (time-dependent), else 0 */
 } orc_record;
 
 /* One flight of a history (event log): where it ended, its length, and the
@@ -126,7 +141,7 @@ typedef struct {
   double d;                      /* flight length */
   double e;                      /* energy (continuous energy), else 0 */
   int32_t cell, region, group;   /* lattice cell j * nx + i, ring region, group or energy bin */
-  int32_t type;                  /* 1 collision, 2 surface crossing, 3 leak */
+  int32_t type;                  /* 1 collision, 2 surface crossing, 3 leak, 4 census */
 } orc_event;
 
 typedef struct {
@@ -151,7 +166,8 @@ typedef struct {
 
 /* Tally bins: ((cell * (max_rings + 1)) + region) * n_grp + group,
    cell = j * nx + i (continuous energy: n_ebins energy bins in place of the
-   groups; the production tally is then not kept and reads zero). */
+   groups; the production tally is then not kept and reads zero;
+   time-dependent: that index times n_tbins plus the time bin). */
 int64_t orc_n_bins(const orc_problem* p);
 
 int orc_run(const orc_problem* p, orc_output* out);

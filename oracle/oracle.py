@@ -17,8 +17,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "oracle.c")
 
-COUNT_NAMES = ["seg", "col", "cross", "refl", "leak", "abs", "killed", "sites", "scat", "cutoff"]
-FATE = {"alive": 0, "absorbed": 1, "leaked": 2, "killed": 3, "cutoff": 4}
+COUNT_NAMES = ["seg", "col", "cross", "refl", "leak", "abs", "killed", "sites", "scat", "cutoff",
+               "census"]
+FATE = {"alive": 0, "absorbed": 1, "leaked": 2, "killed": 3, "cutoff": 4, "census": 5}
 TAG_SRC, TAG_TRANSPORT, TAG_RESAMPLE = 1, 2, 3
 
 
@@ -52,7 +53,12 @@ class _Problem(C.Structure):
         ("max_events", C.c_int64), ("n_threads", C.c_int32),
         ("ext_state", C.c_void_p),
         ("ce", C.c_void_p),
+        ("time", C.c_void_p),
     ]
+
+
+class _Time(C.Structure):
+    _fields_ = [("n_tbins", C.c_int32), ("t_edges", C.c_void_p), ("speed", C.c_void_p)]
 
 
 class _CE(C.Structure):
@@ -71,7 +77,7 @@ RECORD_DTYPE = np.dtype([
     ("n_seg", "<i4"), ("n_col", "<i4"), ("n_cross", "<i4"), ("n_refl", "<i4"),
     ("fate", "<i4"), ("n_sites", "<i4"), ("g_final", "<i4"), ("ctr_final", "<u4"),
     ("tl_sum", "<f8"), ("kcol_sum", "<f8"), ("x_final", "<f8"), ("y_final", "<f8"),
-    ("e_final", "<f8"),
+    ("e_final", "<f8"), ("t_final", "<f8"),
 ])
 
 
@@ -79,7 +85,8 @@ class _Record(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("n_seg", "n_col", "n_cross", "n_refl", "fate",
                                           "n_sites", "g_final")] + [
         ("ctr_final", C.c_uint32), ("tl_sum", C.c_double), ("kcol_sum", C.c_double),
-        ("x_final", C.c_double), ("y_final", C.c_double), ("e_final", C.c_double)]
+        ("x_final", C.c_double), ("y_final", C.c_double), ("e_final", C.c_double),
+        ("t_final", C.c_double)]
 
 
 EVENT_DTYPE = np.dtype([
@@ -102,7 +109,7 @@ class _Output(C.Structure):
     ]
 
 
-assert C.sizeof(_Record) == RECORD_DTYPE.itemsize == 72
+assert C.sizeof(_Record) == RECORD_DTYPE.itemsize == 80
 
 _lib = None
 
@@ -345,6 +352,15 @@ def run(problem, n_threads=None, records=False, per_gen_tallies=False, bank_cap=
     P.n_threads = n_threads if n_threads else (os.cpu_count() or 1)
     P.ext_state = _ptr(ext)
     P.ce = None if ce is None else C.addressof(ce_s)
+    tm = problem.get("time")
+    if tm is not None:
+        t_s = _Time()
+        edges = arr(tm["t_edges"], np.float64)
+        t_s.n_tbins = len(edges) - 1
+        t_s.t_edges = edges.ctypes.data
+        t_s.speed = arr(tm["speed"], np.float64).ctypes.data
+        keep.append(t_s)
+        P.time = C.addressof(t_s)
 
     L = lib()
     nb = L.orc_n_bins(C.byref(P))

@@ -342,6 +342,37 @@ def ce_homogeneous(ce, n_per_gen, n_gen, n_inactive, seed, fixed_source=False, p
                                ent=(4, 4)))
 
 
+# ---------------------------------------------------------------------------
+# time-dependent fixed source (input tables only)
+# ---------------------------------------------------------------------------
+
+# speeds of the 7 groups, fast to thermal (cm/s): log-spaced from about
+# 2 MeV neutrons (2e9 cm/s) to thermal ones (2.2e5 cm/s)
+GROUP_SPEEDS_7 = np.geomspace(2.0e9, 2.2e5, N_GROUPS)
+
+
+def with_time(problem, t_edges, speed=None):
+    """Copy of a fixed-source multigroup problem with a time grid: a pulse
+    at t = 0, flux tallied per time bin, census at the last edge."""
+    p = dict(problem)
+    g = problem["xs"]["sig_t"].shape[1]
+    v = GROUP_SPEEDS_7 if speed is None else np.asarray(speed, float)
+    assert len(v) == g
+    p["time"] = dict(t_edges=np.asarray(t_edges, float), speed=v)
+    p["run"] = dict(problem["run"], fixed_source=True)
+    return p
+
+
+def pulsed_lattice(n_per_gen=1_000_000, n_gen=10, seed=6):
+    """The 17x17 lattice driven by a source pulse at t = 0 (fission as
+    capture): flux per pin, group and time bin (0, then 12 log bins from
+    1e-9 s to 1e-3 s), census at 1 ms."""
+    lat = lattice_17x17(n_per_gen=n_per_gen, n_gen=n_gen, n_inactive=0, seed=seed)
+    lat = with_run(lat, fixed_source=True)
+    edges = np.concatenate([[0.0], np.geomspace(1e-9, 1e-3, 12)])
+    return with_time(lat, edges)
+
+
 def with_run(problem, **kw):
     """Copy of a problem with some run parameters replaced."""
     p = dict(problem)
@@ -354,13 +385,15 @@ def n_bins(problem):
     geo = problem["geometry"]
     per = (len(problem["ce"]["e_edges"]) - 1 if "ce" in problem
            else problem["xs"]["sig_t"].shape[1])
+    if "time" in problem:
+        per *= len(problem["time"]["t_edges"]) - 1
     return geo["nx"] * geo["ny"] * (geo["radii"].shape[1] + 1) * per
 
 
 def digest(problem):
     """sha256 over every array and scalar of a problem (records the inputs)."""
     h = hashlib.sha256()
-    for part in ("geometry", "xs", "ce", "run"):
+    for part in ("geometry", "xs", "ce", "time", "run"):
         if part not in problem:
             continue
         d = problem[part]

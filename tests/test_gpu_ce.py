@@ -121,7 +121,7 @@ def test_ce_fp32_mixed_against_fp64():
         assert np.array_equal(g32[k], g32b[k]), k
     assert np.array_equal(g32["records"], g32b["records"])
     n = prob["run"]["n_per_gen"]
-    seg, col, cross, refl, leak, ab, killed, sites, scat, cut = g32["gen_counts"].T
+    seg, col, cross, refl, leak, ab, killed, sites, scat, cut, *_ = g32["gen_counts"].T
     assert np.all(ab + leak + killed + cut == n) and np.all(killed == 0)
     assert np.all(col == scat + ab) and np.all(seg == col + cross)
     g64 = mcx.run(prob)
@@ -159,7 +159,7 @@ def test_ce_bench_configuration_invariants():
     prob = P.ce_pin_cell()
     g = mcx.run(prob)
     n = prob["run"]["n_per_gen"]
-    seg, col, cross, refl, leak, ab, killed, sites, scat, cut = g["gen_counts"].T
+    seg, col, cross, refl, leak, ab, killed, sites, scat, cut, *_ = g["gen_counts"].T
     assert np.all(ab + leak + killed + cut == n)
     assert np.all(killed == 0) and np.all(leak == 0)
     assert np.all(col == scat + ab)

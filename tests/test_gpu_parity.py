@@ -245,7 +245,7 @@ def test_full_size_invariants_in_bench_configuration():
     prob = P.lattice_17x17()
     g = mcx.run(prob)
     n = prob["run"]["n_per_gen"]
-    seg, col, cross, refl, leak, ab, killed, sites, scat, cutoff = g["gen_counts"].T
+    seg, col, cross, refl, leak, ab, killed, sites, scat, cutoff, *_ = g["gen_counts"].T
     assert np.all(ab + leak + killed == n)
     assert np.all(killed == 0)
     assert np.all(col == scat + ab)

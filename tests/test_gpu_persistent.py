@@ -247,7 +247,7 @@ def test_full_batch_512_problems():
         k, cnt = b.results()
     finally:
         b.close()
-    seg, col, cross, refl, leak, ab, killed, sites, scat, cutoff = cnt.T
+    seg, col, cross, refl, leak, ab, killed, sites, scat, cutoff, *_ = cnt.T
     assert np.all(ab + leak + killed == n)
     assert np.all(killed == 0) and np.all(leak == 0)  # reflective cells
     assert np.all(col == scat + ab)

@@ -173,7 +173,7 @@ def test_ce_pin_cell_balance_and_bank(oracle):
     prob = P.ce_pin_cell(n_per_gen=3000, n_gen=4, n_inactive=1)
     r = oracle.run(prob, records=True, bank_cap=10000)
     n = prob["run"]["n_per_gen"]
-    seg, col, cross, refl, leak, ab, killed, sites, scat, cut = r["gen_counts"].T
+    seg, col, cross, refl, leak, ab, killed, sites, scat, cut, *_ = r["gen_counts"].T
     assert np.all(ab + leak + killed + cut == n)
     assert np.all(col == scat + ab)
     assert np.all(seg == col + cross)

@@ -166,7 +166,7 @@ def test_balance_and_records(oracle):
     r = oracle.run(prob, records=True, per_gen_tallies=True)
     n = prob["run"]["n_per_gen"]
     c = r["gen_counts"]
-    seg, col, cross, refl, leak, ab, killed, sites, scat, cutoff = c.T
+    seg, col, cross, refl, leak, ab, killed, sites, scat, cutoff, *_ = c.T
     assert np.all(ab + leak + killed == n)
     assert np.all(killed == 0)
     assert np.all(col == scat + ab)
