@@ -55,7 +55,13 @@ enum mcx_status {
 enum { MCX_FP64 = 0, MCX_FP32_MIXED = 1 };
 enum { MCX_ENGINE_EVENT = 0, MCX_ENGINE_PERSISTENT = 1 };
 enum { MCX_VACUUM = 0, MCX_REFLECT = 1 };
-enum { MCX_FATE_ABSORBED = 1, MCX_FATE_LEAKED = 2, MCX_FATE_KILLED = 3, MCX_FATE_CUTOFF = 4 };
+enum {
+  MCX_FATE_ABSORBED = 1,
+  MCX_FATE_LEAKED = 2,
+  MCX_FATE_KILLED = 3,
+  MCX_FATE_CUTOFF = 4,
+  MCX_FATE_CENSUS = 5
+};
 
 /* Per-generation counters, in this order (mcx_get_generation_stats). */
 enum {
@@ -69,7 +75,8 @@ enum {
   MCX_CNT_SITES = 7,  /* fission sites banked */
   MCX_CNT_SCAT = 8,   /* scatters */
   MCX_CNT_CUTOFF = 9, /* histories ended below the energy cutoff (continuous energy) */
-  MCX_N_CNT = 10
+  MCX_CNT_CENSUS = 10, /* histories that reached the end of the time grid (time-dependent) */
+  MCX_N_CNT = 11
 };
 
 typedef struct {
@@ -156,12 +163,14 @@ typedef struct {
   double kcol_sum;          /* sum of nu_sig_f / sig_t over collisions */
   double x_final, y_final;
   double e_final;           /* final energy (continuous energy), else 0 */
+  double t_final;           /* final time (time-dependent mode), else 0 */
 } mcx_record;
 
 /* One logged flight (event_log > 0): position after it, its length, the
    energy it flew at (continuous energy, else 0), the lattice cell
    (j * nx + i), ring region and group or energy bin it flew in, and how it
-   ended: 1 collision, 2 surface crossing, 3 leak.  Unused entries are 0. */
+   ended: 1 collision, 2 surface crossing, 3 leak, 4 census.  Unused entries
+   are 0. */
 typedef struct {
   double x, y, d, e;
   int32_t cell, region, group, type;
@@ -259,6 +268,18 @@ typedef struct {
 
 /* Copy and validate continuous-energy data; replaces multigroup data. */
 int mcx_load_ce_xs(mcx_ctx* ctx, const mcx_ce_data* ce);
+
+/* Time-dependent fixed source (paper Sec. 1: MC/DC's time-dependent mode):
+   every history starts at t = 0 from the fixed source (mcx_source with
+   fixed_source = 1, fission treated as capture); a flight of length d in
+   group g lasts d / speed[g]; the flux tally gains n_tbins time bins (bin
+   index * n_tbins + time bin), each flight adding the length it flies
+   inside each bin; a history still flying at t_edges[n_tbins] stops there
+   (MCX_FATE_CENSUS).  t_edges[0] = 0, strictly increasing; speed in cm/s,
+   one per group (n_grp must match the loaded data at bind time).  Event
+   engine, multigroup.  n_tbins = 0 switches the mode off. */
+int mcx_load_time_grid(mcx_ctx* ctx, int32_t n_tbins, const double* t_edges,
+                       const double* speed, int32_t n_grp);
 
 int mcx_seed_source(mcx_ctx* ctx, const mcx_source* src);
 

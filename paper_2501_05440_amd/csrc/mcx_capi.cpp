@@ -155,6 +155,9 @@ struct mcx_ctx {
   std::vector<int> last_s, last_chi, fissile;
   mcx_source src{};
 
+  // time-dependent fixed source (empty t_edges = off)
+  std::vector<double> t_edges, t_speed;
+
   // continuous-energy data (ce = true replaces the multigroup tables)
   bool ce = false;
   int ce_n_nuc = 0, ce_n_pts = 0, ce_max_nuc = 0, ce_n_ebins = 0;
@@ -583,6 +586,29 @@ int mcx_load_ce_xs(mcx_ctx* c, const mcx_ce_data* d) {
   return MCX_OK;
 }
 
+int mcx_load_time_grid(mcx_ctx* c, int32_t n_tbins, const double* t_edges, const double* speed,
+                       int32_t n_grp) {
+  if (!c) return MCX_EINVAL;
+  c->bound = false;
+  if (n_tbins == 0) {
+    c->t_edges.clear();
+    c->t_speed.clear();
+    return MCX_OK;
+  }
+  if (n_tbins < 0 || n_tbins > 4096 || !t_edges || !speed || n_grp < 1 || n_grp > 65535)
+    return fail(c, MCX_EINVAL, "time grid sizes");
+  if (!(t_edges[0] == 0.0)) return fail(c, MCX_EINVAL, "the time grid starts at 0");
+  for (int k = 0; k < n_tbins; ++k)
+    if (!(t_edges[k] < t_edges[k + 1]) || !std::isfinite(t_edges[k + 1]))
+      return fail(c, MCX_EINVAL, "time edges must increase");
+  for (int g = 0; g < n_grp; ++g)
+    if (!(speed[g] > 0.0) || !std::isfinite(speed[g]))
+      return fail(c, MCX_EINVAL, "group speeds must be positive");
+  c->t_edges.assign(t_edges, t_edges + n_tbins + 1);
+  c->t_speed.assign(speed, speed + n_grp);
+  return MCX_OK;
+}
+
 int mcx_seed_source(mcx_ctx* c, const mcx_source* s) {
   if (!c || !s) return MCX_EINVAL;
   if (s->n_per_gen < 1 || s->n_per_gen > (int64_t(1) << 30))
@@ -602,7 +628,8 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   const size_t N = batch ? 0 : (size_t)c->src.n_per_gen;
   const int mr1 = c->max_rings + 1;
   const size_t MG = (size_t)c->n_mat * c->G;
-  const int nb = batch ? c->batch_bins : c->nx * c->ny * mr1 * c->G;
+  const int nt = c->t_edges.empty() ? 1 : (int)c->t_edges.size() - 1;
+  const int nb = batch ? c->batch_bins : c->nx * c->ny * mr1 * c->G * nt;
   const uint64_t n_hist = batch ? c->batch_hist : (uint64_t)N;
   const bool persistent = batch || c->opt.engine == MCX_ENGINE_PERSISTENT;
   // copies of the flux accumulators, spread over workgroups by index: a
@@ -642,6 +669,10 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   T.mat_nuc = cv.take<int>(c->ce_mat_nuc.size());
   T.mat_dens = cv.take<double>(c->ce_dens.size());
   T.e_edges = cv.take<double>(c->ce_edges.size());
+  T.nt = nt;
+  T.t_edges = c->t_edges.empty() ? nullptr : cv.take<double>(c->t_edges.size());
+  T.speed = c->t_edges.empty() ? nullptr : cv.take<double>(c->t_speed.size());
+  T.t_max = c->t_edges.empty() ? 0.0 : c->t_edges.back();
   const bool fp32 = c->opt.precision == MCX_FP32_MIXED;
   const bool ce32 = ce && fp32;
   T.e_grid_f = cv.take<float>(ce32 ? c->ce_grid.size() : 0);
@@ -667,6 +698,7 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
     k.ctr = cv.take<uint32_t>(N);
     k.id = cv.take<uint32_t>(N);
     k.nseg = cv.take<uint32_t>(N);
+    k.t = c->t_edges.empty() ? nullptr : cv.take<double>(N);
     if (fp32) {
       k.w = cv.take<float>(ce ? N : 0);
       k.e = cv.take<float>(ce ? N : 0);
@@ -765,6 +797,7 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
       R.x_final = rc.take<double>(N);
       R.y_final = rc.take<double>(N);
       R.e_final = rc.take<double>(N);
+      R.t_final = rc.take<double>(N);
       R.ev_cap = c->opt.event_log;
       R.ev = c->opt.event_log > 0 ? rc.take<EvEntry>(N * (size_t)c->opt.event_log) : nullptr;
       if (pass == 0) {
@@ -816,6 +849,12 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
   if ((uintptr_t)ptr % 256) return fail(c, MCX_EINVAL, "workspace must be 256-byte aligned");
   if (c->ce && c->opt.engine != MCX_ENGINE_EVENT)
     return fail(c, MCX_EINVAL, "continuous energy runs on the event engine");
+  if (!c->t_edges.empty() && (c->batch || c->ce || !c->src.fixed_source ||
+                              c->opt.engine != MCX_ENGINE_EVENT ||
+                              (int)c->t_speed.size() != c->G))
+    return fail(c, MCX_EINVAL,
+                "the time-dependent mode runs multigroup fixed-source problems on the event engine "
+                "with one speed per group");
   if (c->ce && c->opt.precision == MCX_FP32_MIXED && c->ce_hash_f.empty())
     return fail(c, MCX_EINVAL, "the energy grid is not strictly increasing in binary32");
   // materials referenced by the geometry must exist (batches: checked per problem)
@@ -960,6 +999,10 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
   HIP_TRY(c, up(T.cum_s_f, c->cum_s_f.data(), c->cum_s_f.size() * sizeof(float)));
   HIP_TRY(c, up(T.cum_chi_f, c->cum_chi_f.data(), c->cum_chi_f.size() * sizeof(float)));
   if (c->batch) HIP_TRY(c, up(c->d.probs, pd.data(), pd.size() * sizeof(ProbDesc)));
+  if (T.t_edges) {
+    HIP_TRY(c, up(T.t_edges, c->t_edges.data(), c->t_edges.size() * sizeof(double)));
+    HIP_TRY(c, up(T.speed, c->t_speed.data(), c->t_speed.size() * sizeof(double)));
+  }
   if (c->ce) {
     HIP_TRY(c, up(T.e_grid, c->ce_grid.data(), c->ce_grid.size() * sizeof(double)));
     HIP_TRY(c, up(T.ce_xs, c->ce_xs.data(), c->ce_xs.size() * sizeof(double)));
@@ -1190,10 +1233,11 @@ static int generation_end(mcx_ctx* c, int gen) {
     double* xf = rc.take<double>(N);
     double* yf = rc.take<double>(N);
     double* ef = rc.take<double>(N);
+    double* tf = rc.take<double>(N);
     mcx_record* out = c->h_rec.data() + (size_t)gen * N;
     for (uint32_t i = 0; i < N; ++i) {
       out[i] = mcx_record{n_seg[i], n_col[i], n_cross[i], n_refl[i], fate[i], (int32_t)ns[i],
-                          g_final[i], ctr[i], tl[i], kc[i], xf[i], yf[i], ef[i]};
+                          g_final[i], ctr[i], tl[i], kc[i], xf[i], yf[i], ef[i], tf[i]};
     }
     if (c->opt.event_log > 0) {
       const size_t ne = (size_t)N * c->opt.event_log;
@@ -1366,6 +1410,8 @@ uint64_t fingerprint(const mcx_ctx* c) {
   fnv(&h, c->ce_dens.data(), c->ce_dens.size());
   fnv(&h, c->ce_mat_nuc.data(), c->ce_mat_nuc.size());
   fnv(&h, c->ce_edges.data(), c->ce_edges.size());
+  fnv(&h, c->t_edges.data(), c->t_edges.size());
+  fnv(&h, c->t_speed.data(), c->t_speed.size());
   const uint64_t src[] = {c->src.seed, (uint64_t)c->src.n_per_gen, (uint64_t)c->src.fixed_source,
                           c->src.problem_id, (uint64_t)c->src.ent_nx, (uint64_t)c->src.ent_ny};
   fnv(&h, src, 6);

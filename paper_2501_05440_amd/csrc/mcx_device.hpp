@@ -22,7 +22,14 @@
 namespace mcx {
 
 enum : int { BC_VACUUM = 0, BC_REFLECT = 1 };
-enum : int { FATE_ALIVE = 0, FATE_ABSORBED = 1, FATE_LEAKED = 2, FATE_KILLED = 3, FATE_CUTOFF = 4 };
+enum : int {
+  FATE_ALIVE = 0,
+  FATE_ABSORBED = 1,
+  FATE_LEAKED = 2,
+  FATE_KILLED = 3,
+  FATE_CUTOFF = 4,
+  FATE_CENSUS = 5
+};
 enum : int {
   CNT_SEG = 0,
   CNT_COL = 1,
@@ -34,11 +41,12 @@ enum : int {
   CNT_SITES = 7,
   CNT_SCAT = 8,
   CNT_CUTOFF = 9,      // histories ended below the energy cutoff (continuous energy)
-  N_CNT = 10,          // counters reported per generation
-  CNT_ADV_ITEMS = 10,  // lanes processed by advance kernels
-  CNT_COL_ITEMS = 11,  // lanes processed by collide kernels
-  CNT_ADV_SEGS = 12,   // flights made inside advance kernels
-  N_CNT_ALL = 13
+  CNT_CENSUS = 10,     // histories that reached the end of the time grid
+  N_CNT = 11,          // counters reported per generation
+  CNT_ADV_ITEMS = 11,  // lanes processed by advance kernels
+  CNT_COL_ITEMS = 12,  // lanes processed by collide kernels
+  CNT_ADV_SEGS = 13,   // flights made inside advance kernels
+  N_CNT_ALL = 14
 };
 enum : int { K_COL = 0, K_TL = 1, K_ABS = 2 };
 constexpr int STRIPES = 64;  // copies of each global accumulator (atomic contention)
@@ -129,6 +137,12 @@ struct Tables {
   uint32_t hash_base_f;
   double nu, watt_a, watt_b, e_max, e_cut;
   double q_ktl;            // fixed-point scale of the track-length k terms
+  // time-dependent fixed source (t_edges != null): nt time bins per tally
+  // bin, group speeds, census at t_max
+  int nt;
+  const double* t_edges;   // [nt + 1]
+  const double* speed;     // [G] cm/s
+  double t_max;
 };
 
 // Particle bank in structure-of-arrays form.
@@ -142,6 +156,7 @@ struct Bank {
   uint32_t* ctr;  // transport-stream draws consumed
   uint32_t* id;   // source index of the history
   uint32_t* nseg; // flights made so far (event guard)
+  double* t;      // time-dependent mode: time since the source pulse
   void* w;        // continuous energy: z direction cosine (working precision)
   void* e;        // continuous energy: energy, eV (working precision)
 };
@@ -158,7 +173,7 @@ struct Sites {
 
 // One logged flight: position after it, its length and energy, the cell,
 // region and group (or energy bin) it flew in, and how it ended
-// (1 collision, 2 surface crossing, 3 leak).
+// (1 collision, 2 surface crossing, 3 leak, 4 census).
 struct EvEntry {
   double x, y, d, e;
   int cell, region, group, type;
@@ -178,6 +193,7 @@ struct Records {
   double* x_final;
   double* y_final;
   double* e_final;
+  double* t_final;
   EvEntry* ev;  // [history][ev_cap] flights, or null
   int ev_cap;
 };

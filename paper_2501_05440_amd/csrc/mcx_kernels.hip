@@ -50,6 +50,7 @@ __global__ void k_birth(Tables T, uint32_t gen, uint32_t n, const double* sx, co
   p.ctr = rs.draw;
   p.id = id;
   p.nseg = 0;
+  p.t = 0.0;
   store_part(out, id, p);
 }
 
@@ -91,13 +92,14 @@ __global__ void __launch_bounds__(1024) k_advance(Tables T, uint32_t gen, uint32
       ev = segment<R, REC, false>(T, T.geo, p, rs, A, Rc, &refl);
       p.nseg += 1;
       c_seg += 1;
-      c_cross += ev != EV_COLLIDE ? 1u : 0u;
+      c_cross += (ev == EV_CROSS || ev == EV_LEAK) ? 1u : 0u;
       c_refl += refl ? 1u : 0u;
       if (ev != EV_CROSS) break;
     }
     p.ctr = rs.draw;
     if (ev == EV_KILL) die<R, REC>(p, FATE_KILLED, A, Rc);
     if (ev == EV_LEAK) die<R, REC>(p, FATE_LEAKED, A, Rc);
+    if (ev == EV_CENSUS) die<R, REC>(p, FATE_CENSUS, A, Rc);
   }
   __shared__ uint32_t lds[2 * (MAX_WAVES + 1)];
   uint32_t pl, pc;
@@ -109,6 +111,7 @@ __global__ void __launch_bounds__(1024) k_advance(Tables T, uint32_t gen, uint32
   wave_count(A.cnt + CNT_REFL * STRIPES, c_refl);
   wave_flag(A.cnt + CNT_LEAK * STRIPES, ev == EV_LEAK);
   wave_flag(A.cnt + CNT_KILLED * STRIPES, ev == EV_KILL);
+  wave_flag(A.cnt + CNT_CENSUS * STRIPES, ev == EV_CENSUS);
   wave_flag(A.cnt + CNT_ADV_ITEMS * STRIPES, k < n_in);
   wave_count(A.cnt + CNT_ADV_SEGS * STRIPES, c_seg);
 }
@@ -170,7 +173,7 @@ __global__ void __launch_bounds__(256) k_tail(Tables T, uint32_t gen, Bank in,
   const uint32_t n_in = *n_in_p;
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long c_seg = 0, c_col = 0, c_cross = 0, c_refl = 0, c_leak = 0, c_abs = 0,
-                     c_kill = 0, c_sites = 0, c_scat = 0;
+                     c_kill = 0, c_sites = 0, c_scat = 0, c_cen = 0;
   unsigned long long kcol[2] = {0, 0}, kabs[2] = {0, 0};
   if (k < n_in) {
     const double k_used = *A.k_used;
@@ -193,6 +196,12 @@ __global__ void __launch_bounds__(256) k_tail(Tables T, uint32_t gen, Bank in,
         ++c_leak;
         p.ctr = rs.draw;
         die<R, REC>(p, FATE_LEAKED, A, Rc);
+        break;
+      }
+      if (ev == EV_CENSUS) {
+        ++c_cen;
+        p.ctr = rs.draw;
+        die<R, REC>(p, FATE_CENSUS, A, Rc);
         break;
       }
       if (ev == EV_CROSS) {
@@ -235,6 +244,7 @@ __global__ void __launch_bounds__(256) k_tail(Tables T, uint32_t gen, Bank in,
   wave_count(A.cnt + CNT_KILLED * STRIPES, c_kill);
   wave_count(A.cnt + CNT_SITES * STRIPES, c_sites);
   wave_count(A.cnt + CNT_SCAT * STRIPES, c_scat);
+  wave_count(A.cnt + CNT_CENSUS * STRIPES, c_cen);
   wave_acc_halves(A.k + K_COL * STRIPES * 2, kcol[0], kcol[1]);
   wave_acc_halves(A.k + K_ABS * STRIPES * 2, kabs[0], kabs[1]);
 }
@@ -361,15 +371,15 @@ __global__ void __launch_bounds__(1024) k_gen_tallies(Tables T, uint32_t gen, ui
                                                       double* gen_tal, double* gen_k) {
   __shared__ double ps[1024], pc[1024];
   const int nb = T.n_bins;
-  const int per_cell = T.geo.mr1 * T.G;
+  const int per_cell = T.geo.mr1 * T.G * T.nt;
   double s = 0.0, cmp = 0.0;  // Neumaier pair of this thread
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
     const double flux = flux_total(A.tally + 2 * (size_t)b, T.tally_stripes, 2 * (size_t)nb,
                                    A.tally_t + 2 * (size_t)b) /
                         T.q_flux;
     const int cell = b / per_cell;
-    const int r = (b / T.G) % T.geo.mr1;
-    const int g = b % T.G;
+    const int r = (b / (T.G * T.nt)) % T.geo.mr1;
+    const int g = (b / T.nt) % T.G;
     const int m = T.geo.mats[T.geo.pin_map[cell] * T.geo.mr1 + r];
     // continuous energy: nu_sig_f varies inside a bin; no production tally
     const double prod = T.ce ? 0.0 : T.nusf[m * T.G + g] * flux;

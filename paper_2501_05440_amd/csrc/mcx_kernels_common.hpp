@@ -100,6 +100,7 @@ struct Part {
   R u, v;
   int i, j, r, g;
   uint32_t nsite, ctr, id, nseg;
+  double t;  // time since the source pulse (time-dependent mode)
 };
 
 template <class R>
@@ -119,6 +120,7 @@ __device__ __forceinline__ Part<R> load_part(const Bank& b, uint32_t k) {
   p.ctr = b.ctr[k];
   p.id = b.id[k];
   p.nseg = b.nseg[k];
+  p.t = b.t ? b.t[k] : 0.0;
   return p;
 }
 
@@ -133,9 +135,10 @@ __device__ __forceinline__ void store_part(const Bank& b, uint32_t k, const Part
   b.ctr[k] = p.ctr;
   b.id[k] = p.id;
   b.nseg[k] = p.nseg;
+  if (b.t) b.t[k] = p.t;
 }
 
-enum : int { EV_NONE = 0, EV_COLLIDE = 1, EV_CROSS = 2, EV_LEAK = 3, EV_KILL = 4 };
+enum : int { EV_NONE = 0, EV_COLLIDE = 1, EV_CROSS = 2, EV_LEAK = 3, EV_KILL = 4, EV_CENSUS = 5 };
 
 template <class R, bool REC>
 __device__ __forceinline__ void die(const Part<R>& p, int fate, const Accum& A,
@@ -147,6 +150,7 @@ __device__ __forceinline__ void die(const Part<R>& p, int fate, const Accum& A,
     Rc.ctr_final[p.id] = p.ctr;
     Rc.x_final[p.id] = p.x;
     Rc.y_final[p.id] = p.y;
+    Rc.t_final[p.id] = p.t;
   }
 }
 
@@ -187,25 +191,71 @@ __device__ __forceinline__ int segment(const Tables& T, const Geo& L, Part<R>& p
   if (t_out < d_bnd) d_bnd = t_out;
   if (t_in < d_bnd) d_bnd = t_in;
 
-  const bool collide = (double)d_col < d_bnd;
-  const double d = collide ? (double)d_col : d_bnd;
+  bool collide = (double)d_col < d_bnd;
+  double d = collide ? (double)d_col : d_bnd;
+  // time-dependent mode: the flight stops at the end of the time grid if
+  // that comes first (census)
+  bool census = false;
+  double vg = 0.0;
+  if (T.t_edges) {
+    vg = T.speed[p.g];
+    const double d_cen = (T.t_max - p.t) * vg;
+    if (d_cen < d) {
+      d = d_cen;
+      census = true;
+      collide = false;
+    }
+  }
   p.x = p.x + d * u;
   p.y = p.y + d * v;
 
-  // track-length flux tally of this bin (cell, region, group); nu_sig_f is
-  // constant in a bin, so the production tally and the track-length k
-  // estimator follow from the flux sums at the end of the generation
-  const int bin = L.bin_base + (c * L.mr1 + p.r) * T.G + p.g;
-  const uint64_t qf = quantize(d, T.q_flux);
-  if (HALVES) {
-    if (qf) {
-      atomicAdd(A.tally_t + 2 * bin, (unsigned long long)(qf & 0xFFFFFFFFull));
-      atomicAdd(A.tally_t + 2 * bin + 1, (unsigned long long)(qf >> 32));
+  // track-length flux tally of this bin (cell, region, group[, time bin]);
+  // nu_sig_f is constant in a bin, so the production tally and the
+  // track-length k estimator follow from the flux sums at the end of the
+  // generation
+  const int bin = L.bin_base + ((c * L.mr1 + p.r) * T.G + p.g) * T.nt;
+  unsigned long long* tb =
+      A.tally + (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
+  if (T.t_edges) {
+    // split the flight over the time bins it spans
+    double t1 = census ? T.t_max : p.t + d / vg;
+    if (t1 > T.t_max) t1 = T.t_max;
+    int lo_b = 0, hi_b = T.nt;
+    while (hi_b - lo_b > 1) {
+      const int mid = lo_b + (hi_b - lo_b) / 2;
+      if (T.t_edges[mid] <= p.t)
+        lo_b = mid;
+      else
+        hi_b = mid;
     }
+    for (int b = lo_b; b < T.nt; ++b) {
+      const double e0 = T.t_edges[b], e1 = T.t_edges[b + 1];
+      const double lo = e0 > p.t ? e0 : p.t;
+      const double hi = e1 < t1 ? e1 : t1;
+      if (hi > lo) {
+        const uint64_t q = quantize((hi - lo) * vg, T.q_flux);
+        if (HALVES) {
+          if (q) {
+            atomicAdd(A.tally_t + 2 * (bin + b), (unsigned long long)(q & 0xFFFFFFFFull));
+            atomicAdd(A.tally_t + 2 * (bin + b) + 1, (unsigned long long)(q >> 32));
+          }
+        } else {
+          acc_add(tb + 2 * (bin + b), q);
+        }
+      }
+      if (e1 >= t1) break;
+    }
+    p.t = t1;
   } else {
-    unsigned long long* tb =
-        A.tally + (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
-    acc_add(tb + 2 * bin, qf);
+    const uint64_t qf = quantize(d, T.q_flux);
+    if (HALVES) {
+      if (qf) {
+        atomicAdd(A.tally_t + 2 * bin, (unsigned long long)(qf & 0xFFFFFFFFull));
+        atomicAdd(A.tally_t + 2 * bin + 1, (unsigned long long)(qf >> 32));
+      }
+    } else {
+      acc_add(tb + 2 * bin, qf);
+    }
   }
   int k_ev = 0;
   if (REC) {
@@ -214,6 +264,10 @@ __device__ __forceinline__ int segment(const Tables& T, const Geo& L, Part<R>& p
     Rc.tl_sum[p.id] += d;
   }
   *refl_out = false;
+  if (census) {
+    if (REC) log_flight(Rc, p.id, k_ev, p.x, p.y, d, 0.0, c, p.r, p.g, 4);
+    return EV_CENSUS;
+  }
   if (collide) {
     if (REC) log_flight(Rc, p.id, k_ev, p.x, p.y, d, 0.0, c, p.r, p.g, 1);
     return EV_COLLIDE;

@@ -248,11 +248,11 @@ __global__ void __launch_bounds__(PB) k_persistent(Tables T, uint32_t gen, Accum
       const int ev = segment<R, false, false>(T, L, p, rs, A, Rc, &refl);
       p.ctr = rs.draw;
       M.nseg[s] += 1;
-      if (ev != EV_COLLIDE) M.ncross[s] += 1;
+      if (ev == EV_CROSS || ev == EV_LEAK) M.ncross[s] += 1;
       if (refl) M.nrefl[s] += 1;
       slot_store(M, s, p);
-      if (ev == EV_LEAK) {
-        slot_death(M, s, p, FATE_LEAKED, 0, A, H);
+      if (ev == EV_LEAK || ev == EV_CENSUS) {
+        slot_death(M, s, p, ev == EV_LEAK ? FATE_LEAKED : FATE_CENSUS, 0, A, H);
       } else if (ev == EV_COLLIDE) {
         uint8_t st = SL_COL;
         if (sort) {
@@ -341,6 +341,7 @@ __global__ void __launch_bounds__(256) k_hist_reduce(Tables T, HistOut H, Accum 
     v[CNT_ABS] += q[HO_FATE] == FATE_ABSORBED;
     v[CNT_KILLED] += q[HO_FATE] == FATE_KILLED;
     v[CNT_CUTOFF] += q[HO_FATE] == FATE_CUTOFF;
+    v[CNT_CENSUS] += q[HO_FATE] == FATE_CENSUS;
     v[N_CNT + 0] += H.kcol[2 * h + 0];
     v[N_CNT + 1] += H.kcol[2 * h + 1];
     v[N_CNT + 2] += H.kabs[h] & 0xFFFFFFFFull;

@@ -18,8 +18,9 @@ OK, EINVAL, ESTATE, ENOMEM, EDEVICE, ELOST, EGUARD, EEXTINCT, EOVERFLOW = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 FP64, FP32_MIXED = 0, 1
 ENGINE_EVENT, ENGINE_PERSISTENT = 0, 1
-N_CNT = 10
-COUNT_NAMES = ["seg", "col", "cross", "refl", "leak", "abs", "killed", "sites", "scat", "cutoff"]
+N_CNT = 11
+COUNT_NAMES = ["seg", "col", "cross", "refl", "leak", "abs", "killed", "sites", "scat", "cutoff",
+               "census"]
 
 # every function the header declares
 EXPORTS = [
@@ -30,6 +31,7 @@ EXPORTS = [
     "mcx_diag_philox", "mcx_last_error", "mcx_destroy", "mcx_load_batch", "mcx_run_batch",
     "mcx_get_batch_results", "mcx_get_batch_tallies", "mcx_autotune", "mcx_load_ce_xs",
     "mcx_continue_generations", "mcx_checkpoint", "mcx_restore", "mcx_get_event_log",
+    "mcx_load_time_grid",
 ]
 
 
@@ -102,7 +104,7 @@ RECORD_DTYPE = np.dtype([
     ("n_seg", "<i4"), ("n_col", "<i4"), ("n_cross", "<i4"), ("n_refl", "<i4"),
     ("fate", "<i4"), ("n_sites", "<i4"), ("g_final", "<i4"), ("ctr_final", "<u4"),
     ("tl_sum", "<f8"), ("kcol_sum", "<f8"), ("x_final", "<f8"), ("y_final", "<f8"),
-    ("e_final", "<f8"),
+    ("e_final", "<f8"), ("t_final", "<f8"),
 ])
 
 _lib = None
@@ -147,6 +149,7 @@ def lib():
         "mcx_checkpoint": ([vp, vp, C.POINTER(C.c_size_t)], C.c_int),
         "mcx_restore": ([vp, vp, C.c_size_t], C.c_int),
         "mcx_get_event_log": ([vp, i32, dp, i64], C.c_int),
+        "mcx_load_time_grid": ([vp, i32, dp, dp, i32], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -274,6 +277,13 @@ class Context:
         else:
             (n_mat, n_grp), ptrs = _xs(problem["xs"], k)
             self._check(L.mcx_load_mg_xs(h, n_mat, n_grp, *ptrs))
+        n_t = 1
+        if "time" in problem:
+            edges = _arr(problem["time"]["t_edges"], np.float64, k)
+            speed = _arr(problem["time"]["speed"], np.float64, k)
+            n_t = len(edges) - 1
+            self._check(L.mcx_load_time_grid(h, n_t, edges.ctypes.data, speed.ctypes.data,
+                                             len(speed)))
         s = Source()
         s.seed, s.n_per_gen = rp["seed"], rp["n_per_gen"]
         s.fixed_source, s.problem_id = int(rp["fixed_source"]), rp["problem_id"]
@@ -285,7 +295,7 @@ class Context:
         self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=f"cuda:{device}")
         self._check(L.mcx_bind_workspace(h, self.workspace.data_ptr(), nbytes.value,
                                          self.n_gen_max))
-        self.n_bins = geo["nx"] * geo["ny"] * (g.max_rings + 1) * n_grp
+        self.n_bins = geo["nx"] * geo["ny"] * (g.max_rings + 1) * n_grp * n_t
         self.n_per_gen = rp["n_per_gen"]
         self.n_gen = None
 

@@ -365,11 +365,12 @@ def with_time(problem, t_edges, speed=None):
 
 def pulsed_lattice(n_per_gen=1_000_000, n_gen=10, seed=6):
     """The 17x17 lattice driven by a source pulse at t = 0 (fission as
-    capture): flux per pin, group and time bin (0, then 12 log bins from
-    1e-9 s to 1e-3 s), census at 1 ms."""
+    capture): flux per pin, group and time bin (0, then 11 log bins from
+    1e-9 s to 1e-5 s), census at 10 us, where about a quarter of the
+    histories are still flying."""
     lat = lattice_17x17(n_per_gen=n_per_gen, n_gen=n_gen, n_inactive=0, seed=seed)
     lat = with_run(lat, fixed_source=True)
-    edges = np.concatenate([[0.0], np.geomspace(1e-9, 1e-3, 12)])
+    edges = np.concatenate([[0.0], np.geomspace(1e-9, 1e-5, 12)])
     return with_time(lat, edges)
 
 
