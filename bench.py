@@ -71,6 +71,7 @@ def parse():
     ap.add_argument("--n-fp32", type=int, default=10_000_000)
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-problem batch")
     ap.add_argument("--no-ce", action="store_true", help="skip the continuous-energy pin cell")
+    ap.add_argument("--no-time", action="store_true", help="skip the pulsed (time-dependent) lattice")
     ap.add_argument("--no-persistent", action="store_true",
                     help="skip the lattice on the persistent engine")
     ap.add_argument("--tune-cache", default=None,
@@ -238,6 +239,46 @@ def ce_measurement(P, mcx, steps):
     return out
 
 
+def time_dependent_measurement(P, mcx, steps, cpu):
+    """The pulsed 17x17 lattice (fixed source, fission as capture), 1e6
+    histories x 10 batches, flux in 12 time bins, census at 10 us: FP64
+    event engine, and the oracle on one batch."""
+    import torch
+    prob = P.pulsed_lattice()
+    n = prob["run"]["n_per_gen"] * prob["run"]["n_gen"]
+    ctx = mcx.Context(prob, time_kernels=True)
+    ctx.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.run()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    t = ctx.timing()
+    _, c = ctx.generation_stats()
+    ctx.close()
+    out = {"histories_per_s": round(n / sec, 1),
+           "events_per_s": round(float(c[:, 0].sum()) / sec, 1),
+           "ms_per_step": round(sec * 1e3, 2),
+           "segments_per_history": round(float(c[:, 0].sum()) / n, 3),
+           "census_fraction": round(float(c[:, 10].sum()) / n, 5),
+           "leak_fraction": round(float(c[:, 4].sum()) / n, 5),
+           "kernel_ms_per_step": {"advance": round(t["advance_ms"], 2),
+                                  "collide": round(t["collide_ms"], 2),
+                                  "tail": round(t["tail_ms"], 2)},
+           "workload": "pulsed lattice_17x17_7g: source pulse at t = 0, fission as capture, "
+                       "1e6 histories x 10 batches, 12 time bins to 10 us, FP64 event engine"}
+    if cpu:
+        from oracle import oracle as O
+        cores = os.cpu_count() or 1
+        c0 = time.perf_counter()
+        O.run(P.with_run(prob, n_gen=1), n_threads=cores)
+        dt = time.perf_counter() - c0
+        out["cpu_oracle"] = {"histories_per_s": round(prob["run"]["n_per_gen"] / dt, 1),
+                             "cores": cores, "sample": "first batch (1e6 histories)"}
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -350,6 +391,11 @@ def main():
         print("[bench] continuous-energy pin cell", file=sys.stderr, flush=True)
         ce = ce_measurement(P, mcx, 1)
 
+    td = None
+    if not a.no_time:
+        print("[bench] pulsed lattice (time-dependent fixed source)", file=sys.stderr, flush=True)
+        td = time_dependent_measurement(P, mcx, 1, not a.no_cpu_baseline)
+
     extra = None
     if not a.no_fp32:
         print(f"[bench] FP64 vs FP32-mixed at {a.n_fp32} histories/gen", file=sys.stderr, flush=True)
@@ -384,6 +430,7 @@ def main():
         "fp32_mixed": extra,
         "batch": batch,
         "continuous_energy": ce,
+        "time_dependent": td,
     }
     print(json.dumps(out), flush=True)
 

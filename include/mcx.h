@@ -49,7 +49,9 @@ enum mcx_status {
   MCX_ELOST = -5,      /* source sampling found no fissile point */
   MCX_EGUARD = -6,     /* histories stopped by the per-history event guard */
   MCX_EEXTINCT = -7,   /* empty fission bank in a k-eigenvalue generation */
-  MCX_EOVERFLOW = -8   /* fission bank or per-history site count overflow */
+  MCX_EOVERFLOW = -8   /* fission bank or per-history site count overflow, or 2^32
+                          flights or more in one generation or batch (the limit
+                          of the exact flux accumulators) */
 };
 
 enum { MCX_FP64 = 0, MCX_FP32_MIXED = 1 };

@@ -117,7 +117,7 @@ struct Dev {
   double *k_used = nullptr, *xi0 = nullptr, *k_stat = nullptr;
   double *tal_stat = nullptr;  // [mean flux | mean prod | sigma flux | sigma prod]
   uint32_t* ent_hist = nullptr;
-  double* ent_term = nullptr;
+  double* tl_part = nullptr;  // per-block production sums of the generation tallies
   uint32_t* gen_status = nullptr;  // [n_gen_max] status bits per generation
   // persistent engine: per-history outputs, work counter
   unsigned long long* h_kcol = nullptr;
@@ -632,10 +632,11 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   const int nb = batch ? c->batch_bins : c->nx * c->ny * mr1 * c->G * nt;
   const uint64_t n_hist = batch ? c->batch_hist : (uint64_t)N;
   const bool persistent = batch || c->opt.engine == MCX_ENGINE_PERSISTENT;
-  // copies of the flux accumulators, spread over workgroups by index: a
-  // batch's workgroups all work on the few problems whose histories are in
-  // flight, so its few bins get every copy (up to 16 Mi words)
-  const int stripe_words = batch ? (1 << 24) : 65536;
+  // copies of the flux accumulators, spread over workgroups by index (up to
+  // 64 copies in 1 Mi words; a batch's workgroups all work on the few
+  // problems whose histories are in flight, so its few bins get every copy,
+  // in up to 16 Mi words)
+  const int stripe_words = batch ? (1 << 24) : (1 << 20);
   const int stripes = std::max(1, std::min(STRIPES, stripe_words / std::max(1, 2 * nb)));
   const uint32_t fis_cap = (uint32_t)std::min<size_t>(2 * N + 4096, 0xFFFFFFF0u);
   const size_t n_ent = (size_t)c->src.ent_nx * c->src.ent_ny;
@@ -669,6 +670,7 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   T.mat_nuc = cv.take<int>(c->ce_mat_nuc.size());
   T.mat_dens = cv.take<double>(c->ce_dens.size());
   T.e_edges = cv.take<double>(c->ce_edges.size());
+  T.time = c->t_edges.empty() ? 0 : 1;
   T.nt = nt;
   T.t_edges = c->t_edges.empty() ? nullptr : cv.take<double>(c->t_edges.size());
   T.speed = c->t_edges.empty() ? nullptr : cv.take<double>(c->t_speed.size());
@@ -774,7 +776,7 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   d.gen_m = cv.take<uint32_t>(n_gen_max);
   d.gen_tal = cv.take<double>((size_t)2 * nb * n_gen_max);
   d.tal_stat = cv.take<double>((size_t)4 * nb);
-  d.ent_term = cv.take<double>(n_ent);
+  d.tl_part = cv.take<double>((size_t)2 * std::max(1, gen_tally_blocks(nb)));
   d.k_stat = cv.take<double>(6);
   d.k_used = cv.take<double>(1);
   d.xi0 = cv.take<double>(1);
@@ -1197,15 +1199,16 @@ static int generation_end(mcx_ctx* c, int gen) {
   Accum& A = c->d.A;
   const bool rec = c->opt.record_histories != 0;
   const uint32_t N = c->d.N;
-  HIP_TRY(c, launch_gen_totals(T, gen, N, A, c->d.gen_k, c->d.gen_cnt, c->d.gen_m, c->d.k_used, c->d.xi0, s));
-  HIP_TRY(c, launch_gen_tallies(T, gen, N, A, c->d.gen_tal, c->d.gen_k, s));
+  HIP_TRY(c, launch_gen_tallies(T, gen, N, A, c->d.gen_tal, c->d.tl_part, s));
+  HIP_TRY(c, launch_gen_totals(T, gen, N, A, c->d.tl_part, c->d.gen_k, c->d.gen_cnt, c->d.gen_m,
+                               c->d.k_used, c->d.xi0, s));
   if (!T.fixed_source) {
     HIP_TRY(c, launch_scan(A.nsite_id, N, c->d.chunk_sum, c->d.offs, c->d.scan_total, s));
     HIP_TRY(c, launch_gen_check(T, A.n_fis, c->d.scan_total, A.status, s));
     HIP_TRY(c, launch_canon(A.fis, A.n_fis, c->d.offs, A.nsite_id, c->d.fis_cap, c->d.can_x,
                             c->d.can_y, c->d.can_g, c->d.can_e, A.status, c->d.fis_cap, s));
     HIP_TRY(c, launch_entropy(T, gen, c->d.can_x, c->d.can_y, A.n_fis, c->d.fis_cap, c->d.ent_hist,
-                              c->d.ent_term, c->d.gen_h, c->d.fis_cap, s));
+                              c->d.gen_h, c->d.fis_cap, s));
     HIP_TRY(c, launch_comb(N, A.n_fis, c->d.fis_cap, c->d.xi0, c->d.can_x, c->d.can_y,
                            c->d.can_g, c->d.can_e, c->d.src_x, c->d.src_y, c->d.src_g,
                            c->d.src_e, s));
@@ -1252,6 +1255,7 @@ static int generation_end(mcx_ctx* c, int gen) {
 static int status_error(mcx_ctx* c, uint32_t st) {
   if (st & ST_SOURCE) return fail(c, MCX_ELOST, "source sampling found no fissile point");
   if (st & ST_OVERFLOW) return fail(c, MCX_EOVERFLOW, "fission bank overflow");
+  if (st & ST_TALLY) return fail(c, MCX_EOVERFLOW, "2^32 or more flights in one generation");
   if (st & (ST_SITE_SEQ | ST_SCAN)) return fail(c, MCX_EDEVICE, "inconsistent fission bank");
   if (st & ST_EXTINCT) return fail(c, MCX_EEXTINCT, "fission bank is empty");
   return fail(c, MCX_EDEVICE, "generation skipped");
@@ -1840,6 +1844,9 @@ int mcx_run_batch(mcx_ctx* c) {
   c->h_bcnt.resize((size_t)N_CNT * c->n_probs);
   HIP_TRY(c, hipMemcpy(c->h_bk.data(), c->d.prob_kres, c->h_bk.size() * 8, hipMemcpyDeviceToHost));
   HIP_TRY(c, hipMemcpy(c->h_bcnt.data(), c->d.prob_cnt, c->h_bcnt.size() * 8, hipMemcpyDeviceToHost));
+  uint64_t flights = 0;
+  for (int p = 0; p < c->n_probs; ++p) flights += c->h_bcnt[(size_t)p * N_CNT + CNT_SEG];
+  if (flights >= (1ull << 32)) st |= ST_TALLY;
   if (st) return status_error(c, st);
   c->batch_ran = true;
   for (int p = 0; p < c->n_probs; ++p)

@@ -137,12 +137,17 @@ struct Tables {
   uint32_t hash_base_f;
   double nu, watt_a, watt_b, e_max, e_cut;
   double q_ktl;            // fixed-point scale of the track-length k terms
-  // time-dependent fixed source (t_edges != null): nt time bins per tally
-  // bin, group speeds, census at t_max
+  // time-dependent fixed source (time != 0): nt time bins per tally bin,
+  // group speeds, census at t_max
+  int time;
   int nt;
   const double* t_edges;   // [nt + 1]
   const double* speed;     // [G] cm/s
   double t_max;
+  // double-double tables of ln and sin/cos(2 pi t), bound on the device at
+  // kernel entry (constant memory, or a copy in LDS)
+  const double* lt;
+  const double* sct;
 };
 
 // Particle bank in structure-of-arrays form.
@@ -236,7 +241,8 @@ enum : uint32_t {
   ST_SCAN = 4u,
   ST_SOURCE = 8u,
   ST_EXTINCT = 16u,
-  ST_SKIPPED = 32u
+  ST_SKIPPED = 32u,
+  ST_TALLY = 64u  // 2^32 or more flights: a tail-kernel flux word may have wrapped
 };
 
 // ---------------------------------------------------------------------------
@@ -320,12 +326,13 @@ MCX_HD int sample_cum(R xi, const R* cum, int n, int last_nz) {
 
 // Isotropic direction from two draws; only (u, v) matter in z-invariant
 // geometry (w = 2 xi_mu - 1 sets the in-plane speed sqrt(1 - w^2)).
-MCX_HD void isotropic_uv(double xi_mu, double xi_phi, double* u, double* v) {
+MCX_HD void isotropic_uv(double xi_mu, double xi_phi, double* u, double* v,
+                         const double* sct = sc_tab()) {
   const double w = 2.0 * xi_mu - 1.0;
   const double s2 = 1.0 - w * w;
   const double s = sqrt(s2 > 0.0 ? s2 : 0.0);
   double c, sn;
-  cr_cossin_2pi(xi_phi, sc_tab(), &c, &sn);
+  cr_cossin_2pi(xi_phi, sct, &c, &sn);
   *u = s * c;
   *v = s * sn;
 }

@@ -65,12 +65,13 @@ __global__ void k_birth(Tables T, uint32_t gen, uint32_t n, const double* sx, co
 // Particles still flying go to the live bank of the next iteration,
 // particles that collide go to the collision bank; leaks and guard kills end
 // here.  Block 0 clears the counters the next iteration appends to.
-template <class R, bool REC>
-__global__ void __launch_bounds__(1024) k_advance(Tables T, uint32_t gen, uint32_t flights, Bank in,
+template <class R, bool REC, bool LDS>
+__global__ void __launch_bounds__(1024) k_advance(Tables T0, uint32_t gen, uint32_t flights, Bank in,
                                                   const uint32_t* __restrict__ n_in_p, Bank live,
                                                   uint32_t* n_live, Bank col, uint32_t* n_col,
                                                   Accum A, Records Rc, uint32_t* clr_live,
                                                   uint32_t* clr_col) {
+  const Tables T = kernel_tables<R, LDS>(T0);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *clr_live = 0;
     *clr_col = 0;
@@ -118,10 +119,11 @@ __global__ void __launch_bounds__(1024) k_advance(Tables T, uint32_t gen, uint32
 
 // Process the collision bank: collision estimator, fission-bank append
 // (block-aggregated reservation), scatter to the live bank or absorb.
-template <class R, bool REC>
-__global__ void __launch_bounds__(1024) k_collide(Tables T, uint32_t gen, Bank in,
+template <class R, bool REC, bool LDS>
+__global__ void __launch_bounds__(1024) k_collide(Tables T0, uint32_t gen, Bank in,
                                                   const uint32_t* __restrict__ n_in_p, Bank live,
                                                   uint32_t* n_live, Accum A, Records Rc) {
+  const Tables T = kernel_tables<R, LDS>(T0);
   const uint32_t n_in = *n_in_p;
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = k < n_in;
@@ -166,10 +168,11 @@ __global__ void __launch_bounds__(1024) k_collide(Tables T, uint32_t gen, Bank i
 // History-based finish of the last live particles: one lane runs its
 // particle's remaining flights and collisions to the end (the same
 // operations as the event kernels, in the same order).
-template <class R, bool REC>
-__global__ void __launch_bounds__(256) k_tail(Tables T, uint32_t gen, Bank in,
+template <class R, bool REC, bool LDS>
+__global__ void __launch_bounds__(256) k_tail(Tables T0, uint32_t gen, Bank in,
                                               const uint32_t* __restrict__ n_in_p, Accum A,
                                               Records Rc) {
+  const Tables T = kernel_tables<R, LDS>(T0);
   const uint32_t n_in = *n_in_p;
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long c_seg = 0, c_col = 0, c_cross = 0, c_refl = 0, c_leak = 0, c_abs = 0,
@@ -180,6 +183,10 @@ __global__ void __launch_bounds__(256) k_tail(Tables T, uint32_t gen, Bank in,
     Part<R> p = load_part<R>(in, k);
     Stream rs(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
     int64_t nseg = p.nseg;
+    // Let the particle's loads complete here, so that the loop head does not
+    // wait on the memory counter, which in every later pass would also wait
+    // for the previous flight's tally atomics.
+    __builtin_amdgcn_s_waitcnt(0);
     for (;;) {
       if (nseg >= T.max_events) {
         p.ctr = rs.draw;
@@ -342,38 +349,93 @@ __global__ void k_canon(Sites fis, const uint32_t* n_fis_p, const uint32_t* offs
   }
 }
 
-// Generation totals: k estimators, counters, next k_used and combing offset.
-__global__ void k_gen_totals(Tables T, uint32_t gen, uint32_t n, Accum A, double* gen_k,
-                             unsigned long long* gen_cnt, uint32_t* gen_m, double* k_used,
-                             double* xi0) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  // multigroup: the track-length estimator follows from the flux tallies
+// Exact wave-wide sums (one wave of 64 lanes, one stripe per lane).
+__device__ __forceinline__ void wave_sum128(unsigned long long& w0, unsigned long long& w1) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o0 = __shfl_xor(w0, off), o1 = __shfl_xor(w1, off);
+    const unsigned long long t = w0 + o0;
+    w1 += o1 + (t < w0 ? 1ull : 0ull);
+    w0 = t;
+  }
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Neumaier pair (s, c) plus (x, cx).
+__device__ __forceinline__ void neu_add(double& s, double& c, double x, double cx) {
+  const double t = s + x;
+  c += cx + (fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s);
+  s = t;
+}
+
+// Generation totals (one wave): k estimators from the exact accumulators
+// (multigroup track length from the per-block production sums of
+// k_gen_tallies, in block order), event counters, bank size, the k used by
+// the next generation and the combing offset.
+__global__ void __launch_bounds__(64) k_gen_totals(Tables T, uint32_t gen, uint32_t n, Accum A,
+                                                   const double* tl_part, int n_part,
+                                                   double* gen_k, unsigned long long* gen_cnt,
+                                                   uint32_t* gen_m, double* k_used, double* xi0) {
+  static_assert(STRIPES == 64, "one accumulator stripe per lane");
+  const int lane = (int)threadIdx.x;
   const double inv_q[3] = {1.0 / T.q_kcol, T.ce ? 1.0 / T.q_ktl : 0.0, 1.0 / T.q_kabs};
-  for (int e = 0; e < 3; e += T.ce ? 1 : 2) {
-    const double v = stripes_to_double(A.k + (size_t)e * STRIPES * 2, STRIPES, 2) * inv_q[e];
-    gen_k[3 * gen + e] = v / (double)n;
+  double kv[3] = {0.0, 0.0, 0.0};
+  for (int e = 0; e < 3; ++e) {
+    unsigned long long w0 = A.k[((size_t)e * STRIPES + lane) * 2];
+    unsigned long long w1 = A.k[((size_t)e * STRIPES + lane) * 2 + 1];
+    wave_sum128(w0, w1);
+    kv[e] = u128_to_double(w0, w1) * inv_q[e];
   }
   for (int c = 0; c < N_CNT_ALL; ++c) {
-    unsigned long long s = 0;
-    for (int t = 0; t < STRIPES; ++t) s += A.cnt[c * STRIPES + t];
-    gen_cnt[(size_t)gen * N_CNT_ALL + c] = s;
+    const unsigned long long v = wave_sum_u64(A.cnt[c * STRIPES + lane]);
+    if (lane == 0) gen_cnt[(size_t)gen * N_CNT_ALL + c] = v;
+    if (lane == 0 && c == CNT_SEG && v >= (1ull << 32)) atomicOr(A.status, ST_TALLY);
   }
+  // multigroup track-length estimator: lane-strided partials, then a
+  // fixed-order butterfly
+  double ts = 0.0, tc = 0.0;
+  if (!T.ce) {
+    for (int b = lane; b < n_part; b += 64) neu_add(ts, tc, tl_part[2 * b], tl_part[2 * b + 1]);
+    for (int off = 32; off > 0; off >>= 1) {
+      const double os = __shfl_xor(ts, off), oc = __shfl_xor(tc, off);
+      if (lane & off) {
+        double s2 = os, c2 = oc;
+        neu_add(s2, c2, ts, tc);
+        ts = s2;
+        tc = c2;
+      } else {
+        neu_add(ts, tc, os, oc);
+      }
+    }
+  }
+  if (lane != 0) return;
+  gen_k[3 * gen + 0] = kv[0] / (double)n;
+  gen_k[3 * gen + 1] = T.ce ? kv[1] / (double)n : (ts + tc) / (double)n;
+  gen_k[3 * gen + 2] = kv[2] / (double)n;
   gen_m[gen] = *A.n_fis;
   if (!T.fixed_source) *k_used = gen_k[3 * gen + 0];
   Stream rs(T.seed, TAG_RESAMPLE, 0, gen, T.prob, 0);
   *xi0 = rs.next();
 }
 
-// Generation tallies per source particle: flux from the exact sums, the
-// production nu_sig_f(bin) * flux, and the track-length k estimator as the
-// sum of the production over bins (compensated, fixed order; one block).
-__global__ void __launch_bounds__(1024) k_gen_tallies(Tables T, uint32_t gen, uint32_t n, Accum A,
-                                                      double* gen_tal, double* gen_k) {
-  __shared__ double ps[1024], pc[1024];
+// Generation tallies per source particle: flux from the exact sums and the
+// production nu_sig_f(bin) * flux, one bin per thread; each block leaves the
+// compensated sum of its production terms (a fixed-order tree) for the
+// track-length k estimator.
+constexpr int GT_BLOCK = 256;
+
+__global__ void __launch_bounds__(GT_BLOCK) k_gen_tallies(Tables T, uint32_t gen, uint32_t n,
+                                                          Accum A, double* gen_tal,
+                                                          double* tl_part) {
+  __shared__ double ps[GT_BLOCK], pc[GT_BLOCK];
   const int nb = T.n_bins;
-  const int per_cell = T.geo.mr1 * T.G * T.nt;
-  double s = 0.0, cmp = 0.0;  // Neumaier pair of this thread
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+  const int b = (int)(blockIdx.x * GT_BLOCK + threadIdx.x);
+  double prod = 0.0;
+  if (b < nb) {
+    const int per_cell = T.geo.mr1 * T.G * T.nt;
     const double flux = flux_total(A.tally + 2 * (size_t)b, T.tally_stripes, 2 * (size_t)nb,
                                    A.tally_t + 2 * (size_t)b) /
                         T.q_flux;
@@ -382,30 +444,29 @@ __global__ void __launch_bounds__(1024) k_gen_tallies(Tables T, uint32_t gen, ui
     const int g = (b / T.nt) % T.G;
     const int m = T.geo.mats[T.geo.pin_map[cell] * T.geo.mr1 + r];
     // continuous energy: nu_sig_f varies inside a bin; no production tally
-    const double prod = T.ce ? 0.0 : T.nusf[m * T.G + g] * flux;
+    prod = T.ce ? 0.0 : T.nusf[m * T.G + g] * flux;
     gen_tal[(size_t)gen * 2 * nb + b] = flux / (double)n;
     gen_tal[(size_t)gen * 2 * nb + nb + b] = prod / (double)n;
-    const double t = s + prod;
-    cmp += fabs(s) >= fabs(prod) ? (s - t) + prod : (prod - t) + s;
-    s = t;
   }
-  ps[threadIdx.x] = s;
-  pc[threadIdx.x] = cmp;
+  ps[threadIdx.x] = prod;
+  pc[threadIdx.x] = 0.0;
   __syncthreads();
-  if (threadIdx.x == 0 && !T.ce) {
-    double a = 0.0, ac = 0.0;
-    for (unsigned k = 0; k < blockDim.x; ++k) {
-      const double parts[2] = {ps[k], pc[k]};
-      for (int e = 0; e < 2; ++e) {
-        const double x = parts[e];
-        const double t = a + x;
-        ac += fabs(a) >= fabs(x) ? (a - t) + x : (x - t) + a;
-        a = t;
-      }
+  for (int h = GT_BLOCK / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      double s = ps[threadIdx.x], c = pc[threadIdx.x];
+      neu_add(s, c, ps[threadIdx.x + h], pc[threadIdx.x + h]);
+      ps[threadIdx.x] = s;
+      pc[threadIdx.x] = c;
     }
-    gen_k[3 * gen + 1] = (a + ac) / (double)n;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    tl_part[2 * blockIdx.x] = ps[0];
+    tl_part[2 * blockIdx.x + 1] = pc[0];
   }
 }
+
+int gen_tally_blocks(int n_bins) { return (n_bins + GT_BLOCK - 1) / GT_BLOCK; }
 
 // Shannon entropy of the canonical bank over the entropy mesh: per-block
 // histograms in LDS (meshes up to LDS_HIST bins), merged with one global
@@ -438,26 +499,28 @@ __global__ void __launch_bounds__(256) k_entropy_hist(Tables T, const double* cx
       if (h[b]) atomicAdd(&hist[b], h[b]);
 }
 
-// H = -sum_b p_b log2 p_b: the terms in parallel, the sum in bin order.
+// H = -sum_b p_b log2 p_b: the terms in parallel, summed in a fixed-order
+// tree.
 __global__ void __launch_bounds__(256) k_entropy_final(Tables T, uint32_t gen,
                                                       const uint32_t* hist, const uint32_t* n_p,
-                                                      double* term, double* gen_h) {
+                                                      double* gen_h) {
+  __shared__ double red[256];
   const uint32_t m = *n_p;
   const int nb = T.ent_nx * T.ent_ny;
+  double acc = 0.0;
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-    double t = 0.0;
     if (m > 0 && hist[b] > 0) {
       const double p = (double)hist[b] / (double)m;
-      t = p * log2(p);
+      acc += p * log2(p);
     }
-    term[b] = t;
   }
+  red[threadIdx.x] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double h = 0.0;
-    for (int b = 0; b < nb; ++b) h -= term[b];
-    gen_h[gen] = h;
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) gen_h[gen] = -red[0];
 }
 
 // Consistency of the generation's bank: scan total equals the number of
@@ -583,13 +646,23 @@ hipError_t launch_birth(int prec, const Tables& T, uint32_t gen, uint32_t n, con
   return hipGetLastError();
 }
 
+// The event kernels run on LDS copies of the tables when they fit.
+static size_t mg_lds_bytes(int prec, const Tables& T) {
+  const size_t b = lds_tables_bytes(T, prec == 0 ? sizeof(double) : sizeof(float));
+  return b <= LDS_TABLES_MAX ? b : 0;
+}
+
 template <class R, bool REC>
-static void advance_k(dim3 g, dim3 b, hipStream_t s, const Tables& T, uint32_t gen, uint32_t flights,
-                      const Bank& in, const uint32_t* n_in, const Bank& live, uint32_t* n_live,
-                      const Bank& col, uint32_t* n_col, const Accum& A, const Records& Rc,
-                      uint32_t* clr_live, uint32_t* clr_col) {
-  hipLaunchKernelGGL((k_advance<R, REC>), g, b, 0, s, T, gen, flights, in, n_in, live, n_live, col,
-                     n_col, A, Rc, clr_live, clr_col);
+static void advance_k(dim3 g, dim3 b, size_t lb, hipStream_t s, const Tables& T, uint32_t gen,
+                      uint32_t flights, const Bank& in, const uint32_t* n_in, const Bank& live,
+                      uint32_t* n_live, const Bank& col, uint32_t* n_col, const Accum& A,
+                      const Records& Rc, uint32_t* clr_live, uint32_t* clr_col) {
+  if (lb)
+    hipLaunchKernelGGL((k_advance<R, REC, true>), g, b, lb, s, T, gen, flights, in, n_in, live,
+                       n_live, col, n_col, A, Rc, clr_live, clr_col);
+  else
+    hipLaunchKernelGGL((k_advance<R, REC, false>), g, b, 0, s, T, gen, flights, in, n_in, live,
+                       n_live, col, n_col, A, Rc, clr_live, clr_col);
 }
 
 hipError_t launch_advance(int prec, bool rec, const Tables& T, uint32_t gen, uint32_t flights,
@@ -598,22 +671,35 @@ hipError_t launch_advance(int prec, bool rec, const Tables& T, uint32_t gen, uin
                           const Records& Rc, uint32_t* clr_live, uint32_t* clr_col,
                           uint32_t bound, int block, hipStream_t s) {
   const dim3 g(std::max(1u, nblk(bound, block))), b(block);
+  const size_t lb = mg_lds_bytes(prec, T);
   if (prec == 0) {
     if (rec)
-      advance_k<double, true>(g, b, s, T, gen, flights, in, n_in, live, n_live, col, n_col, A, Rc,
-                              clr_live, clr_col);
+      advance_k<double, true>(g, b, lb, s, T, gen, flights, in, n_in, live, n_live, col, n_col, A,
+                              Rc, clr_live, clr_col);
     else
-      advance_k<double, false>(g, b, s, T, gen, flights, in, n_in, live, n_live, col, n_col, A, Rc,
-                               clr_live, clr_col);
+      advance_k<double, false>(g, b, lb, s, T, gen, flights, in, n_in, live, n_live, col, n_col,
+                               A, Rc, clr_live, clr_col);
   } else {
     if (rec)
-      advance_k<float, true>(g, b, s, T, gen, flights, in, n_in, live, n_live, col, n_col, A, Rc,
-                             clr_live, clr_col);
+      advance_k<float, true>(g, b, lb, s, T, gen, flights, in, n_in, live, n_live, col, n_col, A,
+                             Rc, clr_live, clr_col);
     else
-      advance_k<float, false>(g, b, s, T, gen, flights, in, n_in, live, n_live, col, n_col, A, Rc,
-                              clr_live, clr_col);
+      advance_k<float, false>(g, b, lb, s, T, gen, flights, in, n_in, live, n_live, col, n_col,
+                              A, Rc, clr_live, clr_col);
   }
   return hipGetLastError();
+}
+
+template <class R, bool REC>
+static void collide_k(dim3 g, dim3 b, size_t lb, hipStream_t s, const Tables& T, uint32_t gen,
+                      const Bank& in, const uint32_t* n_in, const Bank& live, uint32_t* n_live,
+                      const Accum& A, const Records& Rc) {
+  if (lb)
+    hipLaunchKernelGGL((k_collide<R, REC, true>), g, b, lb, s, T, gen, in, n_in, live, n_live, A,
+                       Rc);
+  else
+    hipLaunchKernelGGL((k_collide<R, REC, false>), g, b, 0, s, T, gen, in, n_in, live, n_live, A,
+                       Rc);
 }
 
 hipError_t launch_collide(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in,
@@ -621,37 +707,45 @@ hipError_t launch_collide(int prec, bool rec, const Tables& T, uint32_t gen, con
                           const Accum& A, const Records& Rc, uint32_t bound, int block,
                           hipStream_t s) {
   const dim3 g(std::max(1u, nblk(bound, block))), b(block);
+  const size_t lb = mg_lds_bytes(prec, T);
   if (prec == 0) {
     if (rec)
-      hipLaunchKernelGGL((k_collide<double, true>), g, b, 0, s, T, gen, in, n_in, live, n_live, A,
-                         Rc);
+      collide_k<double, true>(g, b, lb, s, T, gen, in, n_in, live, n_live, A, Rc);
     else
-      hipLaunchKernelGGL((k_collide<double, false>), g, b, 0, s, T, gen, in, n_in, live, n_live,
-                         A, Rc);
+      collide_k<double, false>(g, b, lb, s, T, gen, in, n_in, live, n_live, A, Rc);
   } else {
     if (rec)
-      hipLaunchKernelGGL((k_collide<float, true>), g, b, 0, s, T, gen, in, n_in, live, n_live, A,
-                         Rc);
+      collide_k<float, true>(g, b, lb, s, T, gen, in, n_in, live, n_live, A, Rc);
     else
-      hipLaunchKernelGGL((k_collide<float, false>), g, b, 0, s, T, gen, in, n_in, live, n_live, A,
-                         Rc);
+      collide_k<float, false>(g, b, lb, s, T, gen, in, n_in, live, n_live, A, Rc);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_tail(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in, const uint32_t* n_in, const Accum& A, const Records& Rc,
-                       uint32_t bound, hipStream_t s) {
+template <class R, bool REC>
+static void tail_k(dim3 g, dim3 b, size_t lb, hipStream_t s, const Tables& T, uint32_t gen,
+                   const Bank& in, const uint32_t* n_in, const Accum& A, const Records& Rc) {
+  if (lb)
+    hipLaunchKernelGGL((k_tail<R, REC, true>), g, b, lb, s, T, gen, in, n_in, A, Rc);
+  else
+    hipLaunchKernelGGL((k_tail<R, REC, false>), g, b, 0, s, T, gen, in, n_in, A, Rc);
+}
+
+hipError_t launch_tail(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in,
+                       const uint32_t* n_in, const Accum& A, const Records& Rc, uint32_t bound,
+                       hipStream_t s) {
   const dim3 g(std::max(1u, nblk(bound, 64))), b(64);
+  const size_t lb = mg_lds_bytes(prec, T);
   if (prec == 0) {
     if (rec)
-      hipLaunchKernelGGL((k_tail<double, true>), g, b, 0, s, T, gen, in, n_in, A, Rc);
+      tail_k<double, true>(g, b, lb, s, T, gen, in, n_in, A, Rc);
     else
-      hipLaunchKernelGGL((k_tail<double, false>), g, b, 0, s, T, gen, in, n_in, A, Rc);
+      tail_k<double, false>(g, b, lb, s, T, gen, in, n_in, A, Rc);
   } else {
     if (rec)
-      hipLaunchKernelGGL((k_tail<float, true>), g, b, 0, s, T, gen, in, n_in, A, Rc);
+      tail_k<float, true>(g, b, lb, s, T, gen, in, n_in, A, Rc);
     else
-      hipLaunchKernelGGL((k_tail<float, false>), g, b, 0, s, T, gen, in, n_in, A, Rc);
+      tail_k<float, false>(g, b, lb, s, T, gen, in, n_in, A, Rc);
   }
   return hipGetLastError();
 }
@@ -684,25 +778,26 @@ hipError_t launch_canon(const Sites& fis, const uint32_t* n_fis, const uint32_t*
 }
 
 hipError_t launch_gen_totals(const Tables& T, uint32_t gen, uint32_t n, const Accum& A,
-                             double* gen_k, unsigned long long* gen_cnt, uint32_t* gen_m,
-                             double* k_used, double* xi0, hipStream_t s) {
-  hipLaunchKernelGGL(k_gen_totals, dim3(1), dim3(64), 0, s, T, gen, n, A, gen_k, gen_cnt, gen_m,
-                     k_used, xi0);
+                             const double* tl_part, double* gen_k, unsigned long long* gen_cnt,
+                             uint32_t* gen_m, double* k_used, double* xi0, hipStream_t s) {
+  hipLaunchKernelGGL(k_gen_totals, dim3(1), dim3(64), 0, s, T, gen, n, A, tl_part,
+                     gen_tally_blocks(T.n_bins), gen_k, gen_cnt, gen_m, k_used, xi0);
   return hipGetLastError();
 }
 
 hipError_t launch_gen_tallies(const Tables& T, uint32_t gen, uint32_t n, const Accum& A,
-                              double* gen_tal, double* gen_k, hipStream_t s) {
-  hipLaunchKernelGGL(k_gen_tallies, dim3(1), dim3(1024), 0, s, T, gen, n, A, gen_tal, gen_k);
+                              double* gen_tal, double* tl_part, hipStream_t s) {
+  hipLaunchKernelGGL(k_gen_tallies, dim3(std::max(1, gen_tally_blocks(T.n_bins))),
+                     dim3(GT_BLOCK), 0, s, T, gen, n, A, gen_tal, tl_part);
   return hipGetLastError();
 }
 
 hipError_t launch_entropy(const Tables& T, uint32_t gen, const double* cx, const double* cy,
-                          const uint32_t* n_p, uint32_t cap, uint32_t* hist, double* term,
-                          double* gen_h, uint32_t bound, hipStream_t s) {
+                          const uint32_t* n_p, uint32_t cap, uint32_t* hist, double* gen_h,
+                          uint32_t bound, hipStream_t s) {
   const unsigned g = std::max(1u, std::min(nblk(bound, 256 * 16), 1024u));
   hipLaunchKernelGGL(k_entropy_hist, dim3(g), dim3(256), 0, s, T, cx, cy, n_p, cap, hist);
-  hipLaunchKernelGGL(k_entropy_final, dim3(1), dim3(256), 0, s, T, gen, hist, n_p, term, gen_h);
+  hipLaunchKernelGGL(k_entropy_final, dim3(1), dim3(256), 0, s, T, gen, hist, n_p, gen_h);
   return hipGetLastError();
 }
 

@@ -26,14 +26,16 @@ struct Prec;
 template <>
 struct Prec<double> {
   static __device__ __forceinline__ double xi(double u) { return u; }
-  static __device__ __forceinline__ double dcol(double xi, double st) {
-    return -cr_log(xi, log_tab()) / st;
+  static __device__ __forceinline__ double dcol(double xi, double st,
+                                               const double* lt = log_tab()) {
+    return -cr_log(xi, lt) / st;
   }
   static __device__ __forceinline__ double plane(double x, double lo, double hi, double u) {
     return dist_plane(x, lo, hi, u);
   }
-  static __device__ __forceinline__ void iso(double xm, double xp, double* u, double* v) {
-    isotropic_uv(xm, xp, u, v);
+  static __device__ __forceinline__ void iso(double xm, double xp, double* u, double* v,
+                                             const double* sct = sc_tab()) {
+    isotropic_uv(xm, xp, u, v, sct);
   }
 };
 
@@ -44,7 +46,9 @@ struct Prec<float> {
     const float f = (float)u;
     return f < 1.0f ? f : 0x1.fffffep-1f;
   }
-  static __device__ __forceinline__ float dcol(float xi, float st) { return -logf(xi) / st; }
+  static __device__ __forceinline__ float dcol(float xi, float st, const double* = nullptr) {
+    return -logf(xi) / st;
+  }
   static __device__ __forceinline__ float plane(double x, double lo, double hi, float u) {
     float t;
     if (u > 0.0f) {
@@ -56,7 +60,8 @@ struct Prec<float> {
     }
     return t < 0.0f ? 0.0f : t;
   }
-  static __device__ __forceinline__ void iso(float xm, float xp, float* u, float* v) {
+  static __device__ __forceinline__ void iso(float xm, float xp, float* u, float* v,
+                                             const double* = nullptr) {
     const float w = 2.0f * xm - 1.0f;
     const float s2 = 1.0f - w * w;
     const float s = sqrtf(s2 > 0.0f ? s2 : 0.0f);
@@ -88,6 +93,106 @@ __device__ __forceinline__ XSView<double> xs_view<double>(const Tables& T) {
 template <>
 __device__ __forceinline__ XSView<float> xs_view<float>(const Tables& T) {
   return XSView<float>{T.sig_t_f, T.nusf_f, T.sst_f, T.cum_s_f, T.cum_chi_f};
+}
+
+// ---------------------------------------------------------------------------
+// LDS copies of the multigroup tables
+//
+// The lookups of a flight form a dependent chain: lattice cell -> universe ->
+// ring material -> cross section, then the ln table, and at a collision the
+// scattering row and the sin/cos table.  Through the cache hierarchy each
+// link costs a vector-memory round trip, which is what bounds a lone history
+// (the tail).  When the lattice and the working-precision cross sections fit
+// in a few KB, every block of the event kernels first copies them into LDS
+// and runs on the copies.
+// ---------------------------------------------------------------------------
+
+constexpr size_t LDS_TABLES_MAX = 32768;  // bytes per block
+
+MCX_HD size_t lds_round8(size_t b) { return (b + 7) & ~(size_t)7; }
+
+// Bytes of the LDS copy for element size rb of the working precision.
+MCX_HD size_t lds_tables_bytes(const Tables& T, size_t rb) {
+  const Geo& L = T.geo;
+  const size_t nc = (size_t)L.nx * (size_t)L.ny, nu = (size_t)T.n_univ;
+  const size_t mg = (size_t)T.n_mat * (size_t)T.G;
+  return lds_round8(nc * 4) + lds_round8(nu * 4) + lds_round8(nu * (size_t)L.mr1 * 4) +
+         lds_round8(nu * (size_t)L.max_rings * 8) + 4 * lds_round8(mg * rb) +
+         lds_round8(mg * (size_t)T.G * rb) + lds_round8(mg * 4) + lds_round8((size_t)T.n_mat * 4) +
+         (2 * MCX_LOG_TAB_N + 4 * MCX_SINCOS_TAB_N) * 8 +
+         (T.time ? ((size_t)T.nt + 1 + (size_t)T.G) * 8 : 0);
+}
+
+__device__ __forceinline__ const void* lds_put(char* base, uint32_t* off, const void* src,
+                                               size_t bytes) {
+  uint32_t* d = reinterpret_cast<uint32_t*>(base + *off);
+  const uint32_t* s = static_cast<const uint32_t*>(src);
+  const uint32_t n = (uint32_t)(bytes / 4);
+  for (uint32_t w = threadIdx.x; w < n; w += blockDim.x) d[w] = s[w];
+  *off += (uint32_t)lds_round8(bytes);
+  return d;
+}
+
+template <class R>
+__device__ __forceinline__ void set_xs_view(Tables& T, const XSView<R>& X);
+
+template <>
+__device__ __forceinline__ void set_xs_view<double>(Tables& T, const XSView<double>& X) {
+  T.sig_t = X.sig_t;
+  T.nusf = X.nusf;
+  T.sst = X.sst;
+  T.cum_s = X.cum_s;
+  T.cum_chi = X.cum_chi;
+}
+
+template <>
+__device__ __forceinline__ void set_xs_view<float>(Tables& T, const XSView<float>& X) {
+  T.sig_t_f = X.sig_t;
+  T.nusf_f = X.nusf;
+  T.sst_f = X.sst;
+  T.cum_s_f = X.cum_s;
+  T.cum_chi_f = X.cum_chi;
+}
+
+// The tables a kernel runs on: with LDS, copies made by the whole block
+// (every thread of the block must call this, before any early exit);
+// otherwise the arguments with the math tables of constant memory.
+template <class R, bool LDS>
+__device__ __forceinline__ Tables kernel_tables(const Tables& T0) {
+  Tables T = T0;
+  if constexpr (!LDS) {
+    T.lt = log_tab();
+    T.sct = sc_tab();
+  } else {
+    extern __shared__ __align__(16) char lds_tab[];
+    const Geo& L = T0.geo;
+    const size_t nc = (size_t)L.nx * L.ny, nu = (size_t)T0.n_univ;
+    const size_t mg = (size_t)T0.n_mat * T0.G, rb = sizeof(R);
+    uint32_t off = 0;
+    T.geo.pin_map = (const int*)lds_put(lds_tab, &off, L.pin_map, nc * 4);
+    T.geo.n_rings = (const int*)lds_put(lds_tab, &off, L.n_rings, nu * 4);
+    T.geo.mats = (const int*)lds_put(lds_tab, &off, L.mats, nu * L.mr1 * 4);
+    T.geo.radii = (const double*)lds_put(lds_tab, &off, L.radii, nu * L.max_rings * 8);
+    const XSView<R> X = xs_view<R>(T0);
+    XSView<R> Y;
+    Y.sig_t = (const R*)lds_put(lds_tab, &off, X.sig_t, mg * rb);
+    Y.nusf = (const R*)lds_put(lds_tab, &off, X.nusf, mg * rb);
+    Y.sst = (const R*)lds_put(lds_tab, &off, X.sst, mg * rb);
+    Y.cum_chi = (const R*)lds_put(lds_tab, &off, X.cum_chi, mg * rb);
+    Y.cum_s = (const R*)lds_put(lds_tab, &off, X.cum_s, mg * T0.G * rb);
+    set_xs_view<R>(T, Y);
+    T.last_s = (const int*)lds_put(lds_tab, &off, T0.last_s, mg * 4);
+    T.last_chi = (const int*)lds_put(lds_tab, &off, T0.last_chi, (size_t)T0.n_mat * 4);
+    T.lt = (const double*)lds_put(lds_tab, &off, log_tab(), 2 * MCX_LOG_TAB_N * 8);
+    T.sct = (const double*)lds_put(lds_tab, &off, sc_tab(), 4 * MCX_SINCOS_TAB_N * 8);
+    // (without a time grid the pointers are set but never read, so that
+    // every table access of the kernel stays an LDS access)
+    const size_t nte = T0.time ? (size_t)T0.nt + 1 : 0, nsp = T0.time ? (size_t)T0.G : 0;
+    T.t_edges = (const double*)lds_put(lds_tab, &off, T0.t_edges, nte * 8);
+    T.speed = (const double*)lds_put(lds_tab, &off, T0.speed, nsp * 8);
+    __syncthreads();
+  }
+  return T;
 }
 
 // ---------------------------------------------------------------------------
@@ -172,7 +277,7 @@ __device__ __forceinline__ int segment(const Tables& T, const Geo& L, Part<R>& p
 
   // distance to collision: exponential with mean 1 / sig_t
   const R xi = Prec<R>::xi(rs.next());
-  const R d_col = Prec<R>::dcol(xi, st);
+  const R d_col = Prec<R>::dcol(xi, st, T.lt);
 
   // distance to boundary: the cell's planes ahead and the region's rings
   const double xlo = L.x0 + (double)p.i * L.pitch, xhi = L.x0 + (double)(p.i + 1) * L.pitch;
@@ -197,7 +302,7 @@ __device__ __forceinline__ int segment(const Tables& T, const Geo& L, Part<R>& p
   // that comes first (census)
   bool census = false;
   double vg = 0.0;
-  if (T.t_edges) {
+  if (T.time) {
     vg = T.speed[p.g];
     const double d_cen = (T.t_max - p.t) * vg;
     if (d_cen < d) {
@@ -216,7 +321,7 @@ __device__ __forceinline__ int segment(const Tables& T, const Geo& L, Part<R>& p
   const int bin = L.bin_base + ((c * L.mr1 + p.r) * T.G + p.g) * T.nt;
   unsigned long long* tb =
       A.tally + (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
-  if (T.t_edges) {
+  if (T.time) {
     // split the flight over the time bins it spans
     double t1 = census ? T.t_max : p.t + d / vg;
     if (t1 > T.t_max) t1 = T.t_max;
@@ -374,7 +479,7 @@ __device__ __forceinline__ bool collide_rest(const Tables& T, Part<R>& p, Stream
     p.g = sample_cum(xg, X.cum_s + (size_t)row * G, G, T.last_s[row]);
     const R xm = Prec<R>::xi(rs.next());
     const R xp = Prec<R>::xi(rs.next());
-    Prec<R>::iso(xm, xp, &p.u, &p.v);
+    Prec<R>::iso(xm, xp, &p.u, &p.v, T.sct);
     *q_kabs = 0;
     return true;
   }
@@ -479,10 +584,12 @@ __device__ __forceinline__ double stripes_to_double(const unsigned long long* pa
 }
 
 // Exact flux sum of one bin: the striped 128-bit pairs of the event kernels
-// plus the (low-half sum, high-half sum) pair of the tail kernel.
-__device__ __forceinline__ double flux_total(const unsigned long long* pairs, int n_stripes, size_t stride,
-                             const unsigned long long* halves) {
-  unsigned long long w0 = 0, w1 = 0;
+// plus the (low-half sum, high-half sum) pair of the tail kernel (exact while
+// each of its words takes fewer than 2^32 terms, which the flight count of
+// the generation bounds).
+__device__ __forceinline__ double flux_total(const unsigned long long* pairs, int n_stripes,
+                                             size_t stride, const unsigned long long* halves) {
+  unsigned long long w0 = 0, w1 = 0;  // value = w1 * 2^64 + w0
   for (int s = 0; s < n_stripes; ++s) {
     const unsigned long long lo = pairs[(size_t)s * stride + 0];
     const unsigned long long hi = pairs[(size_t)s * stride + 1];
@@ -499,6 +606,5 @@ __device__ __forceinline__ double flux_total(const unsigned long long* pairs, in
   w0 = t;
   return u128_to_double(w0, w1);
 }
-
 
 }  // namespace mcx

@@ -38,14 +38,18 @@ hipError_t launch_canon(const Sites& fis, const uint32_t* n_fis, const uint32_t*
                         const uint32_t* nsite_id, uint32_t cap, double* cx, double* cy,
                         int32_t* cg, double* ce, uint32_t* status, uint32_t bound,
                         hipStream_t s);
-hipError_t launch_gen_totals(const Tables& T, uint32_t gen, uint32_t n, const Accum& A,
-                             double* gen_k, unsigned long long* gen_cnt, uint32_t* gen_m,
-                             double* k_used, double* xi0, hipStream_t s);
+// k_gen_tallies leaves one (sum, compensation) pair per block in tl_part
+// (gen_tally_blocks(n_bins) pairs); k_gen_totals, launched after it, sums
+// them into the track-length estimator.
+int gen_tally_blocks(int n_bins);
 hipError_t launch_gen_tallies(const Tables& T, uint32_t gen, uint32_t n, const Accum& A,
-                              double* gen_tal, double* gen_k, hipStream_t s);
+                              double* gen_tal, double* tl_part, hipStream_t s);
+hipError_t launch_gen_totals(const Tables& T, uint32_t gen, uint32_t n, const Accum& A,
+                             const double* tl_part, double* gen_k, unsigned long long* gen_cnt,
+                             uint32_t* gen_m, double* k_used, double* xi0, hipStream_t s);
 hipError_t launch_entropy(const Tables& T, uint32_t gen, const double* cx, const double* cy,
-                          const uint32_t* n_p, uint32_t cap, uint32_t* hist, double* term,
-                          double* gen_h, uint32_t bound, hipStream_t s);
+                          const uint32_t* n_p, uint32_t cap, uint32_t* hist, double* gen_h,
+                          uint32_t bound, hipStream_t s);
 hipError_t launch_comb(uint32_t n, const uint32_t* m_p, uint32_t cap, const double* xi0,
                        const double* cx, const double* cy, const int32_t* cg, const double* ce,
                        double* sx, double* sy, int32_t* sg, double* se, hipStream_t s);

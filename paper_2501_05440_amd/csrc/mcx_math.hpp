@@ -163,16 +163,6 @@ MCX_HD dd dd_mul_d(dd x, double y) {
   return fast_two_sum(p.hi, p.lo);
 }
 
-MCX_HD dd dd_div(dd x, dd y) {
-  const double q1 = x.hi / y.hi;
-  dd r = dd_add(x, dd_neg(dd_mul_d(y, q1)));
-  const double q2 = r.hi / y.hi;
-  r = dd_add(r, dd_neg(dd_mul_d(y, q2)));
-  const double q3 = r.hi / y.hi;
-  dd q = fast_two_sum(q1, q2);
-  return dd_add(q, dd{q3, 0.0});
-}
-
 MCX_HD uint64_t as_u64(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   return (uint64_t)__double_as_longlong(x);
@@ -222,13 +212,19 @@ MCX_HD double cr_log(double x, const double* log_tab) {
   const int j = (int)rint(m * 256.0);
   const double F = (double)j * 0x1p-8;
   const double f = m - F;  // exact
-  const double uh = f / F;
-  const double ul = fma(-uh, F, f) / F;
-  const dd u{uh, ul};
-  dd den = two_sum(2.0, uh);
-  den.lo += ul;
-  den = fast_two_sum(den.hi, den.lo);
-  const dd s = dd_div(u, den);
+  // s = u / (2 + u) = f / (m + F) in double-double: D = m + F exactly as a
+  // pair and one reciprocal of its high part; the quotient's residual comes
+  // from an fma (exact up to a rounding of relative size 2^-105), and the low
+  // part takes one more residual step, so that it is within about half an
+  // ulp of the true remainder quotient (the reciprocal alone is off by up to
+  // 2^-53 relative, too much for arguments next to 1)
+  const dd D = two_sum(m, F);
+  const double rD = 1.0 / D.hi;
+  const double sh = f * rD;
+  const double rem = fma(-sh, D.hi, f) - sh * D.lo;
+  const double sl1 = rem * rD;
+  const double rem2 = fma(-sl1, D.hi, rem) - sl1 * D.lo;
+  const dd s = fast_two_sum(sh, sl1 + rem2 * rD);
   const dd s2 = dd_mul(s, s);
   const dd s3 = dd_mul(s2, s);
   const double z = s2.hi;

@@ -143,11 +143,12 @@ __device__ __forceinline__ void slot_death(SlotMem<R, S>& M, int s, const Part<R
 }
 
 template <class R, int PB, int S>
-__global__ void __launch_bounds__(PB) k_persistent(Tables T, uint32_t gen, Accum A, HistOut H,
+__global__ void __launch_bounds__(PB) k_persistent(Tables T0, uint32_t gen, Accum A, HistOut H,
                                                    uint32_t* work, uint32_t tau,
                                                    const double* sx, const double* sy,
                                                    const int32_t* sg,
                                                    const uint32_t* prev_status, int sort) {
+  const Tables T = kernel_tables<R, false>(T0);
   extern __shared__ unsigned char lds_raw[];
   SlotMem<R, S>& M = *reinterpret_cast<SlotMem<R, S>*>(lds_raw);
   const ProbDesc* P = T.probs;

@@ -50,6 +50,16 @@ def test_host_math_edges(oracle):
     assert np.array_equal(mcx.host_math(1, t), [oracle.cr_cossin_2pi(v) for v in t])
 
 
+def test_host_log_next_to_one_and_table_knots(oracle):
+    """Arguments 1 - k 2^-53 and 1 + k 2^-52 have logarithms within about
+    2^-105 relative of a rounding midpoint; so do arguments next to the
+    ends of the reduction interval."""
+    k = np.arange(1, 4097, dtype=np.float64)
+    x = np.concatenate([1 - k * 2.0**-53, 1 + k * 2.0**-52, 181 / 256 * (1 + k * 2.0**-52),
+                        362 / 256 * (1 - k * 2.0**-53), 0.5 - k * 2.0**-54])
+    assert np.array_equal(mcx.host_math(0, x), [oracle.cr_log(v) for v in x])
+
+
 def test_host_math_rejects_bad_selector():
     with pytest.raises(mcx.MCXError):
         mcx.host_math(9, np.ones(3))
