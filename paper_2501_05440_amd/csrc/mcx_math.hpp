@@ -56,11 +56,22 @@ struct u64x4 {
   uint64_t v[4];
 };
 
-MCX_HD uint64_t mulhi64(uint64_t a, uint64_t b) {
+// Full 64 x 64 -> 128-bit product.  On the device, from four 32 x 32 + 64
+// multiply-adds (each partial sum below fits in 64 bits), which yields the
+// low and the high word together.
+MCX_HD void mul128(uint64_t a, uint64_t b, uint64_t* lo, uint64_t* hi) {
 #if defined(__HIP_DEVICE_COMPILE__)
-  return __umul64hi(a, b);
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const uint64_t p00 = (uint64_t)a0 * b0;
+  const uint64_t t = (uint64_t)a0 * b1 + (p00 >> 32);
+  const uint64_t u = (uint64_t)a1 * b0 + (uint32_t)t;
+  *lo = (u << 32) | (uint32_t)p00;
+  *hi = (uint64_t)a1 * b1 + (t >> 32) + (u >> 32);
 #else
-  return (uint64_t)(((unsigned __int128)a * b) >> 64);
+  const unsigned __int128 p = (unsigned __int128)a * b;
+  *lo = (uint64_t)p;
+  *hi = (uint64_t)(p >> 64);
 #endif
 }
 
@@ -70,8 +81,9 @@ MCX_HD u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, u
   const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint64_t hi0 = mulhi64(M0, c0), lo0 = M0 * c0;
-    const uint64_t hi1 = mulhi64(M1, c2), lo1 = M1 * c2;
+    uint64_t hi0, lo0, hi1, lo1;
+    mul128(M0, c0, &lo0, &hi0);
+    mul128(M1, c2, &lo1, &hi1);
     const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
     c1 = lo1;
