@@ -24,7 +24,6 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per processed particle (FP64 bank entry: x, y, u, v as f64,
 # cell, group|sites, draw counter, id, flight count as u32 = 52 B)
 STATE_BYTES = 52
-SITE_BYTES = 28  # banked fission site: x, y (f64), group, parent, sequence (u32)
 TALLY_BYTES_ADV = 16  # one 64-bit fixed-point flux atomic (read-modify-write) per flight
 COUNTERS = os.path.join(ROOT, "profiles", "k_advance_lattice17x17_counters.md")
 KERNEL_SOURCES = ["paper_2501_05440_amd/csrc/mcx_kernels.hip",
@@ -297,14 +296,16 @@ def main():
     N, G = a.n_per_gen, a.n_gen
     print(f"[bench] lattice 17x17, {N} histories x {G} generations, steps={a.steps} "
           f"warmup={a.warmup}", file=sys.stderr, flush=True)
+    # the timed steps record HIP events around the advance launches only (each
+    # event between two launches delays the next one a little)
     ctx = mcx.Context(prob, device=0, block_size=a.block, tail_threshold=a.tail,
-                      time_kernels=True, flights=a.flights)
+                      time_kernels="advance", flights=a.flights)
     for w in range(a.warmup):
         ctx.run()
         print(f"[bench] warmup {w + 1}/{a.warmup} done", file=sys.stderr, flush=True)
     tot = dict(advance_ms=0.0, collide_ms=0.0, tail_ms=0.0, n_advance=0, n_collide=0,
                advance_items=0, collide_items=0, advance_segments=0, n_iterations=0, run_ms=0.0)
-    segs = cols = scats = sites = 0
+    segs = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(a.steps):
@@ -314,9 +315,6 @@ def main():
             tot[key] += t[key]
         _, c = ctx.generation_stats()
         segs += int(c[:, 0].sum())
-        cols += int(c[:, 1].sum())
-        sites += int(c[:, 7].sum())
-        scats += int(c[:, 8].sum())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
@@ -325,35 +323,38 @@ def main():
     histories = a.steps * N * G
     value = histories / elapsed
 
-    # roofline of the dominant event kernel
+    # per-kernel breakdown: one more step, outside the timed region, with every
+    # event kernel timed
+    bctx = mcx.Context(prob, device=0, block_size=a.block, tail_threshold=a.tail,
+                       time_kernels=True, flights=a.flights)
+    bctx.run()
+    brk = bctx.timing()
+    bctx.close()
+
+    # roofline of the dominant event kernel, the advance kernel (the largest
+    # summed time of the breakdown step), timed over the timed steps
     adv_avg_ms = tot["advance_ms"] / max(1, tot["n_advance"])
-    col_avg_ms = tot["collide_ms"] / max(1, tot["n_collide"])
     adv_items = tot["advance_items"] / max(1, tot["n_advance"])
-    col_items = tot["collide_items"] / max(1, tot["n_collide"])
     adv_flights = tot["advance_segments"] / max(1, tot["advance_items"])
     adv_bytes = 2 * STATE_BYTES + TALLY_BYTES_ADV * adv_flights
-    col_bytes = STATE_BYTES + STATE_BYTES * (scats / max(1, cols)) + SITE_BYTES * (sites / max(1, cols))
-    if tot["advance_ms"] >= tot["collide_ms"]:
-        name, avg_ms, per_launch = "k_advance", adv_avg_ms, adv_items * adv_bytes
-        per_item = adv_bytes
-    else:
-        name, avg_ms, per_launch = "k_collide", col_avg_ms, col_items * col_bytes
-        per_item = col_bytes
+    name, avg_ms, per_launch = "k_advance", adv_avg_ms, adv_items * adv_bytes
+    per_item = adv_bytes
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     traffic = None
-    tpi = measured_traffic_per_item() if name == "k_advance" else None
+    tpi = measured_traffic_per_item()
     if tpi is not None:
         traffic = round(tpi * adv_items)  # HBM bytes per launch
     roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "bytes_per_item": round(per_item, 2),
-                "items_per_launch": round(adv_items if name == "k_advance" else col_items, 1),
+                "items_per_launch": round(adv_items, 1),
                 "avg_launch_us": round(avg_ms * 1e3, 2),
                 "flights_per_advance_item": round(adv_flights, 4),
                 "iterations_per_generation": round(tot["n_iterations"] / (a.steps * G), 2),
-                "kernel_ms_per_step": {"advance": round(tot["advance_ms"] / a.steps, 2),
-                                       "collide": round(tot["collide_ms"] / a.steps, 2),
-                                       "tail": round(tot["tail_ms"] / a.steps, 2)}}
+                "kernel_ms_per_step": {"advance": round(brk["advance_ms"], 2),
+                                       "collide": round(brk["collide_ms"], 2),
+                                       "tail": round(brk["tail_ms"], 2),
+                                       "note": "one extra step with every event kernel timed"}}
 
     cpu = None
     if not a.no_cpu_baseline:

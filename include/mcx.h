@@ -94,7 +94,9 @@ typedef struct {
                                read back; 0 = default (4) */
   int64_t max_events;       /* per-history segment guard; 0 = 100000 */
   int32_t record_histories; /* 1: keep one mcx_record per history per generation */
-  int32_t time_kernels;     /* 1: time every event kernel with HIP events (mcx_get_timing) */
+  int32_t time_kernels;     /* 1: time every event kernel with HIP events (mcx_get_timing);
+                               2: time only the advance kernels (fewer events between
+                               launches, each of which delays the next launch a little) */
   /* Engine.  MCX_ENGINE_EVENT launches one kernel per event class and
      iteration over banks compacted in device memory (the structure of the
      paper's Sec. 2).  MCX_ENGINE_PERSISTENT runs each generation (or batch)
@@ -179,7 +181,8 @@ typedef struct {
 } mcx_event;
 
 /* Timing of the last mcx_run_generations or mcx_run_batch.  The *_ms kernel sums are filled
-   when time_kernels = 1 (events recorded on the stream around each launch);
+   when time_kernels = 1 (events recorded on the stream around each launch; with
+   time_kernels = 2 only advance_ms / n_advance);
    *_items count the particles each kernel class processed. */
 typedef struct {
   double run_ms;            /* stream time of the whole run, generation ends included */

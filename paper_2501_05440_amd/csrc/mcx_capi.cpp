@@ -1042,12 +1042,14 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
 
 // Enqueue a timing event pair around a launch when kernel timing is on.
 static hipError_t time_mark(mcx_ctx* c, int kind, bool begin) {
-  if (!c->opt.time_kernels) return hipSuccess;
+  if (!c->opt.time_kernels || (c->opt.time_kernels == 2 && kind != 0)) return hipSuccess;
   if (begin) c->ev_kind.push_back(kind);
   const size_t k = (c->ev_kind.size() - 1) * 2 + (begin ? 0 : 1);
   while (c->ev_pool.size() <= k) {
     hipEvent_t e;
-    hipError_t r = hipEventCreate(&e);
+    // device-scope release: a timing mark must not flush caches to the
+    // system between two kernels (the default system-scope release does)
+    hipError_t r = hipEventCreateWithFlags(&e, hipEventReleaseToDevice);
     if (r != hipSuccess) return r;
     c->ev_pool.push_back(e);
   }

@@ -262,7 +262,8 @@ class Context:
         o.flights = flights
         o.event_log = event_log
         self.event_log = event_log
-        o.time_kernels = int(bool(time_kernels))
+        # True / 1: every event kernel; "advance" / 2: the advance kernels only
+        o.time_kernels = 2 if time_kernels in ("advance", 2) else int(bool(time_kernels))
         h = C.c_void_p()
         self._check(L.mcx_create(C.byref(h), C.byref(o)), None)
         self.h = h
