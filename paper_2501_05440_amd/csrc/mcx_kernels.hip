@@ -71,12 +71,13 @@ __global__ void __launch_bounds__(1024) k_advance(Tables T0, uint32_t gen, uint3
                                                   uint32_t* n_live, Bank col, uint32_t* n_col,
                                                   Accum A, Records Rc, uint32_t* clr_live,
                                                   uint32_t* clr_col) {
-  const Tables T = kernel_tables<R, LDS>(T0);
+  const uint32_t n_in = *n_in_p;
+  // blocks past the live count (grids are sized from a bound) skip the copy
+  const Tables T = kernel_tables<R, LDS>(T0, blockIdx.x * blockDim.x < n_in);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *clr_live = 0;
     *clr_col = 0;
   }
-  const uint32_t n_in = *n_in_p;
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   int ev = EV_NONE;
   uint32_t c_seg = 0, c_cross = 0, c_refl = 0;
@@ -123,8 +124,8 @@ template <class R, bool REC, bool LDS>
 __global__ void __launch_bounds__(1024) k_collide(Tables T0, uint32_t gen, Bank in,
                                                   const uint32_t* __restrict__ n_in_p, Bank live,
                                                   uint32_t* n_live, Accum A, Records Rc) {
-  const Tables T = kernel_tables<R, LDS>(T0);
   const uint32_t n_in = *n_in_p;
+  const Tables T = kernel_tables<R, LDS>(T0, blockIdx.x * blockDim.x < n_in);
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = k < n_in;
   const double k_used = *A.k_used;
@@ -172,8 +173,8 @@ template <class R, bool REC, bool LDS>
 __global__ void __launch_bounds__(256) k_tail(Tables T0, uint32_t gen, Bank in,
                                               const uint32_t* __restrict__ n_in_p, Accum A,
                                               Records Rc) {
-  const Tables T = kernel_tables<R, LDS>(T0);
   const uint32_t n_in = *n_in_p;
+  const Tables T = kernel_tables<R, LDS>(T0, blockIdx.x * blockDim.x < n_in);
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long c_seg = 0, c_col = 0, c_cross = 0, c_refl = 0, c_leak = 0, c_abs = 0,
                      c_kill = 0, c_sites = 0, c_scat = 0, c_cen = 0;

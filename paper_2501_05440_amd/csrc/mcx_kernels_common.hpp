@@ -124,10 +124,10 @@ MCX_HD size_t lds_tables_bytes(const Tables& T, size_t rb) {
 }
 
 __device__ __forceinline__ const void* lds_put(char* base, uint32_t* off, const void* src,
-                                               size_t bytes) {
+                                               size_t bytes, bool copy) {
   uint32_t* d = reinterpret_cast<uint32_t*>(base + *off);
   const uint32_t* s = static_cast<const uint32_t*>(src);
-  const uint32_t n = (uint32_t)(bytes / 4);
+  const uint32_t n = copy ? (uint32_t)(bytes / 4) : 0u;
   for (uint32_t w = threadIdx.x; w < n; w += blockDim.x) d[w] = s[w];
   *off += (uint32_t)lds_round8(bytes);
   return d;
@@ -155,10 +155,11 @@ __device__ __forceinline__ void set_xs_view<float>(Tables& T, const XSView<float
 }
 
 // The tables a kernel runs on: with LDS, copies made by the whole block
-// (every thread of the block must call this, before any early exit);
+// (every thread of the block must call this, before any early exit; a block
+// with no work passes copy = false and must then not read the tables);
 // otherwise the arguments with the math tables of constant memory.
 template <class R, bool LDS>
-__device__ __forceinline__ Tables kernel_tables(const Tables& T0) {
+__device__ __forceinline__ Tables kernel_tables(const Tables& T0, bool copy = true) {
   Tables T = T0;
   if constexpr (!LDS) {
     T.lt = log_tab();
@@ -169,27 +170,27 @@ __device__ __forceinline__ Tables kernel_tables(const Tables& T0) {
     const size_t nc = (size_t)L.nx * L.ny, nu = (size_t)T0.n_univ;
     const size_t mg = (size_t)T0.n_mat * T0.G, rb = sizeof(R);
     uint32_t off = 0;
-    T.geo.pin_map = (const int*)lds_put(lds_tab, &off, L.pin_map, nc * 4);
-    T.geo.n_rings = (const int*)lds_put(lds_tab, &off, L.n_rings, nu * 4);
-    T.geo.mats = (const int*)lds_put(lds_tab, &off, L.mats, nu * L.mr1 * 4);
-    T.geo.radii = (const double*)lds_put(lds_tab, &off, L.radii, nu * L.max_rings * 8);
+    T.geo.pin_map = (const int*)lds_put(lds_tab, &off, L.pin_map, nc * 4, copy);
+    T.geo.n_rings = (const int*)lds_put(lds_tab, &off, L.n_rings, nu * 4, copy);
+    T.geo.mats = (const int*)lds_put(lds_tab, &off, L.mats, nu * L.mr1 * 4, copy);
+    T.geo.radii = (const double*)lds_put(lds_tab, &off, L.radii, nu * L.max_rings * 8, copy);
     const XSView<R> X = xs_view<R>(T0);
     XSView<R> Y;
-    Y.sig_t = (const R*)lds_put(lds_tab, &off, X.sig_t, mg * rb);
-    Y.nusf = (const R*)lds_put(lds_tab, &off, X.nusf, mg * rb);
-    Y.sst = (const R*)lds_put(lds_tab, &off, X.sst, mg * rb);
-    Y.cum_chi = (const R*)lds_put(lds_tab, &off, X.cum_chi, mg * rb);
-    Y.cum_s = (const R*)lds_put(lds_tab, &off, X.cum_s, mg * T0.G * rb);
+    Y.sig_t = (const R*)lds_put(lds_tab, &off, X.sig_t, mg * rb, copy);
+    Y.nusf = (const R*)lds_put(lds_tab, &off, X.nusf, mg * rb, copy);
+    Y.sst = (const R*)lds_put(lds_tab, &off, X.sst, mg * rb, copy);
+    Y.cum_chi = (const R*)lds_put(lds_tab, &off, X.cum_chi, mg * rb, copy);
+    Y.cum_s = (const R*)lds_put(lds_tab, &off, X.cum_s, mg * T0.G * rb, copy);
     set_xs_view<R>(T, Y);
-    T.last_s = (const int*)lds_put(lds_tab, &off, T0.last_s, mg * 4);
-    T.last_chi = (const int*)lds_put(lds_tab, &off, T0.last_chi, (size_t)T0.n_mat * 4);
-    T.lt = (const double*)lds_put(lds_tab, &off, log_tab(), 2 * MCX_LOG_TAB_N * 8);
-    T.sct = (const double*)lds_put(lds_tab, &off, sc_tab(), 4 * MCX_SINCOS_TAB_N * 8);
+    T.last_s = (const int*)lds_put(lds_tab, &off, T0.last_s, mg * 4, copy);
+    T.last_chi = (const int*)lds_put(lds_tab, &off, T0.last_chi, (size_t)T0.n_mat * 4, copy);
+    T.lt = (const double*)lds_put(lds_tab, &off, log_tab(), 2 * MCX_LOG_TAB_N * 8, copy);
+    T.sct = (const double*)lds_put(lds_tab, &off, sc_tab(), 4 * MCX_SINCOS_TAB_N * 8, copy);
     // (without a time grid the pointers are set but never read, so that
     // every table access of the kernel stays an LDS access)
     const size_t nte = T0.time ? (size_t)T0.nt + 1 : 0, nsp = T0.time ? (size_t)T0.G : 0;
-    T.t_edges = (const double*)lds_put(lds_tab, &off, T0.t_edges, nte * 8);
-    T.speed = (const double*)lds_put(lds_tab, &off, T0.speed, nsp * 8);
+    T.t_edges = (const double*)lds_put(lds_tab, &off, T0.t_edges, nte * 8, copy);
+    T.speed = (const double*)lds_put(lds_tab, &off, T0.speed, nsp * 8, copy);
     __syncthreads();
   }
   return T;
