@@ -747,7 +747,7 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   d.cnt_col = cv.take<uint32_t>(n_cnt_slots);
   // per-generation accumulators, zeroed together
   const size_t w_tally = (size_t)stripes * 2 * nb;
-  const size_t w_tally_t = (size_t)2 * nb;
+  const size_t w_tally_t = (size_t)stripes * 2 * nb;
   const size_t w_k = 3 * STRIPES * 2;
   const size_t w_cnt = (size_t)N_CNT_ALL * STRIPES;
   const size_t w_misc = 2 + (n_ent + 1) / 2;

@@ -367,15 +367,14 @@ __device__ __forceinline__ int segment_ce(const Tables& T, const Geo& L, PartCE<
   const int b = ce_interval<R>(CEP<R>::edges(T), T.n_ebins + 1, p.e);
   const int bin = L.bin_base + (c * L.mr1 + p.r) * T.n_ebins + b;
   const uint64_t qf = quantize(d, T.q_flux);
+  const size_t stripe_off = (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
   if (HALVES) {
     if (qf) {
-      atomicAdd(A.tally_t + 2 * bin, (unsigned long long)(qf & 0xFFFFFFFFull));
-      atomicAdd(A.tally_t + 2 * bin + 1, (unsigned long long)(qf >> 32));
+      atomicAdd(A.tally_t + stripe_off + 2 * bin, (unsigned long long)(qf & 0xFFFFFFFFull));
+      atomicAdd(A.tally_t + stripe_off + 2 * bin + 1, (unsigned long long)(qf >> 32));
     }
   } else {
-    unsigned long long* tb =
-        A.tally + (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
-    acc_add(tb + 2 * bin, qf);
+    acc_add(A.tally + stripe_off + 2 * bin, qf);
   }
   *q_tl = quantize(d * (double)nusf, T.q_ktl);
   int k_ev = 0;
@@ -686,67 +685,81 @@ __global__ void __launch_bounds__(256) k_ce_tail(Tables T, uint32_t gen, Bank in
   unsigned long long c_seg = 0, c_col = 0, c_cross = 0, c_refl = 0, c_leak = 0, c_abs = 0,
                      c_kill = 0, c_sites = 0, c_scat = 0, c_cut = 0;
   unsigned long long kcol[2] = {0, 0}, kabs[2] = {0, 0}, ktl[2] = {0, 0};
-  if (k < n_in) {
-    const double k_used = *A.k_used;
-    PartCE<R> p = load_ce<R>(in, k);
-    Stream rs(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
-    int64_t nseg = p.nseg;
-    for (;;) {
+  // one pass of the loop is one flight of every live lane of the wave; the
+  // fission sites of a pass are reserved with one atomic per wave
+  const double k_used = *A.k_used;
+  bool live = k < n_in;
+  PartCE<R> p;
+  Stream rs(T.seed, TAG_TRANSPORT, 0, gen, T.prob, 0);
+  int64_t nseg = 0;
+  if (live) {
+    p = load_ce<R>(in, k);
+    rs = Stream(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
+    nseg = p.nseg;
+  }
+  while (__ballot(live) != 0ull) {
+    bool col = false;
+    ColCE<R> c{};
+    uint32_t nf = 0;
+    if (live) {
       if (nseg >= T.max_events) {
         p.ctr = rs.draw;
         die_ce<R, REC>(p, FATE_KILLED, A, Rc, T);
         ++c_kill;
-        break;
+        live = false;
+      } else {
+        bool refl = false;
+        uint64_t q = 0;
+        const int ev = segment_ce<R, REC, true>(T, T.geo, p, rs, A, Rc, &refl, &q);
+        ktl[0] += q & 0xFFFFFFFFull;
+        ktl[1] += q >> 32;
+        ++nseg;
+        ++c_seg;
+        if (ev == EV_LEAK) {
+          ++c_cross;
+          ++c_leak;
+          p.ctr = rs.draw;
+          die_ce<R, REC>(p, FATE_LEAKED, A, Rc, T);
+          live = false;
+        } else if (ev == EV_CROSS) {
+          ++c_cross;
+          c_refl += refl ? 1 : 0;
+        } else {
+          ++c_col;
+          c = col_ce<R>(T, T.geo, p);
+          const double kc = (double)(c.nusf / c.x.st);
+          const uint64_t qk = quantize(kc, T.q_kcol);
+          kcol[0] += qk & 0xFFFFFFFFull;
+          kcol[1] += qk >> 32;
+          if (REC) {
+            Rc.n_col[p.id] += 1;
+            Rc.kcol_sum[p.id] += kc;
+          }
+          nf = fission_count_ce<R>(T, c, rs, k_used);
+          col = true;
+        }
       }
-      bool refl = false;
-      uint64_t q = 0;
-      const int ev = segment_ce<R, REC, true>(T, T.geo, p, rs, A, Rc, &refl, &q);
-      ktl[0] += q & 0xFFFFFFFFull;
-      ktl[1] += q >> 32;
-      ++nseg;
-      ++c_seg;
-      if (ev == EV_LEAK) {
-        ++c_cross;
-        ++c_leak;
-        p.ctr = rs.draw;
-        die_ce<R, REC>(p, FATE_LEAKED, A, Rc, T);
-        break;
-      }
-      if (ev == EV_CROSS) {
-        ++c_cross;
-        c_refl += refl ? 1 : 0;
-        continue;
-      }
-      ++c_col;
-      const ColCE<R> c = col_ce<R>(T, T.geo, p);
-      const double kc = (double)(c.nusf / c.x.st);
-      const uint64_t qk = quantize(kc, T.q_kcol);
-      kcol[0] += qk & 0xFFFFFFFFull;
-      kcol[1] += qk >> 32;
-      if (REC) {
-        Rc.n_col[p.id] += 1;
-        Rc.kcol_sum[p.id] += kc;
-      }
-      const uint32_t nf = fission_count_ce<R>(T, c, rs, k_used);
-      const uint32_t slot = nf ? atomicAdd(A.n_fis, nf) : 0u;
+    }
+    const uint32_t slot = __ballot(nf != 0) ? wave_reserve(nf, A.n_fis) : 0u;
+    if (col) {
       c_sites += nf;
       uint64_t qa = 0;
       const int fate = collide_rest_ce<R>(T, p, rs, c, nf, slot, A, &qa);
       if (fate == FATE_ALIVE) {
         ++c_scat;
-        continue;
-      }
-      p.ctr = rs.draw;
-      if (fate == FATE_CUTOFF) {
-        ++c_scat;
-        ++c_cut;
       } else {
-        kabs[0] += qa & 0xFFFFFFFFull;
-        kabs[1] += qa >> 32;
-        ++c_abs;
+        p.ctr = rs.draw;
+        if (fate == FATE_CUTOFF) {
+          ++c_scat;
+          ++c_cut;
+        } else {
+          kabs[0] += qa & 0xFFFFFFFFull;
+          kabs[1] += qa >> 32;
+          ++c_abs;
+        }
+        die_ce<R, REC>(p, fate, A, Rc, T);
+        live = false;
       }
-      die_ce<R, REC>(p, fate, A, Rc, T);
-      break;
     }
   }
   wave_count(A.cnt + CNT_SEG * STRIPES, c_seg);

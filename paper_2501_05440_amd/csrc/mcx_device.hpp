@@ -222,7 +222,7 @@ MCX_HD void log_flight(const Records& Rc, uint32_t id, int k, double x, double y
 // Per-generation accumulators (zeroed at the start of every generation).
 struct Accum {
   unsigned long long* tally;  // flux: [stripe][bin] (lo, hi) 128-bit pairs
-  unsigned long long* tally_t;  // flux from the tail kernel: [bin] (sum of low, high 32-bit halves)
+  unsigned long long* tally_t;  // flux from the tail kernels: [stripe][bin] (sum of low, high 32-bit halves)
   unsigned long long* k;      // [3][STRIPES][2 halves]
   unsigned long long* cnt;    // [N_CNT_ALL][STRIPES]
   uint32_t* n_fis;            // fission sites appended

@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(1024) k_collide(Tables T0, uint32_t gen, Bank 
 
 // History-based finish of the last live particles: one lane runs its
 // particle's remaining flights and collisions to the end (the same
-// operations as the event kernels, in the same order).
+// operations as the event kernels, in the same order).  One wave per block.
 template <class R, bool REC, bool LDS>
 __global__ void __launch_bounds__(256) k_tail(Tables T0, uint32_t gen, Bank in,
                                               const uint32_t* __restrict__ n_in_p, Accum A,
@@ -179,68 +179,83 @@ __global__ void __launch_bounds__(256) k_tail(Tables T0, uint32_t gen, Bank in,
   unsigned long long c_seg = 0, c_col = 0, c_cross = 0, c_refl = 0, c_leak = 0, c_abs = 0,
                      c_kill = 0, c_sites = 0, c_scat = 0, c_cen = 0;
   unsigned long long kcol[2] = {0, 0}, kabs[2] = {0, 0};
-  if (k < n_in) {
-    const double k_used = *A.k_used;
-    Part<R> p = load_part<R>(in, k);
-    Stream rs(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
-    int64_t nseg = p.nseg;
-    // Let the particle's loads complete here, so that the loop head does not
-    // wait on the memory counter, which in every later pass would also wait
-    // for the previous flight's tally atomics.
-    __builtin_amdgcn_s_waitcnt(0);
-    for (;;) {
+  // One pass of the loop is one flight of every live lane of the wave, so
+  // the fission sites of the collisions of a pass are reserved together (one
+  // atomic per wave, at a point all lanes reach): per-lane atomics on the one
+  // bank counter would serialise.
+  const double k_used = *A.k_used;
+  bool live = k < n_in;
+  Part<R> p;
+  Stream rs(T.seed, TAG_TRANSPORT, 0, gen, T.prob, 0);
+  int64_t nseg = 0;
+  if (live) {
+    p = load_part<R>(in, k);
+    rs = Stream(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
+    nseg = p.nseg;
+  }
+  // Let the particle's loads complete here, so that the loop head does not
+  // wait on the memory counter, which in every later pass would also wait
+  // for the previous flight's tally atomics.
+  __builtin_amdgcn_s_waitcnt(0);
+  while (__ballot(live) != 0ull) {
+    bool col = false;
+    ColXS<R> x{0, R(1), R(0)};
+    uint32_t nf = 0;
+    if (live) {
       if (nseg >= T.max_events) {
         p.ctr = rs.draw;
         die<R, REC>(p, FATE_KILLED, A, Rc);
         ++c_kill;
-        break;
+        live = false;
+      } else {
+        bool refl = false;
+        const int ev = segment<R, REC, true>(T, T.geo, p, rs, A, Rc, &refl);
+        ++nseg;
+        ++c_seg;
+        if (ev == EV_LEAK) {
+          ++c_cross;
+          ++c_leak;
+          p.ctr = rs.draw;
+          die<R, REC>(p, FATE_LEAKED, A, Rc);
+          live = false;
+        } else if (ev == EV_CENSUS) {
+          ++c_cen;
+          p.ctr = rs.draw;
+          die<R, REC>(p, FATE_CENSUS, A, Rc);
+          live = false;
+        } else if (ev == EV_CROSS) {
+          ++c_cross;
+          c_refl += refl ? 1 : 0;
+        } else {
+          ++c_col;
+          x = col_xs(T, T.geo, p);
+          const double kc = (double)(x.nusf / x.st);
+          const uint64_t q = quantize(kc, T.q_kcol);
+          kcol[0] += q & 0xFFFFFFFFull;
+          kcol[1] += q >> 32;
+          if (REC) {
+            Rc.n_col[p.id] += 1;
+            Rc.kcol_sum[p.id] += kc;
+          }
+          nf = fission_count(T, x, rs, k_used);
+          col = true;
+        }
       }
-      bool refl = false;
-      const int ev = segment<R, REC, true>(T, T.geo, p, rs, A, Rc, &refl);
-      ++nseg;
-      ++c_seg;
-      if (ev == EV_LEAK) {
-        ++c_cross;
-        ++c_leak;
-        p.ctr = rs.draw;
-        die<R, REC>(p, FATE_LEAKED, A, Rc);
-        break;
-      }
-      if (ev == EV_CENSUS) {
-        ++c_cen;
-        p.ctr = rs.draw;
-        die<R, REC>(p, FATE_CENSUS, A, Rc);
-        break;
-      }
-      if (ev == EV_CROSS) {
-        ++c_cross;
-        c_refl += refl ? 1 : 0;
-        continue;
-      }
-      ++c_col;
-      const ColXS<R> x = col_xs(T, T.geo, p);
-      const double kc = (double)(x.nusf / x.st);
-      const uint64_t q = quantize(kc, T.q_kcol);
-      kcol[0] += q & 0xFFFFFFFFull;
-      kcol[1] += q >> 32;
-      if (REC) {
-        Rc.n_col[p.id] += 1;
-        Rc.kcol_sum[p.id] += kc;
-      }
-      const uint32_t nf = fission_count(T, x, rs, k_used);
-      const uint32_t slot = nf ? atomicAdd(A.n_fis, nf) : 0u;
+    }
+    const uint32_t slot = __ballot(nf != 0) ? wave_reserve(nf, A.n_fis) : 0u;
+    if (col) {
       c_sites += nf;
       uint64_t qa = 0;
-      const bool alive = collide_rest<R, REC>(T, p, rs, x, nf, slot, A, &qa);
-      if (!alive) {
+      if (collide_rest<R, REC>(T, p, rs, x, nf, slot, A, &qa)) {
+        ++c_scat;
+      } else {
         kabs[0] += qa & 0xFFFFFFFFull;
         kabs[1] += qa >> 32;
         ++c_abs;
         p.ctr = rs.draw;
         die<R, REC>(p, FATE_ABSORBED, A, Rc);
-        break;
+        live = false;
       }
-      ++c_scat;
     }
   }
   wave_count(A.cnt + CNT_SEG * STRIPES, c_seg);

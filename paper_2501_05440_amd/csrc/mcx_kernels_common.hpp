@@ -320,8 +320,9 @@ __device__ __forceinline__ int segment(const Tables& T, const Geo& L, Part<R>& p
   // track-length k estimator follow from the flux sums at the end of the
   // generation
   const int bin = L.bin_base + ((c * L.mr1 + p.r) * T.G + p.g) * T.nt;
-  unsigned long long* tb =
-      A.tally + (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
+  const size_t stripe_off = (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
+  unsigned long long* tb = A.tally + stripe_off;
+  unsigned long long* tt = A.tally_t + stripe_off;
   if (T.time) {
     // split the flight over the time bins it spans
     double t1 = census ? T.t_max : p.t + d / vg;
@@ -342,8 +343,8 @@ __device__ __forceinline__ int segment(const Tables& T, const Geo& L, Part<R>& p
         const uint64_t q = quantize((hi - lo) * vg, T.q_flux);
         if (HALVES) {
           if (q) {
-            atomicAdd(A.tally_t + 2 * (bin + b), (unsigned long long)(q & 0xFFFFFFFFull));
-            atomicAdd(A.tally_t + 2 * (bin + b) + 1, (unsigned long long)(q >> 32));
+            atomicAdd(tt + 2 * (bin + b), (unsigned long long)(q & 0xFFFFFFFFull));
+            atomicAdd(tt + 2 * (bin + b) + 1, (unsigned long long)(q >> 32));
           }
         } else {
           acc_add(tb + 2 * (bin + b), q);
@@ -356,8 +357,8 @@ __device__ __forceinline__ int segment(const Tables& T, const Geo& L, Part<R>& p
     const uint64_t qf = quantize(d, T.q_flux);
     if (HALVES) {
       if (qf) {
-        atomicAdd(A.tally_t + 2 * bin, (unsigned long long)(qf & 0xFFFFFFFFull));
-        atomicAdd(A.tally_t + 2 * bin + 1, (unsigned long long)(qf >> 32));
+        atomicAdd(tt + 2 * bin, (unsigned long long)(qf & 0xFFFFFFFFull));
+        atomicAdd(tt + 2 * bin + 1, (unsigned long long)(qf >> 32));
       }
     } else {
       acc_add(tb + 2 * bin, qf);
@@ -585,26 +586,27 @@ __device__ __forceinline__ double stripes_to_double(const unsigned long long* pa
 }
 
 // Exact flux sum of one bin: the striped 128-bit pairs of the event kernels
-// plus the (low-half sum, high-half sum) pair of the tail kernel (exact while
-// each of its words takes fewer than 2^32 terms, which the flight count of
-// the generation bounds).
+// plus the striped (low-half sum, high-half sum) pairs of the tail kernels
+// (exact while each of their words takes fewer than 2^32 terms, which the
+// flight count of the generation bounds).
 __device__ __forceinline__ double flux_total(const unsigned long long* pairs, int n_stripes,
                                              size_t stride, const unsigned long long* halves) {
   unsigned long long w0 = 0, w1 = 0;  // value = w1 * 2^64 + w0
   for (int s = 0; s < n_stripes; ++s) {
     const unsigned long long lo = pairs[(size_t)s * stride + 0];
     const unsigned long long hi = pairs[(size_t)s * stride + 1];
-    const unsigned long long t = w0 + lo;
+    unsigned long long t = w0 + lo;
     w1 += hi + ((t < w0) ? 1ull : 0ull);
     w0 = t;
+    const unsigned long long a = halves[(size_t)s * stride + 0];  // a + b * 2^32
+    const unsigned long long b = halves[(size_t)s * stride + 1];
+    t = w0 + a;
+    w1 += (t < w0) ? 1ull : 0ull;
+    w0 = t;
+    t = w0 + (b << 32);
+    w1 += ((t < w0) ? 1ull : 0ull) + (b >> 32);
+    w0 = t;
   }
-  const unsigned long long a = halves[0], b = halves[1];  // a + b * 2^32
-  unsigned long long t = w0 + a;
-  w1 += (t < w0) ? 1ull : 0ull;
-  w0 = t;
-  t = w0 + (b << 32);
-  w1 += ((t < w0) ? 1ull : 0ull) + (b >> 32);
-  w0 = t;
   return u128_to_double(w0, w1);
 }
 
