@@ -167,3 +167,26 @@ def test_time_mode_refusals():
     with pytest.raises(mcx.MCXError) as e:
         mcx.Context(eig)
     assert e.value.code == mcx.EINVAL
+
+
+def test_fp32_mixed_time_mode_is_balanced_and_close_to_fp64():
+    """FP32-mixed in the time-dependent mode: independent of the launch
+    configuration, balanced, and its census and leakage fractions within
+    statistics of FP64 on the same streams."""
+    banner("pulsed lattice FP32-mixed vs FP64")
+    prob = P.pulsed_lattice(n_per_gen=50000, n_gen=4)
+    a = mcx.run(prob, precision="fp32", record=True)
+    b = mcx.run(prob, precision="fp32", record=True, flights=1, tail_threshold=-1, block_size=64)
+    assert np.array_equal(a["records"], b["records"])
+    assert np.array_equal(a["flux_mean"], b["flux_mean"])
+    n = prob["run"]["n_per_gen"]
+    seg, col, cross, refl, leak, ab, killed, sites, scat, cut, cen = a["gen_counts"].T
+    assert np.all(ab + leak + cen == n) and np.all(killed == 0) and np.all(sites == 0)
+    g = mcx.run(prob)
+    tot = n * prob["run"]["n_gen"]
+    for idx in (4, 10):  # leaked, census
+        p32 = a["gen_counts"][:, idx].sum() / tot
+        p64 = g["gen_counts"][:, idx].sum() / tot
+        assert abs(p32 - p64) < 5 * math.sqrt(p64 * (1 - p64) / tot) + 1e-12, (idx, p32, p64)
+    t32 = a["records"]["t_final"]
+    assert np.all(t32[a["records"]["fate"] == FATE_CENSUS] == prob["time"]["t_edges"][-1])
