@@ -5,11 +5,14 @@ One step is one full power iteration of the 17x17-pin, 7-group lattice
 (1e6 histories per generation, 60 generations, 20 inactive) in FP64 with the
 event engine, with the problem data and workspace resident on the GPU.
 Prints one JSON line with histories/s (value), events/s, the roofline of the
-dominant event kernel (timed with HIP events on the run's stream) and the
-CPU oracle timed on a bounded sample of the same workload; beside them the
-same lattice on the persistent engine, the FP64 / FP32-mixed comparison at
-1e7 histories per generation, and the 512-problem fixed-source batch in one
-persistent launch against the same problems run one at a time.
+dominant event kernel (the advance kernel, timed with HIP events on the
+run's stream around each of its launches in the timed steps) and the CPU
+oracle timed on a bounded sample of the same workload; beside them the same
+lattice on the persistent engine and as one history-based kernel per
+generation, the FP64 / FP32-mixed comparison at 1e7 histories per
+generation, the 512-problem fixed-source batch in one persistent launch
+against the same problems run one at a time, the continuous-energy pin cell
+and the pulsed (time-dependent) lattice.
 """
 import argparse
 import json
