@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TIME_STRIDE = 4  # the timed steps time the advance launches of every 4th generation
 # algorithmic bytes per processed particle (FP64 bank entry: x, y, u, v as f64,
 # cell, group|sites, draw counter, id, flight count as u32 = 52 B)
 STATE_BYTES = 52
@@ -299,10 +300,11 @@ def main():
     N, G = a.n_per_gen, a.n_gen
     print(f"[bench] lattice 17x17, {N} histories x {G} generations, steps={a.steps} "
           f"warmup={a.warmup}", file=sys.stderr, flush=True)
-    # the timed steps record HIP events around the advance launches only (each
-    # event between two launches delays the next one a little)
+    # the timed steps record HIP events around the advance launches of every
+    # TIME_STRIDE-th generation (each event between two launches delays the
+    # next one a little); the generations are statistically alike
     ctx = mcx.Context(prob, device=0, block_size=a.block, tail_threshold=a.tail,
-                      time_kernels="advance", flights=a.flights)
+                      time_kernels="advance", time_stride=TIME_STRIDE, flights=a.flights)
     for w in range(a.warmup):
         ctx.run()
         print(f"[bench] warmup {w + 1}/{a.warmup} done", file=sys.stderr, flush=True)
@@ -337,7 +339,7 @@ def main():
     # roofline of the dominant event kernel, the advance kernel (the largest
     # summed time of the breakdown step), timed over the timed steps
     adv_avg_ms = tot["advance_ms"] / max(1, tot["n_advance"])
-    adv_items = tot["advance_items"] / max(1, tot["n_advance"])
+    adv_items = tot["advance_items"] / max(1, tot["n_iterations"])  # every launch
     adv_flights = tot["advance_segments"] / max(1, tot["advance_items"])
     adv_bytes = 2 * STATE_BYTES + TALLY_BYTES_ADV * adv_flights
     name, avg_ms, per_launch = "k_advance", adv_avg_ms, adv_items * adv_bytes
@@ -352,6 +354,8 @@ def main():
                 "traffic": traffic, "bytes_per_item": round(per_item, 2),
                 "items_per_launch": round(adv_items, 1),
                 "avg_launch_us": round(avg_ms * 1e3, 2),
+                "timed_launches": int(tot["n_advance"]),
+                "timed_generation_stride": TIME_STRIDE,
                 "flights_per_advance_item": round(adv_flights, 4),
                 "iterations_per_generation": round(tot["n_iterations"] / (a.steps * G), 2),
                 "kernel_ms_per_step": {"advance": round(brk["advance_ms"], 2),

@@ -122,6 +122,9 @@ typedef struct {
   int32_t event_log;        /* > 0 (with record_histories = 1): keep the first event_log
                                flights of every history in every generation as mcx_event
                                entries (mcx_get_event_log); at most 65536 */
+  int32_t time_stride;      /* with time_kernels: time the launches of generations
+                               g % time_stride == 0 only (the timing events of the
+                               others are left out); 0 or 1 = every generation */
 } mcx_options;
 
 /* Lattice of pin universes (paper Sec. 1: CSG geometry).  Cell (i, j),
@@ -182,7 +185,8 @@ typedef struct {
 
 /* Timing of the last mcx_run_generations or mcx_run_batch.  The *_ms kernel sums are filled
    when time_kernels = 1 (events recorded on the stream around each launch; with
-   time_kernels = 2 only advance_ms / n_advance);
+   time_kernels = 2 only advance_ms / n_advance; with time_stride > 1 over the timed
+   generations only, while the *_items, advance_segments and n_iterations count all);
    *_items count the particles each kernel class processed. */
 typedef struct {
   double run_ms;            /* stream time of the whole run, generation ends included */

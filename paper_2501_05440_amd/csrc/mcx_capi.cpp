@@ -213,6 +213,7 @@ struct mcx_ctx {
   hipEvent_t ev_ring[RING]{};
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;
   std::vector<hipEvent_t> ev_pool;
+  bool time_gen = true;  // the current generation's launches are timed
   std::vector<int> ev_kind;  // 0 advance, 1 collide, 2 tail (pairs in ev_pool)
 };
 
@@ -1042,7 +1043,8 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
 
 // Enqueue a timing event pair around a launch when kernel timing is on.
 static hipError_t time_mark(mcx_ctx* c, int kind, bool begin) {
-  if (!c->opt.time_kernels || (c->opt.time_kernels == 2 && kind != 0)) return hipSuccess;
+  if (!c->opt.time_kernels || (c->opt.time_kernels == 2 && kind != 0) || !c->time_gen)
+    return hipSuccess;
   if (begin) c->ev_kind.push_back(kind);
   const size_t k = (c->ev_kind.size() - 1) * 2 + (begin ? 0 : 1);
   while (c->ev_pool.size() <= k) {
@@ -1080,6 +1082,7 @@ static int collect_kernel_times(mcx_ctx* c) {
 static int generation_end(mcx_ctx* c, int gen);
 
 static int run_generation(mcx_ctx* c, int gen) {
+  c->time_gen = c->opt.time_stride <= 1 || gen % c->opt.time_stride == 0;
   hipStream_t s = c->stream;
   const Tables& T = c->d.T;
   Accum& A = c->d.A;
@@ -1820,6 +1823,7 @@ static int build_batch_graph(mcx_ctx* c) {
 }
 
 int mcx_run_batch(mcx_ctx* c) {
+  if (c) c->time_gen = true;
   if (!c) return MCX_EINVAL;
   if (!c->batch) return fail(c, MCX_ESTATE, "no batch loaded");
   if (!c->bound) return fail(c, MCX_ESTATE, "bind a workspace first");
