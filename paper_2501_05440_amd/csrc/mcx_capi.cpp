@@ -14,6 +14,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <deque>
 #include <vector>
 
 #include "mcx.h"
@@ -1127,6 +1128,9 @@ static int run_generation(mcx_ctx* c, int gen) {
   // upper bound for every later iteration
   uint32_t bound = N;
   int64_t known = 0, it = 0;
+  // live counts on their way to the host: (iteration, ring slot)
+  std::deque<std::pair<int64_t, int>> pending;
+  int64_t n_sent = 0;
   const int64_t tail = c->opt.tail_threshold != 0
                            ? (int64_t)c->opt.tail_threshold
                            : std::max<int64_t>(DEFAULT_TAIL, (int64_t)N / 8);
@@ -1177,11 +1181,19 @@ static int run_generation(mcx_ctx* c, int gen) {
     cur = 1 - cur;
     ++it;
     c->timing.n_iterations += 1;
-    HIP_TRY(c, hipMemcpyAsync(&c->h_pin[it % RING], c->d.cnt_live + it, sizeof(uint32_t),
-                              hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipEventRecord(c->ev_ring[it % RING], s));
-    while (known < it) {
-      hipEvent_t e = c->ev_ring[(known + 1) % RING];
+    // The count goes to the host every other iteration while the tail is far
+    // (each copy and its event delay the next launch a few microseconds), and
+    // every iteration near it.  Counts never grow within a generation, so an
+    // older count is an upper bound for every later iteration.
+    if (it % 2 == 0 || (tail > 0 && (int64_t)bound <= 2 * tail)) {
+      const int slot = (int)(n_sent++ % RING);
+      HIP_TRY(c, hipMemcpyAsync(&c->h_pin[slot], c->d.cnt_live + it, sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, s));
+      HIP_TRY(c, hipEventRecord(c->ev_ring[slot], s));
+      pending.emplace_back(it, slot);
+    }
+    while (!pending.empty()) {
+      hipEvent_t e = c->ev_ring[pending.front().second];
       hipError_t q = hipEventQuery(e);
       if (q == hipErrorNotReady && it - known >= c->opt.lookahead) {
         HIP_TRY(c, hipEventSynchronize(e));
@@ -1189,8 +1201,9 @@ static int run_generation(mcx_ctx* c, int gen) {
       }
       if (q == hipErrorNotReady) break;
       if (q != hipSuccess) return hip_fail(c, q, "hipEventQuery");
-      ++known;
-      bound = c->h_pin[known % RING];
+      known = pending.front().first;
+      bound = c->h_pin[pending.front().second];
+      pending.pop_front();
     }
   }
 
