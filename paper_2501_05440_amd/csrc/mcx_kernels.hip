@@ -438,23 +438,52 @@ __global__ void __launch_bounds__(64) k_gen_totals(Tables T, uint32_t gen, uint3
 }
 
 // Generation tallies per source particle: flux from the exact sums and the
-// production nu_sig_f(bin) * flux, one bin per thread; each block leaves the
-// compensated sum of its production terms (a fixed-order tree) for the
-// track-length k estimator.
-constexpr int GT_BLOCK = 256;
+// production nu_sig_f(bin) * flux.  A block takes GT_BINS consecutive bins,
+// lane l of every wave bin l, the waves splitting the stripes (coalesced
+// reads of each stripe's row), then one wave finishes the exact sums; each
+// block leaves the compensated sum of its production terms (a fixed-order
+// tree) for the track-length k estimator.
+constexpr int GT_BINS = 64;
+constexpr int GT_WAVES = 8;
 
-__global__ void __launch_bounds__(GT_BLOCK) k_gen_tallies(Tables T, uint32_t gen, uint32_t n,
-                                                          Accum A, double* gen_tal,
-                                                          double* tl_part) {
-  __shared__ double ps[GT_BLOCK], pc[GT_BLOCK];
+__global__ void __launch_bounds__(64 * GT_WAVES) k_gen_tallies(Tables T, uint32_t gen, uint32_t n,
+                                                                Accum A, double* gen_tal,
+                                                                double* tl_part) {
+  __shared__ unsigned long long s0[GT_WAVES][GT_BINS], s1[GT_WAVES][GT_BINS];
   const int nb = T.n_bins;
-  const int b = (int)(blockIdx.x * GT_BLOCK + threadIdx.x);
+  const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+  const int b = (int)blockIdx.x * GT_BINS + lane;
+  const size_t stride = 2 * (size_t)nb;
+  unsigned long long w0 = 0, w1 = 0;  // w1 * 2^64 + w0
+  if (b < nb) {
+    for (int st = w; st < T.tally_stripes; st += GT_WAVES) {
+      const unsigned long long* pr = A.tally + (size_t)st * stride + 2 * (size_t)b;
+      const unsigned long long* hv = A.tally_t + (size_t)st * stride + 2 * (size_t)b;
+      unsigned long long t = w0 + pr[0];
+      w1 += pr[1] + (t < w0 ? 1ull : 0ull);
+      w0 = t;
+      const unsigned long long a = hv[0], c = hv[1];  // a + c * 2^32
+      t = w0 + a;
+      w1 += t < w0 ? 1ull : 0ull;
+      w0 = t;
+      t = w0 + (c << 32);
+      w1 += (t < w0 ? 1ull : 0ull) + (c >> 32);
+      w0 = t;
+    }
+  }
+  s0[w][lane] = w0;
+  s1[w][lane] = w1;
+  __syncthreads();
+  if (w != 0) return;
+  for (int k = 1; k < GT_WAVES; ++k) {
+    const unsigned long long t = w0 + s0[k][lane];
+    w1 += s1[k][lane] + (t < w0 ? 1ull : 0ull);
+    w0 = t;
+  }
   double prod = 0.0;
   if (b < nb) {
+    const double flux = u128_to_double(w0, w1) / T.q_flux;
     const int per_cell = T.geo.mr1 * T.G * T.nt;
-    const double flux = flux_total(A.tally + 2 * (size_t)b, T.tally_stripes, 2 * (size_t)nb,
-                                   A.tally_t + 2 * (size_t)b) /
-                        T.q_flux;
     const int cell = b / per_cell;
     const int r = (b / (T.G * T.nt)) % T.geo.mr1;
     const int g = (b / T.nt) % T.G;
@@ -464,25 +493,26 @@ __global__ void __launch_bounds__(GT_BLOCK) k_gen_tallies(Tables T, uint32_t gen
     gen_tal[(size_t)gen * 2 * nb + b] = flux / (double)n;
     gen_tal[(size_t)gen * 2 * nb + nb + b] = prod / (double)n;
   }
-  ps[threadIdx.x] = prod;
-  pc[threadIdx.x] = 0.0;
-  __syncthreads();
-  for (int h = GT_BLOCK / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) {
-      double s = ps[threadIdx.x], c = pc[threadIdx.x];
-      neu_add(s, c, ps[threadIdx.x + h], pc[threadIdx.x + h]);
-      ps[threadIdx.x] = s;
-      pc[threadIdx.x] = c;
+  // fixed-order butterfly over the wave's 64 production terms
+  double ps = prod, pc = 0.0;
+  for (int off = 32; off > 0; off >>= 1) {
+    const double os = __shfl_xor(ps, off), oc = __shfl_xor(pc, off);
+    if (lane & off) {
+      double s2 = os, c2 = oc;
+      neu_add(s2, c2, ps, pc);
+      ps = s2;
+      pc = c2;
+    } else {
+      neu_add(ps, pc, os, oc);
     }
-    __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    tl_part[2 * blockIdx.x] = ps[0];
-    tl_part[2 * blockIdx.x + 1] = pc[0];
+  if (lane == 0) {
+    tl_part[2 * blockIdx.x] = ps;
+    tl_part[2 * blockIdx.x + 1] = pc;
   }
 }
 
-int gen_tally_blocks(int n_bins) { return (n_bins + GT_BLOCK - 1) / GT_BLOCK; }
+int gen_tally_blocks(int n_bins) { return (n_bins + GT_BINS - 1) / GT_BINS; }
 
 // Shannon entropy of the canonical bank over the entropy mesh: per-block
 // histograms in LDS (meshes up to LDS_HIST bins), merged with one global
@@ -804,7 +834,7 @@ hipError_t launch_gen_totals(const Tables& T, uint32_t gen, uint32_t n, const Ac
 hipError_t launch_gen_tallies(const Tables& T, uint32_t gen, uint32_t n, const Accum& A,
                               double* gen_tal, double* tl_part, hipStream_t s) {
   hipLaunchKernelGGL(k_gen_tallies, dim3(std::max(1, gen_tally_blocks(T.n_bins))),
-                     dim3(GT_BLOCK), 0, s, T, gen, n, A, gen_tal, tl_part);
+                     dim3(64 * GT_WAVES), 0, s, T, gen, n, A, gen_tal, tl_part);
   return hipGetLastError();
 }
 
