@@ -237,6 +237,31 @@ MCX_HD double cr_log(double x, const double* log_tab) {
   const double sl1 = rem * rD;
   const double rem2 = fma(-sl1, D.hi, rem) - sl1 * D.lo;
   const dd s = fast_two_sum(sh, sl1 + rem2 * rD);
+  const int k = j - MCX_LOG_TAB_J0;
+  const double lnF_hi = log_tab[2 * k], lnF_lo = log_tab[2 * k + 1];
+  {
+    // Quick evaluation: the leading terms e ln2_hi + ln F_hi + 2 s.hi summed
+    // exactly, everything else (2 atanh(s) - 2 s and the low parts) in plain
+    // double.  Its error stays below 2^-69 of the result (the low-part sum
+    // and the series are under 2^-19 of it and carry relative errors near
+    // 2^-51), so if the remainder of the rounded sum keeps 2^-67 of the
+    // result away from the rounding boundary (half an ulp, a quarter below
+    // a power of two), that rounding is the correct one; else the
+    // double-double evaluation below decides.
+    const double z = s.hi * s.hi;
+    const double tail =
+        s.hi * z *
+        (2.0 / 3.0 + z * (2.0 / 5.0 + z * (2.0 / 7.0 + z * (2.0 / 9.0 + z * (2.0 / 11.0)))));
+    const dd a = fast_two_sum((double)e * MCX_LN2_HI, lnF_hi);  // e ln2_hi is exact
+    const dd b = two_sum(a.hi, 2.0 * s.hi);
+    const double small = ((a.lo + lnF_lo) + (double)e * MCX_LN2_LO) + (2.0 * s.lo + tail);
+    const dd q = fast_two_sum(b.hi, b.lo + small);
+    if (q.hi == 0.0) return 0.0;  // x = 1
+    const uint64_t qb = as_u64(q.hi);
+    double half = as_f64((((qb >> 52) & 0x7FFull) - 53ull) << 52);
+    if ((qb & 0x000FFFFFFFFFFFFFull) == 0 && (q.lo < 0.0) == (q.hi > 0.0)) half *= 0.5;
+    if (fabs(q.lo) + fabs(q.hi) * 0x1p-67 < half) return q.hi;
+  }
   const dd s2 = dd_mul(s, s);
   const dd s3 = dd_mul(s2, s);
   const double z = s2.hi;
@@ -245,8 +270,7 @@ MCX_HD double cr_log(double x, const double* log_tab) {
   dd at = dd_add(s, dd_mul(s3, third));
   at = dd_add(at, dd{s3.hi * p, 0.0});
   const dd l1p{2.0 * at.hi, 2.0 * at.lo};
-  const int k = j - MCX_LOG_TAB_J0;
-  const dd lnF{log_tab[2 * k], log_tab[2 * k + 1]};
+  const dd lnF{lnF_hi, lnF_lo};
   const dd eln2 = fast_two_sum((double)e * MCX_LN2_HI, (double)e * MCX_LN2_LO);
   const dd r = dd_add(dd_add(eln2, lnF), l1p);
   return r.hi + r.lo;
