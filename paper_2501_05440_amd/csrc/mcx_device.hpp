@@ -325,16 +325,21 @@ MCX_HD int sample_cum(R xi, const R* cum, int n, int last_nz) {
 }
 
 // Isotropic direction from two draws; only (u, v) matter in z-invariant
-// geometry (w = 2 xi_mu - 1 sets the in-plane speed sqrt(1 - w^2)).
-MCX_HD void isotropic_uv(double xi_mu, double xi_phi, double* u, double* v,
-                         const double* sct = sc_tab()) {
+// geometry (w = 2 xi_mu - 1 sets the in-plane speed sqrt(1 - w^2)).  The _cs
+// form takes cos and sin of the azimuth 2 pi xi_phi already evaluated.
+MCX_HD void isotropic_uv_cs(double xi_mu, double c, double sn, double* u, double* v) {
   const double w = 2.0 * xi_mu - 1.0;
   const double s2 = 1.0 - w * w;
   const double s = sqrt(s2 > 0.0 ? s2 : 0.0);
-  double c, sn;
-  cr_cossin_2pi(xi_phi, sct, &c, &sn);
   *u = s * c;
   *v = s * sn;
+}
+
+MCX_HD void isotropic_uv(double xi_mu, double xi_phi, double* u, double* v,
+                         const double* sct = sc_tab()) {
+  double c, sn;
+  cr_cossin_2pi(xi_phi, sct, &c, &sn);
+  isotropic_uv_cs(xi_mu, c, sn, u, v);
 }
 
 // ---------------------------------------------------------------------------

@@ -186,18 +186,64 @@ __global__ void __launch_bounds__(256) k_tail(Tables T0, uint32_t gen, Bank in,
   const double k_used = *A.k_used;
   bool live = k < n_in;
   Part<R> p;
-  Stream rs(T.seed, TAG_TRANSPORT, 0, gen, T.prob, 0);
+  // FP64: draws through the wavefront's draw cache once few histories remain
+  constexpr bool CACHE = std::is_same<R, double>::value;
+  using S = typename std::conditional<CACHE, CachedStream, Stream>::type;
+  S rs = Stream(T.seed, TAG_TRANSPORT, 0, gen, T.prob, 0);
   int64_t nseg = 0;
   if (live) {
     p = load_part<R>(in, k);
     rs = Stream(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
     nseg = p.nseg;
   }
+  // live lanes when the cache was set up (their ranks are the cache slots)
+  unsigned long long slots = 0ull;
   // Let the particle's loads complete here, so that the loop head does not
   // wait on the memory counter, which in every later pass would also wait
   // for the previous flight's tally atomics.
   __builtin_amdgcn_s_waitcnt(0);
   while (__ballot(live) != 0ull) {
+    if constexpr (CACHE) {
+      if (slots == 0ull) {
+        const unsigned long long lm = __ballot(live);
+        if (__popcll(lm) <= TC_SLOTS) slots = lm;
+      }
+      if (slots != 0ull) {
+        const bool need = live && (int)rs.clen - (int)(rs.draw - rs.cbase) < TC_LOW;
+        const unsigned long long nm = __ballot(need);
+        if (nm != 0ull) {
+          // lane t evaluates draw t % TC_WORDS of the window of slot t / TC_WORDS
+          const uint32_t t = lane_id();
+          const int sl = (int)(t / TC_WORDS);
+          unsigned long long m = slots;
+          for (int i = 0; i < sl && m != 0ull; ++i) m &= m - 1ull;
+          const int owner = m != 0ull ? __ffsll((long long)m) - 1 : -1;
+          const int src = owner >= 0 ? owner : 0;
+          const uint32_t d0 = __shfl(rs.draw, src);
+          const uint32_t hid = __shfl(p.id, src);
+          if (owner >= 0 && ((nm >> owner) & 1ull)) {
+            const uint32_t w = d0 + t % TC_WORDS;
+            const u64x4 b = philox4x64_10(w >> 2, hid, gen, T.prob, T.seed, TAG_TRANSPORT);
+            const uint32_t q = w & 3u;
+            const uint64_t word = q == 0 ? b.v[0] : q == 1 ? b.v[1] : q == 2 ? b.v[2] : b.v[3];
+            DrawEntry e;
+            e.u = u01(word);
+            e.ln = cr_log(e.u, T.lt);
+            cr_cossin_2pi(e.u, T.sct, &e.c, &e.s);
+            tc_cache[t] = e;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          if (need) {
+            const int my = __popcll(slots & ((1ull << t) - 1ull));
+            rs.ebase = (uint32_t)(my * TC_WORDS);
+            rs.cbase = rs.draw;
+            rs.clen = TC_WORDS;
+          }
+        }
+      }
+    }
     bool col = false;
     ColXS<R> x{0, R(1), R(0)};
     uint32_t nf = 0;
@@ -209,7 +255,7 @@ __global__ void __launch_bounds__(256) k_tail(Tables T0, uint32_t gen, Bank in,
         live = false;
       } else {
         bool refl = false;
-        const int ev = segment<R, REC, true>(T, T.geo, p, rs, A, Rc, &refl);
+        const int ev = segment<R, REC, true, S>(T, T.geo, p, rs, A, Rc, &refl);
         ++nseg;
         ++c_seg;
         if (ev == EV_LEAK) {

@@ -4,6 +4,8 @@
 // collision, source sampling, block scans and exact-sum conversions.
 #pragma once
 
+#include <type_traits>
+
 #include "mcx_launch.hpp"
 
 namespace mcx {
@@ -71,6 +73,87 @@ struct Prec<float> {
     *v = s * sn;
   }
 };
+
+// ---------------------------------------------------------------------------
+// draw cache of a sparse tail wavefront
+//
+// Near the end of a generation a tail wavefront holds a few long histories
+// and many idle lanes, and each history's flights are a serial chain whose
+// largest links are the Philox block, the correctly rounded ln of the
+// distance to collision and cos/sin of the scattering azimuth.  The transport
+// stream of a history is fixed in advance (its draws depend only on the
+// history id and the draw index), so when at most TC_SLOTS histories remain
+// live the wavefront's lanes evaluate the next TC_WORDS draws of each one
+// side by side: every lane one draw, with its uniform, ln and cos/sin of 2 pi
+// times it, written to LDS.  The history then takes its draws from there and
+// falls back to evaluating them itself past the end of its window.  The
+// values are the ones the history would compute, so results do not change.
+// ---------------------------------------------------------------------------
+
+constexpr int TC_SLOTS = 4;    // histories served per wavefront
+constexpr int TC_WORDS = 16;   // draws per history and refill (TC_SLOTS * TC_WORDS = 64)
+constexpr int TC_LOW = 6;      // refill when fewer draws than this remain
+
+struct DrawEntry {
+  double u, ln, c, s;  // uniform, ln(u), cos(2 pi u), sin(2 pi u)
+};
+
+// The wavefront's windows (tail kernels run one wavefront per block).
+static __shared__ DrawEntry tc_cache[TC_SLOTS * TC_WORDS];
+
+struct CachedStream : Stream {
+  uint32_t ebase;        // first entry of this history's window
+  uint32_t cbase, clen;  // draw index of that entry, entries valid
+  int last;              // entry of the last draw, or -1 if evaluated here
+
+  __device__ CachedStream(const Stream& s)
+      : Stream(s), ebase(0), cbase(0), clen(0), last(-1) {}
+
+  __device__ double next() {
+    const uint32_t o = draw - cbase;
+    if (o < clen) {
+      last = (int)(ebase + o);
+      draw += 1u;
+      return tc_cache[last].u;
+    }
+    last = -1;
+    return Stream::next();
+  }
+};
+
+// Distance to collision from the next draw.
+template <class R, class S>
+__device__ __forceinline__ R draw_dcol(S& rs, R st, const double* lt) {
+  const R xi = Prec<R>::xi(rs.next());
+  return Prec<R>::dcol(xi, st, lt);
+}
+
+template <>
+__device__ __forceinline__ double draw_dcol<double, CachedStream>(CachedStream& rs, double st,
+                                                                  const double* lt) {
+  const double xi = rs.next();
+  const double l = rs.last >= 0 ? tc_cache[rs.last].ln : cr_log(xi, lt);
+  return -l / st;
+}
+
+// Isotropic direction from the next two draws.
+template <class R, class S>
+__device__ __forceinline__ void draw_iso(S& rs, R* u, R* v, const double* sct) {
+  const R xm = Prec<R>::xi(rs.next());
+  const R xp = Prec<R>::xi(rs.next());
+  Prec<R>::iso(xm, xp, u, v, sct);
+}
+
+template <>
+__device__ __forceinline__ void draw_iso<double, CachedStream>(CachedStream& rs, double* u,
+                                                               double* v, const double* sct) {
+  const double xm = rs.next();
+  const double xp = rs.next();
+  if (rs.last >= 0)
+    isotropic_uv_cs(xm, tc_cache[rs.last].c, tc_cache[rs.last].s, u, v);
+  else
+    isotropic_uv(xm, xp, u, v, sct);
+}
 
 // Cross-section tables of the working precision.
 template <class R>
@@ -266,8 +349,8 @@ __device__ __forceinline__ void die(const Part<R>& p, int fate, const Accum& A,
 // HALVES: add the flux term as two non-returning 32-bit-half atomics (the
 // tail kernel, where a returning atomic's latency is not hidden by other
 // waves); otherwise one returning 64-bit atomic with a carry word.
-template <class R, bool REC, bool HALVES>
-__device__ __forceinline__ int segment(const Tables& T, const Geo& L, Part<R>& p, Stream& rs,
+template <class R, bool REC, bool HALVES, class S = Stream>
+__device__ __forceinline__ int segment(const Tables& T, const Geo& L, Part<R>& p, S& rs,
                                        const Accum& A, const Records& Rc, bool* refl_out) {
   const XSView<R> X = xs_view<R>(T);
   const int c = p.j * L.nx + p.i;
@@ -277,8 +360,7 @@ __device__ __forceinline__ int segment(const Tables& T, const Geo& L, Part<R>& p
   const R st = X.sig_t[m * T.G + p.g];
 
   // distance to collision: exponential with mean 1 / sig_t
-  const R xi = Prec<R>::xi(rs.next());
-  const R d_col = Prec<R>::dcol(xi, st, T.lt);
+  const R d_col = draw_dcol<R>(rs, st, T.lt);
 
   // distance to boundary: the cell's planes ahead and the region's rings
   const double xlo = L.x0 + (double)p.i * L.pitch, xhi = L.x0 + (double)(p.i + 1) * L.pitch;
@@ -438,8 +520,8 @@ __device__ __forceinline__ ColXS<R> col_xs(const Tables& T, const Geo& L, const 
   return ColXS<R>{m, X.sig_t[m * T.G + p.g], X.nusf[m * T.G + p.g]};
 }
 
-template <class R>
-__device__ __forceinline__ uint32_t fission_count(const Tables& T, const ColXS<R>& x, Stream& rs,
+template <class R, class S>
+__device__ __forceinline__ uint32_t fission_count(const Tables& T, const ColXS<R>& x, S& rs,
                                                   double k_used) {
   if (T.fixed_source || !(x.nusf > R(0))) return 0u;
   const R xf = Prec<R>::xi(rs.next());
@@ -451,8 +533,8 @@ __device__ __forceinline__ uint32_t fission_count(const Tables& T, const ColXS<R
 // Collision, second part: write the nf sites reserved at slot, then scatter
 // (probability sig_s / sig_t: new group from the scattering row, isotropic
 // direction) or absorb.  Returns true if the particle scatters.
-template <class R, bool REC>
-__device__ __forceinline__ bool collide_rest(const Tables& T, Part<R>& p, Stream& rs,
+template <class R, bool REC, class S>
+__device__ __forceinline__ bool collide_rest(const Tables& T, Part<R>& p, S& rs,
                                              const ColXS<R>& x, uint32_t nf, uint32_t slot,
                                              const Accum& A, uint64_t* q_kabs) {
   const XSView<R> X = xs_view<R>(T);
@@ -479,9 +561,7 @@ __device__ __forceinline__ bool collide_rest(const Tables& T, Part<R>& p, Stream
     const R xg = Prec<R>::xi(rs.next());
     const int row = x.m * G + p.g;
     p.g = sample_cum(xg, X.cum_s + (size_t)row * G, G, T.last_s[row]);
-    const R xm = Prec<R>::xi(rs.next());
-    const R xp = Prec<R>::xi(rs.next());
-    Prec<R>::iso(xm, xp, &p.u, &p.v, T.sct);
+    draw_iso<R>(rs, &p.u, &p.v, T.sct);
     *q_kabs = 0;
     return true;
   }
