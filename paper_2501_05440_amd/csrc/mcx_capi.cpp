@@ -478,7 +478,8 @@ int mcx_load_mg_xs(mcx_ctx* c, int32_t n_mat, int32_t n_grp, const double* sig_t
 int mcx_load_ce_xs(mcx_ctx* c, const mcx_ce_data* d) {
   if (!c || !d) return MCX_EINVAL;
   if (d->n_nuc < 1 || d->n_pts < 2 || d->n_mat < 1 || d->max_nuc < 1 || d->n_ebins < 1 ||
-      (int64_t)d->n_nuc * d->n_pts > (int64_t(1) << 28) || !d->e_grid || !d->sig_t ||
+      (int64_t)d->n_nuc * d->n_pts > (int64_t(1) << 28) ||
+      (int64_t)d->n_mat * d->max_nuc * d->n_pts > (int64_t(1) << 28) || !d->e_grid || !d->sig_t ||
       !d->sig_s || !d->sig_f || !d->awr || !d->mat_n || !d->mat_nuc || !d->mat_dens ||
       !d->e_edges)
     return fail(c, MCX_EINVAL, "continuous-energy sizes");
@@ -525,14 +526,22 @@ int mcx_load_ce_xs(mcx_ctx* c, const mcx_ce_data* d) {
     }
   }
   if (!(sigt_min > 0.0)) return fail(c, MCX_EINVAL, "a material has zero total cross section");
-  // interleave (t, s, f, 0) per point so one interval of one nuclide is 64 contiguous bytes
-  std::vector<double> xs(NP * 4);
-  for (size_t k = 0; k < NP; ++k) {
-    xs[4 * k + 0] = d->sig_t[k];
-    xs[4 * k + 1] = d->sig_s[k];
-    xs[4 * k + 2] = d->sig_f[k];
-    xs[4 * k + 3] = 0.0;
-  }
+  // (t, f, s, 0) of each nuclide of each material, packed by material, then
+  // grid point, then the material's nuclides: a lookup reads one interval
+  // of one material, which is one contiguous block of 2 * max_nuc * 32 bytes
+  // (a layout by nuclide spreads it over one 64-byte piece per nuclide), and
+  // a flight, which needs t and f only, one 16-byte load per nuclide and point
+  const size_t MX = (size_t)d->max_nuc;
+  std::vector<double> xs((size_t)d->n_mat * d->n_pts * MX * 4, 0.0);
+  for (int m = 0; m < d->n_mat; ++m)
+    for (int q = 0; q < d->n_pts; ++q)
+      for (int k = 0; k < d->mat_n[m]; ++k) {
+        const size_t src = (size_t)d->mat_nuc[m * d->max_nuc + k] * d->n_pts + q;
+        double* e = &xs[(((size_t)m * d->n_pts + q) * MX + k) * 4];
+        e[0] = d->sig_t[src];
+        e[1] = d->sig_f[src];
+        e[2] = d->sig_s[src];
+      }
   if (c->batch) {
     c->has_geo = false;
     c->batch = false;

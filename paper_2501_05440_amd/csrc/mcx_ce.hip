@@ -88,15 +88,24 @@ struct CEP<double> {
   static __device__ __forceinline__ void cossin_2pi(double t, double* c, double* s) {
     cr_cossin_2pi(t, sc_tab(), c, s);
   }
-  // one interval of one nuclide: (t, s, f) at both ends
-  static __device__ __forceinline__ void micro(const Tables& T, int n, int gi, double f, double* t,
-                                               double* s, double* fi) {
-    const double2* a =
-        reinterpret_cast<const double2*>(T.ce_xs + ((size_t)n * T.n_pts + gi) * 4);
-    const double2 ts0 = a[0], f0 = a[1], ts1 = a[2], f1 = a[3];
-    *t = ts0.x + f * (ts1.x - ts0.x);
-    *s = ts0.y + f * (ts1.y - ts0.y);
-    *fi = f0.x + f * (f1.x - f0.x);
+  // one interval of nuclide k of material m: (t, s, f) at both ends; the
+  // entries are (t, f, s, 0), so without s (the flights) one 16-byte load
+  // per grid point does
+  template <bool S>
+  static __device__ __forceinline__ void micro(const Tables& T, int m, int k, int gi, double f,
+                                               double* t, double* s, double* fi) {
+    const double2* a = reinterpret_cast<const double2*>(
+        T.ce_xs + (((size_t)m * T.n_pts + gi) * T.max_nuc + k) * 4);
+    const int nx = 2 * T.max_nuc;  // the next grid point, in double2
+    const double2 tf0 = a[0], tf1 = a[nx];
+    *t = tf0.x + f * (tf1.x - tf0.x);
+    *fi = tf0.y + f * (tf1.y - tf0.y);
+    if (S) {
+      const double s0 = a[1].x, s1 = a[nx + 1].x;
+      *s = s0 + f * (s1 - s0);
+    } else {
+      *s = 0.0;
+    }
   }
   static constexpr double rot_eps = 1e-10;
 };
@@ -112,13 +121,15 @@ struct CEP<float> {
   static __device__ __forceinline__ void cossin_2pi(float t, float* c, float* s) {
     sincospif(2.0f * t, s, c);
   }
-  static __device__ __forceinline__ void micro(const Tables& T, int n, int gi, float f, float* t,
-                                               float* s, float* fi) {
-    const float4* a = reinterpret_cast<const float4*>(T.ce_xs_f + ((size_t)n * T.n_pts + gi) * 4);
-    const float4 p0 = a[0], p1 = a[1];
+  template <bool S>
+  static __device__ __forceinline__ void micro(const Tables& T, int m, int k, int gi, float f,
+                                               float* t, float* s, float* fi) {
+    const float4* a = reinterpret_cast<const float4*>(
+        T.ce_xs_f + (((size_t)m * T.n_pts + gi) * T.max_nuc + k) * 4);
+    const float4 p0 = a[0], p1 = a[T.max_nuc];
     *t = p0.x + f * (p1.x - p0.x);
-    *s = p0.y + f * (p1.y - p0.y);
-    *fi = p0.z + f * (p1.z - p0.z);
+    *fi = p0.y + f * (p1.y - p0.y);
+    *s = S ? p0.z + f * (p1.z - p0.z) : 0.0f;
   }
   // binary32 loses 1 - w^2 to cancellation much earlier than binary64
   static constexpr float rot_eps = 1e-4f;
@@ -195,7 +206,8 @@ struct CEXS {
   R f;           // interpolation fraction
 };
 
-template <class R>
+// Macroscopic cross sections at e (the scattering one only if S).
+template <class R, bool S>
 __device__ __forceinline__ CEXS<R> ce_macro(const Tables& T, int m, R e) {
   CEXS<R> x;
   const R* grid = CEP<R>::grid(T);
@@ -209,10 +221,9 @@ __device__ __forceinline__ CEXS<R> ce_macro(const Tables& T, int m, R e) {
   const int nn = T.mat_n[m];
   const R* dens = CEP<R>::dens(T);
   for (int k = 0; k < nn; ++k) {
-    const int n = T.mat_nuc[m * T.max_nuc + k];
     const R d = dens[m * T.max_nuc + k];
     R t, s, fi;
-    CEP<R>::micro(T, n, x.gi, x.f, &t, &s, &fi);
+    CEP<R>::template micro<S>(T, m, k, x.gi, x.f, &t, &s, &fi);
     st = st + d * t;
     ss = ss + d * s;
     sf = sf + d * fi;
@@ -336,7 +347,7 @@ __device__ __forceinline__ int segment_ce(const Tables& T, const Geo& L, PartCE<
   const int un = L.pin_map[c];
   const int nr = L.n_rings[un];
   const int m = L.mats[un * L.mr1 + p.r];
-  const CEXS<R> X = ce_macro<R>(T, m, p.e);
+  const CEXS<R> X = ce_macro<R, false>(T, m, p.e);
   const R st = X.st;
   const R nusf = (R)T.nu * X.sf;
 
@@ -443,7 +454,7 @@ __device__ __forceinline__ ColCE<R> col_ce(const Tables& T, const Geo& L, const 
   ColCE<R> c;
   const int un = L.pin_map[p.j * L.nx + p.i];
   c.m = L.mats[un * L.mr1 + p.r];
-  c.x = ce_macro<R>(T, c.m, p.e);
+  c.x = ce_macro<R, true>(T, c.m, p.e);
   c.nusf = (R)T.nu * c.x.sf;
   return c;
 }
@@ -489,9 +500,8 @@ __device__ __forceinline__ int collide_rest_ce(const Tables& T, PartCE<R>& p, St
   int pick = -1, last_nz = -1;
   R mt = R(0), ms = R(0), last_t = R(0), last_s = R(0);
   for (int k = 0; k < nn; ++k) {
-    const int n = T.mat_nuc[c.m * T.max_nuc + k];
     R t, s, fi;
-    CEP<R>::micro(T, n, c.x.gi, c.x.f, &t, &s, &fi);
+    CEP<R>::template micro<true>(T, c.m, k, c.x.gi, c.x.f, &t, &s, &fi);
     const R term = dens[c.m * T.max_nuc + k] * t;
     cum = cum + term;
     if (term > R(0)) {

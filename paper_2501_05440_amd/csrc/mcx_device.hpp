@@ -116,7 +116,8 @@ struct Tables {
   int ce;
   int n_pts, max_nuc, n_ebins;
   const double* e_grid;    // [n_pts] increasing, eV
-  const double* ce_xs;     // [n_nuc][n_pts][4]: sig_t, sig_s, sig_f, 0 (barns)
+  const double* ce_xs;     // [n_mat][n_pts][max_nuc][4]: sig_t, sig_f, sig_s, 0 (barns)
+                           // of the material's nuclides in material order
   const double* awr;       // [n_nuc]
   const int* mat_n;        // [n_mat]
   const int* mat_nuc;      // [n_mat][max_nuc]
@@ -124,7 +125,7 @@ struct Tables {
   const double* e_edges;   // [n_ebins + 1]
   // binary32 copies for the FP32-mixed mode
   const float* e_grid_f;
-  const float* ce_xs_f;    // [n_nuc][n_pts][4]
+  const float* ce_xs_f;    // [n_mat][n_pts][max_nuc][4]
   const float* awr_f;
   const float* mat_dens_f;
   const float* e_edges_f;
