@@ -88,22 +88,24 @@ struct CEP<double> {
   static __device__ __forceinline__ void cossin_2pi(double t, double* c, double* s) {
     cr_cossin_2pi(t, sc_tab(), c, s);
   }
-  // one interval of nuclide k of material m: (t, s, f) at both ends; the
-  // entries are (t, f, s, 0), so without s (the flights) one 16-byte load
-  // per grid point does
+  // one interval of nuclide k of material m: (t, s, f) at both ends; without
+  // s (the flights) from the (t, f) copy, one 16-byte load per grid point
   template <bool S>
   static __device__ __forceinline__ void micro(const Tables& T, int m, int k, int gi, double f,
                                                double* t, double* s, double* fi) {
-    const double2* a = reinterpret_cast<const double2*>(
-        T.ce_xs + (((size_t)m * T.n_pts + gi) * T.max_nuc + k) * 4);
-    const int nx = 2 * T.max_nuc;  // the next grid point, in double2
-    const double2 tf0 = a[0], tf1 = a[nx];
-    *t = tf0.x + f * (tf1.x - tf0.x);
-    *fi = tf0.y + f * (tf1.y - tf0.y);
+    const size_t e = ((size_t)m * T.n_pts + gi) * T.max_nuc + k;
     if (S) {
-      const double s0 = a[1].x, s1 = a[nx + 1].x;
-      *s = s0 + f * (s1 - s0);
+      const double2* a = reinterpret_cast<const double2*>(T.ce_xs + e * 4);
+      const int nx = 2 * T.max_nuc;  // the next grid point, in double2
+      const double2 tf0 = a[0], s0 = a[1], tf1 = a[nx], s1 = a[nx + 1];
+      *t = tf0.x + f * (tf1.x - tf0.x);
+      *fi = tf0.y + f * (tf1.y - tf0.y);
+      *s = s0.x + f * (s1.x - s0.x);
     } else {
+      const double2* a = reinterpret_cast<const double2*>(T.ce_tf) + e;
+      const double2 tf0 = a[0], tf1 = a[T.max_nuc];
+      *t = tf0.x + f * (tf1.x - tf0.x);
+      *fi = tf0.y + f * (tf1.y - tf0.y);
       *s = 0.0;
     }
   }
@@ -124,12 +126,20 @@ struct CEP<float> {
   template <bool S>
   static __device__ __forceinline__ void micro(const Tables& T, int m, int k, int gi, float f,
                                                float* t, float* s, float* fi) {
-    const float4* a = reinterpret_cast<const float4*>(
-        T.ce_xs_f + (((size_t)m * T.n_pts + gi) * T.max_nuc + k) * 4);
-    const float4 p0 = a[0], p1 = a[T.max_nuc];
-    *t = p0.x + f * (p1.x - p0.x);
-    *fi = p0.y + f * (p1.y - p0.y);
-    *s = S ? p0.z + f * (p1.z - p0.z) : 0.0f;
+    const size_t e = ((size_t)m * T.n_pts + gi) * T.max_nuc + k;
+    if (S) {
+      const float4* a = reinterpret_cast<const float4*>(T.ce_xs_f) + e;
+      const float4 p0 = a[0], p1 = a[T.max_nuc];
+      *t = p0.x + f * (p1.x - p0.x);
+      *fi = p0.y + f * (p1.y - p0.y);
+      *s = p0.z + f * (p1.z - p0.z);
+    } else {
+      const float2* a = reinterpret_cast<const float2*>(T.ce_tf_f) + e;
+      const float2 p0 = a[0], p1 = a[T.max_nuc];
+      *t = p0.x + f * (p1.x - p0.x);
+      *fi = p0.y + f * (p1.y - p0.y);
+      *s = 0.0f;
+    }
   }
   // binary32 loses 1 - w^2 to cancellation much earlier than binary64
   static constexpr float rot_eps = 1e-4f;

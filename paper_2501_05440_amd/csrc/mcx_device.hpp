@@ -118,6 +118,7 @@ struct Tables {
   const double* e_grid;    // [n_pts] increasing, eV
   const double* ce_xs;     // [n_mat][n_pts][max_nuc][4]: sig_t, sig_f, sig_s, 0 (barns)
                            // of the material's nuclides in material order
+  const double* ce_tf;     // [n_mat][n_pts][max_nuc][2]: sig_t, sig_f (the flights' copy)
   const double* awr;       // [n_nuc]
   const int* mat_n;        // [n_mat]
   const int* mat_nuc;      // [n_mat][max_nuc]
@@ -126,6 +127,7 @@ struct Tables {
   // binary32 copies for the FP32-mixed mode
   const float* e_grid_f;
   const float* ce_xs_f;    // [n_mat][n_pts][max_nuc][4]
+  const float* ce_tf_f;    // [n_mat][n_pts][max_nuc][2]
   const float* awr_f;
   const float* mat_dens_f;
   const float* e_edges_f;
