@@ -95,17 +95,27 @@ def timed_runs(ctx, steps):
 
 def fp32_mixed_comparison(P, mcx, n, n_gen, n_inactive):
     """Lattice at n histories per generation: FP64 and FP32-mixed throughput
-    and the k-eff difference (pcm) with its standard deviation."""
+    and the k-eff difference (pcm) with its standard deviation, and the
+    per-pin flux differences."""
     import math
+
+    import numpy as np
     prob = P.lattice_17x17(n_per_gen=n, n_gen=n_gen, n_inactive=n_inactive)
+    geo = prob["geometry"]
+    cells, per_cell = geo["ny"] * geo["nx"], (geo["radii"].shape[1] + 1) * prob["xs"]["sig_t"].shape[1]
     out = {}
     res = {}
+    pins = {}
     for prec in ("fp64", "fp32"):
         ctx = mcx.Context(prob, precision=prec, time_kernels=True)
         sec = timed_runs(ctx, 1)
         km, ks, pg = ctx.keff()
         t = ctx.timing()
         res[prec] = (km, ks, pg)
+        # per-pin flux (all rings and groups of a lattice cell) and its sigma
+        tl = ctx.tallies()
+        pins[prec] = (tl["flux_mean"].reshape(cells, per_cell).sum(axis=1),
+                      np.sqrt((tl["flux_sigma"].reshape(cells, per_cell) ** 2).sum(axis=1)))
         ctx.close()
         out[prec] = {"histories_per_s": round(n * n_gen / sec, 1), "ms_per_step": round(sec * 1e3, 2),
                      "k_col": round(float(km[0]), 7), "sigma": round(float(ks[0]), 7)}
@@ -126,6 +136,13 @@ def fp32_mixed_comparison(P, mcx, n, n_gen, n_inactive):
     out["sigma_pcm"] = round(sig * 1e5, 3)
     out["paired_sigma_pcm"] = round(float(d.std(ddof=1) / math.sqrt(len(d))) * 1e5, 3)
     out["speedup_fp32_over_fp64"] = round(out["fp32"]["histories_per_s"] / out["fp64"]["histories_per_s"], 3)
+    (f64, s64), (f32, s32) = pins["fp64"], pins["fp32"]
+    rel = np.abs(f32 - f64) / f64
+    out["pin_flux"] = {"max_rel_diff": float(f"{rel.max():.3e}"),
+                       "rms_rel_diff": float(f"{np.sqrt(np.mean(rel ** 2)):.3e}"),
+                       "max_rel_sigma_fp64": float(f"{(s64 / f64).max():.3e}"),
+                       "mean_abs_diff_over_sigma": round(float(np.mean(np.abs(f32 - f64) / np.hypot(s32, s64))), 3),
+                       "pins": int(cells)}
     out["workload"] = f"lattice_17x17_7g, {n} histories/gen x {n_gen} gens ({n_inactive} inactive)"
     return out
 
