@@ -91,6 +91,30 @@ def test_ce_flat_infinite_medium_and_cutoff(oracle):
     assert np.all(cut + ab == 3000) and np.all(cut > 0.9 * 3000)
 
 
+def test_ce_uneven_and_shared_materials(oracle):
+    """Materials of different sizes (3 and 5 nuclides, so the packed table
+    has unused entries) that share a nuclide: history parity with the
+    oracle, FP64 and, in the FP32-mixed mode, launch-configuration
+    independence."""
+    banner("CE uneven and shared materials")
+    ce = dict(P.ce_data())
+    mat_nuc = ce["mat_nuc"].copy()
+    mat_dens = ce["mat_dens"].copy()
+    mat_nuc[0, :3] = [9, 8, 2]          # fuel: two fissile nuclides and a moderator one
+    mat_nuc[0, 3:] = 0
+    mat_dens[0, 3:] = 0.0
+    ce.update(mat_n=np.array([3, 5], np.int32), mat_nuc=mat_nuc, mat_dens=mat_dens)
+    prob = P.ce_pin_cell(n_per_gen=2000, n_gen=3, n_inactive=1, data=ce)
+    g = mcx.run(prob, record=True, per_gen_tallies=True)
+    o = oracle.run(prob, records=True, per_gen_tallies=True)
+    compare(g, o)
+    assert_close(g["gen_flux"], o["gen_flux"], what="gen_flux")
+    a = mcx.run(prob, precision="fp32", record=True)
+    b = mcx.run(prob, precision="fp32", record=True, flights=1, tail_threshold=-1, block_size=64)
+    assert np.array_equal(a["records"], b["records"])
+    assert np.array_equal(a["gen_k"], b["gen_k"])
+
+
 def test_ce_event_guard(oracle):
     banner("CE event guard")
     prob = P.with_run(P.ce_pin_cell(n_per_gen=1500, n_gen=2, n_inactive=1), max_events=20)
