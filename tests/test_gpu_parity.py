@@ -304,3 +304,24 @@ def test_full_size_invariants_in_bench_configuration():
     k_used = np.concatenate([[1.0], g["gen_k"][:-1, 0]])
     expect = n * g["gen_k"][:, 0] / k_used
     assert np.all(np.abs(sites - expect) < 4 * np.sqrt(col / 4.0))
+
+
+@pytest.mark.parametrize("tail", [1 << 30, 0])
+def test_flights_with_many_draws_through_the_tail(oracle, tail):
+    """Collisions that bank several sites each (nu_sig_f = 2 sigma_t with
+    k_used = 1 in generation 0, so a collision flight takes 8 or more draws):
+    in the tail kernel such a flight runs past the end of its window of
+    precomputed draws and finishes by evaluating the rest itself.  Every
+    history through the tail (threshold above N) and through the event
+    kernels, against the oracle, with the generation's bank."""
+    banner(f"many draws per flight, tail threshold {tail}")
+    xs = P.one_group(1.0, 0.2, 2.0)
+    prob = P.homogeneous(xs, 2000, 2, 1, seed=41)
+    g = mcx.run(prob, record=True, bank=True, tail_threshold=tail)
+    o = oracle.run(prob, records=True, bank_cap=20000)
+    assert np.array_equal(g["gen_counts"], o["gen_counts"])
+    assert g["gen_counts"][0, 7] > 2 * 2000  # more than two sites per history
+    for gen in range(2):
+        compare_records(g["records"][gen], o["records"][gen], f"gen {gen}")
+    assert_close(g["gen_k"], o["gen_k"], what="gen_k")
+    assert np.array_equal(g["bank"], o["bank"])
