@@ -325,3 +325,28 @@ def test_flights_with_many_draws_through_the_tail(oracle, tail):
         compare_records(g["records"][gen], o["records"][gen], f"gen {gen}")
     assert_close(g["gen_k"], o["gen_k"], what="gen_k")
     assert np.array_equal(g["bank"], o["bank"])
+
+
+def test_pin_cell_against_stored_oracle_results():
+    """The 7-group pin cell, 1e4 histories x 30 generations, against the
+    oracle's results stored in tests/golden/ (no oracle run needed): event
+    counts exactly, k estimators, entropy and the active flux mean and sigma
+    to 1e-12 relative (flux within the fixed-point quantum)."""
+    import json
+    import os
+    banner("pin cell 1e4 x 30 against tests/golden")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "pin_cell_7g_1e4x30.json")
+    with open(path) as f:
+        gd = json.load(f)
+    pr = dict(gd["problem"])
+    pr.pop("name")
+    prob = P.pin_cell(**pr)
+    g = mcx.run(prob)
+    assert list(mcx.COUNT_NAMES) == gd["count_names"]
+    assert np.array_equal(g["gen_counts"], np.array(gd["gen_counts"]))
+    assert_close(g["gen_k"], np.array(gd["gen_k"]), what="gen_k")
+    assert_close(g["gen_entropy"], np.array(gd["gen_entropy"]), what="entropy")
+    atol = flux_atol(g, prob)
+    assert_close(g["flux_mean"], np.array(gd["flux_mean"]), what="flux_mean", atol=atol)
+    assert_close(g["flux_sigma"], np.array(gd["flux_sigma"]), what="flux_sigma", atol=atol)
