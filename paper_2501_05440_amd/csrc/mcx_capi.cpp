@@ -166,8 +166,8 @@ struct mcx_ctx {
   std::vector<int> ce_mat_n, ce_mat_nuc;
   double ce_nu = 0, ce_watt_a = 0, ce_watt_b = 0, ce_e_max = 0, ce_e_cut = 0;
   double ce_sigt_min = 0;
-  std::vector<double> ce_tf;     // (t, f) pairs of ce_xs, same order
-  std::vector<float> ce_f32[6];  // binary32 grid, tables, masses, densities, edges, (t, f)
+  std::vector<double> ce_tf, ce_s;  // ce_xs split into (t, f) pairs and s, same order
+  std::vector<float> ce_f32[6];     // binary32 grid, (t, f), masses, densities, edges, s
   std::vector<int> ce_hash, ce_hash_f;
   int ce_hash_shift = 0, ce_hash_shift_f = 0;
   uint64_t ce_hash_base = 0;
@@ -547,13 +547,17 @@ int mcx_load_ce_xs(mcx_ctx* c, const mcx_ce_data* d) {
     c->has_geo = false;
     c->batch = false;
   }
-  // the flights' copy: (t, f) only, half the bytes to cache
-  std::vector<double> tf(xs.size() / 2);
+  // the device holds the table as (t, f) pairs, which every lookup reads,
+  // and s alone, which a collision needs for one nuclide (and an absorption
+  // for all): less to cache than whole (t, f, s) entries
+  std::vector<double> tf(xs.size() / 2), sv(xs.size() / 4);
   for (size_t e = 0; e < xs.size() / 4; ++e) {
     tf[2 * e] = xs[4 * e];
     tf[2 * e + 1] = xs[4 * e + 1];
+    sv[e] = xs[4 * e + 2];
   }
   c->ce_tf = std::move(tf);
+  c->ce_s = std::move(sv);
   c->ce_xs = std::move(xs);
   c->ce_grid.assign(d->e_grid, d->e_grid + d->n_pts);
   c->ce_awr.assign(d->awr, d->awr + d->n_nuc);
@@ -683,8 +687,8 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   const bool ce = c->ce;
   T.ce = ce ? 1 : 0;
   T.e_grid = cv.take<double>(c->ce_grid.size());
-  T.ce_xs = cv.take<double>(c->ce_xs.size());
   T.ce_tf = cv.take<double>(c->ce_tf.size());
+  T.ce_s = cv.take<double>(c->ce_s.size());
   T.awr = cv.take<double>(c->ce_awr.size());
   T.mat_n = cv.take<int>(c->ce_mat_n.size());
   T.mat_nuc = cv.take<int>(c->ce_mat_nuc.size());
@@ -698,8 +702,8 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   const bool fp32 = c->opt.precision == MCX_FP32_MIXED;
   const bool ce32 = ce && fp32;
   T.e_grid_f = cv.take<float>(ce32 ? c->ce_grid.size() : 0);
-  T.ce_xs_f = cv.take<float>(ce32 ? c->ce_xs.size() : 0);
   T.ce_tf_f = cv.take<float>(ce32 ? c->ce_tf.size() : 0);
+  T.ce_s_f = cv.take<float>(ce32 ? c->ce_s.size() : 0);
   T.awr_f = cv.take<float>(ce32 ? c->ce_awr.size() : 0);
   T.mat_dens_f = cv.take<float>(ce32 ? c->ce_dens.size() : 0);
   T.e_edges_f = cv.take<float>(ce32 ? c->ce_edges.size() : 0);
@@ -1028,8 +1032,8 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
   }
   if (c->ce) {
     HIP_TRY(c, up(T.e_grid, c->ce_grid.data(), c->ce_grid.size() * sizeof(double)));
-    HIP_TRY(c, up(T.ce_xs, c->ce_xs.data(), c->ce_xs.size() * sizeof(double)));
     HIP_TRY(c, up(T.ce_tf, c->ce_tf.data(), c->ce_tf.size() * sizeof(double)));
+    HIP_TRY(c, up(T.ce_s, c->ce_s.data(), c->ce_s.size() * sizeof(double)));
     HIP_TRY(c, up(T.awr, c->ce_awr.data(), c->ce_awr.size() * sizeof(double)));
     HIP_TRY(c, up(T.mat_n, c->ce_mat_n.data(), c->ce_mat_n.size() * sizeof(int)));
     HIP_TRY(c, up(T.mat_nuc, c->ce_mat_nuc.data(), c->ce_mat_nuc.size() * sizeof(int)));
@@ -1045,13 +1049,13 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
         return f;
       };
       c->ce_f32[0] = to_f(c->ce_grid);
-      c->ce_f32[1] = to_f(c->ce_xs);
+      c->ce_f32[1] = to_f(c->ce_tf);
       c->ce_f32[2] = to_f(c->ce_awr);
       c->ce_f32[3] = to_f(c->ce_dens);
       c->ce_f32[4] = to_f(c->ce_edges);
-      c->ce_f32[5] = to_f(c->ce_tf);
-      const float* dst[6] = {T.e_grid_f, T.ce_xs_f, T.awr_f, T.mat_dens_f, T.e_edges_f,
-                             T.ce_tf_f};
+      c->ce_f32[5] = to_f(c->ce_s);
+      const float* dst[6] = {T.e_grid_f, T.ce_tf_f, T.awr_f, T.mat_dens_f, T.e_edges_f,
+                             T.ce_s_f};
       for (int k = 0; k < 6; ++k)
         HIP_TRY(c, up(dst[k], c->ce_f32[k].data(), c->ce_f32[k].size() * sizeof(float)));
     }

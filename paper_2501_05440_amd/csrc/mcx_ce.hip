@@ -88,26 +88,22 @@ struct CEP<double> {
   static __device__ __forceinline__ void cossin_2pi(double t, double* c, double* s) {
     cr_cossin_2pi(t, sc_tab(), c, s);
   }
-  // one interval of nuclide k of material m: (t, s, f) at both ends; without
-  // s (the flights) from the (t, f) copy, one 16-byte load per grid point
-  template <bool S>
-  static __device__ __forceinline__ void micro(const Tables& T, int m, int k, int gi, double f,
-                                               double* t, double* s, double* fi) {
+  // one interval of nuclide k of material m: t and f at both ends (one
+  // 16-byte load per grid point), interpolated
+  static __device__ __forceinline__ void micro_tf(const Tables& T, int m, int k, int gi, double f,
+                                                  double* t, double* fi) {
     const size_t e = ((size_t)m * T.n_pts + gi) * T.max_nuc + k;
-    if (S) {
-      const double2* a = reinterpret_cast<const double2*>(T.ce_xs + e * 4);
-      const int nx = 2 * T.max_nuc;  // the next grid point, in double2
-      const double2 tf0 = a[0], s0 = a[1], tf1 = a[nx], s1 = a[nx + 1];
-      *t = tf0.x + f * (tf1.x - tf0.x);
-      *fi = tf0.y + f * (tf1.y - tf0.y);
-      *s = s0.x + f * (s1.x - s0.x);
-    } else {
-      const double2* a = reinterpret_cast<const double2*>(T.ce_tf) + e;
-      const double2 tf0 = a[0], tf1 = a[T.max_nuc];
-      *t = tf0.x + f * (tf1.x - tf0.x);
-      *fi = tf0.y + f * (tf1.y - tf0.y);
-      *s = 0.0;
-    }
+    const double2* a = reinterpret_cast<const double2*>(T.ce_tf) + e;
+    const double2 tf0 = a[0], tf1 = a[T.max_nuc];
+    *t = tf0.x + f * (tf1.x - tf0.x);
+    *fi = tf0.y + f * (tf1.y - tf0.y);
+  }
+  // the same for s
+  static __device__ __forceinline__ double micro_s(const Tables& T, int m, int k, int gi,
+                                                   double f) {
+    const size_t e = ((size_t)m * T.n_pts + gi) * T.max_nuc + k;
+    const double s0 = T.ce_s[e], s1 = T.ce_s[e + T.max_nuc];
+    return s0 + f * (s1 - s0);
   }
   static constexpr double rot_eps = 1e-10;
 };
@@ -123,23 +119,18 @@ struct CEP<float> {
   static __device__ __forceinline__ void cossin_2pi(float t, float* c, float* s) {
     sincospif(2.0f * t, s, c);
   }
-  template <bool S>
-  static __device__ __forceinline__ void micro(const Tables& T, int m, int k, int gi, float f,
-                                               float* t, float* s, float* fi) {
+  static __device__ __forceinline__ void micro_tf(const Tables& T, int m, int k, int gi, float f,
+                                                  float* t, float* fi) {
     const size_t e = ((size_t)m * T.n_pts + gi) * T.max_nuc + k;
-    if (S) {
-      const float4* a = reinterpret_cast<const float4*>(T.ce_xs_f) + e;
-      const float4 p0 = a[0], p1 = a[T.max_nuc];
-      *t = p0.x + f * (p1.x - p0.x);
-      *fi = p0.y + f * (p1.y - p0.y);
-      *s = p0.z + f * (p1.z - p0.z);
-    } else {
-      const float2* a = reinterpret_cast<const float2*>(T.ce_tf_f) + e;
-      const float2 p0 = a[0], p1 = a[T.max_nuc];
-      *t = p0.x + f * (p1.x - p0.x);
-      *fi = p0.y + f * (p1.y - p0.y);
-      *s = 0.0f;
-    }
+    const float2* a = reinterpret_cast<const float2*>(T.ce_tf_f) + e;
+    const float2 p0 = a[0], p1 = a[T.max_nuc];
+    *t = p0.x + f * (p1.x - p0.x);
+    *fi = p0.y + f * (p1.y - p0.y);
+  }
+  static __device__ __forceinline__ float micro_s(const Tables& T, int m, int k, int gi, float f) {
+    const size_t e = ((size_t)m * T.n_pts + gi) * T.max_nuc + k;
+    const float s0 = T.ce_s_f[e], s1 = T.ce_s_f[e + T.max_nuc];
+    return s0 + f * (s1 - s0);
   }
   // binary32 loses 1 - w^2 to cancellation much earlier than binary64
   static constexpr float rot_eps = 1e-4f;
@@ -211,13 +202,13 @@ __device__ __forceinline__ int grid_interval<float>(const Tables& T, float e) {
 
 template <class R>
 struct CEXS {
-  R st, ss, sf;  // macroscopic total, scattering, fission
+  R st, sf;      // macroscopic total, fission
   int gi;        // grid interval
   R f;           // interpolation fraction
 };
 
-// Macroscopic cross sections at e (the scattering one only if S).
-template <class R, bool S>
+// Macroscopic total and fission cross sections at e.
+template <class R>
 __device__ __forceinline__ CEXS<R> ce_macro(const Tables& T, int m, R e) {
   CEXS<R> x;
   const R* grid = CEP<R>::grid(T);
@@ -227,21 +218,32 @@ __device__ __forceinline__ CEXS<R> ce_macro(const Tables& T, int m, R e) {
   if (f < R(0)) f = R(0);
   if (f > R(1)) f = R(1);
   x.f = f;
-  R st = R(0), ss = R(0), sf = R(0);
+  R st = R(0), sf = R(0);
   const int nn = T.mat_n[m];
   const R* dens = CEP<R>::dens(T);
   for (int k = 0; k < nn; ++k) {
     const R d = dens[m * T.max_nuc + k];
-    R t, s, fi;
-    CEP<R>::template micro<S>(T, m, k, x.gi, x.f, &t, &s, &fi);
+    R t, fi;
+    CEP<R>::micro_tf(T, m, k, x.gi, x.f, &t, &fi);
     st = st + d * t;
-    ss = ss + d * s;
     sf = sf + d * fi;
   }
   x.st = st;
-  x.ss = ss;
   x.sf = sf;
   return x;
+}
+
+// Macroscopic scattering cross section at the interval and fraction of x.
+template <class R>
+__device__ __forceinline__ R ce_macro_s(const Tables& T, int m, const CEXS<R>& x) {
+  R ss = R(0);
+  const int nn = T.mat_n[m];
+  const R* dens = CEP<R>::dens(T);
+  for (int k = 0; k < nn; ++k) {
+    const R d = dens[m * T.max_nuc + k];
+    ss = ss + d * CEP<R>::micro_s(T, m, k, x.gi, x.f);
+  }
+  return ss;
 }
 
 // One attempt of the Watt sampler: a Maxwellian W of temperature a from
@@ -357,7 +359,7 @@ __device__ __forceinline__ int segment_ce(const Tables& T, const Geo& L, PartCE<
   const int un = L.pin_map[c];
   const int nr = L.n_rings[un];
   const int m = L.mats[un * L.mr1 + p.r];
-  const CEXS<R> X = ce_macro<R, false>(T, m, p.e);
+  const CEXS<R> X = ce_macro<R>(T, m, p.e);
   const R st = X.st;
   const R nusf = (R)T.nu * X.sf;
 
@@ -464,7 +466,7 @@ __device__ __forceinline__ ColCE<R> col_ce(const Tables& T, const Geo& L, const 
   ColCE<R> c;
   const int un = L.pin_map[p.j * L.nx + p.i];
   c.m = L.mats[un * L.mr1 + p.r];
-  c.x = ce_macro<R, true>(T, c.m, p.e);
+  c.x = ce_macro<R>(T, c.m, p.e);
   c.nusf = (R)T.nu * c.x.sf;
   return c;
 }
@@ -508,28 +510,27 @@ __device__ __forceinline__ int collide_rest_ce(const Tables& T, PartCE<R>& p, St
   const R* dens = CEP<R>::dens(T);
   R cum = R(0);
   int pick = -1, last_nz = -1;
-  R mt = R(0), ms = R(0), last_t = R(0), last_s = R(0);
+  R mt = R(0), last_t = R(0);
   for (int k = 0; k < nn; ++k) {
-    R t, s, fi;
-    CEP<R>::template micro<true>(T, c.m, k, c.x.gi, c.x.f, &t, &s, &fi);
+    R t, fi;
+    CEP<R>::micro_tf(T, c.m, k, c.x.gi, c.x.f, &t, &fi);
     const R term = dens[c.m * T.max_nuc + k] * t;
     cum = cum + term;
     if (term > R(0)) {
       last_nz = k;
       last_t = t;
-      last_s = s;
     }
     if (pick < 0 && target < cum) {
       pick = k;
       mt = t;
-      ms = s;
     }
   }
   if (pick < 0) {
     pick = last_nz;
     mt = last_t;
-    ms = last_s;
   }
+  // the scattering cross section of the chosen nuclide only
+  const R ms = pick >= 0 ? CEP<R>::micro_s(T, c.m, pick, c.x.gi, c.x.f) : R(0);
   const int nuc = T.mat_nuc[c.m * T.max_nuc + (pick < 0 ? 0 : pick)];
   const R xr = Prec<R>::xi(rs.next());
   if (xr * mt < ms) {
@@ -542,7 +543,9 @@ __device__ __forceinline__ int collide_rest_ce(const Tables& T, PartCE<R>& p, St
     rotate<R>(mu, xp, &p.u, &p.v, &p.w);
     return FATE_ALIVE;
   }
-  *q_kabs = c.nusf > R(0) ? quantize((double)(c.nusf / (c.x.st - c.x.ss)), T.q_kabs) : 0;
+  *q_kabs = c.nusf > R(0)
+                ? quantize((double)(c.nusf / (c.x.st - ce_macro_s<R>(T, c.m, c.x))), T.q_kabs)
+                : 0;
   return FATE_ABSORBED;
 }
 

@@ -116,9 +116,9 @@ struct Tables {
   int ce;
   int n_pts, max_nuc, n_ebins;
   const double* e_grid;    // [n_pts] increasing, eV
-  const double* ce_xs;     // [n_mat][n_pts][max_nuc][4]: sig_t, sig_f, sig_s, 0 (barns)
-                           // of the material's nuclides in material order
-  const double* ce_tf;     // [n_mat][n_pts][max_nuc][2]: sig_t, sig_f (the flights' copy)
+  const double* ce_tf;     // [n_mat][n_pts][max_nuc][2]: sig_t, sig_f (barns) of the
+                           // material's nuclides in material order
+  const double* ce_s;      // [n_mat][n_pts][max_nuc]: sig_s
   const double* awr;       // [n_nuc]
   const int* mat_n;        // [n_mat]
   const int* mat_nuc;      // [n_mat][max_nuc]
@@ -126,8 +126,8 @@ struct Tables {
   const double* e_edges;   // [n_ebins + 1]
   // binary32 copies for the FP32-mixed mode
   const float* e_grid_f;
-  const float* ce_xs_f;    // [n_mat][n_pts][max_nuc][4]
   const float* ce_tf_f;    // [n_mat][n_pts][max_nuc][2]
+  const float* ce_s_f;     // [n_mat][n_pts][max_nuc]
   const float* awr_f;
   const float* mat_dens_f;
   const float* e_edges_f;
