@@ -207,29 +207,97 @@ struct CEXS {
   R f;           // interpolation fraction
 };
 
-// Macroscopic total and fission cross sections at e.
+// Grid interval of e and the interpolation fraction in it.
 template <class R>
-__device__ __forceinline__ CEXS<R> ce_macro(const Tables& T, int m, R e) {
-  CEXS<R> x;
+__device__ __forceinline__ void ce_locate(const Tables& T, R e, int* gi, R* fr) {
   const R* grid = CEP<R>::grid(T);
-  x.gi = grid_interval<R>(T, e);
-  const R e0 = grid[x.gi], e1 = grid[x.gi + 1];
+  *gi = grid_interval<R>(T, e);
+  const R e0 = grid[*gi], e1 = grid[*gi + 1];
   R f = (e - e0) / (e1 - e0);
   if (f < R(0)) f = R(0);
   if (f > R(1)) f = R(1);
-  x.f = f;
+  *fr = f;
+}
+
+// Macroscopic total and fission cross sections of material m at (gi, f).
+template <class R>
+__device__ __forceinline__ void ce_sums(const Tables& T, int m, int gi, R fr, R* st_out,
+                                        R* sf_out) {
   R st = R(0), sf = R(0);
   const int nn = T.mat_n[m];
   const R* dens = CEP<R>::dens(T);
   for (int k = 0; k < nn; ++k) {
     const R d = dens[m * T.max_nuc + k];
     R t, fi;
-    CEP<R>::micro_tf(T, m, k, x.gi, x.f, &t, &fi);
+    CEP<R>::micro_tf(T, m, k, gi, fr, &t, &fi);
     st = st + d * t;
     sf = sf + d * fi;
   }
-  x.st = st;
-  x.sf = sf;
+  *st_out = st;
+  *sf_out = sf;
+}
+
+// Macroscopic total and fission cross sections at e.
+template <class R>
+__device__ __forceinline__ CEXS<R> ce_macro(const Tables& T, int m, R e) {
+  CEXS<R> x;
+  ce_locate<R>(T, e, &x.gi, &x.f);
+  ce_sums<R>(T, m, x.gi, x.f, &x.st, &x.sf);
+  return x;
+}
+
+// The lookups of the last energy: its interval and the sums of the last two
+// materials at it.  A particle keeps its energy from one collision to the
+// next, so the flights in between that stay in, or come back to, a
+// material (ring crossings, reflections) reuse them; the values are the ones
+// a new lookup computes.
+template <class R>
+struct CECache {
+  R e;  // energy of gi and f, -1 when empty
+  int gi;
+  R f;
+  int m0, m1, next;
+  R st0, sf0, st1, sf1;
+};
+
+template <class R>
+__device__ __forceinline__ void ce_cache_clear(CECache<R>& c) {
+  c.e = R(-1);
+  c.m0 = -1;
+  c.m1 = -1;
+  c.next = 0;
+}
+
+template <class R>
+__device__ __forceinline__ CEXS<R> ce_macro_cached(const Tables& T, int m, R e, CECache<R>& c) {
+  CEXS<R> x;
+  if (!(c.e == e)) {
+    ce_locate<R>(T, e, &c.gi, &c.f);
+    c.e = e;
+    c.m0 = -1;
+    c.m1 = -1;
+  }
+  x.gi = c.gi;
+  x.f = c.f;
+  if (c.m0 == m) {
+    x.st = c.st0;
+    x.sf = c.sf0;
+  } else if (c.m1 == m) {
+    x.st = c.st1;
+    x.sf = c.sf1;
+  } else {
+    ce_sums<R>(T, m, x.gi, x.f, &x.st, &x.sf);
+    if (c.next == 0) {
+      c.m0 = m;
+      c.st0 = x.st;
+      c.sf0 = x.sf;
+    } else {
+      c.m1 = m;
+      c.st1 = x.st;
+      c.sf1 = x.sf;
+    }
+    c.next ^= 1;
+  }
   return x;
 }
 
@@ -354,12 +422,12 @@ __device__ __forceinline__ void die_ce(const PartCE<R>& p, int fate, const Accum
 template <class R, bool REC, bool HALVES>
 __device__ __forceinline__ int segment_ce(const Tables& T, const Geo& L, PartCE<R>& p, Stream& rs,
                                           const Accum& A, const Records& Rc, bool* refl_out,
-                                          uint64_t* q_tl) {
+                                          uint64_t* q_tl, CECache<R>& cache) {
   const int c = p.j * L.nx + p.i;
   const int un = L.pin_map[c];
   const int nr = L.n_rings[un];
   const int m = L.mats[un * L.mr1 + p.r];
-  const CEXS<R> X = ce_macro<R>(T, m, p.e);
+  const CEXS<R> X = ce_macro_cached<R>(T, m, p.e, cache);
   const R st = X.st;
   const R nusf = (R)T.nu * X.sf;
 
@@ -616,6 +684,8 @@ __global__ void __launch_bounds__(1024) k_ce_advance(Tables T, uint32_t gen, uin
   if (k < n_in) {
     p = load_ce<R>(in, k);
     Stream rs(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
+    CECache<R> cache;
+    ce_cache_clear(cache);
     for (uint32_t f = 0; f < flights; ++f) {
       if ((int64_t)p.nseg >= T.max_events) {
         ev = EV_KILL;
@@ -623,7 +693,7 @@ __global__ void __launch_bounds__(1024) k_ce_advance(Tables T, uint32_t gen, uin
       }
       bool refl = false;
       uint64_t q = 0;
-      ev = segment_ce<R, REC, false>(T, T.geo, p, rs, A, Rc, &refl, &q);
+      ev = segment_ce<R, REC, false>(T, T.geo, p, rs, A, Rc, &refl, &q, cache);
       tl_lo += q & 0xFFFFFFFFull;
       tl_hi += q >> 32;
       p.nseg += 1;
@@ -714,6 +784,8 @@ __global__ void __launch_bounds__(256) k_ce_tail(Tables T, uint32_t gen, Bank in
   bool live = k < n_in;
   PartCE<R> p;
   Stream rs(T.seed, TAG_TRANSPORT, 0, gen, T.prob, 0);
+  CECache<R> cache;
+  ce_cache_clear(cache);
   int64_t nseg = 0;
   if (live) {
     p = load_ce<R>(in, k);
@@ -733,7 +805,7 @@ __global__ void __launch_bounds__(256) k_ce_tail(Tables T, uint32_t gen, Bank in
       } else {
         bool refl = false;
         uint64_t q = 0;
-        const int ev = segment_ce<R, REC, true>(T, T.geo, p, rs, A, Rc, &refl, &q);
+        const int ev = segment_ce<R, REC, true>(T, T.geo, p, rs, A, Rc, &refl, &q, cache);
         ktl[0] += q & 0xFFFFFFFFull;
         ktl[1] += q >> 32;
         ++nseg;
