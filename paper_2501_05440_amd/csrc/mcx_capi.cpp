@@ -733,6 +733,17 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
       k.w = cv.take<double>(ce ? N : 0);
       k.e = cv.take<double>(ce ? N : 0);
     }
+    const size_t nx = (ce && b == 2) ? N : 0;  // lookups handed to the collision kernel
+    k.xgi = cv.take<int32_t>(nx);
+    if (fp32) {
+      k.xf = cv.take<float>(nx);
+      k.xst = cv.take<float>(nx);
+      k.xsf = cv.take<float>(nx);
+    } else {
+      k.xf = cv.take<double>(nx);
+      k.xst = cv.take<double>(nx);
+      k.xsf = cv.take<double>(nx);
+    }
   }
   d.src_x = cv.take<double>(N);
   d.src_y = cv.take<double>(N);

@@ -529,12 +529,29 @@ struct ColCE {
   R nusf;
 };
 
+// The collision point's material and lookup: from the flight's cache (the
+// tail kernel) or as stored with the particle by the flight kernel.
 template <class R>
-__device__ __forceinline__ ColCE<R> col_ce(const Tables& T, const Geo& L, const PartCE<R>& p) {
+__device__ __forceinline__ ColCE<R> col_ce(const Tables& T, const Geo& L, const PartCE<R>& p,
+                                           CECache<R>& cache) {
   ColCE<R> c;
   const int un = L.pin_map[p.j * L.nx + p.i];
   c.m = L.mats[un * L.mr1 + p.r];
-  c.x = ce_macro<R>(T, c.m, p.e);
+  c.x = ce_macro_cached<R>(T, c.m, p.e, cache);
+  c.nusf = (R)T.nu * c.x.sf;
+  return c;
+}
+
+template <class R>
+__device__ __forceinline__ ColCE<R> col_ce_stored(const Tables& T, const Geo& L,
+                                                  const PartCE<R>& p, const Bank& b, uint32_t k) {
+  ColCE<R> c;
+  const int un = L.pin_map[p.j * L.nx + p.i];
+  c.m = L.mats[un * L.mr1 + p.r];
+  c.x.gi = b.xgi[k];
+  c.x.f = static_cast<const R*>(b.xf)[k];
+  c.x.st = static_cast<const R*>(b.xst)[k];
+  c.x.sf = static_cast<const R*>(b.xsf)[k];
   c.nusf = (R)T.nu * c.x.sf;
   return c;
 }
@@ -681,6 +698,7 @@ __global__ void __launch_bounds__(1024) k_ce_advance(Tables T, uint32_t gen, uin
   uint32_t c_seg = 0, c_cross = 0, c_refl = 0;
   unsigned long long tl_lo = 0, tl_hi = 0;
   PartCE<R> p;
+  CEXS<R> X{};
   if (k < n_in) {
     p = load_ce<R>(in, k);
     Stream rs(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
@@ -705,12 +723,23 @@ __global__ void __launch_bounds__(1024) k_ce_advance(Tables T, uint32_t gen, uin
     p.ctr = rs.draw;
     if (ev == EV_KILL) die_ce<R, REC>(p, FATE_KILLED, A, Rc, T);
     if (ev == EV_LEAK) die_ce<R, REC>(p, FATE_LEAKED, A, Rc, T);
+    // the collision point's lookup (a hit in the cache) goes with the particle
+    if (ev == EV_COLLIDE) {
+      const Geo& L = T.geo;
+      X = ce_macro_cached<R>(T, L.mats[L.pin_map[p.j * L.nx + p.i] * L.mr1 + p.r], p.e, cache);
+    }
   }
   __shared__ uint32_t lds[2 * (MAX_WAVES + 1)];
   uint32_t pl, pc;
   block_append2(ev == EV_CROSS, ev == EV_COLLIDE, n_live, n_col, lds, &pl, &pc);
   if (ev == EV_CROSS) store_ce<R>(live, pl, p);
-  if (ev == EV_COLLIDE) store_ce<R>(col, pc, p);
+  if (ev == EV_COLLIDE) {
+    store_ce<R>(col, pc, p);
+    col.xgi[pc] = X.gi;
+    static_cast<R*>(col.xf)[pc] = X.f;
+    static_cast<R*>(col.xst)[pc] = X.st;
+    static_cast<R*>(col.xsf)[pc] = X.sf;
+  }
   wave_count(A.cnt + CNT_SEG * STRIPES, c_seg);
   wave_count(A.cnt + CNT_CROSS * STRIPES, c_cross);
   wave_count(A.cnt + CNT_REFL * STRIPES, c_refl);
@@ -738,7 +767,7 @@ __global__ void __launch_bounds__(1024) k_ce_collide(Tables T, uint32_t gen, Ban
   if (valid) {
     p = load_ce<R>(in, k);
     rs = Stream(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
-    c = col_ce<R>(T, T.geo, p);
+    c = col_ce_stored<R>(T, T.geo, p, in, k);
     const double kc = (double)(c.nusf / c.x.st);
     q_kcol = quantize(kc, T.q_kcol);
     if (REC) {
@@ -821,7 +850,7 @@ __global__ void __launch_bounds__(256) k_ce_tail(Tables T, uint32_t gen, Bank in
           c_refl += refl ? 1 : 0;
         } else {
           ++c_col;
-          c = col_ce<R>(T, T.geo, p);
+          c = col_ce<R>(T, T.geo, p, cache);
           const double kc = (double)(c.nusf / c.x.st);
           const uint64_t qk = quantize(kc, T.q_kcol);
           kcol[0] += qk & 0xFFFFFFFFull;

@@ -167,6 +167,13 @@ struct Bank {
   double* t;      // time-dependent mode: time since the source pulse
   void* w;        // continuous energy: z direction cosine (working precision)
   void* e;        // continuous energy: energy, eV (working precision)
+  // continuous energy, collision bank only: the lookup of the collision
+  // point made by the flight that ended there (grid interval, fraction,
+  // macroscopic total and fission cross sections, working precision)
+  int32_t* xgi;
+  void* xf;
+  void* xst;
+  void* xsf;
 };
 
 // Fission sites as banked (unordered) and in canonical (parent, seq) order.
