@@ -605,9 +605,10 @@ __device__ __forceinline__ int collide_rest_ce(const Tables& T, PartCE<R>& p, St
       last_nz = k;
       last_t = t;
     }
-    if (pick < 0 && target < cum) {
+    if (target < cum) {  // the first such k; the later ones do not matter
       pick = k;
       mt = t;
+      break;
     }
   }
   if (pick < 0) {
