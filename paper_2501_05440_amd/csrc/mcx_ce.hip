@@ -362,17 +362,23 @@ __device__ __forceinline__ void rotate(R mu, R xi_phi, R* pu, R* pv, R* pw) {
   R sm = R(1) - mu * mu;
   sm = sm > R(0) ? CEP<R>::sqrt(sm) : R(0);
   const R a = R(1) - w * w;
+  // new values in locals, stored once (stores through the pointers in two
+  // orders put the particle in scratch memory)
+  R nu, nv, nw;
   if (a > CEP<R>::rot_eps) {
     const R t = CEP<R>::sqrt(a);
-    *pu = mu * u + sm * (u * w * c - v * s) / t;
-    *pv = mu * v + sm * (v * w * c + u * s) / t;
-    *pw = mu * w - sm * t * c;
+    nu = mu * u + sm * (u * w * c - v * s) / t;
+    nv = mu * v + sm * (v * w * c + u * s) / t;
+    nw = mu * w - sm * t * c;
   } else {
     const R t = CEP<R>::sqrt(R(1) - u * u);
-    *pv = mu * v + sm * (v * u * c - w * s) / t;
-    *pw = mu * w + sm * (w * u * c + v * s) / t;
-    *pu = mu * u - sm * t * c;
+    nv = mu * v + sm * (v * u * c - w * s) / t;
+    nw = mu * w + sm * (w * u * c + v * s) / t;
+    nu = mu * u - sm * t * c;
   }
+  *pu = nu;
+  *pv = nv;
+  *pw = nw;
 }
 
 // Source site: rejection in the lattice box (FP64) until the point is

@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(PB) k_persistent(Tables T0, uint32_t gen, Accu
         const int s = M.list[t];
         const uint64_t h = (uint64_t)M.base + t;
         const int pi = P ? problem_of(P, T.n_probs, h) : 0;
-        const Geo& L = P ? P[pi].geo : T.geo;
+        const Geo L = P ? P[pi].geo : T.geo;  // a copy keeps T out of scratch
         const uint64_t seed = P ? P[pi].seed : T.seed;
         const uint64_t prob = P ? P[pi].prob : T.prob;
         const uint64_t lid = h - (P ? P[pi].hist_base : 0ull);
@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(PB) k_persistent(Tables T0, uint32_t gen, Accu
       const int s = M.list[t];
       Part<R> p = slot_load(M, s, P);
       const int pi = P ? M.prob[s] : 0;
-      const Geo& L = P ? P[pi].geo : T.geo;
+      const Geo L = P ? P[pi].geo : T.geo;  // a copy keeps T out of scratch
       if ((int64_t)M.nseg[s] >= T.max_events) {
         slot_death(M, s, p, FATE_KILLED, 0, A, H);
         continue;
@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(PB) k_persistent(Tables T0, uint32_t gen, Accu
       if (valid) {
         p = slot_load(M, s, P);
         pi = P ? M.prob[s] : 0;
-        const Geo& L = P ? P[pi].geo : T.geo;
+        const Geo L = P ? P[pi].geo : T.geo;  // a copy keeps T out of scratch
         rs = Stream(P ? P[pi].seed : T.seed, TAG_TRANSPORT, p.id, gen, P ? P[pi].prob : T.prob,
                     p.ctr);
         x = col_xs(T, L, p);
