@@ -302,8 +302,8 @@ def time_dependent_measurement(P, mcx, steps, cpu):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU design is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}): sharding histories over "
+              "several GPUs is designed but not built", file=sys.stderr)
         sys.exit(2)
     import torch
 
