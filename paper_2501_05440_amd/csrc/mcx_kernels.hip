@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(1024) k_collide(Tables T0, uint32_t gen, Bank 
 // particle's remaining flights and collisions to the end (the same
 // operations as the event kernels, in the same order).  One wave per block.
 template <class R, bool REC, bool LDS>
-__global__ void __launch_bounds__(256) k_tail(Tables T0, uint32_t gen, Bank in,
+__global__ void __launch_bounds__(64) k_tail(Tables T0, uint32_t gen, Bank in,
                                               const uint32_t* __restrict__ n_in_p, Accum A,
                                               Records Rc) {
   const uint32_t n_in = *n_in_p;
