@@ -444,15 +444,25 @@ __global__ void __launch_bounds__(64) k_gen_totals(Tables T, uint32_t gen, uint3
   static_assert(STRIPES == 64, "one accumulator stripe per lane");
   const int lane = (int)threadIdx.x;
   const double inv_q[3] = {1.0 / T.q_kcol, T.ce ? 1.0 / T.q_ktl : 0.0, 1.0 / T.q_kabs};
-  double kv[3] = {0.0, 0.0, 0.0};
+  // every load first: the stores below could alias them, so loads left in
+  // the loops would wait one memory round trip each
+  unsigned long long kw[3][2], cw[N_CNT_ALL];
+#pragma unroll
   for (int e = 0; e < 3; ++e) {
-    unsigned long long w0 = A.k[((size_t)e * STRIPES + lane) * 2];
-    unsigned long long w1 = A.k[((size_t)e * STRIPES + lane) * 2 + 1];
-    wave_sum128(w0, w1);
-    kv[e] = u128_to_double(w0, w1) * inv_q[e];
+    kw[e][0] = A.k[((size_t)e * STRIPES + lane) * 2];
+    kw[e][1] = A.k[((size_t)e * STRIPES + lane) * 2 + 1];
   }
+#pragma unroll
+  for (int c = 0; c < N_CNT_ALL; ++c) cw[c] = A.cnt[c * STRIPES + lane];
+  double kv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    wave_sum128(kw[e][0], kw[e][1]);
+    kv[e] = u128_to_double(kw[e][0], kw[e][1]) * inv_q[e];
+  }
+#pragma unroll
   for (int c = 0; c < N_CNT_ALL; ++c) {
-    const unsigned long long v = wave_sum_u64(A.cnt[c * STRIPES + lane]);
+    const unsigned long long v = wave_sum_u64(cw[c]);
     if (lane == 0) gen_cnt[(size_t)gen * N_CNT_ALL + c] = v;
     if (lane == 0 && c == CNT_SEG && v >= (1ull << 32)) atomicOr(A.status, ST_TALLY);
   }
