@@ -1192,6 +1192,14 @@ int orc_run(const orc_problem* p, orc_output* out) {
       }
     }
 
+    if (out->source)
+      for (int64_t id = 0; id < N; ++id) {
+        double* o = out->source + ((int64_t)gen * N + id) * 3;
+        o[0] = src_x[id];
+        o[1] = src_y[id];
+        o[2] = p->ce ? src_e[id] : (double)src_g[id];
+      }
+
     C.gen = gen;
     C.k_used = k_used;
     C.src_x = src_x;

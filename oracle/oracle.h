@@ -161,6 +161,9 @@ typedef struct {
   int64_t bank_len;              /* out */
   orc_event* events;             /* [n_gen][n_per_gen][event_cap] flights, or NULL */
   int32_t event_cap;             /* flights logged per history (later ones are not) */
+  double* source;                /* [n_gen][n_per_gen][3] = x, y, g (energy in eV for
+                                    continuous energy) of every generation's source
+                                    sites, or NULL */
   char errmsg[256];
 } orc_output;
 

@@ -105,6 +105,7 @@ class _Output(C.Structure):
         ("records", C.c_void_p),
         ("bank", C.c_void_p), ("bank_cap", C.c_int64), ("bank_len", C.c_int64),
         ("events", C.c_void_p), ("event_cap", C.c_int32),
+        ("source", C.c_void_p),
         ("errmsg", C.c_char * 256),
     ]
 
@@ -301,7 +302,7 @@ def _ptr(a):
 
 
 def run(problem, n_threads=None, records=False, per_gen_tallies=False, bank_cap=0,
-        ext_state=None, events=0):
+        ext_state=None, events=0, source=False):
     """Run the oracle on a problem dict; returns a dict of numpy arrays."""
     geo, rp = problem["geometry"], problem["run"]
     ce = problem.get("ce")
@@ -391,6 +392,9 @@ def run(problem, n_threads=None, records=False, per_gen_tallies=False, bank_cap=
         res["events"] = np.zeros((G, N, events), EVENT_DTYPE)
         O.events = _ptr(res["events"])
         O.event_cap = events
+    if source:
+        res["source"] = np.zeros((G, N, 3))
+        O.source = _ptr(res["source"])
     rc = L.orc_run(C.byref(P), C.byref(O))
     if rc != 0:
         raise OracleError(rc, O.errmsg.decode())
