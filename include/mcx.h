@@ -228,10 +228,12 @@ typedef struct {
   int32_t sort;             /* collide lists ordered by material class */
 } mcx_tune;
 
-/* Create a context on opt->device (NULL opt = defaults). */
+/* Create a context on opt->device (NULL opt = defaults).  Project addition,
+   no passage: the paper's runs are driven from Python (Sec. 3). */
 int mcx_create(mcx_ctx** out, const mcx_options* opt);
 
-/* Copy and validate the geometry (MCX_EINVAL on bad sizes, radii, pin map). */
+/* Copy and validate the geometry (paper Sec. 1: constructive solid geometry
+   with surface tracking; MCX_EINVAL on bad sizes, radii, pin map). */
 int mcx_load_geometry(mcx_ctx* ctx, const mcx_geometry* geo);
 
 /* Copy and validate multigroup data (paper Sec. 1: multigroup physics):
@@ -254,7 +256,7 @@ int mcx_load_mg_xs(mcx_ctx* ctx, int32_t n_mat, int32_t n_grp, const double* sig
    (MCX_FATE_CUTOFF).  The flux is tallied per (cell, region, energy bin)
    with n_ebins bins between e_edges; the production tally is not kept
    (reads zero) and the track-length k estimator is summed directly.
-   Event engine, FP64 only. */
+   Event engine, FP64 and FP32-mixed. */
 typedef struct {
   int32_t n_nuc, n_pts;
   const double* e_grid;     /* [n_pts] eV */
@@ -275,7 +277,8 @@ typedef struct {
   const double* e_edges;    /* [n_ebins + 1] strictly increasing, eV */
 } mcx_ce_data;
 
-/* Copy and validate continuous-energy data; replaces multigroup data. */
+/* Copy and validate continuous-energy data (paper Sec. 1: continuous-energy
+   physics; Sec. 4: continuous-energy pin cell); replaces multigroup data. */
 int mcx_load_ce_xs(mcx_ctx* ctx, const mcx_ce_data* ce);
 
 /* Time-dependent fixed source (paper Sec. 1: MC/DC's time-dependent mode):
@@ -290,13 +293,18 @@ int mcx_load_ce_xs(mcx_ctx* ctx, const mcx_ce_data* ce);
 int mcx_load_time_grid(mcx_ctx* ctx, int32_t n_tbins, const double* t_edges,
                        const double* speed, int32_t n_grp);
 
+/* Set the random-number seed, histories per generation and the source of
+   the run (paper Sec. 1: k-eigenvalue and fixed-source modes, random numbers
+   replicable between CPU and GPU). */
 int mcx_seed_source(mcx_ctx* ctx, const mcx_source* src);
 
-/* Bytes of device workspace needed to run up to n_gen_max generations. */
+/* Bytes of device workspace needed to run up to n_gen_max generations.
+   Project addition, no passage (caller-owned device memory). */
 int mcx_workspace_size(mcx_ctx* ctx, int32_t n_gen_max, size_t* bytes);
 
 /* Bind a caller-owned device buffer (256-byte aligned, on opt->device) of at
-   least mcx_workspace_size bytes and upload the tables; MCX_ENOMEM if small. */
+   least mcx_workspace_size bytes and upload the tables; MCX_ENOMEM if small.
+   Project addition, no passage. */
 int mcx_bind_workspace(mcx_ctx* ctx, void* device_ptr, size_t bytes, int32_t n_gen_max);
 
 /* Power iteration (paper Sec. 4: inactive then active cycles): n_gen
@@ -310,79 +318,71 @@ int mcx_run_generations(mcx_ctx* ctx, int32_t n_gen, int32_t n_inactive);
    previous one left, with the same random streams, so a run continued in
    pieces equals one uninterrupted run of the total length.  Statistics
    cover every generation so far with the first run's n_inactive.  The total
-   must stay within n_gen_max. */
+   must stay within n_gen_max.  Project addition, no passage. */
 int mcx_continue_generations(mcx_ctx* ctx, int32_t n_more);
 
 /* Serialize the state a continued run needs after a completed run: the next
    source, k_used and every generation's results so far (not the per-history
    records), tied to the problem, precision and event guard by a
    fingerprint.  buf = NULL: *len receives the size in bytes.  MCX_ENOMEM if
-   *len is too small (then *len receives the size). */
+   *len is too small (then *len receives the size).  Project addition, no
+   passage. */
 int mcx_checkpoint(mcx_ctx* ctx, void* buf, size_t* len);
 
 /* Load a checkpoint into a context bound to the same problem (MCX_EINVAL
    otherwise); the results read back as after the checkpointed run, and
-   mcx_continue_generations proceeds from it. */
+   mcx_continue_generations proceeds from it.  Project addition, no passage. */
 int mcx_restore(mcx_ctx* ctx, const void* buf, size_t len);
 
-/* Active-generation mean and standard deviation of the mean of the
-   collision, track-length and absorption k estimators (mean3, sigma3), and
+/* k-eigenvalue estimates (paper Sec. 1: k-eigenvalue power iteration; Sec. 4:
+   inactive then active cycles): active-generation mean and standard
+   deviation of the mean of the collision, track-length and absorption k
+   estimators (mean3, sigma3), and
    optionally the per-generation values per_gen[n_gen][3] (may be NULL). */
 int mcx_get_keff(mcx_ctx* ctx, double* mean3, double* sigma3, double* per_gen);
 
 /* Per-generation Shannon entropy of the fission bank entropy[n_gen] and
-   counters counts[n_gen][MCX_N_CNT]; either may be NULL. */
+   counters counts[n_gen][MCX_N_CNT]; either may be NULL.  Project addition,
+   no passage (convergence and balance diagnostics of the power iteration,
+   Sec. 4). */
 int mcx_get_generation_stats(mcx_ctx* ctx, double* entropy, int64_t* counts);
 
-/* Continue the last completed run (or a restored checkpoint) by n_more
-   generations: the next generation starts from the source and k_used the
-   previous one left, with the same random streams, so a run continued in
-   pieces equals one uninterrupted run of the total length.  Statistics
-   cover every generation so far with the first run's n_inactive.  The total
-   must stay within n_gen_max. */
-int mcx_continue_generations(mcx_ctx* ctx, int32_t n_more);
-
-/* Serialize the state a continued run needs after a completed run: the next
-   source, k_used and every generation's results so far (not the per-history
-   records), tied to the problem, precision and event guard by a
-   fingerprint.  buf = NULL: *len receives the size in bytes.  MCX_ENOMEM if
-   *len is too small (then *len receives the size). */
-int mcx_checkpoint(mcx_ctx* ctx, void* buf, size_t* len);
-
-/* Load a checkpoint into a context bound to the same problem (MCX_EINVAL
-   otherwise); the results read back as after the checkpointed run, and
-   mcx_continue_generations proceeds from it. */
-int mcx_restore(mcx_ctx* ctx, const void* buf, size_t len);
-
-/* Active-generation mean and standard deviation of the mean of the
+/* Tallies (paper Sec. 2: the transport loop's tally operations):
+   active-generation mean and standard deviation of the mean of the
    track-length flux and nu-fission production per source particle, bin
    ((cell j * nx + i) * (max_rings + 1) + region) * n_grp + group; n_bins must
    equal nx * ny * (max_rings + 1) * n_grp.  Any pointer may be NULL. */
 int mcx_get_tallies(mcx_ctx* ctx, double* flux_mean, double* flux_sigma, double* prod_mean,
                     double* prod_sigma, int64_t n_bins);
 
-/* One generation's flux and production tallies per source particle. */
+/* One generation's flux and production tallies per source particle (Sec. 2
+   tallies, per generation). */
 int mcx_get_generation_tallies(mcx_ctx* ctx, int32_t gen, double* flux, double* prod,
                                int64_t n_bins);
 
 /* Per-history records of generation gen (record_histories = 1), n_per_gen
-   entries indexed by history id. */
+   entries indexed by history id.  Project addition, no passage (debug
+   records for history-by-history parity). */
 int mcx_get_records(mcx_ctx* ctx, int32_t gen, mcx_record* out, int64_t n);
 
 /* Event log of generation gen: n = n_per_gen * event_log entries, history
-   id major. */
+   id major.  Project addition, no passage (debug). */
 int mcx_get_event_log(mcx_ctx* ctx, int32_t gen, mcx_event* out, int64_t n);
 
 /* Canonical fission bank of the last k-eigenvalue generation, ordered by
    (parent history, banking order): xyg[k][3] = x, y, group (energy in eV for
    continuous energy); *len receives
-   the bank size (entries beyond cap are not written). */
+   the bank size (entries beyond cap are not written).  Paper Sec. 2: the
+   fission bank of the event-based loop. */
 int mcx_get_bank(mcx_ctx* ctx, double* xyg, int64_t cap, int64_t* len);
 
+/* Timing of the last run (mcx_timing).  Project addition, no passage
+   (Sec. 5 calls for profiling of the kernels). */
 int mcx_get_timing(mcx_ctx* ctx, mcx_timing* out);
 
 /* Load a batch of independent fixed-source problems (the batched form of
-   the method: many problems of uneven size in one launch).  Every problem is
+   the method: many problems of uneven size in one launch; project addition,
+   no passage).  Every problem is
    validated as by mcx_load_geometry / mcx_load_mg_xs; all must share n_grp;
    1 <= n_probs <= 65535 and the total history count must stay below 2^32.
    Replaces any single problem loaded before (and vice versa); bind a
@@ -393,17 +393,19 @@ int mcx_load_batch(mcx_ctx* ctx, int32_t n_probs, const mcx_problem* probs);
 /* Run the loaded batch: one generation of every problem in one persistent
    launch, recorded once as a HIP graph (fill, transport, per-problem
    reduction) and replayed on ctx's stream.  Blocks until done.  Returns
-   MCX_ELOST, MCX_EGUARD (results readable) or MCX_EDEVICE on failure. */
+   MCX_ELOST, MCX_EGUARD (results readable) or MCX_EDEVICE on failure.
+   Project addition, no passage. */
 int mcx_run_batch(mcx_ctx* ctx);
 
 /* Per-problem results of the last batch, per source particle: k[p][3] =
    collision, track-length and absorption production estimators;
-   counts[p][MCX_N_CNT].  Either may be NULL. */
+   counts[p][MCX_N_CNT].  Either may be NULL.  Project addition, no passage. */
 int mcx_get_batch_results(mcx_ctx* ctx, double* k, int64_t* counts);
 
 /* Flux and production tallies of problem p of the last batch, per source
    particle, in that problem's own bin order (as mcx_get_tallies);
-   n_bins = nx * ny * (max_rings + 1) * n_grp of problem p. */
+   n_bins = nx * ny * (max_rings + 1) * n_grp of problem p.  Project addition,
+   no passage. */
 int mcx_get_batch_tallies(mcx_ctx* ctx, int32_t p, double* flux, double* prod, int64_t n_bins);
 
 /* Pick the persistent-engine configuration (block, slots, grid, tau, then
@@ -413,24 +415,30 @@ int mcx_get_batch_tallies(mcx_ctx* ctx, int32_t p, double* flux, double* prod, i
    cache_path names a text file of earlier results keyed by the workload's
    shape and the device: a hit skips the sweep, a miss appends the winner.
    Results do not depend on the configuration.  Overwrites the results of
-   the last run. */
+   the last run.  Project addition, no passage. */
 int mcx_autotune(mcx_ctx* ctx, const char* cache_path, mcx_tune* best);
 
 /* Diagnostics of the device arithmetic (device pointers, on ctx's stream):
    which = 0: out[i] = ln(in[i]); 1: out[2i], out[2i+1] = cos, sin(2 pi in[i]);
    2: out[i] = sqrt(in[i]); 3: out[i] = uniform(bits of in[i]) mapping of a
-   64-bit word to (0, 1).  Same functions the kernels call. */
+   64-bit word to (0, 1).  Same functions the kernels call.  Project
+   addition, no passage (diagnostics). */
 int mcx_diag_math(mcx_ctx* ctx, int32_t which, const double* d_in, double* d_out, int64_t n);
 
-/* The same functions evaluated on the host (no device needed). */
+/* The same functions evaluated on the host (no device needed).  Project
+   addition, no passage (diagnostics). */
 int mcx_host_math(int32_t which, const double* in, double* out, int64_t n);
 
 /* Philox4x64-10 blocks on the device: in[i] = {c0, c1, c2, c3, k0, k1},
-   out[i] = 4 output words (device pointers). */
+   out[i] = 4 output words (device pointers).  Paper Sec. 1 (replicable
+   counter-based random numbers); diagnostics. */
 int mcx_diag_philox(mcx_ctx* ctx, const uint64_t* d_in, uint64_t* d_out, int64_t n);
 
+/* Message of the last failed call on ctx.  Project addition, no passage. */
 const char* mcx_last_error(const mcx_ctx* ctx);
 
+/* Release the context's host resources (never the caller's workspace).
+   Project addition, no passage. */
 void mcx_destroy(mcx_ctx* ctx);
 
 #ifdef __cplusplus

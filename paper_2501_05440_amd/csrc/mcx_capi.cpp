@@ -445,8 +445,15 @@ int mcx_load_mg_xs(mcx_ctx* c, int32_t n_mat, int32_t n_grp, const double* sig_t
         run += (float)sig_s[mg * n_grp + h];
         cum_s_f[mg * n_grp + h] = run;
       }
+      // a valid row (sum of sig_s <= sig_t in binary64) can round above
+      // binary32 sig_t when scattering is (nearly) the whole cross section:
+      // clamp the running sums there, so the scatter probability is 1
+      if (run > sig_t_f[mg]) {
+        run = sig_t_f[mg];
+        for (int h = 0; h < n_grp; ++h)
+          cum_s_f[mg * n_grp + h] = std::min(cum_s_f[mg * n_grp + h], run);
+      }
       sst_f[mg] = run;
-      if (run > sig_t_f[mg]) return fail(c, MCX_EINVAL, "scattering exceeds sig_t in binary32");
       cchi += (float)chi[mg];
       cum_chi_f[mg] = cchi;
     }
@@ -1453,8 +1460,10 @@ uint64_t fingerprint(const mcx_ctx* c) {
   const int32_t ints[] = {c->nx, c->ny, c->n_univ, c->max_rings, c->bc[0], c->bc[1], c->bc[2],
                           c->bc[3], c->n_mat, c->G, c->opt.precision, c->ce ? 1 : 0};
   fnv(&h, ints, sizeof(ints) / sizeof(ints[0]));
-  const double dbl[] = {c->pitch, c->x0, c->y0, (double)c->opt.max_events};
-  fnv(&h, dbl, 4);
+  const double dbl[] = {c->pitch,    c->x0,        c->y0,        (double)c->opt.max_events,
+                        c->ce_nu,    c->ce_watt_a, c->ce_watt_b, c->ce_e_max,
+                        c->ce_e_cut};
+  fnv(&h, dbl, sizeof(dbl) / sizeof(dbl[0]));
   fnv(&h, c->pin_map.data(), c->pin_map.size());
   fnv(&h, c->n_rings.data(), c->n_rings.size());
   fnv(&h, c->radii.data(), c->radii.size());

@@ -6,12 +6,15 @@
 // keep the event structure of the multigroup path (source, birth, advance
 // with up to `flights` flights, collide, history-based tail) and change the
 // physics:
-//   lookup   the interval of the shared energy grid by bisection, then
-//            Sigma_x(E) = sum over the material's nuclides of
-//            N_k (s_k(E_i) + f (s_k(E_i+1) - s_k(E_i))), f the clipped
-//            interpolation fraction; the per-point triples (t, s, f) are
-//            interleaved so one interval of one nuclide is 64 contiguous
-//            bytes;
+//   lookup   the interval of the shared energy grid (the index a bisection
+//            returns, found from a bucket of the energy's bit pattern and a
+//            short bisection inside it), then Sigma_x(E) = sum over the
+//            material's nuclides of N_k (s_k(E_i) + f (s_k(E_i+1) - s_k(E_i))),
+//            f the clipped interpolation fraction; the flights read (sig_t,
+//            sig_f) pairs packed by [material][grid point][nuclide], so one
+//            lookup of a material is one contiguous block, and a collision
+//            reads sig_s of the sampled nuclide from a separate table in the
+//            same order;
 //   flight   d_col = -ln(xi) / Sigma_t(E); flux tallied per (cell, region,
 //            energy bin); the track-length k term d nu Sigma_f(E) summed
 //            exactly;

@@ -312,7 +312,7 @@ def ce_data(seed=4001, n_nuc=10, n_pts=50_000, n_res=200, n_ebins=100):
     return _CE_CACHE[key]
 
 
-def ce_pin_cell(n_per_gen=1_000_000, n_gen=50, n_inactive=10, seed=5, data=None):
+def ce_pin_cell(n_per_gen=1_000_000, n_gen=50, n_inactive=10, seed=4, data=None):
     """Continuous-energy pin cell (r = 0.54 cm in a 1.26 cm reflective
     square: an infinite lattice), flux tallied per region on 100 log bins."""
     ce = ce_data() if data is None else data

@@ -191,3 +191,22 @@ def test_ce_bench_configuration_invariants():
     km, ks = g["k_mean"], g["k_sigma"]
     for a, b in ((0, 1), (0, 2), (1, 2)):
         assert abs(km[a] - km[b]) < 5 * math.hypot(ks[a], ks[b]), (km, ks)
+
+
+@pytest.mark.parametrize("seed", [4, 14])
+def test_ce_fp32_mixed_full_size_within_10_pcm(seed):
+    """The continuous-energy pin cell at full size (1e6 x 50, 10 inactive):
+    FP32-mixed k_col within 10 pcm and 3 paired sigma of FP64 on the same
+    random streams."""
+    banner(f"CE pin cell 1e6 x 50 FP32-mixed vs FP64, seed {seed}")
+    prob = P.ce_pin_cell(seed=seed)
+    g64 = mcx.run(prob)
+    g32 = mcx.run(prob, precision="fp32")
+    ni = prob["run"]["n_inactive"]
+    d = g32["gen_k"][ni:, 0] - g64["gen_k"][ni:, 0]
+    dk = g32["k_mean"][0] - g64["k_mean"][0]
+    paired = d.std(ddof=1) / math.sqrt(len(d))
+    print(f"seed {seed}: k64 {g64['k_mean'][0]:.7f} k32 {g32['k_mean'][0]:.7f} "
+          f"dk {dk * 1e5:.3f} pcm paired sigma {paired * 1e5:.3f} pcm", flush=True)
+    assert abs(dk) <= 10e-5
+    assert abs(dk) <= 3 * paired

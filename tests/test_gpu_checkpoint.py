@@ -96,3 +96,27 @@ def test_checkpoint_errors():
         assert e.value.code == mcx.EINVAL
     finally:
         c32.close()
+
+
+@pytest.mark.parametrize("field,value", [("nu", 2.5), ("watt_a", 1.0e6), ("watt_b", 2.0e-6),
+                                         ("e_max", 1.9e7), ("e_cut", 2e-5)])
+def test_restore_refuses_other_continuous_energy_scalars(field, value):
+    """A checkpoint is tied to the continuous-energy scalars too (neutrons
+    per fission, Watt spectrum, Watt resampling limit, energy cutoff): a
+    context loaded with another value refuses it."""
+    banner(f"restore refuses a different continuous-energy {field}")
+    prob = P.ce_pin_cell(n_per_gen=500, n_gen=3, n_inactive=1)
+    a = mcx.Context(prob)
+    try:
+        a.run(n_gen=2, n_inactive=1)
+        blob = a.checkpoint()
+    finally:
+        a.close()
+    other = dict(prob, ce=dict(prob["ce"], **{field: value}))
+    b = mcx.Context(other)
+    try:
+        with pytest.raises(mcx.MCXError) as e:
+            b.restore(blob, 2)
+        assert e.value.code == mcx.EINVAL
+    finally:
+        b.close()

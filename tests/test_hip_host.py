@@ -21,6 +21,26 @@ def test_header_declarations_are_bound():
     assert declared() == sorted(mcx.EXPORTS)
 
 
+def test_header_declarations_are_unique_and_cited():
+    """Every entry point is declared once, and the comment in front of it
+    cites the paper's passage that defines the operation or says that it is
+    a project addition with no passage."""
+    text = open(os.path.join(ROOT, "include", "mcx.h")).read()
+    names = re.findall(r"^(?:int|void|const char\*)\s+(mcx_\w+)\(", text, re.M)
+    assert len(names) == len(set(names)), sorted(n for n in names if names.count(n) > 1)
+    decl = re.compile(r"^(?:int|void|const char\*)\s+(mcx_\w+)\(", re.M)
+    prev_end = 0
+    for m in decl.finditer(text):
+        before = text[prev_end:m.start()]
+        # the comment block right in front of the declaration
+        k = before.rfind("*/")
+        assert k >= 0 and before[k + 2:].strip() == "", f"{m.group(1)} has no comment"
+        comment = " ".join(before[before.rfind("/*", 0, k):k].split())
+        assert ("Sec." in comment or "roject addition" in comment), \
+            f"{m.group(1)}: the comment cites no passage and is not marked a project addition"
+        prev_end = text.index(";", m.end()) + 1
+
+
 def test_library_exports_every_symbol():
     L = mcx.lib()
     for name in declared():
