@@ -55,7 +55,7 @@ enum mcx_status {
 };
 
 enum { MCX_FP64 = 0, MCX_FP32_MIXED = 1 };
-enum { MCX_ENGINE_EVENT = 0, MCX_ENGINE_PERSISTENT = 1 };
+enum { MCX_ENGINE_EVENT = 0, MCX_ENGINE_PERSISTENT = 1, MCX_ENGINE_MONOLITHIC = 2 };
 enum { MCX_VACUUM = 0, MCX_REFLECT = 1 };
 enum {
   MCX_FATE_ABSORBED = 1,
@@ -102,9 +102,15 @@ typedef struct {
      paper's Sec. 2).  MCX_ENGINE_PERSISTENT runs each generation (or batch)
      as one kernel whose workgroups keep particles in LDS slots, process them
      event by event over block-local queues, and refill free slots from a
-     global history counter; batches (mcx_load_batch) always use it.  Both
-     engines give identical per-history results.  record_histories requires
-     the event engine. */
+     global history counter; batches (mcx_load_batch) always use it.
+     MCX_ENGINE_MONOLITHIC is the paper's monolithic event (Sec. 2): each
+     launch runs one whole segment of every live particle (flight, then its
+     collision or crossing, in one kernel) from a to-be-processed bank into a
+     processed bank, with no sorting and no history-based tail, until every
+     history has ended; block_size, lookahead, record_histories and
+     time_kernels apply (its launches count as advance launches), flights
+     and tail_threshold do not.  Every engine gives identical per-history
+     results.  record_histories requires the event or monolithic engine. */
   int32_t engine;
   int32_t p_block;          /* persistent: threads per block, 128 or 256; 0 = 256 */
   int32_t p_slots;          /* persistent: particle slots per block, 256 or 512; 0 = 512 */

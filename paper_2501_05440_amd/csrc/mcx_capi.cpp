@@ -260,7 +260,8 @@ int mcx_create(mcx_ctx** out, const mcx_options* opt) {
     delete c;
     return MCX_EINVAL;
   }
-  if (c->opt.engine != MCX_ENGINE_EVENT && c->opt.engine != MCX_ENGINE_PERSISTENT) {
+  if (c->opt.engine != MCX_ENGINE_EVENT && c->opt.engine != MCX_ENGINE_PERSISTENT &&
+      c->opt.engine != MCX_ENGINE_MONOLITHIC) {
     delete c;
     return MCX_EINVAL;
   }
@@ -892,14 +893,15 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
   }
   if (!loaded(c)) return fail(c, MCX_ESTATE, "load and seed first");
   if ((uintptr_t)ptr % 256) return fail(c, MCX_EINVAL, "workspace must be 256-byte aligned");
-  if (c->ce && c->opt.engine != MCX_ENGINE_EVENT)
-    return fail(c, MCX_EINVAL, "continuous energy runs on the event engine");
-  if (!c->t_edges.empty() && (c->batch || c->ce || !c->src.fixed_source ||
-                              c->opt.engine != MCX_ENGINE_EVENT ||
+  const bool launch_per_event =
+      c->opt.engine == MCX_ENGINE_EVENT || c->opt.engine == MCX_ENGINE_MONOLITHIC;
+  if (c->ce && !launch_per_event)
+    return fail(c, MCX_EINVAL, "continuous energy runs on the event or monolithic engine");
+  if (!c->t_edges.empty() && (c->batch || c->ce || !c->src.fixed_source || !launch_per_event ||
                               (int)c->t_speed.size() != c->G))
     return fail(c, MCX_EINVAL,
-                "the time-dependent mode runs multigroup fixed-source problems on the event engine "
-                "with one speed per group");
+                "the time-dependent mode runs multigroup fixed-source problems on the event or "
+                "monolithic engine with one speed per group");
   if (c->ce && c->opt.precision == MCX_FP32_MIXED && c->ce_hash_f.empty())
     return fail(c, MCX_EINVAL, "the energy grid is not strictly increasing in binary32");
   // materials referenced by the geometry must exist (batches: checked per problem)
@@ -1175,9 +1177,13 @@ static int run_generation(mcx_ctx* c, int gen) {
   // live counts on their way to the host: (iteration, ring slot)
   std::deque<std::pair<int64_t, int>> pending;
   int64_t n_sent = 0;
-  const int64_t tail = c->opt.tail_threshold != 0
-                           ? (int64_t)c->opt.tail_threshold
-                           : std::max<int64_t>(DEFAULT_TAIL, (int64_t)N / 8);
+  // the monolithic engine runs its one-segment kernel until every history
+  // has ended (no history-based tail)
+  const bool mono = c->opt.engine == MCX_ENGINE_MONOLITHIC;
+  const int64_t tail = mono ? 0
+                            : c->opt.tail_threshold != 0
+                                  ? (int64_t)c->opt.tail_threshold
+                                  : std::max<int64_t>(DEFAULT_TAIL, (int64_t)N / 8);
   int cur = 0;
   const int block = c->opt.block_size;
   for (;;) {
@@ -1199,6 +1205,18 @@ static int run_generation(mcx_ctx* c, int gen) {
       c->timing.n_tail_launches += 1;
       break;
     }
+    if (mono) {
+      HIP_TRY(c, time_mark(c, 0, true));
+      if (ce)
+        HIP_TRY(c, launch_ce_mono(prec, rec, T, gen, c->d.bank[cur], c->d.cnt_live + it,
+                                  c->d.bank[1 - cur], c->d.cnt_live + it + 1, A, c->d.R,
+                                  c->d.cnt_live + it + 2, bound, block, s));
+      else
+        HIP_TRY(c, launch_mono(prec, rec, T, gen, c->d.bank[cur], c->d.cnt_live + it,
+                               c->d.bank[1 - cur], c->d.cnt_live + it + 1, A, c->d.R,
+                               c->d.cnt_live + it + 2, bound, block, s));
+      HIP_TRY(c, time_mark(c, 0, false));
+    } else {
     HIP_TRY(c, time_mark(c, 0, true));
     const uint32_t fl = (uint32_t)c->opt.flights;
     if (ce)
@@ -1222,6 +1240,7 @@ static int run_generation(mcx_ctx* c, int gen) {
                                 c->d.bank[1 - cur], c->d.cnt_live + it + 1, A, c->d.R, bound,
                                 block, s));
     HIP_TRY(c, time_mark(c, 1, false));
+    }
     cur = 1 - cur;
     ++it;
     c->timing.n_iterations += 1;

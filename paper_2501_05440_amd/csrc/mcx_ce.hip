@@ -911,6 +911,81 @@ __global__ void __launch_bounds__(256) k_ce_tail(Tables T, uint32_t gen, Bank in
   wave_acc_halves(A.k + K_TL * STRIPES * 2, ktl[0], ktl[1]);
 }
 
+// Monolithic event of the continuous-energy path (see k_mono): one segment
+// of every particle per launch, the collision or the crossing in the same
+// kernel, survivors to the processed bank.
+template <class R, bool REC>
+__global__ void __launch_bounds__(1024) k_ce_mono(Tables T, uint32_t gen, Bank in,
+                                                  const uint32_t* __restrict__ n_in_p, Bank out,
+                                                  uint32_t* n_out, Accum A, Records Rc,
+                                                  uint32_t* clr_out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *clr_out = 0;
+  const uint32_t n_in = *n_in_p;
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = k < n_in;
+  const double k_used = *A.k_used;
+  int ev = EV_NONE;
+  bool refl = false;
+  PartCE<R> p;
+  ColCE<R> c{};
+  uint32_t nf = 0;
+  uint64_t q_kcol = 0, q_tl = 0;
+  Stream rs(T.seed, TAG_TRANSPORT, 0, gen, T.prob, 0);
+  if (valid) {
+    p = load_ce<R>(in, k);
+    rs = Stream(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
+    if ((int64_t)p.nseg >= T.max_events) {
+      ev = EV_KILL;
+    } else {
+      CECache<R> cache;
+      ce_cache_clear(cache);
+      ev = segment_ce<R, REC, false>(T, T.geo, p, rs, A, Rc, &refl, &q_tl, cache);
+      p.nseg += 1;
+      if (ev == EV_COLLIDE) {
+        c = col_ce<R>(T, T.geo, p, cache);
+        const double kc = (double)(c.nusf / c.x.st);
+        q_kcol = quantize(kc, T.q_kcol);
+        if (REC) {
+          Rc.n_col[p.id] += 1;
+          Rc.kcol_sum[p.id] += kc;
+        }
+        nf = fission_count_ce<R>(T, c, rs, k_used);
+      }
+    }
+  }
+  __shared__ uint32_t lds[2 * (MAX_WAVES + 1)];
+  const uint32_t slot = block_reserve(nf, A.n_fis, lds);
+  int fate = ev == EV_CROSS ? FATE_ALIVE : FATE_KILLED;
+  uint64_t q_kabs = 0;
+  if (ev == EV_COLLIDE) fate = collide_rest_ce<R>(T, p, rs, c, nf, slot, A, &q_kabs);
+  if (ev == EV_LEAK) fate = FATE_LEAKED;
+  const bool alive = valid && fate == FATE_ALIVE;
+  if (valid) {
+    p.ctr = rs.draw;
+    if (!alive) die_ce<R, REC>(p, fate, A, Rc, T);
+  }
+  const uint32_t po = block_reserve(alive ? 1u : 0u, n_out, lds);
+  if (alive) store_ce<R>(out, po, p);
+  const bool seg = valid && ev != EV_KILL;
+  const bool col = ev == EV_COLLIDE;
+  wave_flag(A.cnt + CNT_SEG * STRIPES, seg);
+  wave_flag(A.cnt + CNT_CROSS * STRIPES, ev == EV_CROSS || ev == EV_LEAK);
+  wave_flag(A.cnt + CNT_REFL * STRIPES, refl);
+  wave_flag(A.cnt + CNT_LEAK * STRIPES, ev == EV_LEAK);
+  wave_flag(A.cnt + CNT_KILLED * STRIPES, ev == EV_KILL);
+  wave_flag(A.cnt + CNT_COL * STRIPES, col);
+  wave_flag(A.cnt + CNT_SCAT * STRIPES, col && fate != FATE_ABSORBED);
+  wave_flag(A.cnt + CNT_ABS * STRIPES, col && fate == FATE_ABSORBED);
+  wave_flag(A.cnt + CNT_CUTOFF * STRIPES, col && fate == FATE_CUTOFF);
+  wave_count(A.cnt + CNT_SITES * STRIPES, nf);
+  wave_flag(A.cnt + CNT_ADV_ITEMS * STRIPES, valid);
+  wave_flag(A.cnt + CNT_ADV_SEGS * STRIPES, seg);
+  wave_flag(A.cnt + CNT_COL_ITEMS * STRIPES, col);
+  wave_acc(A.k + K_COL * STRIPES * 2, q_kcol);
+  wave_acc(A.k + K_ABS * STRIPES * 2, q_kabs);
+  wave_acc(A.k + K_TL * STRIPES * 2, q_tl);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -993,6 +1068,29 @@ hipError_t launch_ce_collide(int prec, bool rec, const Tables& T, uint32_t gen, 
     else
       hipLaunchKernelGGL((k_ce_collide<float, false>), g, b, 0, s, T, gen, in, n_in, live,
                          n_live, A, Rc);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ce_mono(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in,
+                          const uint32_t* n_in, const Bank& out, uint32_t* n_out, const Accum& A,
+                          const Records& Rc, uint32_t* clr_out, uint32_t bound, int block,
+                          hipStream_t s) {
+  const dim3 g(std::max(1u, nblk_ce(bound, block))), b(block);
+  if (prec == 0) {
+    if (rec)
+      hipLaunchKernelGGL((k_ce_mono<double, true>), g, b, 0, s, T, gen, in, n_in, out, n_out, A,
+                         Rc, clr_out);
+    else
+      hipLaunchKernelGGL((k_ce_mono<double, false>), g, b, 0, s, T, gen, in, n_in, out, n_out, A,
+                         Rc, clr_out);
+  } else {
+    if (rec)
+      hipLaunchKernelGGL((k_ce_mono<float, true>), g, b, 0, s, T, gen, in, n_in, out, n_out, A,
+                         Rc, clr_out);
+    else
+      hipLaunchKernelGGL((k_ce_mono<float, false>), g, b, 0, s, T, gen, in, n_in, out, n_out, A,
+                         Rc, clr_out);
   }
   return hipGetLastError();
 }

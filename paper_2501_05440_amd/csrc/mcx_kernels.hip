@@ -318,6 +318,85 @@ __global__ void __launch_bounds__(64) k_tail(Tables T0, uint32_t gen, Bank in,
   wave_acc_halves(A.k + K_ABS * STRIPES * 2, kabs[0], kabs[1]);
 }
 
+// Monolithic event (the paper's GPU scheme, Sec. 2): one launch does
+// exactly one segment of every particle of the to-be-processed bank, all of
+// its operations in one kernel: cross-section lookup, distance to
+// collision, distance to boundary, move, tally, then the collision
+// (fission-bank append, scatter or absorption) or the surface crossing.
+// Survivors go to the processed bank, which the next launch reads (history
+// length truncation with criterion 1); nothing is sorted and no event class
+// gets a kernel of its own, so a wave runs both branches whenever its
+// particles differ.  Block 0 clears the count the next launch appends to.
+template <class R, bool REC, bool LDS>
+__global__ void __launch_bounds__(1024) k_mono(Tables T0, uint32_t gen, Bank in,
+                                               const uint32_t* __restrict__ n_in_p, Bank out,
+                                               uint32_t* n_out, Accum A, Records Rc,
+                                               uint32_t* clr_out) {
+  const uint32_t n_in = *n_in_p;
+  const Tables T = kernel_tables<R, LDS>(T0, blockIdx.x * blockDim.x < n_in);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *clr_out = 0;
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = k < n_in;
+  const double k_used = *A.k_used;
+  int ev = EV_NONE;
+  bool refl = false;
+  Part<R> p;
+  ColXS<R> x{0, R(1), R(0)};
+  uint32_t nf = 0;
+  uint64_t q_kcol = 0;
+  Stream rs(T.seed, TAG_TRANSPORT, 0, gen, T.prob, 0);
+  if (valid) {
+    p = load_part<R>(in, k);
+    rs = Stream(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
+    if ((int64_t)p.nseg >= T.max_events) {
+      ev = EV_KILL;
+    } else {
+      ev = segment<R, REC, false>(T, T.geo, p, rs, A, Rc, &refl);
+      p.nseg += 1;
+      if (ev == EV_COLLIDE) {
+        x = col_xs(T, T.geo, p);
+        const double kc = (double)(x.nusf / x.st);
+        q_kcol = quantize(kc, T.q_kcol);
+        if (REC) {
+          Rc.n_col[p.id] += 1;
+          Rc.kcol_sum[p.id] += kc;
+        }
+        nf = fission_count(T, x, rs, k_used);
+      }
+    }
+  }
+  __shared__ uint32_t lds[2 * (MAX_WAVES + 1)];
+  const uint32_t slot = block_reserve(nf, A.n_fis, lds);
+  bool alive = ev == EV_CROSS;
+  uint64_t q_kabs = 0;
+  if (ev == EV_COLLIDE) alive = collide_rest<R, REC>(T, p, rs, x, nf, slot, A, &q_kabs);
+  if (valid) {
+    p.ctr = rs.draw;
+    if (ev == EV_KILL) die<R, REC>(p, FATE_KILLED, A, Rc);
+    if (ev == EV_LEAK) die<R, REC>(p, FATE_LEAKED, A, Rc);
+    if (ev == EV_CENSUS) die<R, REC>(p, FATE_CENSUS, A, Rc);
+    if (ev == EV_COLLIDE && !alive) die<R, REC>(p, FATE_ABSORBED, A, Rc);
+  }
+  const uint32_t po = block_reserve(alive ? 1u : 0u, n_out, lds);
+  if (alive) store_part(out, po, p);
+  const bool seg = valid && ev != EV_KILL;
+  wave_flag(A.cnt + CNT_SEG * STRIPES, seg);
+  wave_flag(A.cnt + CNT_CROSS * STRIPES, ev == EV_CROSS || ev == EV_LEAK);
+  wave_flag(A.cnt + CNT_REFL * STRIPES, refl);
+  wave_flag(A.cnt + CNT_LEAK * STRIPES, ev == EV_LEAK);
+  wave_flag(A.cnt + CNT_KILLED * STRIPES, ev == EV_KILL);
+  wave_flag(A.cnt + CNT_CENSUS * STRIPES, ev == EV_CENSUS);
+  wave_flag(A.cnt + CNT_COL * STRIPES, ev == EV_COLLIDE);
+  wave_flag(A.cnt + CNT_SCAT * STRIPES, ev == EV_COLLIDE && alive);
+  wave_flag(A.cnt + CNT_ABS * STRIPES, ev == EV_COLLIDE && !alive);
+  wave_count(A.cnt + CNT_SITES * STRIPES, nf);
+  wave_flag(A.cnt + CNT_ADV_ITEMS * STRIPES, valid);
+  wave_flag(A.cnt + CNT_ADV_SEGS * STRIPES, seg);
+  wave_flag(A.cnt + CNT_COL_ITEMS * STRIPES, ev == EV_COLLIDE);
+  wave_acc(A.k + K_COL * STRIPES * 2, q_kcol);
+  wave_acc(A.k + K_ABS * STRIPES * 2, q_kabs);
+}
+
 // ---------------------------------------------------------------------------
 // generation end
 // ---------------------------------------------------------------------------
@@ -848,6 +927,38 @@ hipError_t launch_tail(int prec, bool rec, const Tables& T, uint32_t gen, const 
       tail_k<float, true>(g, b, lb, s, T, gen, in, n_in, A, Rc);
     else
       tail_k<float, false>(g, b, lb, s, T, gen, in, n_in, A, Rc);
+  }
+  return hipGetLastError();
+}
+
+template <class R, bool REC>
+static void mono_k(dim3 g, dim3 b, size_t lb, hipStream_t s, const Tables& T, uint32_t gen,
+                   const Bank& in, const uint32_t* n_in, const Bank& out, uint32_t* n_out,
+                   const Accum& A, const Records& Rc, uint32_t* clr_out) {
+  if (lb)
+    hipLaunchKernelGGL((k_mono<R, REC, true>), g, b, lb, s, T, gen, in, n_in, out, n_out, A, Rc,
+                       clr_out);
+  else
+    hipLaunchKernelGGL((k_mono<R, REC, false>), g, b, 0, s, T, gen, in, n_in, out, n_out, A, Rc,
+                       clr_out);
+}
+
+hipError_t launch_mono(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in,
+                       const uint32_t* n_in, const Bank& out, uint32_t* n_out, const Accum& A,
+                       const Records& Rc, uint32_t* clr_out, uint32_t bound, int block,
+                       hipStream_t s) {
+  const dim3 g(std::max(1u, nblk(bound, block))), b(block);
+  const size_t lb = mg_lds_bytes(prec, T);
+  if (prec == 0) {
+    if (rec)
+      mono_k<double, true>(g, b, lb, s, T, gen, in, n_in, out, n_out, A, Rc, clr_out);
+    else
+      mono_k<double, false>(g, b, lb, s, T, gen, in, n_in, out, n_out, A, Rc, clr_out);
+  } else {
+    if (rec)
+      mono_k<float, true>(g, b, lb, s, T, gen, in, n_in, out, n_out, A, Rc, clr_out);
+    else
+      mono_k<float, false>(g, b, lb, s, T, gen, in, n_in, out, n_out, A, Rc, clr_out);
   }
   return hipGetLastError();
 }

@@ -31,6 +31,13 @@ hipError_t launch_collide(int prec, bool rec, const Tables& T, uint32_t gen, con
                           hipStream_t s);
 hipError_t launch_tail(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in, const uint32_t* n_in, const Accum& A, const Records& Rc,
                        uint32_t bound, hipStream_t s);
+// monolithic event: one segment of every particle per launch, collision or
+// crossing in the same kernel (in -> out, the count of out cleared at clr_out
+// for the launch after)
+hipError_t launch_mono(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in,
+                       const uint32_t* n_in, const Bank& out, uint32_t* n_out, const Accum& A,
+                       const Records& Rc, uint32_t* clr_out, uint32_t bound, int block,
+                       hipStream_t s);
 uint32_t scan_chunks(uint32_t n);
 hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* chunk_sum, uint32_t* out,
                        uint32_t* total, hipStream_t s);
@@ -98,6 +105,10 @@ hipError_t launch_ce_collide(int prec, bool rec, const Tables& T, uint32_t gen, 
                              hipStream_t s);
 hipError_t launch_ce_tail(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in,
                           const uint32_t* n_in, const Accum& A, const Records& Rc, uint32_t bound,
+                          hipStream_t s);
+hipError_t launch_ce_mono(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in,
+                          const uint32_t* n_in, const Bank& out, uint32_t* n_out, const Accum& A,
+                          const Records& Rc, uint32_t* clr_out, uint32_t bound, int block,
                           hipStream_t s);
 hipError_t launch_diag_math(int which, const double* in, double* out, int64_t n, hipStream_t s);
 hipError_t launch_diag_philox(const uint64_t* in, uint64_t* out, int64_t n, hipStream_t s);

@@ -17,7 +17,9 @@ LIB_PATH = os.path.join(HERE, "libmcx.so")
 OK, EINVAL, ESTATE, ENOMEM, EDEVICE, ELOST, EGUARD, EEXTINCT, EOVERFLOW = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 FP64, FP32_MIXED = 0, 1
-ENGINE_EVENT, ENGINE_PERSISTENT = 0, 1
+ENGINE_EVENT, ENGINE_PERSISTENT, ENGINE_MONOLITHIC = 0, 1, 2
+ENGINES = {"event": ENGINE_EVENT, "persistent": ENGINE_PERSISTENT,
+           "monolithic": ENGINE_MONOLITHIC}
 N_CNT = 11
 COUNT_NAMES = ["seg", "col", "cross", "refl", "leak", "abs", "killed", "sites", "scat", "cutoff",
                "census"]
@@ -222,12 +224,12 @@ def _xs(xs, keep):
 def _options(o, precision, device, stream, engine, persistent):
     if precision not in ("fp64", "fp32"):
         raise ValueError("precision is 'fp64' or 'fp32' (FP32-mixed)")
-    if engine not in ("event", "persistent"):
-        raise ValueError("engine is 'event' or 'persistent'")
+    if engine not in ENGINES:
+        raise ValueError(f"engine is one of {sorted(ENGINES)}")
     o.precision = FP64 if precision == "fp64" else FP32_MIXED
     o.device = device
     o.stream = stream.cuda_stream
-    o.engine = ENGINE_EVENT if engine == "event" else ENGINE_PERSISTENT
+    o.engine = ENGINES[engine]
     p = persistent or {}
     o.p_block = p.get("block", 0)
     o.p_slots = p.get("slots", 0)
