@@ -55,7 +55,12 @@ enum mcx_status {
 };
 
 enum { MCX_FP64 = 0, MCX_FP32_MIXED = 1 };
-enum { MCX_ENGINE_EVENT = 0, MCX_ENGINE_PERSISTENT = 1, MCX_ENGINE_MONOLITHIC = 2 };
+enum {
+  MCX_ENGINE_EVENT = 0,
+  MCX_ENGINE_PERSISTENT = 1,
+  MCX_ENGINE_MONOLITHIC = 2,
+  MCX_ENGINE_ASYNC = 3
+};
 enum { MCX_VACUUM = 0, MCX_REFLECT = 1 };
 enum {
   MCX_FATE_ABSORBED = 1,
@@ -109,17 +114,28 @@ typedef struct {
      processed bank, with no sorting and no history-based tail, until every
      history has ended; block_size, lookahead, record_histories and
      time_kernels apply (its launches count as advance launches), flights
-     and tail_threshold do not.  Every engine gives identical per-history
-     results.  record_histories requires the event or monolithic engine. */
+     and tail_threshold do not.  MCX_ENGINE_ASYNC is an asynchronous
+     schedule (Sec. 2 names the runtime's asynchronous scheduler beside the
+     event-based one): one launch per generation (or batch) whose workgroups
+     keep pulling blocks of particles from two global queues, one per event
+     type (advance, collide), or give birth to the next histories, and push
+     every survivor to the queue of its next event, with no grid-wide
+     barrier; particle state lives in a global pool.  p_grid sets its
+     workgroups and flights its flights per advance item; multigroup only,
+     FP64 or FP32-mixed, batches included.  Every engine gives identical
+     per-history results.  record_histories requires the event or
+     monolithic engine. */
   int32_t engine;
   int32_t p_block;          /* persistent: threads per block, 128 or 256; 0 = 256 */
   int32_t p_slots;          /* persistent: particle slots per block, 256 or 512; 0 = 512 */
-  int32_t p_grid;           /* persistent: workgroups; 0 = 2 per compute unit */
+  int32_t p_grid;           /* persistent and asynchronous engines: workgroups;
+                               0 = 2 per compute unit */
   double p_tau;             /* persistent: refill when fewer than p_tau * p_slots particles
                                of a block are live, 0 < p_tau <= 1; 0 = 0.75 */
   int32_t p_sort;           /* persistent: 1 = order each collide list by material class
                                (fissile first) so fission sampling runs in the same waves */
-  int32_t flights;          /* event engine: flights one advance launch makes per particle
+  int32_t flights;          /* event and asynchronous engines: flights one advance step
+                               makes per particle
                                before it returns to the live bank (it stops earlier at a
                                collision, a leak or the guard).  1 = one event per launch,
                                the paper's decomposition; larger values keep a particle in

@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libmcx.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["mcx_kernels.hip", "mcx_persistent.hip", "mcx_ce.hip", "mcx_capi.cpp"]
+SOURCES = ["mcx_kernels.hip", "mcx_persistent.hip", "mcx_ce.hip", "mcx_async.hip", "mcx_capi.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # every product and sum rounds on its own, as the arithmetic is written

@@ -29,6 +29,9 @@ constexpr int DEFAULT_TAIL = 4096;
 constexpr int DEFAULT_LOOKAHEAD = 4;
 constexpr int64_t DEFAULT_MAX_EVENTS = 100000;
 constexpr int DEFAULT_FLIGHTS = 8;
+// polls (about a microsecond each) before a wait of the asynchronous engine
+// gives up and reports an error
+constexpr uint64_t ASYNC_SPIN_LIMIT = 1ull << 22;
 
 struct Carver {
   char* base;
@@ -125,6 +128,8 @@ struct Dev {
   unsigned long long* h_kabs = nullptr;
   uint32_t* h_cnt = nullptr;
   uint32_t* work = nullptr;
+  // asynchronous engine: particle pool and global queues
+  AsyncBufs ab{};
   uint64_t n_hist = 0;
   // batches: problem descriptors and per-problem results
   ProbDesc* probs = nullptr;
@@ -261,11 +266,12 @@ int mcx_create(mcx_ctx** out, const mcx_options* opt) {
     return MCX_EINVAL;
   }
   if (c->opt.engine != MCX_ENGINE_EVENT && c->opt.engine != MCX_ENGINE_PERSISTENT &&
-      c->opt.engine != MCX_ENGINE_MONOLITHIC) {
+      c->opt.engine != MCX_ENGINE_MONOLITHIC && c->opt.engine != MCX_ENGINE_ASYNC) {
     delete c;
     return MCX_EINVAL;
   }
-  if (c->opt.engine == MCX_ENGINE_PERSISTENT && c->opt.record_histories) {
+  if ((c->opt.engine == MCX_ENGINE_PERSISTENT || c->opt.engine == MCX_ENGINE_ASYNC) &&
+      c->opt.record_histories) {
     delete c;
     return MCX_EINVAL;
   }
@@ -662,7 +668,9 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   const int nt = c->t_edges.empty() ? 1 : (int)c->t_edges.size() - 1;
   const int nb = batch ? c->batch_bins : c->nx * c->ny * mr1 * c->G * nt;
   const uint64_t n_hist = batch ? c->batch_hist : (uint64_t)N;
-  const bool persistent = batch || c->opt.engine == MCX_ENGINE_PERSISTENT;
+  const bool async = c->opt.engine == MCX_ENGINE_ASYNC;
+  // per-history outputs: the persistent and asynchronous engines
+  const bool persistent = batch || c->opt.engine == MCX_ENGINE_PERSISTENT || async;
   // copies of the flux accumulators, spread over workgroups by index (up to
   // 64 copies in 1 Mi words; a batch's workgroups all work on the few
   // problems whose histories are in flight, so its few bins get every copy,
@@ -776,6 +784,28 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
     d.h_cnt = cv.take<uint32_t>((size_t)7 * n_hist);
   }
   d.n_hist = n_hist;
+  if (async) {
+    AsyncBufs& B = d.ab;
+    B.x = cv.take<double>(n_hist);
+    B.y = cv.take<double>(n_hist);
+    if (fp32) {
+      B.u = cv.take<float>(n_hist);
+      B.v = cv.take<float>(n_hist);
+    } else {
+      B.u = cv.take<double>(n_hist);
+      B.v = cv.take<double>(n_hist);
+    }
+    B.cell = cv.take<uint32_t>(n_hist);
+    B.gs = cv.take<uint32_t>(n_hist);
+    B.ctr = cv.take<uint32_t>(n_hist);
+    B.prob = cv.take<uint16_t>(n_hist);
+    uint64_t cap = 64;
+    while (cap < n_hist) cap <<= 1;
+    B.mask = (uint32_t)(cap - 1);
+    B.slot[0] = cv.take<uint32_t>(cap);
+    B.slot[1] = cv.take<uint32_t>(cap);
+    B.ctl = cv.take<unsigned long long>(ASYNC_CTL_WORDS);
+  }
   if (batch) {
     d.probs = cv.take<ProbDesc>(c->n_probs);
     d.prob_kres = cv.take<double>((size_t)3 * c->n_probs);
@@ -1156,6 +1186,24 @@ static int run_generation(mcx_ctx* c, int gen) {
                                   s));
     return generation_end(c, gen);
   }
+  if (c->opt.engine == MCX_ENGINE_ASYNC) {
+    // one launch per generation; workgroups pull from the global queues
+    const bool keig = !T.fixed_source;
+    if (gen == 0 && keig)
+      HIP_TRY(c, launch_source(T, gen, N, c->d.src_x, c->d.src_y, c->d.src_g, A.status, s));
+    HIP_TRY(c, launch_async_init(c->d.ab, c->d.n_hist, s));
+    HIP_TRY(c, time_mark(c, 3, true));
+    HIP_TRY(c, launch_async(prec, c->pcfg.grid, T, gen, A, c->d.h_kcol, c->d.h_kabs, c->d.h_cnt,
+                            c->d.ab, (uint32_t)c->opt.flights, ASYNC_SPIN_LIMIT,
+                            keig ? c->d.src_x : nullptr, keig ? c->d.src_y : nullptr,
+                            keig ? c->d.src_g : nullptr,
+                            gen > 0 ? c->d.gen_status + gen - 1 : nullptr, s));
+    HIP_TRY(c, time_mark(c, 3, false));
+    HIP_TRY(c, launch_async_status(c->d.ab, A.status, s));
+    HIP_TRY(c, launch_hist_reduce(T, 1, c->d.h_kcol, c->d.h_kabs, c->d.h_cnt, A, nullptr, nullptr,
+                                  s));
+    return generation_end(c, gen);
+  }
   const bool ce = T.ce != 0;
   const uint32_t* prev_st = gen > 0 ? c->d.gen_status + gen - 1 : nullptr;
   if (ce) {
@@ -1337,6 +1385,8 @@ static int status_error(mcx_ctx* c, uint32_t st) {
   if (st & ST_SOURCE) return fail(c, MCX_ELOST, "source sampling found no fissile point");
   if (st & ST_OVERFLOW) return fail(c, MCX_EOVERFLOW, "fission bank overflow");
   if (st & ST_TALLY) return fail(c, MCX_EOVERFLOW, "2^32 or more flights in one generation");
+  if (st & ST_ASYNC)
+    return fail(c, MCX_EDEVICE, "the asynchronous engine gave up a wait past its bound");
   if (st & (ST_SITE_SEQ | ST_SCAN)) return fail(c, MCX_EDEVICE, "inconsistent fission bank");
   if (st & ST_EXTINCT) return fail(c, MCX_EEXTINCT, "fission bank is empty");
   return fail(c, MCX_EDEVICE, "generation skipped");
@@ -1867,9 +1917,19 @@ static hipError_t enqueue_batch(mcx_ctx* c, hipStream_t s) {
   hipError_t e = launch_fill_u64(d.acc_base, d.acc_words, 0ull, s);
   if (e == hipSuccess)
     e = launch_fill_u64(reinterpret_cast<unsigned long long*>(d.gen_status), 1, 0ull, s);
-  if (e == hipSuccess)
-    e = launch_persistent(prec, c->pcfg, d.T, 0, A, d.h_kcol, d.h_kabs, d.h_cnt, d.work, nullptr,
-                          nullptr, nullptr, nullptr, s);
+  if (e == hipSuccess) {
+    if (c->opt.engine == MCX_ENGINE_ASYNC) {
+      e = launch_async_init(d.ab, d.n_hist, s);
+      if (e == hipSuccess)
+        e = launch_async(prec, c->pcfg.grid, d.T, 0, A, d.h_kcol, d.h_kabs, d.h_cnt, d.ab,
+                         (uint32_t)c->opt.flights, ASYNC_SPIN_LIMIT, nullptr, nullptr, nullptr,
+                         nullptr, s);
+      if (e == hipSuccess) e = launch_async_status(d.ab, A.status, s);
+    } else {
+      e = launch_persistent(prec, c->pcfg, d.T, 0, A, d.h_kcol, d.h_kabs, d.h_cnt, d.work, nullptr,
+                            nullptr, nullptr, nullptr, s);
+    }
+  }
   if (e == hipSuccess)
     e = launch_hist_reduce(d.T, c->n_probs, d.h_kcol, d.h_kabs, d.h_cnt, A, d.prob_cnt, d.prob_k, s);
   if (e == hipSuccess)
@@ -2021,7 +2081,7 @@ static int tune_trial(mcx_ctx* c, const PersistentCfg& cfg, double* ms) {
 int mcx_autotune(mcx_ctx* c, const char* cache_path, mcx_tune* best) {
   if (!c) return MCX_EINVAL;
   if (!c->bound) return fail(c, MCX_ESTATE, "bind a workspace first");
-  if (!c->batch && c->opt.engine != MCX_ENGINE_PERSISTENT)
+  if (c->opt.engine == MCX_ENGINE_ASYNC || (!c->batch && c->opt.engine != MCX_ENGINE_PERSISTENT))
     return fail(c, MCX_ESTATE, "the autotuner configures the persistent engine");
   HIP_TRY(c, hipSetDevice(c->opt.device));
   const std::string key = tune_key(c);

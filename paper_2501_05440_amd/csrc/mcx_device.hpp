@@ -252,7 +252,8 @@ enum : uint32_t {
   ST_SOURCE = 8u,
   ST_EXTINCT = 16u,
   ST_SKIPPED = 32u,
-  ST_TALLY = 64u  // 2^32 or more flights: a tail-kernel flux word may have wrapped
+  ST_TALLY = 64u,  // 2^32 or more flights: a tail-kernel flux word may have wrapped
+  ST_ASYNC = 128u  // the asynchronous engine gave up a wait past its bound
 };
 
 // ---------------------------------------------------------------------------

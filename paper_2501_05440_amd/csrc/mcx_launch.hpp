@@ -80,6 +80,30 @@ hipError_t launch_persistent(int prec, const PersistentCfg& cfg, const Tables& T
                              unsigned long long* h_kabs, uint32_t* h_cnt, uint32_t* work,
                              const double* sx, const double* sy, const int32_t* sg,
                              const uint32_t* prev_status, hipStream_t s);
+// Asynchronous engine: global particle pool and two global queues (advance,
+// collide) of history indices; ctl holds ASYNC_CTL_WORDS words: per queue
+// tail, head, published count, then births, remaining histories, abort flag.
+constexpr int ASYNC_CTL_WORDS = 9;
+struct AsyncBufs {
+  double* x = nullptr;
+  double* y = nullptr;
+  void* u = nullptr;
+  void* v = nullptr;
+  uint32_t* cell = nullptr;
+  uint32_t* gs = nullptr;
+  uint32_t* ctr = nullptr;
+  uint16_t* prob = nullptr;
+  uint32_t* slot[2] = {nullptr, nullptr};
+  unsigned long long* ctl = nullptr;
+  uint32_t mask = 0;  // queue capacity - 1 (a power of two >= the history count)
+};
+hipError_t launch_async_init(const AsyncBufs& B, uint64_t n_hist, hipStream_t s);
+hipError_t launch_async_status(const AsyncBufs& B, uint32_t* status, hipStream_t s);
+hipError_t launch_async(int prec, int grid, const Tables& T, uint32_t gen, const Accum& A,
+                        unsigned long long* h_kcol, unsigned long long* h_kabs, uint32_t* h_cnt,
+                        const AsyncBufs& B, uint32_t flights, uint64_t spin_limit,
+                        const double* sx, const double* sy, const int32_t* sg,
+                        const uint32_t* prev_status, hipStream_t s);
 hipError_t launch_hist_reduce(const Tables& T, int n_probs, unsigned long long* h_kcol,
                               unsigned long long* h_kabs, uint32_t* h_cnt, const Accum& A,
                               unsigned long long* prob_cnt, unsigned long long* prob_k,

@@ -103,25 +103,6 @@ __device__ __forceinline__ uint32_t build_list(SlotMem<R, S>& M, uint8_t want) {
   return build_list_set<R, PB, S>(M, 1u << want, 0);
 }
 
-// The problem of global history index h (binary search of the batch).
-__device__ __forceinline__ int problem_of(const ProbDesc* P, int n, uint64_t h) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (P[mid].hist_base <= h)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
-
-struct HistOut {
-  unsigned long long* kcol;  // [n][2]: sums of the low and high 32-bit halves of q_kcol
-  unsigned long long* kabs;  // [n]: q_kabs of the absorption (0 if none)
-  uint32_t* cnt;             // [n][HO_N]
-};
-enum { HO_SEG = 0, HO_COL, HO_CROSS, HO_REFL, HO_SCAT, HO_SITES, HO_FATE, HO_N };
 
 template <class R, int S>
 __device__ __forceinline__ void slot_death(SlotMem<R, S>& M, int s, const Part<R>& p, int fate,

@@ -17,9 +17,9 @@ LIB_PATH = os.path.join(HERE, "libmcx.so")
 OK, EINVAL, ESTATE, ENOMEM, EDEVICE, ELOST, EGUARD, EEXTINCT, EOVERFLOW = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 FP64, FP32_MIXED = 0, 1
-ENGINE_EVENT, ENGINE_PERSISTENT, ENGINE_MONOLITHIC = 0, 1, 2
+ENGINE_EVENT, ENGINE_PERSISTENT, ENGINE_MONOLITHIC, ENGINE_ASYNC = 0, 1, 2, 3
 ENGINES = {"event": ENGINE_EVENT, "persistent": ENGINE_PERSISTENT,
-           "monolithic": ENGINE_MONOLITHIC}
+           "monolithic": ENGINE_MONOLITHIC, "async": ENGINE_ASYNC}
 N_CNT = 11
 COUNT_NAMES = ["seg", "col", "cross", "refl", "leak", "abs", "killed", "sites", "scat", "cutoff",
                "census"]
@@ -461,10 +461,10 @@ def run(problem, device=0, record=False, per_gen_tallies=False, bank=False, **kw
 
 class Batch(Context):
     """A batch of independent fixed-source problems run in one persistent
-    launch (mcx_load_batch / mcx_run_batch)."""
+    (or asynchronous-engine) launch (mcx_load_batch / mcx_run_batch)."""
 
     def __init__(self, problems, device=0, max_events=None, stream=None, precision="fp64",
-                 persistent=None):
+                 persistent=None, engine="persistent", flights=0):
         import torch
 
         self.problems = problems
@@ -475,7 +475,10 @@ class Batch(Context):
         torch.cuda.set_device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         o = Options()
-        _options(o, precision, device, self.stream, "persistent", persistent)
+        if engine not in ("persistent", "async"):
+            raise ValueError("a batch runs on the persistent or the asynchronous engine")
+        _options(o, precision, device, self.stream, engine, persistent)
+        o.flights = flights
         o.max_events = problems[0]["run"]["max_events"] if max_events is None else max_events
         h = C.c_void_p()
         self._check(L.mcx_create(C.byref(h), C.byref(o)), None)

@@ -96,3 +96,77 @@ def test_monolithic_guard_and_block_size():
     prob = P.lattice_17x17(n_per_gen=30_000, n_gen=3, n_inactive=1)
     same(mcx.run(prob, engine="monolithic", block_size=64),
          mcx.run(prob, engine="monolithic", block_size=1024))
+
+
+# ---------------------------------------------------------------------------
+# asynchronous engine: global per-event-type queues, no grid-wide barrier
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_async_lattice_matches_event_engine(prec):
+    banner(f"async engine: lattice 1e5 x 4 ({prec}) vs event engine")
+    prob = P.lattice_17x17(n_per_gen=100_000, n_gen=4, n_inactive=1)
+    a = mcx.run(prob, engine="async", precision=prec)
+    e = mcx.run(prob, precision=prec)
+    same(a, e)
+
+
+def test_async_pin_cell_matches_oracle(oracle):
+    banner("async engine: pin cell 1e4 x 30 vs oracle")
+    prob = P.pin_cell()
+    g = mcx.run(prob, engine="async")
+    o = oracle.run(prob)
+    compare_runs(g, o, records=False, atol_flux=flux_atol(g, prob))
+
+
+@pytest.mark.parametrize("grid,flights", [(1, 1), (7, 8), (2048, 3)])
+def test_async_launch_shapes_give_identical_results(grid, flights):
+    """One workgroup (every event of every history through one block's
+    queue traffic), a few, and more workgroups than fit at once; one or
+    several flights per advance item."""
+    banner(f"async engine: grid {grid}, flights {flights}")
+    prob = P.lattice_17x17(n_per_gen=20_000, n_gen=3, n_inactive=1)
+    a = mcx.run(prob, engine="async", persistent={"grid": grid}, flights=flights)
+    e = mcx.run(prob)
+    same(a, e)
+
+
+def test_async_fixed_source_and_guard():
+    banner("async engine: fixed-source pin cell and the event guard")
+    prob = P.with_run(P.pin_cell(n_per_gen=30_000, n_gen=3, n_inactive=0), fixed_source=True)
+    same(mcx.run(prob, engine="async"), mcx.run(prob))
+    prob = P.with_run(P.lattice_17x17(n_per_gen=5000, n_gen=2, n_inactive=1), max_events=7)
+    a = mcx.run(prob, engine="async")
+    e = mcx.run(prob)
+    assert a["rc"] == mcx.EGUARD and e["rc"] == mcx.EGUARD
+    same(a, e)
+
+
+def test_async_batch_matches_persistent_batch():
+    banner("async engine: 64-problem batch vs the persistent engine")
+    probs = P.batch_pin_cells(n_problems=64, n_max=40_000)
+    res = {}
+    for eng in ("persistent", "async"):
+        b = mcx.Batch(probs, engine=eng)
+        try:
+            b.run()
+            k, cnt = b.results()
+            tal = [b.tallies_of(p) for p in (0, 17, 63)]
+        finally:
+            b.close()
+        res[eng] = (k, cnt, tal)
+    assert np.array_equal(res["persistent"][0], res["async"][0])
+    assert np.array_equal(res["persistent"][1], res["async"][1])
+    for a, b in zip(res["persistent"][2], res["async"][2]):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_async_refuses_what_it_does_not_run():
+    banner("async engine: refusals")
+    for prob, kw in ((P.ce_pin_cell(n_per_gen=100, n_gen=2, n_inactive=1), {}),
+                     (P.pulsed_lattice(n_per_gen=100, n_gen=1), {}),
+                     (P.pin_cell(n_per_gen=100, n_gen=2, n_inactive=1), {"record": True})):
+        with pytest.raises(mcx.MCXError) as e:
+            mcx.Context(prob, engine="async", **kw)
+        assert e.value.code == mcx.EINVAL
