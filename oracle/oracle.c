@@ -535,6 +535,8 @@ static double watt_sample(const orc_ce* ce, stream_t* s) {
   return ce->e_max;
 }
 
+double orc_speed(double e) { return 2.99792458e10 * sqrt(2.0 * e / 939.56542052e6); }
+
 static int sample_source(const ctx_t* C, int64_t id, int gen, double* sx, double* sy,
                          int32_t* sg, double* se) {
   const orc_problem* p = C->p;
@@ -555,7 +557,7 @@ static int sample_source(const ctx_t* C, int64_t id, int gen, double* sx, double
       *sy = y;
       if (p->ce) {
         *sg = 0;
-        *se = watt_sample(p->ce, &s);
+        *se = p->ce->src_energy > 0.0 ? p->ce->src_energy : watt_sample(p->ce, &s);
       } else {
         double xi = next_uniform(&s);
         *sg = orc_sample_cdf(xi, p->chi + (int64_t)m * p->n_grp, p->n_grp);
@@ -821,6 +823,10 @@ static void run_history_ce(ctx_t* C, int64_t id, chunk_t* ch) {
   int32_t n_seg = 0, n_col = 0, n_cross = 0, n_refl = 0, n_sites = 0;
   int fate = ORC_ALIVE;
   double tl_sum = 0.0, kcol_sum = 0.0;
+  const orc_time* tm = p->time;
+  const int NT = tm ? tm->n_tbins : 1;
+  const double t_max = tm ? tm->t_edges[NT] : 0.0;
+  double t = 0.0; /* time since the source pulse */
 
   for (;;) {
     if (n_seg >= p->max_events) {
@@ -858,17 +864,52 @@ static void run_history_ce(ctx_t* C, int64_t id, chunk_t* ch) {
     n_seg += 1;
     int collide = d_col < d_bnd;
     double d = collide ? d_col : d_bnd;
+    /* time-dependent: the flight stops at the end of the time grid if that
+       comes first (census); its speed is the neutron speed at e */
+    int census = 0;
+    double ve = 0.0;
+    if (tm) {
+      ve = orc_speed(e);
+      double d_cen = (t_max - t) * ve;
+      if (d_cen < d) {
+        d = d_cen;
+        census = 1;
+        collide = 0;
+      }
+    }
     x = x + d * u;
     y = y + d * v;
 
-    /* track-length flux per (cell, region, energy bin); the track-length k
-       estimator sums d nu Sigma_f(E) */
+    /* track-length flux per (cell, region, energy bin[, time bin]); the
+       track-length k estimator sums d nu Sigma_f(E); time-dependent: the
+       flux of each time bin is the length flown in it and the density the
+       time spent in it */
     int b = orc_ce_interval(ce->e_edges, NB + 1, e);
     int64_t bin = ((int64_t)c * C->mr1 + r) * NB + b;
-    nadd(&ch->flux[bin], d);
+    if (tm) {
+      double t1 = census ? t_max : t + d / ve;
+      if (t1 > t_max) t1 = t_max;
+      for (int q = orc_ce_interval(tm->t_edges, NT + 1, t); q < NT; ++q) {
+        double lo = tm->t_edges[q] > t ? tm->t_edges[q] : t;
+        double hi = tm->t_edges[q + 1] < t1 ? tm->t_edges[q + 1] : t1;
+        if (hi > lo) {
+          nadd(&ch->flux[bin * NT + q], (hi - lo) * ve);
+          nadd(&ch->prod[bin * NT + q], hi - lo);
+        }
+        if (tm->t_edges[q + 1] >= t1) break;
+      }
+      t = t1;
+    } else {
+      nadd(&ch->flux[bin], d);
+    }
     nadd(&ch->k[1], d * nusf);
     tl_sum += d;
     const int r_flight = r;
+    if (census) {
+      log_flight(C, id, n_seg - 1, x, y, d, e, c, r_flight, b, 4);
+      fate = ORC_CENSUS;
+      break;
+    }
 
     if (collide) {
       log_flight(C, id, n_seg - 1, x, y, d, e, c, r_flight, b, 1);
@@ -976,6 +1017,7 @@ static void run_history_ce(ctx_t* C, int64_t id, chunk_t* ch) {
   if (fate == ORC_ABSORBED) ch->counts[ORC_C_ABS] += 1;
   if (fate == ORC_KILLED) ch->counts[ORC_C_KILLED] += 1;
   if (fate == ORC_CUTOFF) ch->counts[ORC_C_CUTOFF] += 1;
+  if (fate == ORC_CENSUS) ch->counts[ORC_C_CENSUS] += 1;
   if (C->records) {
     orc_record* rec = &C->records[id];
     rec->n_seg = n_seg;
@@ -991,6 +1033,7 @@ static void run_history_ce(ctx_t* C, int64_t id, chunk_t* ch) {
     rec->x_final = x;
     rec->y_final = y;
     rec->e_final = e;
+    rec->t_final = t;
   }
 }
 
@@ -1055,19 +1098,20 @@ static int validate(const orc_problem* p, orc_output* out) {
   }
   if (p->time) {
     const orc_time* tm = p->time;
-    if (p->ce || !p->fixed_source || tm->n_tbins < 1 || !(tm->t_edges[0] == 0.0))
-      return fail(out, ORC_EINVAL, "time-dependent mode: multigroup fixed source, edges from 0");
+    if (!p->fixed_source || tm->n_tbins < 1 || !(tm->t_edges[0] == 0.0))
+      return fail(out, ORC_EINVAL, "time-dependent mode: fixed source, edges from 0");
     for (int k = 0; k < tm->n_tbins; ++k)
       if (!(tm->t_edges[k] < tm->t_edges[k + 1]) || !isfinite(tm->t_edges[k + 1]))
         return fail(out, ORC_EINVAL, "time edges must increase");
-    for (int g = 0; g < p->n_grp; ++g)
+    for (int g = 0; g < (p->ce ? 0 : p->n_grp); ++g)
       if (!(tm->speed[g] > 0.0) || !isfinite(tm->speed[g]))
         return fail(out, ORC_EINVAL, "group speeds must be positive");
   }
   if (p->ce) {
     const orc_ce* ce = p->ce;
     if (ce->n_nuc < 1 || ce->n_pts < 2 || ce->max_nuc < 1 || ce->n_ebins < 1 || !(ce->nu >= 0.0) ||
-        !(ce->watt_a > 0.0) || !(ce->watt_b >= 0.0) || !(ce->e_max > 0.0) || !(ce->e_cut >= 0.0))
+        !(ce->watt_a > 0.0) || !(ce->watt_b >= 0.0) || !(ce->e_max > 0.0) || !(ce->e_cut >= 0.0) ||
+        !(ce->src_energy >= 0.0) || !isfinite(ce->src_energy))
       return fail(out, ORC_EINVAL, "continuous-energy sizes");
     for (int k = 0; k + 1 < ce->n_pts; ++k)
       if (!(ce->e_grid[k] < ce->e_grid[k + 1])) return fail(out, ORC_EINVAL, "energy grid order");

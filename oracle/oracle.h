@@ -52,15 +52,23 @@ enum {
   ORC_NCOUNT = 11
 };
 
-/* Time-dependent fixed source (Sec. 1: MC/DC's time-dependent mode): every
-   history starts at t = 0, a flight of length d in group g lasts d / v_g,
-   the flux is tallied per time bin by the time the flight spends in it, and
-   a history still flying at the last edge stops there (census). */
+/* Time-dependent fixed source (Sec. 1: MC/DC's time-dependent mode; Sec. 4
+   runs a continuous-energy pin cell in it): every history starts at t = 0,
+   a flight of length d lasts d / v (v the group speed, or for continuous
+   energy the speed of a neutron of the flight's energy, c sqrt(2 E / m c^2)),
+   the flux is tallied per time bin by the length flown in it, and a history
+   still flying at the last edge stops there (census).  For continuous energy
+   the second tally is the neutron density: the time spent per bin. */
 typedef struct {
   int32_t n_tbins;
   const double* t_edges;         /* [n_tbins + 1] increasing, t_edges[0] = 0, s */
-  const double* speed;           /* [n_grp] group speeds, cm/s */
+  const double* speed;           /* [n_grp] group speeds, cm/s (multigroup only) */
 } orc_time;
+
+/* Neutron speed (cm/s) at kinetic energy e (eV), non-relativistic:
+   c sqrt(2 e / m_n c^2) with c = 2.99792458e10 cm/s and
+   m_n c^2 = 939.56542052e6 eV (CODATA 2018). */
+double orc_speed(double e);
 
 /* Continuous-energy data (Sec. 1 lists continuous-energy physics among the
    method's capabilities; Sec. 4 runs a continuous-energy pin cell).
@@ -84,6 +92,8 @@ typedef struct {
   double e_cut;                  /* a scatter below e_cut ends the history (cutoff) */
   int32_t n_ebins;               /* energy bins of the flux tally */
   const double* e_edges;         /* [n_ebins + 1] increasing bin edges, eV */
+  double src_energy;             /* > 0: every source particle starts at this energy
+                                    (eV, no draws); 0: Watt spectrum */
 } orc_ce;
 
 typedef struct {

@@ -69,7 +69,7 @@ class _CE(C.Structure):
         ("max_nuc", C.c_int32), ("mat_n", C.c_void_p), ("mat_nuc", C.c_void_p),
         ("mat_dens", C.c_void_p), ("watt_a", C.c_double), ("watt_b", C.c_double),
         ("e_max", C.c_double), ("e_cut", C.c_double), ("n_ebins", C.c_int32),
-        ("e_edges", C.c_void_p),
+        ("e_edges", C.c_void_p), ("src_energy", C.c_double),
     ]
 
 
@@ -160,6 +160,8 @@ def lib():
         L.orc_elastic.restype = C.c_double
         L.orc_rotate.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_double)]
         L.orc_rotate.restype = None
+        L.orc_speed.argtypes = [C.c_double]
+        L.orc_speed.restype = C.c_double
         _lib = L
     return _lib
 
@@ -243,6 +245,11 @@ def ce_macro(ce, m, e):
     return tuple(o)
 
 
+def speed(e):
+    """Neutron speed in cm/s at energy e in eV."""
+    return lib().orc_speed(float(e))
+
+
 def watt_attempt(a, b, x1, x2, x3, x4):
     return lib().orc_watt_attempt(a, b, x1, x2, x3, x4)
 
@@ -284,6 +291,7 @@ def _ce_struct(ce, keep):
     edges = np.asarray(ce["e_edges"])
     S.n_ebins = len(edges) - 1
     S.e_edges = arr(edges, np.float64)
+    S.src_energy = float(ce.get("src_energy", 0.0))
     return S
 
 
@@ -359,7 +367,7 @@ def run(problem, n_threads=None, records=False, per_gen_tallies=False, bank_cap=
         edges = arr(tm["t_edges"], np.float64)
         t_s.n_tbins = len(edges) - 1
         t_s.t_edges = edges.ctypes.data
-        t_s.speed = arr(tm["speed"], np.float64).ctypes.data
+        t_s.speed = None if tm.get("speed") is None else arr(tm["speed"], np.float64).ctypes.data
         keep.append(t_s)
         P.time = C.addressof(t_s)
 

@@ -352,15 +352,38 @@ GROUP_SPEEDS_7 = np.geomspace(2.0e9, 2.2e5, N_GROUPS)
 
 
 def with_time(problem, t_edges, speed=None):
-    """Copy of a fixed-source multigroup problem with a time grid: a pulse
-    at t = 0, flux tallied per time bin, census at the last edge."""
+    """Copy of a fixed-source problem with a time grid: a pulse at t = 0,
+    flux tallied per time bin, census at the last edge.  Multigroup problems
+    take one speed per group; continuous-energy problems take none (the
+    speed follows from the energy)."""
     p = dict(problem)
-    g = problem["xs"]["sig_t"].shape[1]
-    v = GROUP_SPEEDS_7 if speed is None else np.asarray(speed, float)
-    assert len(v) == g
+    if "ce" in problem:
+        assert speed is None
+        v = None
+    else:
+        g = problem["xs"]["sig_t"].shape[1]
+        v = GROUP_SPEEDS_7 if speed is None else np.asarray(speed, float)
+        assert len(v) == g
     p["time"] = dict(t_edges=np.asarray(t_edges, float), speed=v)
     p["run"] = dict(problem["run"], fixed_source=True)
     return p
+
+
+SOURCE_14MEV = 14.0e6  # eV
+
+
+def ce_pulsed_pin_cell(n_per_gen=1_000_000, n_gen=10, seed=7, data=None):
+    """The continuous-energy pin cell as a time-dependent fixed-source
+    problem, the shape of the paper's second benchmark (Sec. 4): every
+    history starts at t = 0 with 14 MeV, uniform over the fuel, fission
+    treated as capture; flux and neutron density per region, energy bin and
+    time bin (0, then 24 log bins from 1e-10 s to 1e-5 s), census at 10 us
+    (the synthetic resonances absorb most histories within a microsecond)."""
+    ce = dict(ce_data() if data is None else data, src_energy=SOURCE_14MEV)
+    prob = ce_pin_cell(n_per_gen=n_per_gen, n_gen=n_gen, n_inactive=0, seed=seed, data=ce)
+    prob = with_run(prob, fixed_source=True)
+    edges = np.concatenate([[0.0], np.geomspace(1e-10, 1e-5, 25)])
+    return with_time(prob, edges)
 
 
 def pulsed_lattice(n_per_gen=1_000_000, n_gen=10, seed=6):
