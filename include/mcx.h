@@ -297,21 +297,30 @@ typedef struct {
   double e_cut;             /* energy cutoff, eV */
   int32_t n_ebins;
   const double* e_edges;    /* [n_ebins + 1] strictly increasing, eV */
+  double src_energy;        /* > 0: every source particle starts at this energy (eV;
+                               the paper's time-dependent pin cell uses 14 MeV,
+                               Sec. 4); 0: Watt spectrum */
 } mcx_ce_data;
 
 /* Copy and validate continuous-energy data (paper Sec. 1: continuous-energy
    physics; Sec. 4: continuous-energy pin cell); replaces multigroup data. */
 int mcx_load_ce_xs(mcx_ctx* ctx, const mcx_ce_data* ce);
 
-/* Time-dependent fixed source (paper Sec. 1: MC/DC's time-dependent mode):
-   every history starts at t = 0 from the fixed source (mcx_source with
-   fixed_source = 1, fission treated as capture); a flight of length d in
-   group g lasts d / speed[g]; the flux tally gains n_tbins time bins (bin
+/* Time-dependent fixed source (paper Sec. 1: MC/DC's time-dependent mode;
+   Sec. 4 runs the continuous-energy pin cell in it): every history starts
+   at t = 0 from the fixed source (mcx_source with fixed_source = 1, fission
+   treated as capture); a flight of length d lasts d / v, v = speed[g] for
+   multigroup data and, for continuous energy, the speed of a neutron of the
+   flight's energy, c sqrt(2 E / m c^2) (c = 2.99792458e10 cm/s,
+   m c^2 = 939.56542052e6 eV); the flux tally gains n_tbins time bins (bin
    index * n_tbins + time bin), each flight adding the length it flies
    inside each bin; a history still flying at t_edges[n_tbins] stops there
-   (MCX_FATE_CENSUS).  t_edges[0] = 0, strictly increasing; speed in cm/s,
-   one per group (n_grp must match the loaded data at bind time).  Event
-   engine, multigroup.  n_tbins = 0 switches the mode off. */
+   (MCX_FATE_CENSUS).  For continuous energy the production tally holds the
+   neutron density instead: the time spent per bin per source particle, in
+   seconds.  t_edges[0] = 0, strictly increasing; multigroup: speed in cm/s,
+   one per group (n_grp must match the loaded data at bind time);
+   continuous energy: speed = NULL and n_grp = 0.  Event or monolithic
+   engine.  n_tbins = 0 switches the mode off. */
 int mcx_load_time_grid(mcx_ctx* ctx, int32_t n_tbins, const double* t_edges,
                        const double* speed, int32_t n_grp);
 

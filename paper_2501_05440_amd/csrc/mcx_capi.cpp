@@ -170,6 +170,7 @@ struct mcx_ctx {
   std::vector<double> ce_grid, ce_xs, ce_awr, ce_dens, ce_edges;
   std::vector<int> ce_mat_n, ce_mat_nuc;
   double ce_nu = 0, ce_watt_a = 0, ce_watt_b = 0, ce_e_max = 0, ce_e_cut = 0;
+  double ce_src_energy = 0;
   double ce_sigt_min = 0;
   std::vector<double> ce_tf, ce_s;  // ce_xs split into (t, f) pairs and s, same order
   std::vector<float> ce_f32[6];     // binary32 grid, (t, f), masses, densities, edges, s
@@ -499,7 +500,8 @@ int mcx_load_ce_xs(mcx_ctx* c, const mcx_ce_data* d) {
       !d->e_edges)
     return fail(c, MCX_EINVAL, "continuous-energy sizes");
   if (!(d->nu >= 0.0) || !std::isfinite(d->nu) || !(d->watt_a > 0.0) || !(d->watt_b >= 0.0) ||
-      !(d->e_max > 0.0) || !(d->e_cut >= 0.0) || !std::isfinite(d->e_max))
+      !(d->e_max > 0.0) || !(d->e_cut >= 0.0) || !std::isfinite(d->e_max) ||
+      !(d->src_energy >= 0.0) || !std::isfinite(d->src_energy))
     return fail(c, MCX_EINVAL, "continuous-energy constants");
   for (int k = 0; k + 1 < d->n_pts; ++k)
     if (!(d->e_grid[k] < d->e_grid[k + 1]) || !std::isfinite(d->e_grid[k + 1]) ||
@@ -588,6 +590,7 @@ int mcx_load_ce_xs(mcx_ctx* c, const mcx_ce_data* d) {
   c->ce_watt_b = d->watt_b;
   c->ce_e_max = d->e_max;
   c->ce_e_cut = d->e_cut;
+  c->ce_src_energy = d->src_energy;
   c->ce_sigt_min = sigt_min;
   build_hash<double, uint64_t>(c->ce_grid, &c->ce_hash, &c->ce_hash_shift, &c->ce_hash_base);
   {
@@ -632,7 +635,9 @@ int mcx_load_time_grid(mcx_ctx* c, int32_t n_tbins, const double* t_edges, const
     c->t_speed.clear();
     return MCX_OK;
   }
-  if (n_tbins < 0 || n_tbins > 4096 || !t_edges || !speed || n_grp < 1 || n_grp > 65535)
+  // multigroup: one speed per group; continuous energy: no speeds (NULL, 0)
+  if (n_tbins < 0 || n_tbins > 4096 || !t_edges || (speed && (n_grp < 1 || n_grp > 65535)) ||
+      (!speed && n_grp != 0))
     return fail(c, MCX_EINVAL, "time grid sizes");
   if (!(t_edges[0] == 0.0)) return fail(c, MCX_EINVAL, "the time grid starts at 0");
   for (int k = 0; k < n_tbins; ++k)
@@ -642,7 +647,10 @@ int mcx_load_time_grid(mcx_ctx* c, int32_t n_tbins, const double* t_edges, const
     if (!(speed[g] > 0.0) || !std::isfinite(speed[g]))
       return fail(c, MCX_EINVAL, "group speeds must be positive");
   c->t_edges.assign(t_edges, t_edges + n_tbins + 1);
-  c->t_speed.assign(speed, speed + n_grp);
+  if (speed)
+    c->t_speed.assign(speed, speed + n_grp);
+  else
+    c->t_speed.clear();
   return MCX_OK;
 }
 
@@ -826,7 +834,9 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   const size_t w_cnt = (size_t)N_CNT_ALL * STRIPES;
   const size_t w_misc = 2 + (n_ent + 1) / 2;
   const size_t w_prob = batch ? (size_t)c->n_probs * (N_CNT + 4) : 0;
-  d.acc_words = w_tally + w_tally_t + w_k + w_cnt + w_prob + w_misc;
+  // continuous-energy time-dependent mode: the density accumulators
+  const size_t w_dens = (ce && !c->t_edges.empty()) ? w_tally + w_tally_t : 0;
+  d.acc_words = w_tally + w_tally_t + w_k + w_cnt + w_prob + w_misc + w_dens;
   d.acc_base = cv.take<unsigned long long>(d.acc_words);
   if (base) {
     A.tally = d.acc_base;
@@ -842,6 +852,9 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
     A.n_fis = reinterpret_cast<uint32_t*>(pw);
     d.work = reinterpret_cast<uint32_t*>(pw + 1);
     d.ent_hist = reinterpret_cast<uint32_t*>(pw + 2);
+    pw += w_misc;
+    A.dens = w_dens ? pw : nullptr;
+    A.dens_t = w_dens ? pw + w_tally : nullptr;
   }
   // results
   d.gen_k = cv.take<double>((size_t)3 * n_gen_max);
@@ -927,11 +940,12 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
       c->opt.engine == MCX_ENGINE_EVENT || c->opt.engine == MCX_ENGINE_MONOLITHIC;
   if (c->ce && !launch_per_event)
     return fail(c, MCX_EINVAL, "continuous energy runs on the event or monolithic engine");
-  if (!c->t_edges.empty() && (c->batch || c->ce || !c->src.fixed_source || !launch_per_event ||
-                              (int)c->t_speed.size() != c->G))
+  if (!c->t_edges.empty() &&
+      (c->batch || !c->src.fixed_source || !launch_per_event ||
+       (c->ce ? !c->t_speed.empty() : (int)c->t_speed.size() != c->G)))
     return fail(c, MCX_EINVAL,
-                "the time-dependent mode runs multigroup fixed-source problems on the event or "
-                "monolithic engine with one speed per group");
+                "the time-dependent mode runs fixed-source problems on the event or monolithic "
+                "engine, with one speed per group (multigroup) or none (continuous energy)");
   if (c->ce && c->opt.precision == MCX_FP32_MIXED && c->ce_hash_f.empty())
     return fail(c, MCX_EINVAL, "the energy grid is not strictly increasing in binary32");
   // materials referenced by the geometry must exist (batches: checked per problem)
@@ -1037,6 +1051,9 @@ int mcx_bind_workspace(mcx_ctx* c, void* ptr, size_t bytes, int32_t n_gen_max) {
   T.q_kcol = fixed_point_scale(kc_max);
   T.q_kabs = fixed_point_scale(ka_max);
   T.q_ktl = fixed_point_scale(ktl_max * 1.01);
+  // a density term is the time spent in one time bin, at most the census time
+  T.q_dens = fixed_point_scale(c->t_edges.empty() ? 1.0 : c->t_edges.back() * 1.01);
+  T.src_energy = c->ce_src_energy;
   T.max_events = c->opt.max_events;
   T.n_pts = c->ce_n_pts;
   T.max_nuc = c->ce_max_nuc;
@@ -1531,7 +1548,7 @@ uint64_t fingerprint(const mcx_ctx* c) {
   fnv(&h, ints, sizeof(ints) / sizeof(ints[0]));
   const double dbl[] = {c->pitch,    c->x0,        c->y0,        (double)c->opt.max_events,
                         c->ce_nu,    c->ce_watt_a, c->ce_watt_b, c->ce_e_max,
-                        c->ce_e_cut};
+                        c->ce_e_cut, c->ce_src_energy};
   fnv(&h, dbl, sizeof(dbl) / sizeof(dbl[0]));
   fnv(&h, c->pin_map.data(), c->pin_map.size());
   fnv(&h, c->n_rings.data(), c->n_rings.size());

@@ -38,7 +38,15 @@ struct PartCE {
   R u, v, w, e;
   int i, j, r;
   uint32_t nsite, ctr, id, nseg;
+  double t;  // time since the source pulse (time-dependent mode)
 };
+
+// Speed (cm/s) of a neutron of kinetic energy e (eV): c sqrt(2 e / m c^2),
+// c = 2.99792458e10 cm/s, m c^2 = 939.56542052e6 eV (binary64 in both
+// precisions, like the time it advances).
+__device__ __forceinline__ double neutron_speed(double e) {
+  return 2.99792458e10 * sqrt(2.0 * e / 939.56542052e6);
+}
 
 template <class R>
 __device__ __forceinline__ PartCE<R> load_ce(const Bank& b, uint32_t k) {
@@ -57,6 +65,7 @@ __device__ __forceinline__ PartCE<R> load_ce(const Bank& b, uint32_t k) {
   p.ctr = b.ctr[k];
   p.id = b.id[k];
   p.nseg = b.nseg[k];
+  p.t = b.t ? b.t[k] : 0.0;
   return p;
 }
 
@@ -73,6 +82,7 @@ __device__ __forceinline__ void store_ce(const Bank& b, uint32_t k, const PartCE
   b.ctr[k] = p.ctr;
   b.id[k] = p.id;
   b.nseg[k] = p.nseg;
+  if (b.t) b.t[k] = p.t;
 }
 
 // Precision policy of the continuous-energy path: the tables and the
@@ -402,7 +412,7 @@ __device__ __forceinline__ bool sample_source_ce(const Tables& T, const Geo& L, 
     if (T.fissile[m]) {
       *sx = x;
       *sy = y;
-      *se = (double)watt_sample<R>(T, s);
+      *se = T.src_energy > 0.0 ? T.src_energy : (double)watt_sample<R>(T, s);
       return true;
     }
   }
@@ -423,6 +433,23 @@ __device__ __forceinline__ void die_ce(const PartCE<R>& p, int fate, const Accum
     Rc.x_final[p.id] = p.x;
     Rc.y_final[p.id] = p.y;
     Rc.e_final[p.id] = (double)p.e;
+    Rc.t_final[p.id] = p.t;
+  }
+}
+
+// Add a fixed-point term to the pair (lo, hi) of bin `bin` of a striped
+// accumulator: one returning 64-bit atomic with carry, or (HALVES, the tail
+// kernel) two non-returning atomics on the low and high 32-bit halves.
+template <bool HALVES>
+__device__ __forceinline__ void tally_add(unsigned long long* pairs, unsigned long long* halves,
+                                          size_t stripe_off, int bin, uint64_t q) {
+  if (HALVES) {
+    if (q) {
+      atomicAdd(halves + stripe_off + 2 * bin, (unsigned long long)(q & 0xFFFFFFFFull));
+      atomicAdd(halves + stripe_off + 2 * bin + 1, (unsigned long long)(q >> 32));
+    }
+  } else {
+    acc_add(pairs + stripe_off + 2 * bin, q);
   }
 }
 
@@ -459,22 +486,53 @@ __device__ __forceinline__ int segment_ce(const Tables& T, const Geo& L, PartCE<
   if (t_out < d_bnd) d_bnd = t_out;
   if (t_in < d_bnd) d_bnd = t_in;
 
-  const bool collide = (double)d_col < d_bnd;
-  const double d = collide ? (double)d_col : d_bnd;
+  bool collide = (double)d_col < d_bnd;
+  double d = collide ? (double)d_col : d_bnd;
+  // time-dependent mode: the flight stops at the end of the time grid if
+  // that comes first (census); it flies at the speed of its energy
+  bool census = false;
+  double ve = 0.0;
+  if (T.time) {
+    ve = neutron_speed((double)p.e);
+    const double d_cen = (T.t_max - p.t) * ve;
+    if (d_cen < d) {
+      d = d_cen;
+      census = true;
+      collide = false;
+    }
+  }
   p.x = p.x + d * u;
   p.y = p.y + d * v;
 
+  // flux per (cell, region, energy bin[, time bin]); time-dependent: the
+  // length flown and the time spent (density) in each time bin it spans
   const int b = ce_interval<R>(CEP<R>::edges(T), T.n_ebins + 1, p.e);
-  const int bin = L.bin_base + (c * L.mr1 + p.r) * T.n_ebins + b;
-  const uint64_t qf = quantize(d, T.q_flux);
+  const int bin = L.bin_base + ((c * L.mr1 + p.r) * T.n_ebins + b) * T.nt;
   const size_t stripe_off = (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
-  if (HALVES) {
-    if (qf) {
-      atomicAdd(A.tally_t + stripe_off + 2 * bin, (unsigned long long)(qf & 0xFFFFFFFFull));
-      atomicAdd(A.tally_t + stripe_off + 2 * bin + 1, (unsigned long long)(qf >> 32));
+  if (T.time) {
+    double t1 = census ? T.t_max : p.t + d / ve;
+    if (t1 > T.t_max) t1 = T.t_max;
+    int lo_b = 0, hi_b = T.nt;
+    while (hi_b - lo_b > 1) {
+      const int mid = lo_b + (hi_b - lo_b) / 2;
+      if (T.t_edges[mid] <= p.t)
+        lo_b = mid;
+      else
+        hi_b = mid;
     }
+    for (int q = lo_b; q < T.nt; ++q) {
+      const double e0 = T.t_edges[q], e1 = T.t_edges[q + 1];
+      const double lo = e0 > p.t ? e0 : p.t;
+      const double hi = e1 < t1 ? e1 : t1;
+      if (hi > lo) {
+        tally_add<HALVES>(A.tally, A.tally_t, stripe_off, bin + q, quantize((hi - lo) * ve, T.q_flux));
+        tally_add<HALVES>(A.dens, A.dens_t, stripe_off, bin + q, quantize(hi - lo, T.q_dens));
+      }
+      if (e1 >= t1) break;
+    }
+    p.t = t1;
   } else {
-    acc_add(A.tally + stripe_off + 2 * bin, qf);
+    tally_add<HALVES>(A.tally, A.tally_t, stripe_off, bin, quantize(d, T.q_flux));
   }
   *q_tl = quantize(d * (double)nusf, T.q_ktl);
   int k_ev = 0;
@@ -484,6 +542,10 @@ __device__ __forceinline__ int segment_ce(const Tables& T, const Geo& L, PartCE<
     Rc.tl_sum[p.id] += d;
   }
   *refl_out = false;
+  if (census) {
+    if (REC) log_flight(Rc, p.id, k_ev, p.x, p.y, d, (double)p.e, c, p.r, b, 4);
+    return EV_CENSUS;
+  }
   if (collide) {
     if (REC) log_flight(Rc, p.id, k_ev, p.x, p.y, d, (double)p.e, c, p.r, b, 1);
     return EV_COLLIDE;
@@ -689,6 +751,7 @@ __global__ void k_ce_birth(Tables T, uint32_t gen, uint32_t n, const double* sx,
   p.ctr = rs.draw;
   p.id = id;
   p.nseg = 0;
+  p.t = 0.0;
   store_ce<R>(out, id, p);
 }
 
@@ -726,13 +789,14 @@ __global__ void __launch_bounds__(1024) k_ce_advance(Tables T, uint32_t gen, uin
       tl_hi += q >> 32;
       p.nseg += 1;
       c_seg += 1;
-      c_cross += ev != EV_COLLIDE ? 1u : 0u;
+      c_cross += (ev == EV_CROSS || ev == EV_LEAK) ? 1u : 0u;
       c_refl += refl ? 1u : 0u;
       if (ev != EV_CROSS) break;
     }
     p.ctr = rs.draw;
     if (ev == EV_KILL) die_ce<R, REC>(p, FATE_KILLED, A, Rc, T);
     if (ev == EV_LEAK) die_ce<R, REC>(p, FATE_LEAKED, A, Rc, T);
+    if (ev == EV_CENSUS) die_ce<R, REC>(p, FATE_CENSUS, A, Rc, T);
     // the collision point's lookup (a hit in the cache) goes with the particle
     if (ev == EV_COLLIDE) {
       const Geo& L = T.geo;
@@ -755,6 +819,7 @@ __global__ void __launch_bounds__(1024) k_ce_advance(Tables T, uint32_t gen, uin
   wave_count(A.cnt + CNT_REFL * STRIPES, c_refl);
   wave_flag(A.cnt + CNT_LEAK * STRIPES, ev == EV_LEAK);
   wave_flag(A.cnt + CNT_KILLED * STRIPES, ev == EV_KILL);
+  wave_flag(A.cnt + CNT_CENSUS * STRIPES, ev == EV_CENSUS);
   wave_flag(A.cnt + CNT_ADV_ITEMS * STRIPES, k < n_in);
   wave_count(A.cnt + CNT_ADV_SEGS * STRIPES, c_seg);
   wave_acc_halves(A.k + K_TL * STRIPES * 2, tl_lo, tl_hi);
@@ -815,7 +880,7 @@ __global__ void __launch_bounds__(256) k_ce_tail(Tables T, uint32_t gen, Bank in
   const uint32_t n_in = *n_in_p;
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long c_seg = 0, c_col = 0, c_cross = 0, c_refl = 0, c_leak = 0, c_abs = 0,
-                     c_kill = 0, c_sites = 0, c_scat = 0, c_cut = 0;
+                     c_kill = 0, c_sites = 0, c_scat = 0, c_cut = 0, c_cen = 0;
   unsigned long long kcol[2] = {0, 0}, kabs[2] = {0, 0}, ktl[2] = {0, 0};
   // one pass of the loop is one flight of every live lane of the wave; the
   // fission sites of a pass are reserved with one atomic per wave
@@ -854,6 +919,11 @@ __global__ void __launch_bounds__(256) k_ce_tail(Tables T, uint32_t gen, Bank in
           ++c_leak;
           p.ctr = rs.draw;
           die_ce<R, REC>(p, FATE_LEAKED, A, Rc, T);
+          live = false;
+        } else if (ev == EV_CENSUS) {
+          ++c_cen;
+          p.ctr = rs.draw;
+          die_ce<R, REC>(p, FATE_CENSUS, A, Rc, T);
           live = false;
         } else if (ev == EV_CROSS) {
           ++c_cross;
@@ -906,6 +976,7 @@ __global__ void __launch_bounds__(256) k_ce_tail(Tables T, uint32_t gen, Bank in
   wave_count(A.cnt + CNT_SITES * STRIPES, c_sites);
   wave_count(A.cnt + CNT_SCAT * STRIPES, c_scat);
   wave_count(A.cnt + CNT_CUTOFF * STRIPES, c_cut);
+  wave_count(A.cnt + CNT_CENSUS * STRIPES, c_cen);
   wave_acc_halves(A.k + K_COL * STRIPES * 2, kcol[0], kcol[1]);
   wave_acc_halves(A.k + K_ABS * STRIPES * 2, kabs[0], kabs[1]);
   wave_acc_halves(A.k + K_TL * STRIPES * 2, ktl[0], ktl[1]);
@@ -959,6 +1030,7 @@ __global__ void __launch_bounds__(1024) k_ce_mono(Tables T, uint32_t gen, Bank i
   uint64_t q_kabs = 0;
   if (ev == EV_COLLIDE) fate = collide_rest_ce<R>(T, p, rs, c, nf, slot, A, &q_kabs);
   if (ev == EV_LEAK) fate = FATE_LEAKED;
+  if (ev == EV_CENSUS) fate = FATE_CENSUS;
   const bool alive = valid && fate == FATE_ALIVE;
   if (valid) {
     p.ctr = rs.draw;
@@ -973,6 +1045,7 @@ __global__ void __launch_bounds__(1024) k_ce_mono(Tables T, uint32_t gen, Bank i
   wave_flag(A.cnt + CNT_REFL * STRIPES, refl);
   wave_flag(A.cnt + CNT_LEAK * STRIPES, ev == EV_LEAK);
   wave_flag(A.cnt + CNT_KILLED * STRIPES, ev == EV_KILL);
+  wave_flag(A.cnt + CNT_CENSUS * STRIPES, ev == EV_CENSUS);
   wave_flag(A.cnt + CNT_COL * STRIPES, col);
   wave_flag(A.cnt + CNT_SCAT * STRIPES, col && fate != FATE_ABSORBED);
   wave_flag(A.cnt + CNT_ABS * STRIPES, col && fate == FATE_ABSORBED);

@@ -140,6 +140,9 @@ struct Tables {
   uint32_t hash_base_f;
   double nu, watt_a, watt_b, e_max, e_cut;
   double q_ktl;            // fixed-point scale of the track-length k terms
+  double q_dens;           // fixed-point scale of the density terms (continuous-energy
+                           // time-dependent mode)
+  double src_energy;       // > 0: continuous-energy source energy, eV (else Watt)
   // time-dependent fixed source (time != 0): nt time bins per tally bin,
   // group speeds, census at t_max
   int time;
@@ -233,6 +236,10 @@ MCX_HD void log_flight(const Records& Rc, uint32_t id, int k, double x, double y
 struct Accum {
   unsigned long long* tally;  // flux: [stripe][bin] (lo, hi) 128-bit pairs
   unsigned long long* tally_t;  // flux from the tail kernels: [stripe][bin] (sum of low, high 32-bit halves)
+  // continuous-energy time-dependent mode: neutron density (time spent per
+  // bin), laid out as tally and tally_t; null otherwise
+  unsigned long long* dens;
+  unsigned long long* dens_t;
   unsigned long long* k;      // [3][STRIPES][2 halves]
   unsigned long long* cnt;    // [N_CNT_ALL][STRIPES]
   uint32_t* n_fis;            // fission sites appended

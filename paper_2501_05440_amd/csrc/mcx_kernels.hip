@@ -581,19 +581,19 @@ __global__ void __launch_bounds__(64) k_gen_totals(Tables T, uint32_t gen, uint3
 constexpr int GT_BINS = 64;
 constexpr int GT_WAVES = 8;
 
-__global__ void __launch_bounds__(64 * GT_WAVES) k_gen_tallies(Tables T, uint32_t gen, uint32_t n,
-                                                                Accum A, double* gen_tal,
-                                                                double* tl_part) {
-  __shared__ unsigned long long s0[GT_WAVES][GT_BINS], s1[GT_WAVES][GT_BINS];
-  const int nb = T.n_bins;
-  const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
-  const int b = (int)blockIdx.x * GT_BINS + lane;
+// Exact sum over the stripes st = w, w + GT_WAVES, ... of bin b: the
+// 128-bit pairs of the event kernels and the (low-half, high-half) sums of
+// the tail kernels; (0, 0) for b >= nb.
+__device__ __forceinline__ void bin_sum_stripes(const unsigned long long* pairs,
+                                                const unsigned long long* halves, int n_stripes,
+                                                int nb, int b, int w, unsigned long long* o0,
+                                                unsigned long long* o1) {
   const size_t stride = 2 * (size_t)nb;
-  unsigned long long w0 = 0, w1 = 0;  // w1 * 2^64 + w0
+  unsigned long long w0 = 0, w1 = 0;
   if (b < nb) {
-    for (int st = w; st < T.tally_stripes; st += GT_WAVES) {
-      const unsigned long long* pr = A.tally + (size_t)st * stride + 2 * (size_t)b;
-      const unsigned long long* hv = A.tally_t + (size_t)st * stride + 2 * (size_t)b;
+    for (int st = w; st < n_stripes; st += GT_WAVES) {
+      const unsigned long long* pr = pairs + (size_t)st * stride + 2 * (size_t)b;
+      const unsigned long long* hv = halves + (size_t)st * stride + 2 * (size_t)b;
       unsigned long long t = w0 + pr[0];
       w1 += pr[1] + (t < w0 ? 1ull : 0ull);
       w0 = t;
@@ -606,25 +606,50 @@ __global__ void __launch_bounds__(64 * GT_WAVES) k_gen_tallies(Tables T, uint32_
       w0 = t;
     }
   }
-  s0[w][lane] = w0;
-  s1[w][lane] = w1;
-  __syncthreads();
-  if (w != 0) return;
-  for (int k = 1; k < GT_WAVES; ++k) {
-    const unsigned long long t = w0 + s0[k][lane];
-    w1 += s1[k][lane] + (t < w0 ? 1ull : 0ull);
-    w0 = t;
+  *o0 = w0;
+  *o1 = w1;
+}
+
+__global__ void __launch_bounds__(64 * GT_WAVES) k_gen_tallies(Tables T, uint32_t gen, uint32_t n,
+                                                                Accum A, double* gen_tal,
+                                                                double* tl_part) {
+  __shared__ unsigned long long s0[GT_WAVES][GT_BINS], s1[GT_WAVES][GT_BINS];
+  const int nb = T.n_bins;
+  const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+  const int b = (int)blockIdx.x * GT_BINS + lane;
+  // the flux accumulators, and in the continuous-energy time-dependent
+  // mode the density ones
+  const bool dens = A.dens != nullptr;
+  unsigned long long v[2][2];  // [flux, density][w0, w1]: w1 * 2^64 + w0
+  for (int a = 0; a < (dens ? 2 : 1); ++a) {
+    bin_sum_stripes(a ? A.dens : A.tally, a ? A.dens_t : A.tally_t, T.tally_stripes, nb, b, w,
+                    &v[a][0], &v[a][1]);
+    s0[w][lane] = v[a][0];
+    s1[w][lane] = v[a][1];
+    __syncthreads();
+    if (w == 0)
+      for (int k = 1; k < GT_WAVES; ++k) {
+        const unsigned long long t = v[a][0] + s0[k][lane];
+        v[a][1] += s1[k][lane] + (t < v[a][0] ? 1ull : 0ull);
+        v[a][0] = t;
+      }
+    __syncthreads();
   }
+  if (w != 0) return;
   double prod = 0.0;
   if (b < nb) {
-    const double flux = u128_to_double(w0, w1) / T.q_flux;
+    const double flux = u128_to_double(v[0][0], v[0][1]) / T.q_flux;
     const int per_cell = T.geo.mr1 * T.G * T.nt;
     const int cell = b / per_cell;
     const int r = (b / (T.G * T.nt)) % T.geo.mr1;
     const int g = (b / T.nt) % T.G;
     const int m = T.geo.mats[T.geo.pin_map[cell] * T.geo.mr1 + r];
-    // continuous energy: nu_sig_f varies inside a bin; no production tally
-    prod = T.ce ? 0.0 : T.nusf[m * T.G + g] * flux;
+    // continuous energy: nu_sig_f varies inside a bin, so there is no
+    // production tally; the time-dependent mode reports the density there
+    if (T.ce)
+      prod = dens ? u128_to_double(v[1][0], v[1][1]) / T.q_dens : 0.0;
+    else
+      prod = T.nusf[m * T.G + g] * flux;
     gen_tal[(size_t)gen * 2 * nb + b] = flux / (double)n;
     gen_tal[(size_t)gen * 2 * nb + nb + b] = prod / (double)n;
   }

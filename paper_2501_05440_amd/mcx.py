@@ -83,7 +83,7 @@ class CEData(C.Structure):
                 ("max_nuc", C.c_int32), ("mat_n", C.c_void_p), ("mat_nuc", C.c_void_p),
                 ("mat_dens", C.c_void_p), ("watt_a", C.c_double), ("watt_b", C.c_double),
                 ("e_max", C.c_double), ("e_cut", C.c_double), ("n_ebins", C.c_int32),
-                ("e_edges", C.c_void_p)]
+                ("e_edges", C.c_void_p), ("src_energy", C.c_double)]
 
 
 class Problem(C.Structure):
@@ -213,6 +213,7 @@ def _ce(ce, keep):
     edges = _arr(ce["e_edges"], np.float64, keep)
     d.n_ebins = len(edges) - 1
     d.e_edges = edges.ctypes.data
+    d.src_energy = float(ce.get("src_energy", 0.0))
     return d
 
 
@@ -285,10 +286,13 @@ class Context:
         n_t = 1
         if "time" in problem:
             edges = _arr(problem["time"]["t_edges"], np.float64, k)
-            speed = _arr(problem["time"]["speed"], np.float64, k)
             n_t = len(edges) - 1
-            self._check(L.mcx_load_time_grid(h, n_t, edges.ctypes.data, speed.ctypes.data,
-                                             len(speed)))
+            if problem["time"].get("speed") is None:
+                self._check(L.mcx_load_time_grid(h, n_t, edges.ctypes.data, None, 0))
+            else:
+                speed = _arr(problem["time"]["speed"], np.float64, k)
+                self._check(L.mcx_load_time_grid(h, n_t, edges.ctypes.data, speed.ctypes.data,
+                                                 len(speed)))
         s = Source()
         s.seed, s.n_per_gen = rp["seed"], rp["n_per_gen"]
         s.fixed_source, s.problem_id = int(rp["fixed_source"]), rp["problem_id"]

@@ -190,3 +190,124 @@ def test_fp32_mixed_time_mode_is_balanced_and_close_to_fp64():
         assert abs(p32 - p64) < 5 * math.sqrt(p64 * (1 - p64) / tot) + 1e-12, (idx, p32, p64)
     t32 = a["records"]["t_final"]
     assert np.all(t32[a["records"]["fate"] == FATE_CENSUS] == prob["time"]["t_edges"][-1])
+
+
+# ---------------------------------------------------------------------------
+# continuous energy (the paper's time-dependent pin cell, Sec. 4): 14 MeV
+# source pulse, speed from the energy, flux and neutron density per time bin
+# ---------------------------------------------------------------------------
+
+def ce_quanta(prob):
+    """Fixed-point quanta of the GPU's flux and density sums: 2^(e - 61),
+    2^e the power of two above 1.01 * 36.8 / min Sigma_t (the longest
+    flight) and above 1.01 * the census time (the longest time in one bin)."""
+    ce = prob["ce"]
+    st_min = math.inf
+    for m in range(len(ce["mat_n"])):
+        st = sum(ce["mat_dens"][m][k] * ce["sig_t"][ce["mat_nuc"][m][k]]
+                 for k in range(ce["mat_n"][m]))
+        st_min = min(st_min, float(np.min(st)))
+    _, e1 = math.frexp(1.01 * 36.8 / st_min)
+    _, e2 = math.frexp(1.01 * prob["time"]["t_edges"][-1])
+    return math.ldexp(1.0, e1 - 61), math.ldexp(1.0, e2 - 61)
+
+
+def compare_ce_time(g, o, prob):
+    assert np.array_equal(g["gen_counts"], o["gen_counts"]), (g["gen_counts"], o["gen_counts"])
+    for gen in range(g["records"].shape[0]):
+        for f in INT_FIELDS:
+            d = g["records"][gen][f] != o["records"][gen][f]
+            assert not d.any(), f"gen {gen} {f}: {d.sum()} differ, first {np.argwhere(d)[:3]}"
+        for f in FP_FIELDS + ["e_final"]:
+            assert_close(g["records"][gen][f], o["records"][gen][f], what=f"gen {gen} {f}")
+    n = prob["run"]["n_per_gen"]
+    qf, qd = ce_quanta(prob)
+    seg = g["gen_counts"][:, 0].astype(float)[:, None]
+    for key, q in (("gen_flux", qf), ("gen_prod", qd)):
+        a, b = g[key], o[key]
+        bad = np.abs(a - b) > RTOL * np.maximum(np.abs(a), np.abs(b)) + seg * q / 2 / n
+        assert not bad.any(), f"{key}: {bad.sum()} bins differ"
+    assert_close(g["gen_k"], o["gen_k"], what="gen_k")
+
+
+@pytest.mark.parametrize("engine", ["event", "monolithic"])
+def test_ce_pulsed_pin_cell_parity(oracle, engine):
+    banner(f"CE pulsed pin cell 3000 x 2 vs oracle ({engine} engine)")
+    prob = P.ce_pulsed_pin_cell(n_per_gen=3000, n_gen=2)
+    g = mcx.run(prob, record=True, per_gen_tallies=True, engine=engine)
+    o = oracle.run(prob, records=True, per_gen_tallies=True)
+    compare_ce_time(g, o, prob)
+    n = prob["run"]["n_per_gen"]
+    c = g["gen_counts"]
+    assert np.all(c[:, 5] + c[:, 9] + c[:, 10] + c[:, 4] == n)
+
+
+def test_ce_pulsed_launch_configurations_agree():
+    banner("CE pulsed pin cell: tail, flights and block size give identical results")
+    prob = P.ce_pulsed_pin_cell(n_per_gen=20_000, n_gen=2)
+    a = mcx.run(prob, record=True)
+    b = mcx.run(prob, record=True, flights=1, tail_threshold=-1, block_size=128)
+    c = mcx.run(prob, record=True, tail_threshold=1 << 30)
+    for r in (b, c):
+        for k in ("gen_counts", "flux_mean", "prod_mean", "gen_k"):
+            assert np.array_equal(a[k], r[k]), k
+        assert np.array_equal(a["records"], r["records"])
+
+
+def test_ce_pulsed_heavy_target_closed_form():
+    """A flat medium of one very heavy nuclide keeps the 1 MeV speed through
+    every scatter: flux and density per time bin follow the one-group decay
+    exp(-Sigma_a v t) (4 sigma), census fraction binomial."""
+    banner("CE heavy-target decay vs closed form")
+    e0 = 1.0e6
+    sig_s, sig_c, sig_f = 3.0, 0.4, 0.1
+    ce = dict(P.ce_flat(sig_s, sig_c, sig_f, 1e12), src_energy=e0)
+    edges = np.array([0.0, 2e-10, 5e-10, 1e-9, 2e-9, 4e-9])
+    prob = P.with_time(P.ce_homogeneous(ce, 100_000, 10, 0, seed=41, fixed_source=True), edges)
+    g = mcx.run(prob)
+    nt = len(edges) - 1
+    sa = sig_c + sig_f
+    v = 2.99792458e10 * math.sqrt(2.0 * e0 / 939.56542052e6)
+    decay = np.exp(-sa * v * edges[:-1]) - np.exp(-sa * v * edges[1:])
+    flux = g["flux_mean"].reshape(-1, nt).sum(0)
+    fsig = np.sqrt((g["flux_sigma"].reshape(-1, nt) ** 2).sum(0))
+    dens = g["prod_mean"].reshape(-1, nt).sum(0)
+    dsig = np.sqrt((g["prod_sigma"].reshape(-1, nt) ** 2).sum(0))
+    assert np.all(np.abs(flux - decay / sa) < 4 * fsig), (flux, decay / sa, fsig)
+    assert np.all(np.abs(dens - decay / (sa * v)) < 4 * dsig), (dens, decay / (sa * v), dsig)
+    n = 100_000 * 10
+    cen = g["gen_counts"][:, 10].sum() / n
+    p = math.exp(-sa * v * edges[-1])
+    assert abs(cen - p) < 4 * math.sqrt(p * (1 - p) / n)
+
+
+def test_ce_pulsed_full_size_first_batch(oracle):
+    """The benchmark's continuous-energy pulsed pin cell at full size
+    (1e6 histories): the first batch history by history."""
+    banner("CE pulsed pin cell 1e6 x 1 records parity")
+    prob = P.ce_pulsed_pin_cell(n_gen=1)
+    g = mcx.run(prob, record=True, per_gen_tallies=True)
+    o = oracle.run(prob, records=True, per_gen_tallies=True)
+    compare_ce_time(g, o, prob)
+
+
+def test_ce_pulsed_fp32_mixed_is_deterministic_and_close_to_fp64():
+    banner("CE pulsed pin cell FP32-mixed vs FP64")
+    prob = P.ce_pulsed_pin_cell(n_per_gen=50_000, n_gen=4)
+    a = mcx.run(prob, precision="fp32", record=True)
+    b = mcx.run(prob, precision="fp32", record=True, flights=1, tail_threshold=-1, block_size=64)
+    assert np.array_equal(a["records"], b["records"])
+    assert np.array_equal(a["prod_mean"], b["prod_mean"])
+    n = prob["run"]["n_per_gen"]
+    seg, col, cross, refl, leak, ab, killed, sites, scat, cut, cen = a["gen_counts"].T
+    assert np.all(ab + cut + cen == n) and np.all(killed == 0) and np.all(sites == 0)
+    g = mcx.run(prob)
+    # the density summed over every bin is the mean time alive: per batch
+    # differences between the precisions stay within their spread
+    nt = len(prob["time"]["t_edges"]) - 1
+    d32 = a["prod_mean"].reshape(-1, nt).sum(0)
+    d64 = g["prod_mean"].reshape(-1, nt).sum(0)
+    s = np.hypot(a["prod_sigma"].reshape(-1, nt), g["prod_sigma"].reshape(-1, nt))
+    s = np.sqrt((s ** 2).sum(0))
+    ok = d64 > 1e-3 * d64.max()
+    assert np.all(np.abs(d32 - d64)[ok] < 5 * s[ok] + 1e-300), (d32, d64, s)
