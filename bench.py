@@ -1,21 +1,25 @@
 #!/usr/bin/env python3
 """Throughput of the event-based Monte Carlo k-eigenvalue path on one MI355X.
 
-One step is one full power iteration of the 17x17-pin, 7-group lattice
-(1e6 histories per generation, 60 generations, 20 inactive) in FP64 with the
+One step is one full power iteration of the 17x17-pin, 7-group lattice at
+1e7 histories per generation (60 generations, 20 inactive) in FP64 on the
 event engine, with the problem data and workspace resident on the GPU.
-Prints one JSON line with histories/s (value), events/s, the roofline of the
-dominant event kernel (the advance kernel, timed with HIP events on the
-run's stream around each of its launches in the timed steps) and the CPU
-oracle timed on a bounded sample of the same workload; beside them the same
-lattice on the persistent engine and as one history-based kernel per
-generation, the FP64 / FP32-mixed comparison at 1e7 histories per
-generation, the 512-problem fixed-source batch in one persistent launch
-against the same problems run one at a time, the continuous-energy pin cell
-and the pulsed (time-dependent) lattice.
+Prints one JSON line with histories/s (value), events/s, the roofline of
+the dominant event kernel (the advance kernel, timed with HIP events on the
+run's stream around its launches in the timed steps), the copy-kernel
+bandwidth of the device, and the CPU oracle timed on a bounded sample of the
+same workload.  Beside them: the same lattice at 1e6 histories per
+generation; the FP32-mixed form at 1e7 histories (k difference in pcm with
+its paired sigma); the engines side by side (decomposed event kernels, the
+paper's monolithic one-segment kernel, the asynchronous global-queue engine,
+the persistent LDS-slot engine); the 512-problem fixed-source batch in one
+launch against the same problems one at a time; the continuous-energy pin
+cell in FP64 and FP32-mixed; and the time-dependent forms (the pulsed
+lattice and the 14 MeV pulsed continuous-energy pin cell).
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -25,15 +29,23 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TIME_STRIDE = 4  # the timed steps time the advance launches of every 4th generation
-# algorithmic bytes per processed particle (FP64 bank entry: x, y, u, v as f64,
-# cell, group|sites, draw counter, id, flight count as u32 = 52 B)
+# algorithmic bytes of the advance kernel per flight segment (the minimum
+# state one flight moves, FP64 multigroup): reads x, y, u, v, w, group, cell,
+# counter (52 B), writes x, y, counter, event (24 B), queue traffic 8 B
+SEGMENT_BYTES = 84
+# the kernel's own accounting per processed particle: the 52-byte bank entry
+# read and written, plus one 16-byte fixed-point flux atomic per flight
 STATE_BYTES = 52
-TALLY_BYTES_ADV = 16  # one 64-bit fixed-point flux atomic (read-modify-write) per flight
-COUNTERS = os.path.join(ROOT, "profiles", "k_advance_lattice17x17_counters.md")
+TALLY_BYTES_ADV = 16
+COUNTERS = os.path.join(ROOT, "profiles", "k_advance_lattice17x17_1e7_counters.md")
 KERNEL_SOURCES = ["paper_2501_05440_amd/csrc/mcx_kernels.hip",
                   "paper_2501_05440_amd/csrc/mcx_kernels_common.hpp",
                   "paper_2501_05440_amd/csrc/mcx_device.hpp",
                   "paper_2501_05440_amd/csrc/mcx_math.hpp"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def measured_traffic_per_item():
@@ -59,7 +71,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n-per-gen", type=int, default=1_000_000)
+    ap.add_argument("--n-per-gen", type=int, default=10_000_000)
     ap.add_argument("--n-gen", type=int, default=60)
     ap.add_argument("--n-inactive", type=int, default=20)
     ap.add_argument("--block", type=int, default=0)
@@ -67,174 +79,164 @@ def parse():
     ap.add_argument("--flights", type=int, default=0,
                     help="flights per particle per advance launch (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-gens", type=int, default=40,
-                    help="generations of the lattice the CPU oracle runs (about 10-15 s)")
-    ap.add_argument("--no-fp32", action="store_true",
-                    help="skip the 1e7-history FP64 / FP32-mixed comparison")
-    ap.add_argument("--n-fp32", type=int, default=10_000_000)
-    ap.add_argument("--no-batch", action="store_true", help="skip the 512-problem batch")
-    ap.add_argument("--no-ce", action="store_true", help="skip the continuous-energy pin cell")
-    ap.add_argument("--no-time", action="store_true", help="skip the pulsed (time-dependent) lattice")
-    ap.add_argument("--no-persistent", action="store_true",
-                    help="skip the lattice on the persistent engine")
+    ap.add_argument("--cpu-gens", type=int, default=4,
+                    help="generations of the headline lattice the CPU oracle runs (about 10 s)")
+    ap.add_argument("--no-extras", action="store_true", help="headline only")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-engines", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-ce", action="store_true")
+    ap.add_argument("--no-time", action="store_true")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (default: a fresh one per run)")
     return ap.parse_args()
 
 
-def timed_runs(ctx, steps):
+def sync():
     import torch
-    ctx.run()  # warm-up
     torch.cuda.synchronize()
+
+
+def timed_runs(ctx, steps, warmup=1):
+    for _ in range(warmup):
+        ctx.run()
+    sync()
     t0 = time.perf_counter()
     for _ in range(steps):
         ctx.run()
-    torch.cuda.synchronize()
+    sync()
     return (time.perf_counter() - t0) / steps
 
 
-def fp32_mixed_comparison(P, mcx, n, n_gen, n_inactive):
-    """Lattice at n histories per generation: FP64 and FP32-mixed throughput
-    and the k-eff difference (pcm) with its standard deviation, and the
-    per-pin flux differences."""
-    import math
+def copy_peak_gbps():
+    """Device-to-device copy of 1 GiB (the copy kernel of the runtime), best
+    of 5, counted as bytes read plus bytes written."""
+    import torch
+    a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    best = math.inf
+    for _ in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    return 2 * 1024 ** 3 / best / 1e9
 
-    import numpy as np
-    prob = P.lattice_17x17(n_per_gen=n, n_gen=n_gen, n_inactive=n_inactive)
-    geo = prob["geometry"]
-    cells, per_cell = geo["ny"] * geo["nx"], (geo["radii"].shape[1] + 1) * prob["xs"]["sig_t"].shape[1]
-    out = {}
-    res = {}
-    pins = {}
-    for prec in ("fp64", "fp32"):
-        ctx = mcx.Context(prob, precision=prec, time_kernels=True)
-        sec = timed_runs(ctx, 1)
-        km, ks, pg = ctx.keff()
-        t = ctx.timing()
-        res[prec] = (km, ks, pg)
-        # per-pin flux (all rings and groups of a lattice cell) and its sigma
-        tl = ctx.tallies()
-        pins[prec] = (tl["flux_mean"].reshape(cells, per_cell).sum(axis=1),
-                      np.sqrt((tl["flux_sigma"].reshape(cells, per_cell) ** 2).sum(axis=1)))
-        ctx.close()
-        out[prec] = {"histories_per_s": round(n * n_gen / sec, 1), "ms_per_step": round(sec * 1e3, 2),
-                     "k_col": round(float(km[0]), 7), "sigma": round(float(ks[0]), 7)}
-        # the advance kernel at this size (direction cosines are binary32 in FP32-mixed)
-        state = STATE_BYTES if prec == "fp64" else STATE_BYTES - 8
-        items = t["advance_items"] / max(1, t["n_advance"])
-        fl = t["advance_segments"] / max(1, t["advance_items"])
-        avg_ms = t["advance_ms"] / max(1, t["n_advance"])
-        ach = items * (2 * state + TALLY_BYTES_ADV * fl) / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-        out[prec]["k_advance_roofline"] = {"achieved_GBps": round(ach, 1),
-                                           "frac": round(ach / HBM_PEAK_GBS, 4),
-                                           "items_per_launch": round(items, 1),
-                                           "avg_launch_us": round(avg_ms * 1e3, 2)}
-    dk = res["fp32"][0][0] - res["fp64"][0][0]
-    sig = math.hypot(res["fp32"][1][0], res["fp64"][1][0])
-    d = res["fp32"][2][n_inactive:, 0] - res["fp64"][2][n_inactive:, 0]
-    out["dk_pcm"] = round(dk * 1e5, 3)
-    out["sigma_pcm"] = round(sig * 1e5, 3)
-    out["paired_sigma_pcm"] = round(float(d.std(ddof=1) / math.sqrt(len(d))) * 1e5, 3)
-    out["speedup_fp32_over_fp64"] = round(out["fp32"]["histories_per_s"] / out["fp64"]["histories_per_s"], 3)
-    (f64, s64), (f32, s32) = pins["fp64"], pins["fp32"]
-    rel = np.abs(f32 - f64) / f64
-    out["pin_flux"] = {"max_rel_diff": float(f"{rel.max():.3e}"),
-                       "rms_rel_diff": float(f"{np.sqrt(np.mean(rel ** 2)):.3e}"),
-                       "max_rel_sigma_fp64": float(f"{(s64 / f64).max():.3e}"),
-                       "mean_abs_diff_over_sigma": round(float(np.mean(np.abs(f32 - f64) / np.hypot(s32, s64))), 3),
-                       "pins": int(cells)}
-    out["workload"] = f"lattice_17x17_7g, {n} histories/gen x {n_gen} gens ({n_inactive} inactive)"
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def paired(g32, g64, ni):
+    d = g32[ni:, 0] - g64[ni:, 0]
+    return float(d.std(ddof=1) / math.sqrt(len(d)))
+
+
+def engine_leg(mcx, prob, engine, steps=1, **kw):
+    ctx = mcx.Context(prob, engine=engine, **kw)
+    tune = ctx.autotune() if engine == "persistent" else None
+    sec = timed_runs(ctx, steps)
+    km, _, _ = ctx.keff()
+    _, c = ctx.generation_stats()
+    ctx.close()
+    n = prob["run"]["n_per_gen"] * prob["run"]["n_gen"]
+    out = {"histories_per_s": round(n / sec, 1), "events_per_s": round(float(c[:, 0].sum()) / sec, 1),
+           "ms_per_step": round(sec * 1e3, 2), "k_col": round(float(km[0]), 7)}
+    if tune:
+        out["tuned"] = {k: tune[k] for k in ("block", "slots", "grid", "tau", "sort")}
     return out
 
 
-def persistent_comparison(P, mcx, prob, event_hps, tune_cache):
-    """The lattice on the persistent engine (autotuned): histories/s."""
-    ctx = mcx.Context(prob, engine="persistent")
-    tune = ctx.autotune(tune_cache)
-    sec = timed_runs(ctx, 1)
-    km, ks, _ = ctx.keff()
-    ctx.close()
-    n = prob["run"]["n_per_gen"] * prob["run"]["n_gen"]
-    return {"histories_per_s": round(n / sec, 1), "ms_per_step": round(sec * 1e3, 2),
-            "speedup_over_event_engine": round(n / sec / event_hps, 3),
-            "k_col": round(float(km[0]), 7),
-            "tuned": {k: tune[k] for k in ("block", "slots", "grid", "tau", "sort")}}
-
-
-def monolithic_comparison(P, mcx, prob, event_hps):
-    """The paper's monolithic form for comparison: every history of a
-    generation run by one history-based kernel (the tail kernel from the
-    first flight)."""
-    ctx = mcx.Context(prob, tail_threshold=1 << 30)
-    sec = timed_runs(ctx, 1)
-    ctx.close()
-    n = prob["run"]["n_per_gen"] * prob["run"]["n_gen"]
-    return {"histories_per_s": round(n / sec, 1), "ms_per_step": round(sec * 1e3, 2),
-            "event_engine_speedup": round(event_hps / (n / sec), 3)}
+def engines_comparison(P, mcx, big):
+    """The same problems on every engine (identical histories): decomposed
+    event kernels, the paper's monolithic one-segment kernel, the
+    asynchronous engine with global per-event-type queues, and the
+    persistent engine."""
+    out = {}
+    c1 = P.lattice_17x17()
+    out["lattice_1e6"] = {e: engine_leg(mcx, c1, e) for e in ("event", "monolithic", "async",
+                                                              "persistent")}
+    log("engines: lattice 1e7 monolithic")
+    out["lattice_1e7_monolithic"] = engine_leg(mcx, big, "monolithic")
+    c4 = P.ce_pin_cell()
+    log("engines: continuous-energy pin cell")
+    out["ce_pin_cell"] = {e: engine_leg(mcx, c4, e) for e in ("event", "monolithic")}
+    for key, legs in (("lattice_1e6", out["lattice_1e6"]), ("ce_pin_cell", out["ce_pin_cell"])):
+        ev = legs["event"]["histories_per_s"]
+        for e, r in legs.items():
+            r["relative_to_event"] = round(r["histories_per_s"] / ev, 3)
+    out["note"] = ("histories per second of each engine on the same problem; every engine gives "
+                   "the same histories bit for bit (k_col equal)")
+    return out
 
 
 def batch_comparison(P, mcx, tune_cache, steps):
-    """512 fixed-source pin cells in one persistent launch (autotuned) against
-    the same problems run one at a time with the FP64 event engine."""
+    """512 fixed-source pin cells in one persistent launch (autotuned) and
+    in one asynchronous-engine launch, against the same problems run one at
+    a time with the FP64 event engine."""
     import numpy as np
-    import torch
     probs = P.batch_pin_cells()
     n = np.array([q["run"]["n_per_gen"] for q in probs])
-    b = mcx.Batch(probs)
-    tune = b.autotune(tune_cache)
-    b.run()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
+    out = {}
+    for eng in ("persistent", "async"):
+        b = mcx.Batch(probs, engine=eng)
+        tune = b.autotune(tune_cache) if eng == "persistent" else None
         b.run()
-    torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / steps
-    k, cnt = b.results()
-    b.close()
-    print(f"[bench] batch: {sec * 1e3:.1f} ms per launch; one-at-a-time baseline", file=sys.stderr,
-          flush=True)
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            b.run()
+        sync()
+        sec = (time.perf_counter() - t0) / steps
+        k, cnt = b.results()
+        b.close()
+        out[eng] = {"histories_per_s": round(n.sum() / sec, 1),
+                    "events_per_s": round(float(cnt[:, 0].sum()) / sec, 1),
+                    "ms_per_batch": round(sec * 1e3, 2), "killed": int(cnt[:, 6].sum())}
+        if tune:
+            out[eng]["tuned"] = {kk: tune[kk] for kk in ("block", "slots", "grid", "tau", "sort")}
+        log(f"batch ({eng}): {sec * 1e3:.1f} ms per launch")
     ctxs = [mcx.Context(q) for q in probs]
     for c in ctxs[:4]:
         c.run()
-    torch.cuda.synchronize()
+    sync()
     t0 = time.perf_counter()
     for c in ctxs:
         c.run()
-    torch.cuda.synchronize()
+    sync()
     base = time.perf_counter() - t0
     for c in ctxs:
         c.close()
-    return {"workload": "512 fixed-source 7-group pin cells, own XS and radius each, "
-                        f"{int(n.min())}..{int(n.max())} histories (total {int(n.sum())}), one "
-                        "persistent launch in a HIP graph, FP64",
-            "histories_per_s": round(n.sum() / sec, 1),
-            "events_per_s": round(float(cnt[:, 0].sum()) / sec, 1),
-            "ms_per_batch": round(sec * 1e3, 2),
-            "one_at_a_time_event_fp64": {"histories_per_s": round(n.sum() / base, 1),
-                                         "ms": round(base * 1e3, 1)},
-            "speedup_over_one_at_a_time": round(base / sec, 3),
-            "tuned": {kk: tune[kk] for kk in ("block", "slots", "grid", "tau", "sort")},
-            "killed": int(cnt[:, 6].sum())}
+    out["workload"] = ("512 fixed-source 7-group pin cells, own XS and radius each, "
+                       f"{int(n.min())}..{int(n.max())} histories (total {int(n.sum())}), one "
+                       "launch in a HIP graph, FP64")
+    out["one_at_a_time_event_fp64"] = {"histories_per_s": round(n.sum() / base, 1),
+                                       "ms": round(base * 1e3, 1)}
+    out["speedup_over_one_at_a_time"] = round(base / (out["persistent"]["ms_per_batch"] * 1e-3), 3)
+    out["async_speedup_over_one_at_a_time"] = round(base / (out["async"]["ms_per_batch"] * 1e-3), 3)
+    return out
 
 
-def ce_measurement(P, mcx, steps):
+def ce_measurement(P, mcx):
     """Continuous-energy pin cell, 1e6 histories x 50 generations (10
-    inactive), event engine, FP64 and FP32-mixed."""
-    import math
-    import torch
+    inactive), event engine, FP64 and FP32-mixed on the same streams."""
     prob = P.ce_pin_cell()
     n = prob["run"]["n_per_gen"] * prob["run"]["n_gen"]
     ni = prob["run"]["n_inactive"]
     out, gk = {}, {}
     for prec in ("fp64", "fp32"):
         ctx = mcx.Context(prob, time_kernels=True, precision=prec)
-        ctx.run()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            ctx.run()
-        torch.cuda.synchronize()
-        sec = (time.perf_counter() - t0) / steps
+        sec = timed_runs(ctx, 1)
         t = ctx.timing()
         km, ks, pg = ctx.keff()
         _, c = ctx.generation_stats()
@@ -248,10 +250,9 @@ def ce_measurement(P, mcx, steps):
                      "kernel_ms_per_step": {"advance": round(t["advance_ms"], 2),
                                             "collide": round(t["collide_ms"], 2),
                                             "tail": round(t["tail_ms"], 2)}}
-    d = gk["fp32"][2][ni:, 0] - gk["fp64"][2][ni:, 0]
     out["dk_pcm"] = round(float(gk["fp32"][0][0] - gk["fp64"][0][0]) * 1e5, 3)
-    out["sigma_pcm"] = round(math.hypot(gk["fp32"][1][0], gk["fp64"][1][0]) * 1e5, 3)
-    out["paired_sigma_pcm"] = round(float(d.std(ddof=1) / math.sqrt(len(d))) * 1e5, 3)
+    out["paired_sigma_pcm"] = round(paired(gk["fp32"][2], gk["fp64"][2], ni) * 1e5, 3)
+    out["within_10_pcm"] = abs(out["dk_pcm"]) <= 10.0
     out["speedup_fp32_over_fp64"] = round(out["fp32"]["histories_per_s"] /
                                           out["fp64"]["histories_per_s"], 3)
     out["workload"] = ("continuous-energy pin cell: 10 nuclides x 50,000-point grid, "
@@ -259,43 +260,51 @@ def ce_measurement(P, mcx, steps):
     return out
 
 
-def time_dependent_measurement(P, mcx, steps, cpu):
-    """The pulsed 17x17 lattice (fixed source, fission as capture), 1e6
-    histories x 10 batches, flux in 12 time bins, census at 10 us: FP64
-    event engine, and the oracle on one batch."""
-    import torch
-    prob = P.pulsed_lattice()
-    n = prob["run"]["n_per_gen"] * prob["run"]["n_gen"]
-    ctx = mcx.Context(prob, time_kernels=True)
-    ctx.run()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ctx.run()
-    torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / steps
-    t = ctx.timing()
-    _, c = ctx.generation_stats()
-    ctx.close()
-    out = {"histories_per_s": round(n / sec, 1),
-           "events_per_s": round(float(c[:, 0].sum()) / sec, 1),
-           "ms_per_step": round(sec * 1e3, 2),
-           "segments_per_history": round(float(c[:, 0].sum()) / n, 3),
-           "census_fraction": round(float(c[:, 10].sum()) / n, 5),
-           "leak_fraction": round(float(c[:, 4].sum()) / n, 5),
-           "kernel_ms_per_step": {"advance": round(t["advance_ms"], 2),
-                                  "collide": round(t["collide_ms"], 2),
-                                  "tail": round(t["tail_ms"], 2)},
-           "workload": "pulsed lattice_17x17_7g: source pulse at t = 0, fission as capture, "
-                       "1e6 histories x 10 batches, 12 time bins to 10 us, FP64 event engine"}
-    if cpu:
-        from oracle import oracle as O
-        cores = os.cpu_count() or 1
-        c0 = time.perf_counter()
-        O.run(P.with_run(prob, n_gen=1), n_threads=cores)
-        dt = time.perf_counter() - c0
-        out["cpu_oracle"] = {"histories_per_s": round(prob["run"]["n_per_gen"] / dt, 1),
-                             "cores": cores, "sample": "first batch (1e6 histories)"}
+def time_dependent_measurement(P, mcx, cpu):
+    """The pulsed 17x17 lattice (1e6 histories x 10 batches, 12 time bins,
+    census at 10 us) and the 14 MeV pulsed continuous-energy pin cell (1e6
+    histories x 10 batches, 25 time bins, census at 10 us, neutron density
+    per bin): FP64 event engine; the oracle on one batch of each."""
+    import numpy as np
+    out = {}
+    for key, prob in (("pulsed_lattice", P.pulsed_lattice()),
+                      ("ce_pulsed_pin_cell", P.ce_pulsed_pin_cell())):
+        n = prob["run"]["n_per_gen"] * prob["run"]["n_gen"]
+        ctx = mcx.Context(prob, time_kernels=True)
+        sec = timed_runs(ctx, 1)
+        t = ctx.timing()
+        _, c = ctx.generation_stats()
+        tl = ctx.tallies()
+        ctx.close()
+        r = {"histories_per_s": round(n / sec, 1),
+             "events_per_s": round(float(c[:, 0].sum()) / sec, 1),
+             "ms_per_step": round(sec * 1e3, 2),
+             "segments_per_history": round(float(c[:, 0].sum()) / n, 3),
+             "census_fraction": round(float(c[:, 10].sum()) / n, 5),
+             "kernel_ms_per_step": {"advance": round(t["advance_ms"], 2),
+                                    "collide": round(t["collide_ms"], 2),
+                                    "tail": round(t["tail_ms"], 2)}}
+        if key == "ce_pulsed_pin_cell":
+            nt = len(prob["time"]["t_edges"]) - 1
+            dens = tl["prod_mean"].reshape(-1, nt).sum(0)
+            r["density_per_time_bin"] = [float(f"{v:.4e}") for v in dens]
+            r["time_edges_s"] = [float(f"{v:.4e}") for v in prob["time"]["t_edges"]]
+            r["workload"] = ("continuous-energy pin cell driven by a 14 MeV pulse, fission as "
+                             "capture, 1e6 histories x 10 batches, 25 time bins to 10 us, "
+                             "flux and neutron density per bin, FP64 event engine")
+        else:
+            r["leak_fraction"] = round(float(c[:, 4].sum()) / n, 5)
+            r["workload"] = ("pulsed lattice_17x17_7g: source pulse at t = 0, fission as capture, "
+                             "1e6 histories x 10 batches, 12 time bins to 10 us, FP64 event engine")
+        if cpu:
+            from oracle import oracle as O
+            cores = os.cpu_count() or 1
+            c0 = time.perf_counter()
+            O.run(P.with_run(prob, n_gen=1), n_threads=cores)
+            dt = time.perf_counter() - c0
+            r["cpu_oracle"] = {"histories_per_s": round(prob["run"]["n_per_gen"] / dt, 1),
+                               "cores": cores, "sample": "first batch (1e6 histories)"}
+        out[key] = r
     return out
 
 
@@ -305,6 +314,7 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {a.gpus}): sharding histories over "
               "several GPUs is designed but not built", file=sys.stderr)
         sys.exit(2)
+    import numpy as np
     import torch
 
     from paper_2501_05440_amd import mcx
@@ -313,10 +323,9 @@ def main():
     if not os.path.exists(mcx.LIB_PATH):
         from paper_2501_05440_amd import build as B
         B.build()
-    prob = P.lattice_17x17(n_per_gen=a.n_per_gen, n_gen=a.n_gen, n_inactive=a.n_inactive)
-    N, G = a.n_per_gen, a.n_gen
-    print(f"[bench] lattice 17x17, {N} histories x {G} generations, steps={a.steps} "
-          f"warmup={a.warmup}", file=sys.stderr, flush=True)
+    N, G, NI = a.n_per_gen, a.n_gen, a.n_inactive
+    prob = P.lattice_17x17(n_per_gen=N, n_gen=G, n_inactive=NI)
+    log(f"lattice 17x17, {N} histories x {G} generations, steps={a.steps} warmup={a.warmup}")
     # the timed steps record HIP events around the advance launches of every
     # TIME_STRIDE-th generation (each event between two launches delays the
     # next one a little); the generations are statistically alike
@@ -324,11 +333,11 @@ def main():
                       time_kernels="advance", time_stride=TIME_STRIDE, flights=a.flights)
     for w in range(a.warmup):
         ctx.run()
-        print(f"[bench] warmup {w + 1}/{a.warmup} done", file=sys.stderr, flush=True)
-    tot = dict(advance_ms=0.0, collide_ms=0.0, tail_ms=0.0, n_advance=0, n_collide=0,
-               advance_items=0, collide_items=0, advance_segments=0, n_iterations=0, run_ms=0.0)
+        log(f"warmup {w + 1}/{a.warmup} done")
+    tot = dict(advance_ms=0.0, n_advance=0, advance_items=0, advance_segments=0,
+               n_iterations=0)
     segs = 0
-    torch.cuda.synchronize()
+    sync()
     t0 = time.perf_counter()
     for k in range(a.steps):
         ctx.run()
@@ -337,10 +346,10 @@ def main():
             tot[key] += t[key]
         _, c = ctx.generation_stats()
         segs += int(c[:, 0].sum())
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    km, ks, _ = ctx.keff()
+    sync()
+    elapsed = time.perf_counter() - t0
+    log(f"timed {a.steps} steps: {elapsed / a.steps * 1e3:.1f} ms per step")
+    km, ks, g64 = ctx.keff()
     ctx.close()
     histories = a.steps * N * G
     value = histories / elapsed
@@ -353,27 +362,40 @@ def main():
     brk = bctx.timing()
     bctx.close()
 
-    # roofline of the dominant event kernel, the advance kernel (the largest
-    # summed time of the breakdown step), timed over the timed steps
+    # roofline of the dominant event kernel, the advance kernel, over the
+    # timed steps: algorithmic bytes = 84 B per flight segment x the
+    # segments of an average launch
     adv_avg_ms = tot["advance_ms"] / max(1, tot["n_advance"])
-    adv_items = tot["advance_items"] / max(1, tot["n_iterations"])  # every launch
-    adv_flights = tot["advance_segments"] / max(1, tot["advance_items"])
-    adv_bytes = 2 * STATE_BYTES + TALLY_BYTES_ADV * adv_flights
-    name, avg_ms, per_launch = "k_advance", adv_avg_ms, adv_items * adv_bytes
-    per_item = adv_bytes
-    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    segs_per_launch = tot["advance_segments"] / max(1, tot["n_iterations"])  # every launch
+    items_per_launch = tot["advance_items"] / max(1, tot["n_iterations"])
+    flights = tot["advance_segments"] / max(1, tot["advance_items"])
+    per_launch = SEGMENT_BYTES * segs_per_launch
+    achieved = per_launch / (adv_avg_ms * 1e-3) / 1e9 if adv_avg_ms > 0 else 0.0
+    own = items_per_launch * (2 * STATE_BYTES + TALLY_BYTES_ADV * flights)
+    own_gbs = own / (adv_avg_ms * 1e-3) / 1e9 if adv_avg_ms > 0 else 0.0
+    copy_gbs = copy_peak_gbps()
     traffic = None
     tpi = measured_traffic_per_item()
     if tpi is not None:
-        traffic = round(tpi * adv_items)  # HBM bytes per launch
-    roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1),
+        traffic = round(tpi * items_per_launch)  # HBM bytes per launch
+    roofline = {"bound": "hbm", "kernel": "k_advance", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "bytes_per_item": round(per_item, 2),
-                "items_per_launch": round(adv_items, 1),
-                "avg_launch_us": round(avg_ms * 1e3, 2),
+                "traffic": traffic,
+                "bytes_per_segment": SEGMENT_BYTES,
+                "segments_per_launch": round(segs_per_launch, 1),
+                "avg_launch_us": round(adv_avg_ms * 1e3, 2),
                 "timed_launches": int(tot["n_advance"]),
                 "timed_generation_stride": TIME_STRIDE,
-                "flights_per_advance_item": round(adv_flights, 4),
+                "frac_of_copy_peak": round(achieved / copy_gbs, 4),
+                "copy_peak_GBps": round(copy_gbs, 1),
+                "kernel_accounting": {"bytes_per_item": round(2 * STATE_BYTES +
+                                                              TALLY_BYTES_ADV * flights, 2),
+                                      "items_per_launch": round(items_per_launch, 1),
+                                      "flights_per_item": round(flights, 4),
+                                      "achieved_GBps": round(own_gbs, 1),
+                                      "frac": round(own_gbs / HBM_PEAK_GBS, 4)},
+                "segments_per_s_in_advance": round(segs_per_launch / (adv_avg_ms * 1e-3), 1)
+                if adv_avg_ms > 0 else 0.0,
                 "iterations_per_generation": round(tot["n_iterations"] / (a.steps * G), 2),
                 "kernel_ms_per_step": {"advance": round(brk["advance_ms"], 2),
                                        "collide": round(brk["collide_ms"], 2),
@@ -385,49 +407,53 @@ def main():
         from oracle import oracle as O
         cores = os.cpu_count() or 1
         sample = P.with_run(prob, n_gen=a.cpu_gens, n_inactive=a.cpu_gens - 1)
-        print(f"[bench] cpu oracle: {a.cpu_gens} generations of {N} histories on {cores} threads",
-              file=sys.stderr, flush=True)
+        log(f"cpu oracle: {a.cpu_gens} generations of {N} histories on {cores} threads")
         c0 = time.perf_counter()
         O.run(sample, n_threads=cores)
-        c1 = time.perf_counter()
-        cpu = {"value": round(a.cpu_gens * N / (c1 - c0), 1), "unit": "histories/s",
-               "cores": cores, "kind": "oracle",
+        dt = time.perf_counter() - c0
+        cpu = {"value": round(a.cpu_gens * N / dt, 1), "unit": "histories/s",
+               "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"first {a.cpu_gens} generations of the same lattice problem "
-                         f"({a.cpu_gens * N} histories, {c1 - c0:.1f} s)"}
+                         f"({a.cpu_gens * N} histories, {dt:.1f} s)"}
 
     import tempfile
     tune_cache = a.tune_cache or os.path.join(tempfile.mkdtemp(), "mcx_tune.txt")
-    pers = None
-    if not a.no_persistent:
-        print("[bench] lattice on the persistent engine", file=sys.stderr, flush=True)
-        pers = persistent_comparison(P, mcx, prob, value, tune_cache)
-    mono = None
-    if not a.no_persistent:
-        print("[bench] lattice as one history-based kernel per generation", file=sys.stderr,
-              flush=True)
-        mono = monolithic_comparison(P, mcx, prob, value)
-    batch = None
-    if not a.no_batch:
-        print("[bench] 512-problem batch", file=sys.stderr, flush=True)
+    extras = not a.no_extras
+    lat1 = fp32 = engines = batch = ce = td = None
+    if extras:
+        log("lattice at 1e6 histories per generation")
+        c1 = P.lattice_17x17(n_gen=G, n_inactive=NI)
+        lat1 = engine_leg(mcx, c1, "event", steps=3)
+        lat1["workload"] = f"lattice_17x17_7g, 1e6 histories/gen x {G} gens ({NI} inactive)"
+    if extras and not a.no_fp32:
+        log(f"FP32-mixed at {N} histories/gen")
+        c32 = mcx.Context(prob, precision="fp32")
+        sec = timed_runs(c32, 1)
+        km32, ks32, g32 = c32.keff()
+        c32.close()
+        h32 = N * G / sec
+        fp32 = {"histories_per_s": round(h32, 1), "ms_per_step": round(sec * 1e3, 2),
+                "k_col": round(float(km32[0]), 7),
+                "dk_pcm": round(float(km32[0] - km[0]) * 1e5, 3),
+                "paired_sigma_pcm": round(paired(g32, g64, NI) * 1e5, 3),
+                "speedup_over_fp64": round(h32 / value, 3)}
+        fp32["within_10_pcm"] = abs(fp32["dk_pcm"]) <= 10.0
+    if extras and not a.no_engines:
+        log("engines side by side")
+        engines = engines_comparison(P, mcx, prob)
+    if extras and not a.no_batch:
+        log("512-problem batch")
         batch = batch_comparison(P, mcx, tune_cache, a.steps)
-
-    ce = None
-    if not a.no_ce:
-        print("[bench] continuous-energy pin cell", file=sys.stderr, flush=True)
-        ce = ce_measurement(P, mcx, 1)
-
-    td = None
-    if not a.no_time:
-        print("[bench] pulsed lattice (time-dependent fixed source)", file=sys.stderr, flush=True)
-        td = time_dependent_measurement(P, mcx, 1, not a.no_cpu_baseline)
-
-    extra = None
-    if not a.no_fp32:
-        print(f"[bench] FP64 vs FP32-mixed at {a.n_fp32} histories/gen", file=sys.stderr, flush=True)
-        extra = fp32_mixed_comparison(P, mcx, a.n_fp32, G, a.n_inactive)
+    if extras and not a.no_ce:
+        log("continuous-energy pin cell")
+        ce = ce_measurement(P, mcx)
+    if extras and not a.no_time:
+        log("time-dependent forms")
+        td = time_dependent_measurement(P, mcx, not a.no_cpu_baseline)
 
     out = {
-        "metric": "histories/s per MI355X (FP64 event-based, k-eigenvalue power iteration)",
+        "metric": "histories/s and events/s per MI355X (FP64 vs FP32-mixed, batched) at <=10 pcm "
+                  "k-eff error",
         "value": round(value, 1),
         "unit": "histories/s",
         "n_gpus": 1,
@@ -440,8 +466,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"lattice_17x17_7g: 17x17 pin cells, 3 fuels + moderator, 7 groups, "
-                               f"vacuum boundary, {N} histories/gen x {G} gens ({a.n_inactive} "
-                               f"inactive), FP64 event-based",
+                               f"vacuum boundary, {N} histories/gen x {G} gens ({NI} inactive), "
+                               f"FP64 event-based",
                    "histories_per_step": N * G, "block_size": a.block or 256,
                    "tail_threshold": a.tail or max(4096, N // 8),
                    "flights_per_advance_launch": a.flights or 8},
@@ -450,9 +476,9 @@ def main():
         "k_eff": {"collision": round(float(km[0]), 6), "sigma": round(float(ks[0]), 6)},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "persistent_engine": pers,
-        "monolithic_history_kernel": mono,
-        "fp32_mixed": extra,
+        "lattice_1e6": lat1,
+        "fp32_mixed": fp32,
+        "engines": engines,
         "batch": batch,
         "continuous_energy": ce,
         "time_dependent": td,
