@@ -78,6 +78,9 @@ def parse():
     ap.add_argument("--tail", type=int, default=0)
     ap.add_argument("--flights", type=int, default=0,
                     help="flights per particle per advance launch (0 = library default)")
+    ap.add_argument("--rounds", type=int, default=0,
+                    help="particles per thread of an advance block, refilled lanes "
+                         "(0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-gens", type=int, default=4,
                     help="generations of the headline lattice the CPU oracle runs (about 10 s)")
@@ -330,7 +333,8 @@ def main():
     # TIME_STRIDE-th generation (each event between two launches delays the
     # next one a little); the generations are statistically alike
     ctx = mcx.Context(prob, device=0, block_size=a.block, tail_threshold=a.tail,
-                      time_kernels="advance", time_stride=TIME_STRIDE, flights=a.flights)
+                      time_kernels="advance", time_stride=TIME_STRIDE, flights=a.flights,
+                      rounds=a.rounds)
     for w in range(a.warmup):
         ctx.run()
         log(f"warmup {w + 1}/{a.warmup} done")
@@ -357,7 +361,7 @@ def main():
     # per-kernel breakdown: one more step, outside the timed region, with every
     # event kernel timed
     bctx = mcx.Context(prob, device=0, block_size=a.block, tail_threshold=a.tail,
-                       time_kernels=True, flights=a.flights)
+                       time_kernels=True, flights=a.flights, rounds=a.rounds)
     bctx.run()
     brk = bctx.timing()
     bctx.close()

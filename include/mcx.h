@@ -147,6 +147,13 @@ typedef struct {
   int32_t time_stride;      /* with time_kernels: time the launches of generations
                                g % time_stride == 0 only (the timing events of the
                                others are left out); 0 or 1 = every generation */
+  int32_t rounds;           /* event engine (multigroup): particles per thread of an
+                               advance block.  1 = one particle per thread; r > 1: a
+                               block owns r x block_size particles and a lane whose
+                               particle stops takes the next one, so lanes do not idle
+                               behind the wave's longest chain of crossings
+                               (r x block_size <= 4096).  Results are identical for
+                               every value.  0 = default */
 } mcx_options;
 
 /* Lattice of pin universes (paper Sec. 1: CSG geometry).  Cell (i, j),

@@ -29,6 +29,7 @@ constexpr int DEFAULT_TAIL = 4096;
 constexpr int DEFAULT_LOOKAHEAD = 4;
 constexpr int64_t DEFAULT_MAX_EVENTS = 100000;
 constexpr int DEFAULT_FLIGHTS = 8;
+constexpr int DEFAULT_ROUNDS = 1;
 // polls (about a microsecond each) before a wait of the asynchronous engine
 // gives up and reports an error
 constexpr uint64_t ASYNC_SPIN_LIMIT = 1ull << 22;
@@ -262,6 +263,11 @@ int mcx_create(mcx_ctx** out, const mcx_options* opt) {
   if (c->opt.lookahead > RING - 2) c->opt.lookahead = RING - 2;
   if (c->opt.max_events <= 0) c->opt.max_events = DEFAULT_MAX_EVENTS;
   if (c->opt.flights == 0) c->opt.flights = DEFAULT_FLIGHTS;
+  if (c->opt.rounds == 0) c->opt.rounds = DEFAULT_ROUNDS;
+  if (c->opt.rounds < 1 || c->opt.rounds * c->opt.block_size > 4096) {
+    delete c;
+    return MCX_EINVAL;
+  }
   if (c->opt.flights < 0 || c->opt.flights > 65536) {
     delete c;
     return MCX_EINVAL;
@@ -1289,6 +1295,12 @@ static int run_generation(mcx_ctx* c, int gen) {
                                    c->d.bank[1 - cur], c->d.cnt_live + it + 1, c->d.bank[2],
                                    c->d.cnt_col + it, A, c->d.R, c->d.cnt_live + it + 2,
                                    c->d.cnt_col + it + 1, bound, block, s));
+    else if (c->opt.rounds > 1)
+      HIP_TRY(c, launch_advance_refill(prec, rec, T, gen, fl, (uint32_t)c->opt.rounds,
+                                       c->d.bank[cur], c->d.cnt_live + it, c->d.bank[1 - cur],
+                                       c->d.cnt_live + it + 1, c->d.bank[2], c->d.cnt_col + it, A,
+                                       c->d.R, c->d.cnt_live + it + 2, c->d.cnt_col + it + 1,
+                                       bound, block, s));
     else
       HIP_TRY(c, launch_advance(prec, rec, T, gen, fl, c->d.bank[cur], c->d.cnt_live + it,
                                 c->d.bank[1 - cur], c->d.cnt_live + it + 1, c->d.bank[2],

@@ -118,6 +118,139 @@ __global__ void __launch_bounds__(1024) k_advance(Tables T0, uint32_t gen, uint3
   wave_count(A.cnt + CNT_ADV_SEGS * STRIPES, c_seg);
 }
 
+// Advance with lanes refilled from the block's chunk of the input bank.
+// Block b owns items [b C, (b + 1) C), C = rounds x blockDim.  A lane runs
+// its particle's flights (up to `flights`, stopping at a collision, a leak,
+// the census or the guard, exactly as k_advance does), then writes the
+// particle back to its input slot, marks the slot's outcome in LDS and takes
+// the next unstarted item of the chunk, so the wave's lanes stay busy until
+// the chunk runs out instead of idling behind the wave's longest chain of
+// crossings.  A wave takes new items only once at least REFILL_MIN of its
+// lanes are free (or none is busy), so each refill's loads serve many lanes.
+// At the end the block appends the chunk's survivors to the live and
+// collision banks in slot order (one atomic per block and queue per pass).
+constexpr uint32_t REFILL_MIN = 16;
+constexpr uint32_t ADV_CHUNK_MAX = 4096;  // rounds x blockDim
+enum : uint8_t { OUT_NONE = 0, OUT_LIVE = 1, OUT_COL = 2 };
+
+template <class R, bool REC, bool LDS>
+__global__ void __launch_bounds__(1024) k_advance_r(Tables T0, uint32_t gen, uint32_t flights,
+                                                    uint32_t rounds, Bank in,
+                                                    const uint32_t* __restrict__ n_in_p,
+                                                    Bank live, uint32_t* n_live, Bank col,
+                                                    uint32_t* n_col, Accum A, Records Rc,
+                                                    uint32_t* clr_live, uint32_t* clr_col) {
+  const uint32_t n_in = *n_in_p;
+  const uint32_t C = rounds * blockDim.x;
+  const uint32_t base = blockIdx.x * C;
+  const Tables T = kernel_tables<R, LDS>(T0, base < n_in);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *clr_live = 0;
+    *clr_col = 0;
+  }
+  const uint32_t n_chunk = base < n_in ? min(C, n_in - base) : 0u;
+  __shared__ uint32_t next;
+  __shared__ uint8_t outcome[ADV_CHUNK_MAX];
+  if (threadIdx.x == 0) next = blockDim.x;
+  __syncthreads();
+
+  uint32_t c_seg = 0, c_cross = 0, c_refl = 0, c_leak = 0, c_kill = 0, c_cen = 0, c_items = 0;
+  uint32_t my = threadIdx.x;
+  bool have = my < n_chunk;
+  Part<R> p;
+  Stream rs(T.seed, TAG_TRANSPORT, 0, gen, T.prob, 0);
+  uint32_t fl = 0;
+  if (have) {
+    p = load_part<R>(in, base + my);
+    rs = Stream(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
+    c_items += 1;
+  }
+  const uint32_t lane = lane_id();
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  while (__ballot(have) != 0ull || next < n_chunk) {
+    if (have) {
+      int ev;
+      bool refl = false;
+      if ((int64_t)p.nseg >= T.max_events) {
+        ev = EV_KILL;
+      } else {
+        ev = segment<R, REC, false>(T, T.geo, p, rs, A, Rc, &refl);
+        p.nseg += 1;
+        c_seg += 1;
+        fl += 1;
+        c_cross += (ev == EV_CROSS || ev == EV_LEAK) ? 1u : 0u;
+        c_refl += refl ? 1u : 0u;
+      }
+      if (ev != EV_CROSS || fl >= flights) {
+        // the particle is done for this launch
+        p.ctr = rs.draw;
+        uint8_t o = OUT_NONE;
+        if (ev == EV_KILL) {
+          die<R, REC>(p, FATE_KILLED, A, Rc);
+          c_kill += 1;
+        } else if (ev == EV_LEAK) {
+          die<R, REC>(p, FATE_LEAKED, A, Rc);
+          c_leak += 1;
+        } else if (ev == EV_CENSUS) {
+          die<R, REC>(p, FATE_CENSUS, A, Rc);
+          c_cen += 1;
+        } else {
+          store_part(in, base + my, p);
+          o = ev == EV_COLLIDE ? OUT_COL : OUT_LIVE;
+        }
+        outcome[my] = o;
+        have = false;
+      }
+    }
+    // refill the free lanes from the chunk, one LDS atomic per wave
+    const unsigned long long free_mask = __ballot(!have);
+    const uint32_t n_free = (uint32_t)__popcll(free_mask);
+    if (n_free >= REFILL_MIN || n_free == 64u) {
+      uint32_t first = 0;
+      const int leader = __ffsll((long long)free_mask) - 1;
+      if ((int)lane == leader) first = atomicAdd(&next, n_free);
+      first = __shfl(first, leader);
+      if (first >= n_chunk) {
+        if (n_free == 64u) break;  // nothing left for this wave
+      } else if (!have) {
+        const uint32_t item = first + (uint32_t)__popcll(free_mask & lt);
+        if (item < n_chunk) {
+          my = item;
+          have = true;
+          fl = 0;
+          p = load_part<R>(in, base + my);
+          rs = Stream(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
+          c_items += 1;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // survivors of the chunk, in slot order, to the live and collision banks
+  __shared__ uint32_t lds[2 * (MAX_WAVES + 1)];
+  for (uint32_t r0 = 0; r0 < C; r0 += blockDim.x) {
+    const uint32_t li = r0 + threadIdx.x;
+    const uint8_t o = li < n_chunk ? outcome[li] : OUT_NONE;
+    uint32_t pl, pc;
+    block_append2(o == OUT_LIVE, o == OUT_COL, n_live, n_col, lds, &pl, &pc);
+    if (o != OUT_NONE) {
+      const Part<R> q = load_part<R>(in, base + li);
+      if (o == OUT_LIVE)
+        store_part(live, pl, q);
+      else
+        store_part(col, pc, q);
+    }
+  }
+  wave_count(A.cnt + CNT_SEG * STRIPES, c_seg);
+  wave_count(A.cnt + CNT_CROSS * STRIPES, c_cross);
+  wave_count(A.cnt + CNT_REFL * STRIPES, c_refl);
+  wave_count(A.cnt + CNT_LEAK * STRIPES, c_leak);
+  wave_count(A.cnt + CNT_KILLED * STRIPES, c_kill);
+  wave_count(A.cnt + CNT_CENSUS * STRIPES, c_cen);
+  wave_count(A.cnt + CNT_ADV_ITEMS * STRIPES, c_items);
+  wave_count(A.cnt + CNT_ADV_SEGS * STRIPES, c_seg);
+}
+
 // Process the collision bank: collision estimator, fission-bank append
 // (block-aggregated reservation), scatter to the live bank or absorb.
 template <class R, bool REC, bool LDS>
@@ -892,6 +1025,47 @@ hipError_t launch_advance(int prec, bool rec, const Tables& T, uint32_t gen, uin
     else
       advance_k<float, false>(g, b, lb, s, T, gen, flights, in, n_in, live, n_live, col, n_col,
                               A, Rc, clr_live, clr_col);
+  }
+  return hipGetLastError();
+}
+
+template <class R, bool REC>
+static void advance_r_k(dim3 g, dim3 b, size_t lb, hipStream_t s, const Tables& T, uint32_t gen,
+                        uint32_t flights, uint32_t rounds, const Bank& in, const uint32_t* n_in,
+                        const Bank& live, uint32_t* n_live, const Bank& col, uint32_t* n_col,
+                        const Accum& A, const Records& Rc, uint32_t* clr_live,
+                        uint32_t* clr_col) {
+  if (lb)
+    hipLaunchKernelGGL((k_advance_r<R, REC, true>), g, b, lb, s, T, gen, flights, rounds, in,
+                       n_in, live, n_live, col, n_col, A, Rc, clr_live, clr_col);
+  else
+    hipLaunchKernelGGL((k_advance_r<R, REC, false>), g, b, 0, s, T, gen, flights, rounds, in,
+                       n_in, live, n_live, col, n_col, A, Rc, clr_live, clr_col);
+}
+
+hipError_t launch_advance_refill(int prec, bool rec, const Tables& T, uint32_t gen,
+                                 uint32_t flights, uint32_t rounds, const Bank& in,
+                                 const uint32_t* n_in, const Bank& live, uint32_t* n_live,
+                                 const Bank& col, uint32_t* n_col, const Accum& A,
+                                 const Records& Rc, uint32_t* clr_live, uint32_t* clr_col,
+                                 uint32_t bound, int block, hipStream_t s) {
+  if (rounds < 1 || rounds * (uint32_t)block > ADV_CHUNK_MAX) return hipErrorInvalidValue;
+  const dim3 g(std::max(1u, nblk(bound, (unsigned)block * rounds))), b(block);
+  const size_t lb = mg_lds_bytes(prec, T);
+  if (prec == 0) {
+    if (rec)
+      advance_r_k<double, true>(g, b, lb, s, T, gen, flights, rounds, in, n_in, live, n_live, col,
+                                n_col, A, Rc, clr_live, clr_col);
+    else
+      advance_r_k<double, false>(g, b, lb, s, T, gen, flights, rounds, in, n_in, live, n_live,
+                                 col, n_col, A, Rc, clr_live, clr_col);
+  } else {
+    if (rec)
+      advance_r_k<float, true>(g, b, lb, s, T, gen, flights, rounds, in, n_in, live, n_live, col,
+                               n_col, A, Rc, clr_live, clr_col);
+    else
+      advance_r_k<float, false>(g, b, lb, s, T, gen, flights, rounds, in, n_in, live, n_live,
+                                col, n_col, A, Rc, clr_live, clr_col);
   }
   return hipGetLastError();
 }

@@ -25,6 +25,14 @@ hipError_t launch_advance(int prec, bool rec, const Tables& T, uint32_t gen, uin
                           uint32_t* n_live, const Bank& col, uint32_t* n_col, const Accum& A,
                           const Records& Rc, uint32_t* clr_live, uint32_t* clr_col,
                           uint32_t bound, int block, hipStream_t s);
+// advance with lanes refilled from a chunk of rounds x block items per
+// block (rounds x block <= 4096); results identical to launch_advance
+hipError_t launch_advance_refill(int prec, bool rec, const Tables& T, uint32_t gen,
+                                 uint32_t flights, uint32_t rounds, const Bank& in,
+                                 const uint32_t* n_in, const Bank& live, uint32_t* n_live,
+                                 const Bank& col, uint32_t* n_col, const Accum& A,
+                                 const Records& Rc, uint32_t* clr_live, uint32_t* clr_col,
+                                 uint32_t bound, int block, hipStream_t s);
 hipError_t launch_collide(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in,
                           const uint32_t* n_in, const Bank& live, uint32_t* n_live,
                           const Accum& A, const Records& Rc, uint32_t bound, int block,

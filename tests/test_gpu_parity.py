@@ -188,6 +188,37 @@ def test_launch_configuration_does_not_change_results(block, tail, look, flights
     assert np.array_equal(ref["records"], got["records"])
 
 
+@pytest.mark.parametrize("block,rounds,flights,prec", [(256, 2, 8, "fp64"), (256, 4, 8, "fp64"),
+                                                       (64, 64, 1, "fp64"), (1024, 4, 3, "fp64"),
+                                                       (128, 8, 65536, "fp64"),
+                                                       (256, 4, 8, "fp32")])
+def test_refilled_advance_gives_identical_results(block, rounds, flights, prec):
+    """The advance kernel whose lanes take the next particle of their block's
+    chunk when theirs stops: bit-identical generation results and records,
+    with ragged chunks (5000 histories), one-lane waves of work (one flight
+    per launch) and particles that never leave the kernel before a
+    collision."""
+    banner(f"refilled advance block={block} rounds={rounds} flights={flights} {prec}")
+    prob = P.lattice_17x17(n_per_gen=5000, n_gen=3, n_inactive=1)
+    ref = mcx.run(prob, record=True, precision=prec)
+    got = mcx.run(prob, record=True, block_size=block, rounds=rounds, flights=flights,
+                  precision=prec)
+    for k in ("gen_k", "gen_entropy", "gen_counts", "flux_mean", "prod_mean", "k_mean"):
+        assert np.array_equal(ref[k], got[k]), k
+    assert np.array_equal(ref["records"], got["records"])
+
+
+def test_refilled_advance_full_size_matches_oracle(oracle):
+    """1e6 histories, the first generation history by history against the
+    oracle, with the refilled advance kernel."""
+    banner("refilled advance: lattice 1e6 x 1 vs oracle")
+    prob = P.lattice_17x17(n_per_gen=1_000_000, n_gen=2, n_inactive=1)
+    g = mcx.run(prob, record=True, rounds=4)
+    o = oracle.run(P.with_run(prob, n_gen=1, n_inactive=0), records=True)
+    assert np.array_equal(g["gen_counts"][0], o["gen_counts"][0])
+    compare_records(g["records"][0], o["records"][0], "gen 0")
+
+
 def test_single_history_and_tiny_runs(oracle):
     """N = 63, 65 in the reflective one-material cell (k_inf = 1.2, so small
     populations survive), N = 1 as fixed-source batches, and N = 1 in the pin
