@@ -81,6 +81,9 @@ def parse():
     ap.add_argument("--rounds", type=int, default=0,
                     help="particles per thread of an advance block, refilled lanes "
                          "(0 = library default)")
+    ap.add_argument("--lds-tally-min", type=int, default=0,
+                    help="live-count bound from which an advance launch stages its flux tally "
+                         "in LDS (0 = library default, negative = never)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-gens", type=int, default=4,
                     help="generations of the headline lattice the CPU oracle runs (about 10 s)")
@@ -334,7 +337,7 @@ def main():
     # next one a little); the generations are statistically alike
     ctx = mcx.Context(prob, device=0, block_size=a.block, tail_threshold=a.tail,
                       time_kernels="advance", time_stride=TIME_STRIDE, flights=a.flights,
-                      rounds=a.rounds)
+                      rounds=a.rounds, lds_tally_min=a.lds_tally_min)
     for w in range(a.warmup):
         ctx.run()
         log(f"warmup {w + 1}/{a.warmup} done")
@@ -361,7 +364,8 @@ def main():
     # per-kernel breakdown: one more step, outside the timed region, with every
     # event kernel timed
     bctx = mcx.Context(prob, device=0, block_size=a.block, tail_threshold=a.tail,
-                       time_kernels=True, flights=a.flights, rounds=a.rounds)
+                       time_kernels=True, flights=a.flights, rounds=a.rounds,
+                       lds_tally_min=a.lds_tally_min)
     bctx.run()
     brk = bctx.timing()
     bctx.close()
@@ -473,7 +477,8 @@ def main():
                                f"vacuum boundary, {N} histories/gen x {G} gens ({NI} inactive), "
                                f"FP64 event-based",
                    "histories_per_step": N * G, "block_size": a.block or 256,
-                   "tail_threshold": a.tail or max(4096, N // 8),
+                   "tail_threshold": a.tail or min(131072, max(4096, N // 8)),
+                   "lds_tally_min": a.lds_tally_min or 524288,
                    "flights_per_advance_launch": a.flights or 8},
         "events_per_s": round(segs / elapsed, 1),
         "segments_per_history": round(segs / histories, 4),

@@ -93,8 +93,8 @@ typedef struct {
   int32_t block_size;       /* threads per block of the event kernels, multiple of 64; 0 = 256 */
   int32_t tail_threshold;   /* live-particle count at or below which one history-based
                                kernel finishes the generation; 0 = default
-                               (max(4096, n_per_gen / 8)); negative = event kernels
-                               until every history ends */
+                               (n_per_gen / 8 within [4096, 131072]); negative = event
+                               kernels until every history ends */
   int32_t lookahead;        /* event iterations enqueued ahead of the last live count
                                read back; 0 = default (4) */
   int64_t max_events;       /* per-history segment guard; 0 = 100000 */
@@ -154,6 +154,13 @@ typedef struct {
                                behind the wave's longest chain of crossings
                                (r x block_size <= 4096).  Results are identical for
                                every value.  0 = default */
+  int32_t lds_tally_min;    /* event engine (multigroup, tables small enough for LDS): an
+                               advance launch whose live-count bound is at least this
+                               stages its flux tally in LDS (each 1024-thread block keeps
+                               16 B per tally bin and adds every bin to device memory once,
+                               instead of one device atomic per flight) when the device's
+                               LDS per block holds it.  Results are identical either way.
+                               0 = default (2^19); negative = never */
 } mcx_options;
 
 /* Lattice of pin universes (paper Sec. 1: CSG geometry).  Cell (i, j),

@@ -26,10 +26,14 @@ namespace {
 
 constexpr int RING = 64;
 constexpr int DEFAULT_TAIL = 4096;
+constexpr int DEFAULT_TAIL_MAX = 1 << 17;  // the tail's serial chains, not its size, bound it
 constexpr int DEFAULT_LOOKAHEAD = 4;
 constexpr int64_t DEFAULT_MAX_EVENTS = 100000;
 constexpr int DEFAULT_FLIGHTS = 8;
 constexpr int DEFAULT_ROUNDS = 1;
+// live-count bound from which an advance launch stages its flux tally in LDS
+constexpr int32_t DEFAULT_LDS_TALLY_MIN = 1 << 19;
+constexpr int LT_BLOCK = 1024;  // threads per block of the LDS-staged advance kernel
 // polls (about a microsecond each) before a wait of the asynchronous engine
 // gives up and reports an error
 constexpr uint64_t ASYNC_SPIN_LIMIT = 1ull << 22;
@@ -184,6 +188,9 @@ struct mcx_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   int n_gen_max = 0;
+  // device limits for the LDS-staged advance kernel
+  int dev_cus = 256;
+  size_t lds_block_max = 65536;
   Dev d;
 
   // results of the last run
@@ -258,11 +265,12 @@ int mcx_create(mcx_ctx** out, const mcx_options* opt) {
     delete c;
     return MCX_EINVAL;
   }
-  // tail_threshold == 0: N / 8, at least DEFAULT_TAIL (resolved per run)
+  // tail_threshold == 0: N / 8 within [DEFAULT_TAIL, DEFAULT_TAIL_MAX] (resolved per run)
   if (c->opt.lookahead <= 0) c->opt.lookahead = DEFAULT_LOOKAHEAD;
   if (c->opt.lookahead > RING - 2) c->opt.lookahead = RING - 2;
   if (c->opt.max_events <= 0) c->opt.max_events = DEFAULT_MAX_EVENTS;
   if (c->opt.flights == 0) c->opt.flights = DEFAULT_FLIGHTS;
+  if (c->opt.lds_tally_min == 0) c->opt.lds_tally_min = DEFAULT_LDS_TALLY_MIN;
   if (c->opt.rounds == 0) c->opt.rounds = DEFAULT_ROUNDS;
   if (c->opt.rounds < 1 || c->opt.rounds * c->opt.block_size > 4096) {
     delete c;
@@ -290,7 +298,11 @@ int mcx_create(mcx_ctx** out, const mcx_options* opt) {
   {
     int dev_cus = 256;
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, c->opt.device) == hipSuccess) dev_cus = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, c->opt.device) == hipSuccess) {
+      dev_cus = prop.multiProcessorCount;
+      c->lds_block_max = prop.sharedMemPerBlock;
+    }
+    c->dev_cus = dev_cus;
     c->pcfg.block = c->opt.p_block ? c->opt.p_block : 256;
     c->pcfg.slots = c->opt.p_slots ? c->opt.p_slots : 512;
     c->pcfg.grid = c->opt.p_grid ? c->opt.p_grid : 2 * dev_cus;
@@ -1254,9 +1266,18 @@ static int run_generation(mcx_ctx* c, int gen) {
   const int64_t tail = mono ? 0
                             : c->opt.tail_threshold != 0
                                   ? (int64_t)c->opt.tail_threshold
-                                  : std::max<int64_t>(DEFAULT_TAIL, (int64_t)N / 8);
+                                  : std::min<int64_t>(DEFAULT_TAIL_MAX,
+                                                      std::max<int64_t>(DEFAULT_TAIL, (int64_t)N / 8));
   int cur = 0;
   const int block = c->opt.block_size;
+  // the LDS-staged advance kernel: multigroup tables in LDS plus 16 B per
+  // tally bin in one block's LDS; as many 1024-thread blocks as are resident
+  int lt_grid = 0;
+  if (!ce && !mono && c->opt.lds_tally_min > 0) {
+    const size_t lb = advance_lt_lds_bytes(prec, T);
+    if (lb > 0 && lb <= c->lds_block_max)
+      lt_grid = c->dev_cus * advance_lt_blocks_per_cu(prec, rec, LT_BLOCK, lb);
+  }
   for (;;) {
     if (bound == 0) break;
     // every live particle makes at least one flight per iteration, so after
@@ -1295,6 +1316,11 @@ static int run_generation(mcx_ctx* c, int gen) {
                                    c->d.bank[1 - cur], c->d.cnt_live + it + 1, c->d.bank[2],
                                    c->d.cnt_col + it, A, c->d.R, c->d.cnt_live + it + 2,
                                    c->d.cnt_col + it + 1, bound, block, s));
+    else if (lt_grid > 0 && (int64_t)bound >= (int64_t)c->opt.lds_tally_min)
+      HIP_TRY(c, launch_advance_lt(prec, rec, T, gen, fl, c->d.bank[cur], c->d.cnt_live + it,
+                                   c->d.bank[1 - cur], c->d.cnt_live + it + 1, c->d.bank[2],
+                                   c->d.cnt_col + it, A, c->d.R, c->d.cnt_live + it + 2,
+                                   c->d.cnt_col + it + 1, bound, LT_BLOCK, lt_grid, s));
     else if (c->opt.rounds > 1)
       HIP_TRY(c, launch_advance_refill(prec, rec, T, gen, fl, (uint32_t)c->opt.rounds,
                                        c->d.bank[cur], c->d.cnt_live + it, c->d.bank[1 - cur],

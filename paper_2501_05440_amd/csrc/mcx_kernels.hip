@@ -118,6 +118,103 @@ __global__ void __launch_bounds__(1024) k_advance(Tables T0, uint32_t gen, uint3
   wave_count(A.cnt + CNT_ADV_SEGS * STRIPES, c_seg);
 }
 
+// Advance with the flux tally staged in LDS.  Each flight of k_advance adds
+// its exact fixed-point flux term to device memory with one atomic, and
+// those atomics (one per flight, executed beyond the compute unit) are what
+// bounds that kernel.  Here a block keeps its own flux words in LDS: per bin
+// the sums of the low and high 32-bit halves of its terms, added with LDS
+// atomics, and walks the input bank in chunks of blockDim particles
+// (grid-stride), so one block serves many particles.  At the end it adds
+// each nonzero bin to the bin's 128-bit device pair once (the exact sum
+// lo + hi 2^32 of the block's terms).  Every other operation is k_advance's,
+// per chunk: particles still flying go to the live bank, colliding ones to
+// the collision bank (one atomic per block, queue and chunk).  The sums are
+// exact, so results equal k_advance's for any grid.  Needs the table copies
+// in LDS; the launcher sizes the dynamic LDS as tables + 16 B per bin.
+template <class R, bool REC>
+__global__ void __launch_bounds__(1024) k_advance_lt(Tables T0, uint32_t gen, uint32_t flights,
+                                                     Bank in, const uint32_t* __restrict__ n_in_p,
+                                                     Bank live, uint32_t* n_live, Bank col,
+                                                     uint32_t* n_col, Accum A, Records Rc,
+                                                     uint32_t* clr_live, uint32_t* clr_col) {
+  const uint32_t n_in = *n_in_p;
+  const bool any = blockIdx.x * blockDim.x < n_in;
+  const Tables T = kernel_tables<R, true>(T0, any);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *clr_live = 0;
+    *clr_col = 0;
+  }
+  if (!any) return;  // the whole block
+  unsigned long long* tw = lds_tally(T);
+  const uint32_t nw = 2u * (uint32_t)T.n_bins;
+  for (uint32_t w = threadIdx.x; w < nw; w += blockDim.x) tw[w] = 0ull;
+  __syncthreads();
+
+  uint32_t c_seg = 0, c_cross = 0, c_refl = 0, c_leak = 0, c_kill = 0, c_cen = 0, c_items = 0;
+  __shared__ uint32_t lds[2 * (MAX_WAVES + 1)];
+  const uint32_t step = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n_in; base += step) {
+    const uint32_t k = base + threadIdx.x;
+    int ev = EV_NONE;
+    Part<R> p;
+    if (k < n_in) {
+      c_items += 1;
+      p = load_part<R>(in, k);
+      Stream rs(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
+      for (uint32_t f = 0; f < flights; ++f) {
+        if ((int64_t)p.nseg >= T.max_events) {
+          ev = EV_KILL;
+          break;
+        }
+        bool refl = false;
+        ev = segment<R, REC, false, Stream, true>(T, T.geo, p, rs, A, Rc, &refl);
+        p.nseg += 1;
+        c_seg += 1;
+        c_cross += (ev == EV_CROSS || ev == EV_LEAK) ? 1u : 0u;
+        c_refl += refl ? 1u : 0u;
+        if (ev != EV_CROSS) break;
+      }
+      p.ctr = rs.draw;
+      if (ev == EV_KILL) {
+        die<R, REC>(p, FATE_KILLED, A, Rc);
+        c_kill += 1;
+      }
+      if (ev == EV_LEAK) {
+        die<R, REC>(p, FATE_LEAKED, A, Rc);
+        c_leak += 1;
+      }
+      if (ev == EV_CENSUS) {
+        die<R, REC>(p, FATE_CENSUS, A, Rc);
+        c_cen += 1;
+      }
+    }
+    uint32_t pl, pc;
+    block_append2(ev == EV_CROSS, ev == EV_COLLIDE, n_live, n_col, lds, &pl, &pc);
+    if (ev == EV_CROSS) store_part(live, pl, p);
+    if (ev == EV_COLLIDE) store_part(col, pc, p);
+  }
+  wave_count(A.cnt + CNT_SEG * STRIPES, c_seg);
+  wave_count(A.cnt + CNT_CROSS * STRIPES, c_cross);
+  wave_count(A.cnt + CNT_REFL * STRIPES, c_refl);
+  wave_count(A.cnt + CNT_LEAK * STRIPES, c_leak);
+  wave_count(A.cnt + CNT_KILLED * STRIPES, c_kill);
+  wave_count(A.cnt + CNT_CENSUS * STRIPES, c_cen);
+  wave_count(A.cnt + CNT_ADV_ITEMS * STRIPES, c_items);
+  wave_count(A.cnt + CNT_ADV_SEGS * STRIPES, c_seg);
+  __syncthreads();
+  // one exact 128-bit add per nonzero bin into this block's stripe
+  unsigned long long* tb =
+      A.tally + (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
+  for (uint32_t b = threadIdx.x; b < (uint32_t)T.n_bins; b += blockDim.x) {
+    const unsigned long long lo = tw[2 * b], hi = tw[2 * b + 1];
+    if ((lo | hi) == 0ull) continue;
+    // lo + hi 2^32 as (w1, w0)
+    const unsigned long long w0 = lo + (hi << 32);
+    const unsigned long long w1 = (hi >> 32) + (w0 < lo ? 1ull : 0ull);
+    acc_add128(tb + 2 * b, w0, w1);
+  }
+}
+
 // Advance with lanes refilled from the block's chunk of the input bank.
 // Block b owns items [b C, (b + 1) C), C = rounds x blockDim.  A lane runs
 // its particle's flights (up to `flights`, stopping at a collision, a leak,
@@ -1025,6 +1122,66 @@ hipError_t launch_advance(int prec, bool rec, const Tables& T, uint32_t gen, uin
     else
       advance_k<float, false>(g, b, lb, s, T, gen, flights, in, n_in, live, n_live, col, n_col,
                               A, Rc, clr_live, clr_col);
+  }
+  return hipGetLastError();
+}
+
+template <class R, bool REC>
+static void advance_lt_k(dim3 g, dim3 b, size_t lb, hipStream_t s, const Tables& T, uint32_t gen,
+                         uint32_t flights, const Bank& in, const uint32_t* n_in, const Bank& live,
+                         uint32_t* n_live, const Bank& col, uint32_t* n_col, const Accum& A,
+                         const Records& Rc, uint32_t* clr_live, uint32_t* clr_col) {
+  hipLaunchKernelGGL((k_advance_lt<R, REC>), g, b, lb, s, T, gen, flights, in, n_in, live, n_live,
+                     col, n_col, A, Rc, clr_live, clr_col);
+}
+
+// Resident blocks per compute unit of the LDS-staged advance kernel for this
+// block size and LDS size (registers and LDS), at least 1.
+int advance_lt_blocks_per_cu(int prec, bool rec, int block, size_t lds) {
+  int n = 0;
+  hipError_t e;
+  if (prec == 0)
+    e = rec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_advance_lt<double, true>, block, lds)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_advance_lt<double, false>, block, lds);
+  else
+    e = rec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_advance_lt<float, true>, block, lds)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_advance_lt<float, false>, block, lds);
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+size_t advance_lt_lds_bytes(int prec, const Tables& T) {
+  const size_t tb = mg_lds_bytes(prec, T);
+  if (tb == 0) return 0;
+  return ((tb + 15) & ~(size_t)15) + 16 * (size_t)T.n_bins;
+}
+
+hipError_t launch_advance_lt(int prec, bool rec, const Tables& T0, uint32_t gen, uint32_t flights,
+                             const Bank& in, const uint32_t* n_in, const Bank& live,
+                             uint32_t* n_live, const Bank& col, uint32_t* n_col, const Accum& A,
+                             const Records& Rc, uint32_t* clr_live, uint32_t* clr_col,
+                             uint32_t bound, int block, int max_grid, hipStream_t s) {
+  const size_t tb = mg_lds_bytes(prec, T0);
+  if (tb == 0 || T0.probs || T0.ce || block < 64 || block > 1024 || block % 64 || max_grid < 1)
+    return hipErrorInvalidValue;
+  Tables T = T0;
+  T.lds_tally_off = (uint32_t)((tb + 15) & ~(size_t)15);
+  const size_t lb = advance_lt_lds_bytes(prec, T0);
+  const unsigned nb = std::max(1u, nblk(bound, (unsigned)block));
+  const dim3 g(std::min(nb, (unsigned)max_grid)), b(block);
+  if (prec == 0) {
+    if (rec)
+      advance_lt_k<double, true>(g, b, lb, s, T, gen, flights, in, n_in, live, n_live, col, n_col,
+                                 A, Rc, clr_live, clr_col);
+    else
+      advance_lt_k<double, false>(g, b, lb, s, T, gen, flights, in, n_in, live, n_live, col,
+                                  n_col, A, Rc, clr_live, clr_col);
+  } else {
+    if (rec)
+      advance_lt_k<float, true>(g, b, lb, s, T, gen, flights, in, n_in, live, n_live, col, n_col,
+                                A, Rc, clr_live, clr_col);
+    else
+      advance_lt_k<float, false>(g, b, lb, s, T, gen, flights, in, n_in, live, n_live, col,
+                                 n_col, A, Rc, clr_live, clr_col);
   }
   return hipGetLastError();
 }

@@ -343,13 +343,45 @@ __device__ __forceinline__ void die(const Part<R>& p, int fate, const Accum& A,
   }
 }
 
+// The block's staged flux words in dynamic LDS (after the table copies):
+// per bin the sums of the low and of the high 32-bit halves of its terms.
+__device__ __forceinline__ unsigned long long* lds_tally(const Tables& T) {
+  extern __shared__ __align__(16) char lds_tab[];
+  return reinterpret_cast<unsigned long long*>(lds_tab + T.lds_tally_off);
+}
+
+// One exact fixed-point flux term q (< 2^61) of bin `bin`.  TLDS: into the
+// block's LDS words as two 32-bit halves (LDS atomics, flushed once per
+// block); HALVES: the same halves as two non-returning atomics on the global
+// half words; otherwise one returning 64-bit atomic on a 128-bit pair with a
+// carry word.
+template <bool HALVES, bool TLDS>
+__device__ __forceinline__ void flux_term(const Tables& T, unsigned long long* tb,
+                                          unsigned long long* tt, int bin, uint64_t q) {
+  if constexpr (TLDS) {
+    if (q) {
+      unsigned long long* w = lds_tally(T);
+      atomicAdd(w + 2 * bin, (unsigned long long)(q & 0xFFFFFFFFull));
+      atomicAdd(w + 2 * bin + 1, (unsigned long long)(q >> 32));
+    }
+  } else if constexpr (HALVES) {
+    if (q) {
+      atomicAdd(tt + 2 * bin, (unsigned long long)(q & 0xFFFFFFFFull));
+      atomicAdd(tt + 2 * bin + 1, (unsigned long long)(q >> 32));
+    }
+  } else {
+    acc_add(tb + 2 * bin, q);
+  }
+}
+
 // One flight: cross-section lookup, distance to collision, distance to the
 // bounding surfaces, move, track-length tally, and the surface crossing if
 // the boundary comes first.  Returns EV_COLLIDE, EV_CROSS or EV_LEAK.
 // HALVES: add the flux term as two non-returning 32-bit-half atomics (the
 // tail kernel, where a returning atomic's latency is not hidden by other
-// waves); otherwise one returning 64-bit atomic with a carry word.
-template <class R, bool REC, bool HALVES, class S = Stream>
+// waves); TLDS: into the block's LDS flux words; otherwise one returning
+// 64-bit atomic with a carry word.
+template <class R, bool REC, bool HALVES, class S = Stream, bool TLDS = false>
 __device__ __forceinline__ int segment(const Tables& T, const Geo& L, Part<R>& p, S& rs,
                                        const Accum& A, const Records& Rc, bool* refl_out) {
   const XSView<R> X = xs_view<R>(T);
@@ -422,29 +454,13 @@ __device__ __forceinline__ int segment(const Tables& T, const Geo& L, Part<R>& p
       const double lo = e0 > p.t ? e0 : p.t;
       const double hi = e1 < t1 ? e1 : t1;
       if (hi > lo) {
-        const uint64_t q = quantize((hi - lo) * vg, T.q_flux);
-        if (HALVES) {
-          if (q) {
-            atomicAdd(tt + 2 * (bin + b), (unsigned long long)(q & 0xFFFFFFFFull));
-            atomicAdd(tt + 2 * (bin + b) + 1, (unsigned long long)(q >> 32));
-          }
-        } else {
-          acc_add(tb + 2 * (bin + b), q);
-        }
+        flux_term<HALVES, TLDS>(T, tb, tt, bin + b, quantize((hi - lo) * vg, T.q_flux));
       }
       if (e1 >= t1) break;
     }
     p.t = t1;
   } else {
-    const uint64_t qf = quantize(d, T.q_flux);
-    if (HALVES) {
-      if (qf) {
-        atomicAdd(tt + 2 * bin, (unsigned long long)(qf & 0xFFFFFFFFull));
-        atomicAdd(tt + 2 * bin + 1, (unsigned long long)(qf >> 32));
-      }
-    } else {
-      acc_add(tb + 2 * bin, qf);
-    }
+    flux_term<HALVES, TLDS>(T, tb, tt, bin, quantize(d, T.q_flux));
   }
   int k_ev = 0;
   if (REC) {

@@ -25,6 +25,18 @@ hipError_t launch_advance(int prec, bool rec, const Tables& T, uint32_t gen, uin
                           uint32_t* n_live, const Bank& col, uint32_t* n_col, const Accum& A,
                           const Records& Rc, uint32_t* clr_live, uint32_t* clr_col,
                           uint32_t bound, int block, hipStream_t s);
+// advance with the flux tally staged in LDS: blocks of `block` threads walk
+// the bank grid-stride (at most max_grid blocks) and add each bin to device
+// memory once; results identical to launch_advance.  Multigroup, tables in
+// LDS; advance_lt_lds_bytes gives its dynamic LDS per block (0: tables do
+// not fit)
+size_t advance_lt_lds_bytes(int prec, const Tables& T);
+int advance_lt_blocks_per_cu(int prec, bool rec, int block, size_t lds);
+hipError_t launch_advance_lt(int prec, bool rec, const Tables& T, uint32_t gen, uint32_t flights,
+                             const Bank& in, const uint32_t* n_in, const Bank& live,
+                             uint32_t* n_live, const Bank& col, uint32_t* n_col, const Accum& A,
+                             const Records& Rc, uint32_t* clr_live, uint32_t* clr_col,
+                             uint32_t bound, int block, int max_grid, hipStream_t s);
 // advance with lanes refilled from a chunk of rounds x block items per
 // block (rounds x block <= 4096); results identical to launch_advance
 hipError_t launch_advance_refill(int prec, bool rec, const Tables& T, uint32_t gen,

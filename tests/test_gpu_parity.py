@@ -219,6 +219,41 @@ def test_refilled_advance_full_size_matches_oracle(oracle):
     compare_records(g["records"][0], o["records"][0], "gen 0")
 
 
+@pytest.mark.parametrize("flights,prec,n", [(8, "fp64", 5000), (1, "fp64", 5000),
+                                           (65536, "fp64", 3001), (8, "fp32", 5000),
+                                           (3, "fp64", 70001)])
+def test_lds_tally_advance_gives_identical_results(flights, prec, n):
+    """The advance kernel that stages the flux tally in LDS (every launch
+    forced onto it) against the one that adds every flight to device memory:
+    bit-identical generation results, tallies and records, for ragged last
+    chunks, one flight per launch, uncapped flights, FP32-mixed, and more
+    particles than the grid holds at once (grid-stride chunks)."""
+    banner(f"LDS-staged tally advance flights={flights} {prec} n={n}")
+    prob = P.lattice_17x17(n_per_gen=n, n_gen=3, n_inactive=1)
+    ref = mcx.run(prob, record=True, precision=prec, lds_tally_min=-1, flights=flights)
+    got = mcx.run(prob, record=True, precision=prec, lds_tally_min=1, flights=flights)
+    for k in ("gen_k", "gen_entropy", "gen_counts", "flux_mean", "prod_mean", "k_mean",
+              "flux_sigma", "prod_sigma"):
+        assert np.array_equal(ref[k], got[k]), k
+    assert np.array_equal(ref["records"], got["records"])
+
+
+def test_lds_tally_advance_full_size_matches_oracle(oracle):
+    """1e6 histories with every advance launch on the LDS-staged tally
+    kernel: the first generation history by history, its event counts and
+    its per-bin flux and production tallies against the oracle."""
+    banner("LDS-staged tally advance: lattice 1e6 x 1 vs oracle")
+    prob = P.lattice_17x17(n_per_gen=1_000_000, n_gen=2, n_inactive=1)
+    g = mcx.run(prob, record=True, lds_tally_min=1, per_gen_tallies=True)
+    o = oracle.run(P.with_run(prob, n_gen=1, n_inactive=0), records=True, per_gen_tallies=True)
+    assert np.array_equal(g["gen_counts"][0], o["gen_counts"][0])
+    compare_records(g["records"][0], o["records"][0], "gen 0")
+    af = flux_atol(g, prob)
+    assert_close(g["gen_flux"][0], o["gen_flux"][0], what="gen 0 flux", atol=af)
+    assert_close(g["gen_prod"][0], o["gen_prod"][0], what="gen 0 production",
+                 atol=af * float(np.max(prob["xs"]["nu_sig_f"])))
+
+
 def test_single_history_and_tiny_runs(oracle):
     """N = 63, 65 in the reflective one-material cell (k_inf = 1.2, so small
     populations survive), N = 1 as fixed-source batches, and N = 1 in the pin
