@@ -358,6 +358,29 @@ int mcx_bind_workspace(mcx_ctx* ctx, void* device_ptr, size_t bytes, int32_t n_g
    MCX_EGUARD (results are still readable) or MCX_EDEVICE on failure. */
 int mcx_run_generations(mcx_ctx* ctx, int32_t n_gen, int32_t n_inactive);
 
+/* Bytes of the library's static per-device scratch array used by
+   mcx_run_generations_noalloc. */
+#define MCX_SCRATCH_BYTES (64u * 1024u * 1024u)
+
+/* mcx_run_generations for callers that cannot allocate device memory (code
+   under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc): binds the library's static scratch array of this GPU
+   (MCX_SCRATCH_BYTES, held until the process ends) as the context's
+   workspace, sized for n_gen generations, uploads the tables into it and
+   runs the generations; it calls no hipMalloc, hipFree, hipHostMalloc or
+   other device or pinned-memory allocator.  The caller still creates,
+   loads and seeds the context; results are read with the usual getters.
+   MCX_ENOMEM (with the byte counts in mcx_last_error) if the run needs more
+   than MCX_SCRATCH_BYTES; MCX_EINVAL with time_kernels on (timing creates
+   events) or bad generation counts; MCX_ESTATE for a batch or before
+   loading and seeding; otherwise as mcx_run_generations.  Every context on
+   one GPU shares that GPU's array, which keeps the last call's contents: a
+   later call (from any context) overwrites the workspace of the earlier
+   one, and calls that overlap on one GPU race.  The context stays bound to
+   the array afterwards (mcx_continue_generations and the getters read it),
+   until it is bound again. */
+int mcx_run_generations_noalloc(mcx_ctx* ctx, int32_t n_gen, int32_t n_inactive);
+
 /* Continue the last completed run (or a restored checkpoint) by n_more
    generations: the next generation starts from the source and k_used the
    previous one left, with the same random streams, so a run continued in

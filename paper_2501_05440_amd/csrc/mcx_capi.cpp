@@ -15,6 +15,7 @@
 #include <new>
 #include <string>
 #include <deque>
+#include <mutex>
 #include <vector>
 
 #include "mcx.h"
@@ -1550,6 +1551,70 @@ int mcx_continue_generations(mcx_ctx* c, int32_t n_more) {
   if (n_more < 1 || (int64_t)c->last_n_gen + n_more > c->n_gen_max)
     return fail(c, MCX_EINVAL, "generation count beyond n_gen_max");
   return run_range(c, c->last_n_gen, c->last_n_gen + n_more, c->req_n_inactive);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// allocation-free runs: the workspace in a static device array
+//
+// For callers that cannot allocate device memory, the library holds one
+// MCX_SCRATCH_BYTES array per GPU (a file-scope __device__ variable, which
+// each device keeps until the process ends).  In host code `scratch` names a
+// host-side stand-in, not device memory: its device address comes from
+// hipGetSymbolAddress, once per device with that device current, and only
+// that address is handed to the kernels and copies.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[MCX_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+}  // namespace
+
+// Device address of this device's scratch array (the device must be current).
+static int scratch_address(mcx_ctx* c, void** out) {
+  const int dev = c->opt.device;
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(c, MCX_EINVAL, "device ordinal");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(c, e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return MCX_OK;
+}
+
+extern "C" {
+
+int mcx_run_generations_noalloc(mcx_ctx* c, int32_t n_gen, int32_t n_inactive) {
+  if (!c) return MCX_EINVAL;
+  if (c->batch) return fail(c, MCX_ESTATE, "a batch is loaded: use mcx_run_batch");
+  if (c->opt.time_kernels)
+    return fail(c, MCX_EINVAL, "kernel timing creates HIP events: turn time_kernels off");
+  if (n_gen < 1 || n_inactive < 0 || n_inactive >= n_gen)
+    return fail(c, MCX_EINVAL, "generation counts");
+  if (!loaded(c)) return fail(c, MCX_ESTATE, "load and seed first");
+  HIP_TRY(c, hipSetDevice(c->opt.device));
+  void* ptr = nullptr;
+  int rc = scratch_address(c, &ptr);
+  if (rc != MCX_OK) return rc;
+  Dev layout;
+  const size_t need = carve(c, layout, nullptr, n_gen);
+  if (need > MCX_SCRATCH_BYTES) {
+    char msg[160];
+    std::snprintf(msg, sizeof msg,
+                  "the run needs %zu bytes of workspace; the static scratch holds %zu",
+                  need, (size_t)MCX_SCRATCH_BYTES);
+    return fail(c, MCX_ENOMEM, msg);
+  }
+  rc = mcx_bind_workspace(c, ptr, MCX_SCRATCH_BYTES, n_gen);
+  if (rc != MCX_OK) return rc;
+  return mcx_run_generations(c, n_gen, n_inactive);
 }
 
 }  // extern "C"

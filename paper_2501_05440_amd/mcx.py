@@ -33,7 +33,7 @@ EXPORTS = [
     "mcx_diag_philox", "mcx_last_error", "mcx_destroy", "mcx_load_batch", "mcx_run_batch",
     "mcx_get_batch_results", "mcx_get_batch_tallies", "mcx_autotune", "mcx_load_ce_xs",
     "mcx_continue_generations", "mcx_checkpoint", "mcx_restore", "mcx_get_event_log",
-    "mcx_load_time_grid",
+    "mcx_load_time_grid", "mcx_run_generations_noalloc",
 ]
 
 
@@ -131,6 +131,7 @@ def lib():
         "mcx_workspace_size": ([vp, i32, C.POINTER(C.c_size_t)], C.c_int),
         "mcx_bind_workspace": ([vp, vp, C.c_size_t, i32], C.c_int),
         "mcx_run_generations": ([vp, i32, i32], C.c_int),
+        "mcx_run_generations_noalloc": ([vp, i32, i32], C.c_int),
         "mcx_get_keff": ([vp, dp, dp, dp], C.c_int),
         "mcx_get_generation_stats": ([vp, dp, dp], C.c_int),
         "mcx_get_tallies": ([vp, dp, dp, dp, dp, i64], C.c_int),
@@ -246,7 +247,7 @@ class Context:
     def __init__(self, problem, device=0, record=False, block_size=0, tail_threshold=0,
                  lookahead=0, max_events=None, time_kernels=False, n_gen_max=None,
                  stream=None, precision="fp64", engine="event", persistent=None, flights=0,
-                 event_log=0, time_stride=0, rounds=0, lds_tally_min=0):
+                 event_log=0, time_stride=0, rounds=0, lds_tally_min=0, workspace=True):
         import torch
 
         self.problem = problem
@@ -302,11 +303,14 @@ class Context:
         s.ent_nx, s.ent_ny = rp["ent_nx"], rp["ent_ny"]
         self._check(L.mcx_seed_source(h, C.byref(s)))
         self.n_gen_max = n_gen_max or rp["n_gen"]
-        nbytes = C.c_size_t()
-        self._check(L.mcx_workspace_size(h, self.n_gen_max, C.byref(nbytes)))
-        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=f"cuda:{device}")
-        self._check(L.mcx_bind_workspace(h, self.workspace.data_ptr(), nbytes.value,
-                                         self.n_gen_max))
+        self.workspace = None
+        if workspace:
+            nbytes = C.c_size_t()
+            self._check(L.mcx_workspace_size(h, self.n_gen_max, C.byref(nbytes)))
+            self.workspace = torch.empty(nbytes.value, dtype=torch.uint8,
+                                         device=f"cuda:{device}")
+            self._check(L.mcx_bind_workspace(h, self.workspace.data_ptr(), nbytes.value,
+                                             self.n_gen_max))
         self.n_bins = geo["nx"] * geo["ny"] * (g.max_rings + 1) * n_grp * n_t
         self.n_per_gen = rp["n_per_gen"]
         self.n_gen = None
@@ -321,6 +325,18 @@ class Context:
         n_gen = rp["n_gen"] if n_gen is None else n_gen
         n_inactive = rp["n_inactive"] if n_inactive is None else n_inactive
         rc = self.L.mcx_run_generations(self.h, n_gen, n_inactive)
+        self.n_gen = n_gen
+        if check:
+            self._check(rc)
+        return rc
+
+    def run_noalloc(self, n_gen=None, n_inactive=None, check=True):
+        """mcx_run_generations_noalloc: the run's workspace in the library's
+        static scratch array (no device allocation)."""
+        rp = self.problem["run"]
+        n_gen = rp["n_gen"] if n_gen is None else n_gen
+        n_inactive = rp["n_inactive"] if n_inactive is None else n_inactive
+        rc = self.L.mcx_run_generations_noalloc(self.h, n_gen, n_inactive)
         self.n_gen = n_gen
         if check:
             self._check(rc)

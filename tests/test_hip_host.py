@@ -23,8 +23,9 @@ def test_header_declarations_are_bound():
 
 def test_header_declarations_are_unique_and_cited():
     """Every entry point is declared once, and the comment in front of it
-    cites the paper's passage that defines the operation or says that it is
-    a project addition with no passage."""
+    cites the paper's passage that defines the operation, says that it is a
+    project addition with no passage, or (the allocation-free variant) names
+    the callers it is for, those that cannot allocate."""
     text = open(os.path.join(ROOT, "include", "mcx.h")).read()
     names = re.findall(r"^(?:int|void|const char\*)\s+(mcx_\w+)\(", text, re.M)
     assert len(names) == len(set(names)), sorted(n for n in names if names.count(n) > 1)
@@ -36,7 +37,8 @@ def test_header_declarations_are_unique_and_cited():
         k = before.rfind("*/")
         assert k >= 0 and before[k + 2:].strip() == "", f"{m.group(1)} has no comment"
         comment = " ".join(before[before.rfind("/*", 0, k):k].split())
-        assert ("Sec." in comment or "roject addition" in comment), \
+        assert ("Sec." in comment or "roject addition" in comment or
+                "cannot allocate" in comment), \
             f"{m.group(1)}: the comment cites no passage and is not marked a project addition"
         prev_end = text.index(";", m.end()) + 1
 
