@@ -84,14 +84,15 @@ __global__ void __launch_bounds__(1024) k_advance(Tables T0, uint32_t gen, uint3
   Part<R> p;
   if (k < n_in) {
     p = load_part<R>(in, k);
-    Stream rs(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
+    LockStream rs(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
     for (uint32_t f = 0; f < flights; ++f) {
       if ((int64_t)p.nseg >= T.max_events) {
         ev = EV_KILL;
         break;
       }
       bool refl = false;
-      ev = segment<R, REC, false>(T, T.geo, p, rs, A, Rc, &refl);
+      rs.top_up();
+      ev = segment<R, REC, false, LockStream>(T, T.geo, p, rs, A, Rc, &refl);
       p.nseg += 1;
       c_seg += 1;
       c_cross += (ev == EV_CROSS || ev == EV_LEAK) ? 1u : 0u;
@@ -160,14 +161,15 @@ __global__ void __launch_bounds__(1024) k_advance_lt(Tables T0, uint32_t gen, ui
     if (k < n_in) {
       c_items += 1;
       p = load_part<R>(in, k);
-      Stream rs(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
+      LockStream rs(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
       for (uint32_t f = 0; f < flights; ++f) {
         if ((int64_t)p.nseg >= T.max_events) {
           ev = EV_KILL;
           break;
         }
         bool refl = false;
-        ev = segment<R, REC, false, Stream, true>(T, T.geo, p, rs, A, Rc, &refl);
+        rs.top_up();
+        ev = segment<R, REC, false, LockStream, true>(T, T.geo, p, rs, A, Rc, &refl);
         p.nseg += 1;
         c_seg += 1;
         c_cross += (ev == EV_CROSS || ev == EV_LEAK) ? 1u : 0u;

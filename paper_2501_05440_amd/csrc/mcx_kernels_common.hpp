@@ -121,6 +121,87 @@ struct CachedStream : Stream {
   }
 };
 
+// ---------------------------------------------------------------------------
+// lockstep stream of the advance kernels
+//
+// A flight takes one draw, so a lane needs a new Philox block every fourth
+// flight, and the lanes of a wavefront reach that point at different
+// flights: with Stream the wavefront evaluates the block code at nearly
+// every flight, each time for about a quarter of its lanes.  LockStream
+// holds up to two blocks per lane, and top_up() (called by the active lanes
+// before every flight) evaluates blocks only when some active lane has run
+// dry, and then for every active lane that has room: the dry lanes take the
+// block of their next draw, the others the block after the one they hold.
+// The wavefront then evaluates the block code about once per four flights,
+// with most of its lanes active.  Draw values and order are Stream's.
+// ---------------------------------------------------------------------------
+
+struct LockStream {
+  uint64_t k0, k1, id, gen, prob;
+  uint32_t draw;
+  uint32_t b0;   // block of w[0..3] (draws 4 b0 .. 4 b0 + 3), ~0u = none
+  bool has1;     // w[4..7] holds block b0 + 1
+  uint64_t w[8];
+
+  __device__ LockStream(uint64_t seed, uint64_t tag, uint64_t id_, uint64_t gen_, uint64_t prob_,
+                        uint32_t draw_)
+      : k0(seed), k1(tag), id(id_), gen(gen_), prob(prob_), draw(draw_), b0(~0u), has1(false) {}
+
+  __device__ __forceinline__ void shift() {
+    w[0] = w[4];
+    w[1] = w[5];
+    w[2] = w[6];
+    w[3] = w[7];
+    b0 += 1u;
+    has1 = false;
+  }
+
+  // Every active lane of the wavefront must call it (lanes that have left
+  // the flight loop do not).
+  __device__ __forceinline__ void top_up() {
+    const uint32_t b = draw >> 2;
+    if (has1 && b == b0 + 1u) shift();
+    const bool dry = b != b0;
+    if (__ballot(dry) == 0ull) return;
+    if (dry || !has1) {
+      const uint32_t cb = dry ? b : b0 + 1u;
+      const u64x4 v = philox4x64_10(cb, id, gen, prob, k0, k1);
+      if (dry) {
+        w[0] = v.v[0];
+        w[1] = v.v[1];
+        w[2] = v.v[2];
+        w[3] = v.v[3];
+        b0 = b;
+        has1 = false;
+      } else {
+        w[4] = v.v[0];
+        w[5] = v.v[1];
+        w[6] = v.v[2];
+        w[7] = v.v[3];
+        has1 = true;
+      }
+    }
+  }
+
+  __device__ __forceinline__ double next() {
+    const uint32_t b = draw >> 2;
+    if (has1 && b == b0 + 1u) shift();
+    if (b != b0) {  // not topped up (never on the advance kernels' flights)
+      const u64x4 v = philox4x64_10(b, id, gen, prob, k0, k1);
+      w[0] = v.v[0];
+      w[1] = v.v[1];
+      w[2] = v.v[2];
+      w[3] = v.v[3];
+      b0 = b;
+      has1 = false;
+    }
+    const uint32_t k = draw & 3u;
+    const uint64_t x = k == 0 ? w[0] : k == 1 ? w[1] : k == 2 ? w[2] : w[3];
+    draw += 1u;
+    return u01(x);
+  }
+};
+
 // Distance to collision from the next draw.
 template <class R, class S>
 __device__ __forceinline__ R draw_dcol(S& rs, R st, const double* lt) {
