@@ -34,9 +34,9 @@ TIME_STRIDE = 4  # the timed steps time the advance launches of every 4th genera
 # counter (52 B), writes x, y, counter, event (24 B), queue traffic 8 B
 SEGMENT_BYTES = 84
 # the kernel's own accounting per processed particle: the 52-byte bank entry
-# read and written, plus one 16-byte fixed-point flux atomic per flight
+# read and written (the flux words of the large launches stay in LDS until
+# one add per bin and block; the small launches add 16 B per flight)
 STATE_BYTES = 52
-TALLY_BYTES_ADV = 16
 COUNTERS = os.path.join(ROOT, "profiles", "k_advance_lattice17x17_1e7_counters.md")
 KERNEL_SOURCES = ["paper_2501_05440_amd/csrc/mcx_kernels.hip",
                   "paper_2501_05440_amd/csrc/mcx_kernels_common.hpp",
@@ -379,14 +379,15 @@ def main():
     flights = tot["advance_segments"] / max(1, tot["advance_items"])
     per_launch = SEGMENT_BYTES * segs_per_launch
     achieved = per_launch / (adv_avg_ms * 1e-3) / 1e9 if adv_avg_ms > 0 else 0.0
-    own = items_per_launch * (2 * STATE_BYTES + TALLY_BYTES_ADV * flights)
+    own = items_per_launch * 2 * STATE_BYTES
     own_gbs = own / (adv_avg_ms * 1e-3) / 1e9 if adv_avg_ms > 0 else 0.0
     copy_gbs = copy_peak_gbps()
     traffic = None
     tpi = measured_traffic_per_item()
     if tpi is not None:
         traffic = round(tpi * items_per_launch)  # HBM bytes per launch
-    roofline = {"bound": "hbm", "kernel": "k_advance", "achieved": round(achieved, 1),
+    roofline = {"bound": "hbm", "kernel": "k_advance_lt / k_advance (the advance step)",
+                "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
                 "bytes_per_segment": SEGMENT_BYTES,
@@ -396,8 +397,7 @@ def main():
                 "timed_generation_stride": TIME_STRIDE,
                 "frac_of_copy_peak": round(achieved / copy_gbs, 4),
                 "copy_peak_GBps": round(copy_gbs, 1),
-                "kernel_accounting": {"bytes_per_item": round(2 * STATE_BYTES +
-                                                              TALLY_BYTES_ADV * flights, 2),
+                "kernel_accounting": {"bytes_per_item": 2 * STATE_BYTES,
                                       "items_per_launch": round(items_per_launch, 1),
                                       "flights_per_item": round(flights, 4),
                                       "achieved_GBps": round(own_gbs, 1),
