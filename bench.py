@@ -476,7 +476,7 @@ def main():
         "config": {"workload": f"lattice_17x17_7g: 17x17 pin cells, 3 fuels + moderator, 7 groups, "
                                f"vacuum boundary, {N} histories/gen x {G} gens ({NI} inactive), "
                                f"FP64 event-based",
-                   "histories_per_step": N * G, "block_size": a.block or 256,
+                   "histories_per_step": N * G, "block_size": a.block or 512,
                    "tail_threshold": a.tail or min(131072, max(4096, N // 8)),
                    "lds_tally_min": a.lds_tally_min or 524288,
                    "flights_per_advance_launch": a.flights or 8},

@@ -26,6 +26,7 @@ using namespace mcx;
 namespace {
 
 constexpr int RING = 64;
+constexpr int DEFAULT_BLOCK = 512;  // event kernels (the collision kernel's reservations)
 constexpr int DEFAULT_TAIL = 4096;
 constexpr int DEFAULT_TAIL_MAX = 1 << 17;  // the tail's serial chains, not its size, bound it
 constexpr int DEFAULT_LOOKAHEAD = 4;
@@ -257,7 +258,7 @@ int mcx_create(mcx_ctx** out, const mcx_options* opt) {
   mcx_ctx* c = new (std::nothrow) mcx_ctx();
   if (!c) return MCX_ENOMEM;
   if (opt) c->opt = *opt;
-  if (c->opt.block_size == 0) c->opt.block_size = 256;
+  if (c->opt.block_size == 0) c->opt.block_size = DEFAULT_BLOCK;
   if (c->opt.block_size < 64 || c->opt.block_size > 1024 || c->opt.block_size % 64) {
     delete c;
     return MCX_EINVAL;

@@ -365,10 +365,15 @@ __global__ void __launch_bounds__(1024) k_collide(Tables T0, uint32_t gen, Bank 
   ColXS<R> x{0, R(1), R(0)};
   uint32_t nf = 0;
   uint64_t q_kcol = 0;
-  Stream rs(T.seed, TAG_TRANSPORT, 0, gen, T.prob, 0);
+  // a collision takes about five draws: both blocks that hold them are
+  // evaluated up front by every lane at once, not at whichever draw each
+  // lane crosses a block boundary
+  LockStream rs(T.seed, TAG_TRANSPORT, 0, gen, T.prob, 0);
   if (valid) {
     p = load_part<R>(in, k);
-    rs = Stream(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
+    rs = LockStream(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
+    rs.top_up();
+    rs.fill_next();
     x = col_xs(T, T.geo, p);
     const double kc = (double)(x.nusf / x.st);
     q_kcol = quantize(kc, T.q_kcol);

@@ -183,6 +183,19 @@ struct LockStream {
     }
   }
 
+  // With the block of the next draw held, also evaluate the one after it
+  // (every active lane at once).
+  __device__ __forceinline__ void fill_next() {
+    if (!has1 && b0 == (draw >> 2)) {
+      const u64x4 v = philox4x64_10(b0 + 1u, id, gen, prob, k0, k1);
+      w[4] = v.v[0];
+      w[5] = v.v[1];
+      w[6] = v.v[2];
+      w[7] = v.v[3];
+      has1 = true;
+    }
+  }
+
   __device__ __forceinline__ double next() {
     const uint32_t b = draw >> 2;
     if (has1 && b == b0 + 1u) shift();
