@@ -129,7 +129,8 @@ typedef struct {
   int32_t p_block;          /* persistent: threads per block, 128 or 256; 0 = 256 */
   int32_t p_slots;          /* persistent: particle slots per block, 256 or 512; 0 = 512 */
   int32_t p_grid;           /* persistent and asynchronous engines: workgroups;
-                               0 = 2 per compute unit */
+                               0 = 2 per compute unit (persistent), 1 per 2 compute
+                               units (asynchronous) */
   double p_tau;             /* persistent: refill when fewer than p_tau * p_slots particles
                                of a block are live, 0 < p_tau <= 1; 0 = 0.75 */
   int32_t p_sort;           /* persistent: 1 = order each collide list by material class

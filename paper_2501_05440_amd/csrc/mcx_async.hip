@@ -25,12 +25,16 @@
 // wait is bounded: past the bound the engine sets an abort flag that every
 // workgroup reads, and the run reports an error instead of hanging.
 //
-// Cross-workgroup visibility (the L2 of each XCD is separate): queue entries
-// and counters are read and written with device-scope atomic operations;
-// particle state is written with ordinary stores followed by a device-scope
-// release fence before the entry that hands the particle over is written,
-// and read after a device-scope acquire fence that follows reading the
-// entry.
+// Cross-workgroup visibility (the L2 of each XCD is separate): everything
+// that passes between workgroups during the launch (queue entries and
+// counters, the particle pool and the per-history counters) is read and
+// written with device-scope relaxed atomic loads and stores, which go to
+// the device's coherence point.  A lane publishes the queue entry of a
+// particle only after its own stores of that particle's state have
+// completed (a wait on its memory counter), and a consumer reads the state
+// at addresses that depend on the entry it read.  Device-scope release and
+// acquire fences would write back and invalidate a whole L2 at every
+// hand-over, which is what they cost on this chip.
 #include "mcx_kernels_common.hpp"
 
 namespace mcx {
@@ -55,7 +59,7 @@ struct AsyncPool {
   uint32_t* cell;
   uint32_t* gs;
   uint32_t* ctr;
-  uint16_t* prob;
+  uint32_t* prob;
 };
 
 struct AsyncCtl {
@@ -68,6 +72,11 @@ struct AsyncCtl {
 
 enum : uint32_t { AT_EXIT = 0, AT_IDLE = 1, AT_ADV = 2, AT_COL = 3, AT_BIRTH = 4 };
 
+// An idle workgroup sleeps k x 127 x 64 cycles after its k-th idle poll in a
+// row, k at most IDLE_SLEEP_MAX (about 50 us); it gives up after
+// spin_limit / IDLE_SLEEP_MAX polls in a row (seconds).
+constexpr uint32_t IDLE_SLEEP_MAX = 16;
+
 __device__ __forceinline__ uint64_t ld_dev(const unsigned long long* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -75,6 +84,15 @@ __device__ __forceinline__ uint32_t ld_dev32(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_dev32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// coherent (device-scope relaxed) load and store of shared state
+template <class T>
+__device__ __forceinline__ T ldc(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void stc(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -94,46 +112,47 @@ template <class R>
 __device__ __forceinline__ Part<R> pool_load(const AsyncPool& S, const HistOut& H, uint32_t h,
                                              uint32_t id) {
   Part<R> p;
-  p.x = S.x[h];
-  p.y = S.y[h];
-  p.u = static_cast<const R*>(S.u)[h];
-  p.v = static_cast<const R*>(S.v)[h];
-  const uint32_t c = S.cell[h];
+  p.x = ldc(S.x + h);
+  p.y = ldc(S.y + h);
+  p.u = ldc(static_cast<const R*>(S.u) + h);
+  p.v = ldc(static_cast<const R*>(S.v) + h);
+  const uint32_t c = ldc(S.cell + h);
   p.i = cell_i(c);
   p.j = cell_j(c);
   p.r = cell_r(c);
-  const uint32_t gs = S.gs[h];
+  const uint32_t gs = ldc(S.gs + h);
   p.g = (int)(gs & 0xFFFFu);
   p.nsite = gs >> 16;
-  p.ctr = S.ctr[h];
+  p.ctr = ldc(S.ctr + h);
   p.id = id;
-  p.nseg = H.cnt[(size_t)h * HO_N + HO_SEG];
+  p.nseg = ldc(H.cnt + (size_t)h * HO_N + HO_SEG);
   p.t = 0.0;
   return p;
 }
 
 template <class R>
 __device__ __forceinline__ void pool_store(const AsyncPool& S, uint32_t h, const Part<R>& p) {
-  S.x[h] = p.x;
-  S.y[h] = p.y;
-  static_cast<R*>(S.u)[h] = p.u;
-  static_cast<R*>(S.v)[h] = p.v;
-  S.cell[h] = pack_cell(p.i, p.j, p.r);
-  S.gs[h] = (uint32_t)p.g | (p.nsite << 16);
-  S.ctr[h] = p.ctr;
+  stc(S.x + h, p.x);
+  stc(S.y + h, p.y);
+  stc(static_cast<R*>(S.u) + h, p.u);
+  stc(static_cast<R*>(S.v) + h, p.v);
+  stc(S.cell + h, (uint32_t)pack_cell(p.i, p.j, p.r));
+  stc(S.gs + h, (uint32_t)p.g | (p.nsite << 16));
+  stc(S.ctr + h, p.ctr);
 }
 
 __device__ __forceinline__ void async_death(const HistOut& H, const Accum& A, uint32_t h,
                                             uint32_t nsite, int fate, uint64_t q_kabs) {
   A.nsite_id[h] = nsite;
-  H.kabs[h] = q_kabs;
-  H.cnt[(size_t)h * HO_N + HO_SITES] = nsite;
-  H.cnt[(size_t)h * HO_N + HO_FATE] = (uint32_t)fate;
+  stc(H.kabs + h, (unsigned long long)q_kabs);
+  stc(H.cnt + (size_t)h * HO_N + HO_SITES, nsite);
+  stc(H.cnt + (size_t)h * HO_N + HO_FATE, (uint32_t)fate);
 }
 
 // Append the lanes with `push` set to queue Q (every thread of the block
-// calls it).  The particles' state must have been stored and released
-// before the call.
+// calls it).  Each pushing lane must have stored its particle's state
+// (coherent stores) before the call; its entry is written once those
+// stores have completed.
 template <int PB>
 __device__ __forceinline__ void q_push(const AsyncQueue& Q, bool push, uint32_t h,
                                        uint32_t* lds, unsigned long long* lds_pos,
@@ -145,6 +164,8 @@ __device__ __forceinline__ void q_push(const AsyncQueue& Q, bool push, uint32_t 
   __syncthreads();
   const unsigned long long pos = *lds_pos;
   if (push) {
+    // this lane's stores of the particle's state have completed
+    __builtin_amdgcn_s_waitcnt(0);
     uint32_t* s = Q.slot + (uint32_t)((pos + off) & Q.mask);
     // the previous round's entry of this slot has been claimed; wait until
     // its consumer has emptied it
@@ -250,7 +271,7 @@ __global__ void __launch_bounds__(PB) k_async(Tables T0, uint32_t gen, Accum A, 
         if (kind == AT_IDLE) {
           if (ld_dev(C.remaining) == 0ull) {
             kind = AT_EXIT;
-          } else if (++sh_idle > C.spin_limit) {
+          } else if (++sh_idle > C.spin_limit / IDLE_SLEEP_MAX) {
             st_dev32(C.abort, 1u);
             kind = AT_EXIT;
           }
@@ -269,7 +290,10 @@ __global__ void __launch_bounds__(PB) k_async(Tables T0, uint32_t gen, Accum A, 
     __syncthreads();
     if (kind == AT_EXIT) break;
     if (kind == AT_IDLE) {
-      __builtin_amdgcn_s_sleep(8);
+      // back off: every idle poll is a device-scope load that competes with
+      // the working blocks' queue traffic
+      const uint32_t naps = (uint32_t)min<uint64_t>(sh_idle, IDLE_SLEEP_MAX);
+      for (uint32_t z = 0; z < naps; ++z) __builtin_amdgcn_s_sleep(127);
       continue;
     }
     const uint32_t t = threadIdx.x;
@@ -305,12 +329,12 @@ __global__ void __launch_bounds__(PB) k_async(Tables T0, uint32_t gen, Accum A, 
         p.nsite = 0;
         p.ctr = rs.draw;
         pool_store(S, h, p);
-        S.prob[h] = (uint16_t)pi;
+        stc(S.prob + h, (uint32_t)pi);
         uint32_t* cnt = H.cnt + (size_t)h * HO_N;
-        for (int e = 0; e < HO_N; ++e) cnt[e] = 0;
-        H.kcol[2 * (size_t)h] = 0;
-        H.kcol[2 * (size_t)h + 1] = 0;
-        H.kabs[h] = 0;
+        for (int e = 0; e < HO_N; ++e) stc(cnt + e, 0u);
+        stc(H.kcol + 2 * (size_t)h, 0ull);
+        stc(H.kcol + 2 * (size_t)h + 1, 0ull);
+        stc(H.kabs + h, 0ull);
         to_adv = true;
       }
     } else {
@@ -318,8 +342,7 @@ __global__ void __launch_bounds__(PB) k_async(Tables T0, uint32_t gen, Accum A, 
       bool ok = true;
       if (valid) h = q_take(C.q[kind == AT_ADV ? 0 : 1], pos + t, C, &ok);
       const bool live = valid && ok;
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      const int pi = live && P ? S.prob[h] : 0;
+      const int pi = live && P ? (int)ldc(S.prob + h) : 0;
       const uint64_t seed = P ? P[pi].seed : T.seed;
       const uint64_t prob = P ? P[pi].prob : T.prob;
       const uint32_t id = live ? (uint32_t)(h - (P ? P[pi].hist_base : 0ull)) : 0u;
@@ -329,7 +352,7 @@ __global__ void __launch_bounds__(PB) k_async(Tables T0, uint32_t gen, Accum A, 
           const Geo L = P ? P[pi].geo : T.geo;
           Part<R> p = pool_load<R>(S, H, h, id);
           uint32_t* cnt = H.cnt + (size_t)h * HO_N;
-          uint32_t ncross = cnt[HO_CROSS], nrefl = cnt[HO_REFL];
+          uint32_t ncross = ldc(cnt + HO_CROSS), nrefl = ldc(cnt + HO_REFL);
           Stream rs(seed, TAG_TRANSPORT, id, gen, prob, p.ctr);
           int ev = EV_NONE;
           for (uint32_t f = 0; f < flights; ++f) {
@@ -345,9 +368,9 @@ __global__ void __launch_bounds__(PB) k_async(Tables T0, uint32_t gen, Accum A, 
             if (ev != EV_CROSS) break;
           }
           p.ctr = rs.draw;
-          cnt[HO_SEG] = p.nseg;
-          cnt[HO_CROSS] = ncross;
-          cnt[HO_REFL] = nrefl;
+          stc(cnt + HO_SEG, p.nseg);
+          stc(cnt + HO_CROSS, ncross);
+          stc(cnt + HO_REFL, nrefl);
           if (ev == EV_KILL || ev == EV_LEAK || ev == EV_CENSUS) {
             async_death(H, A, h, p.nsite,
                         ev == EV_KILL ? FATE_KILLED : ev == EV_LEAK ? FATE_LEAKED : FATE_CENSUS, 0);
@@ -370,9 +393,11 @@ __global__ void __launch_bounds__(PB) k_async(Tables T0, uint32_t gen, Accum A, 
           rs = Stream(seed, TAG_TRANSPORT, id, gen, prob, p.ctr);
           x = col_xs(T, L, p);
           const uint64_t q = quantize((double)(x.nusf / x.st), T.q_kcol);
-          H.kcol[2 * (size_t)h] += q & 0xFFFFFFFFull;
-          H.kcol[2 * (size_t)h + 1] += q >> 32;
-          H.cnt[(size_t)h * HO_N + HO_COL] += 1;
+          unsigned long long* kc = H.kcol + 2 * (size_t)h;
+          stc(kc, ldc(kc) + (q & 0xFFFFFFFFull));
+          stc(kc + 1, ldc(kc + 1) + (q >> 32));
+          uint32_t* cc = H.cnt + (size_t)h * HO_N + HO_COL;
+          stc(cc, ldc(cc) + 1u);
           nf = fission_count(T, x, rs, k_used);
         }
         const uint32_t slot = block_reserve(nf, A.n_fis, lds);
@@ -381,7 +406,8 @@ __global__ void __launch_bounds__(PB) k_async(Tables T0, uint32_t gen, Accum A, 
           const bool alive = collide_rest<R, false>(T, p, rs, x, nf, slot, A, &qa);
           p.ctr = rs.draw;
           if (alive) {
-            H.cnt[(size_t)h * HO_N + HO_SCAT] += 1;
+            uint32_t* cs = H.cnt + (size_t)h * HO_N + HO_SCAT;
+            stc(cs, ldc(cs) + 1u);
             pool_store(S, h, p);
             to_adv = true;
           } else {
@@ -391,8 +417,8 @@ __global__ void __launch_bounds__(PB) k_async(Tables T0, uint32_t gen, Accum A, 
         }
       }
     }
-    // hand the survivors over: their state first, then the queue entries
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // hand the survivors over (q_push publishes an entry once the lane's
+    // state stores have completed)
     q_push<PB>(C.q[0], to_adv, h, lds, &sh_pos, C);
     q_push<PB>(C.q[1], to_col, h, lds, &sh_pos, C);
     __syncthreads();

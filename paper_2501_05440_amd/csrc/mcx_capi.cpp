@@ -307,7 +307,11 @@ int mcx_create(mcx_ctx** out, const mcx_options* opt) {
     c->dev_cus = dev_cus;
     c->pcfg.block = c->opt.p_block ? c->opt.p_block : 256;
     c->pcfg.slots = c->opt.p_slots ? c->opt.p_slots : 512;
-    c->pcfg.grid = c->opt.p_grid ? c->opt.p_grid : 2 * dev_cus;
+    // persistent: two workgroups per CU; asynchronous: one per two CUs (its
+    // queue counters are shared by every workgroup: fewer contend less)
+    c->pcfg.grid = c->opt.p_grid ? c->opt.p_grid
+                                 : c->opt.engine == MCX_ENGINE_ASYNC ? std::max(1, dev_cus / 2)
+                                                                     : 2 * dev_cus;
     c->pcfg.tau = c->opt.p_tau > 0.0 ? c->opt.p_tau : 0.75;
     c->pcfg.sort = c->opt.p_sort;
     if (c->opt.p_sort != 0 && c->opt.p_sort != 1) {
@@ -826,7 +830,7 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
     B.cell = cv.take<uint32_t>(n_hist);
     B.gs = cv.take<uint32_t>(n_hist);
     B.ctr = cv.take<uint32_t>(n_hist);
-    B.prob = cv.take<uint16_t>(n_hist);
+    B.prob = cv.take<uint32_t>(n_hist);
     uint64_t cap = 64;
     while (cap < n_hist) cap <<= 1;
     B.mask = (uint32_t)(cap - 1);

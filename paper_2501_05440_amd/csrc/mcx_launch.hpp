@@ -112,7 +112,7 @@ struct AsyncBufs {
   uint32_t* cell = nullptr;
   uint32_t* gs = nullptr;
   uint32_t* ctr = nullptr;
-  uint16_t* prob = nullptr;
+  uint32_t* prob = nullptr;
   uint32_t* slot[2] = {nullptr, nullptr};
   unsigned long long* ctl = nullptr;
   uint32_t mask = 0;  // queue capacity - 1 (a power of two >= the history count)
