@@ -157,7 +157,7 @@ typedef struct {
                                every value.  0 = default */
   int32_t lds_tally_min;    /* event engine (multigroup, tables small enough for LDS): an
                                advance launch whose live-count bound is at least this
-                               stages its flux tally in LDS (each 1024-thread block keeps
+                               stages its flux tally in LDS (each 768-thread block keeps
                                16 B per tally bin and adds every bin to device memory once,
                                instead of one device atomic per flight) when the device's
                                LDS per block holds it.  Results are identical either way.

@@ -35,7 +35,7 @@ constexpr int DEFAULT_FLIGHTS = 8;
 constexpr int DEFAULT_ROUNDS = 1;
 // live-count bound from which an advance launch stages its flux tally in LDS
 constexpr int32_t DEFAULT_LDS_TALLY_MIN = 1 << 19;
-constexpr int LT_BLOCK = 1024;  // threads per block of the LDS-staged advance kernel
+constexpr int LT_BLOCK = 768;  // threads per block of the LDS-staged advance kernel
 // polls (about a microsecond each) before a wait of the asynchronous engine
 // gives up and reports an error
 constexpr uint64_t ASYNC_SPIN_LIMIT = 1ull << 22;
@@ -1277,7 +1277,7 @@ static int run_generation(mcx_ctx* c, int gen) {
   int cur = 0;
   const int block = c->opt.block_size;
   // the LDS-staged advance kernel: multigroup tables in LDS plus 16 B per
-  // tally bin in one block's LDS; as many 1024-thread blocks as are resident
+  // tally bin in one block's LDS; as many LT_BLOCK-thread blocks as are resident
   int lt_grid = 0;
   if (!ce && !mono && c->opt.lds_tally_min > 0) {
     const size_t lb = advance_lt_lds_bytes(prec, T);

@@ -133,7 +133,10 @@ __global__ void __launch_bounds__(1024) k_advance(Tables T0, uint32_t gen, uint3
 // exact, so results equal k_advance's for any grid.  Needs the table copies
 // in LDS; the launcher sizes the dynamic LDS as tables + 16 B per bin.
 template <class R, bool REC>
-__global__ void __launch_bounds__(1024) k_advance_lt(Tables T0, uint32_t gen, uint32_t flights,
+// 768 threads = 12 wavefronts, three per SIMD, so two blocks (two copies
+// of the LDS flux words) give six wavefronts per SIMD; the register budget
+// that needs is asked for explicitly (a few values spill).
+__global__ void __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(6, 8))) k_advance_lt(Tables T0, uint32_t gen, uint32_t flights,
                                                      Bank in, const uint32_t* __restrict__ n_in_p,
                                                      Bank live, uint32_t* n_live, Bank col,
                                                      uint32_t* n_col, Accum A, Records Rc,
