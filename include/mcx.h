@@ -90,7 +90,8 @@ typedef struct {
   int32_t precision;        /* MCX_FP64 (the paper's precision, Sec. 5) */
   int32_t device;           /* HIP device ordinal the workspace lives on */
   void* stream;             /* hipStream_t for every launch and copy; NULL = null stream */
-  int32_t block_size;       /* threads per block of the event kernels, multiple of 64; 0 = 512 */
+  int32_t block_size;       /* threads per block of the event kernels, multiple of 64; 0 = 512
+                               (multigroup) or 256 (continuous energy) */
   int32_t tail_threshold;   /* live-particle count at or below which one history-based
                                kernel finishes the generation; 0 = default
                                (n_per_gen / 8 within [4096, 131072]); negative = event

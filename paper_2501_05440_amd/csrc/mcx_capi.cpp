@@ -27,6 +27,7 @@ namespace {
 
 constexpr int RING = 64;
 constexpr int DEFAULT_BLOCK = 512;  // event kernels (the collision kernel's reservations)
+constexpr int DEFAULT_BLOCK_CE = 256;  // continuous-energy event kernels
 constexpr int DEFAULT_TAIL = 4096;
 constexpr int DEFAULT_TAIL_MAX = 1 << 17;  // the tail's serial chains, not its size, bound it
 constexpr int DEFAULT_LOOKAHEAD = 4;
@@ -258,8 +259,9 @@ int mcx_create(mcx_ctx** out, const mcx_options* opt) {
   mcx_ctx* c = new (std::nothrow) mcx_ctx();
   if (!c) return MCX_ENOMEM;
   if (opt) c->opt = *opt;
-  if (c->opt.block_size == 0) c->opt.block_size = DEFAULT_BLOCK;
-  if (c->opt.block_size < 64 || c->opt.block_size > 1024 || c->opt.block_size % 64) {
+  // block_size == 0: DEFAULT_BLOCK (multigroup) or DEFAULT_BLOCK_CE, resolved per run
+  if (c->opt.block_size != 0 &&
+      (c->opt.block_size < 64 || c->opt.block_size > 1024 || c->opt.block_size % 64)) {
     delete c;
     return MCX_EINVAL;
   }
@@ -274,7 +276,7 @@ int mcx_create(mcx_ctx** out, const mcx_options* opt) {
   if (c->opt.flights == 0) c->opt.flights = DEFAULT_FLIGHTS;
   if (c->opt.lds_tally_min == 0) c->opt.lds_tally_min = DEFAULT_LDS_TALLY_MIN;
   if (c->opt.rounds == 0) c->opt.rounds = DEFAULT_ROUNDS;
-  if (c->opt.rounds < 1 || c->opt.rounds * c->opt.block_size > 4096) {
+  if (c->opt.rounds < 1 || c->opt.rounds * (c->opt.block_size ? c->opt.block_size : DEFAULT_BLOCK) > 4096) {
     delete c;
     return MCX_EINVAL;
   }
@@ -1275,7 +1277,9 @@ static int run_generation(mcx_ctx* c, int gen) {
                                   : std::min<int64_t>(DEFAULT_TAIL_MAX,
                                                       std::max<int64_t>(DEFAULT_TAIL, (int64_t)N / 8));
   int cur = 0;
-  const int block = c->opt.block_size;
+  // default block: 512 threads for the multigroup event kernels (the
+  // collision kernel's bank reservations), 256 for the continuous-energy ones
+  const int block = c->opt.block_size ? c->opt.block_size : ce ? DEFAULT_BLOCK_CE : DEFAULT_BLOCK;
   // the LDS-staged advance kernel: multigroup tables in LDS plus 16 B per
   // tally bin in one block's LDS; as many LT_BLOCK-thread blocks as are resident
   int lt_grid = 0;

@@ -350,6 +350,50 @@ def test_full_size_first_generations(oracle):
     assert_close(g["gen_prod"], o["gen_prod"], what="gen_prod")
 
 
+def test_headline_size_two_generations_parity(oracle):
+    """The headline lattice at 1e7 histories per generation (the launches
+    stage their flux in LDS, the tail starts at 131,072 live particles):
+    both generations history by history against the oracle, so the first
+    generation's fission bank, its canonical order and the combing at full
+    size are checked through the second generation's histories, plus each
+    generation's event counts, k estimators and flux and production
+    tallies."""
+    banner("lattice 1e7 x 2 records parity")
+    prob = P.lattice_17x17(n_per_gen=10_000_000, n_gen=2, n_inactive=1)
+    g = mcx.run(prob, record=True, per_gen_tallies=True)
+    o = oracle.run(prob, records=True, per_gen_tallies=True)
+    assert np.array_equal(g["gen_counts"], o["gen_counts"])
+    assert_close(g["gen_k"], o["gen_k"], what="gen_k")
+    assert_close(g["gen_entropy"], o["gen_entropy"], what="entropy")
+    for gen in range(2):
+        compare_records(g["records"][gen], o["records"][gen], f"gen {gen}")
+    af = flux_atol(g, prob)
+    assert_close(g["gen_flux"], o["gen_flux"], what="gen_flux", atol=af)
+    assert_close(g["gen_prod"], o["gen_prod"], what="gen_prod",
+                 atol=af * float(np.max(prob["xs"]["nu_sig_f"])))
+
+
+def test_headline_invariants_in_bench_configuration():
+    """The bench's headline run (1e7 x 60, 20 inactive) in its launch
+    configuration: particle, event and site balance in every generation, no
+    guard kills, and the three k estimators agree statistically."""
+    banner("lattice 1e7 x 60 invariants")
+    prob = P.lattice_17x17(n_per_gen=10_000_000)
+    g = mcx.run(prob)
+    n = prob["run"]["n_per_gen"]
+    seg, col, cross, refl, leak, ab, killed, sites, scat, cutoff, *_ = g["gen_counts"].T
+    assert np.all(ab + leak + killed == n)
+    assert np.all(killed == 0)
+    assert np.all(col == scat + ab)
+    assert np.all(seg == col + cross)
+    km, ks = g["k_mean"], g["k_sigma"]
+    for a, b in ((0, 1), (0, 2), (1, 2)):
+        assert abs(km[a] - km[b]) < 4 * math.hypot(ks[a], ks[b]), (km, ks)
+    k_used = np.concatenate([[1.0], g["gen_k"][:-1, 0]])
+    expect = n * g["gen_k"][:, 0] / k_used
+    assert np.all(np.abs(sites - expect) < 4 * np.sqrt(col / 4.0))
+
+
 def test_full_size_invariants_in_bench_configuration():
     """The benchmark run (1e6 x 60, 20 inactive) in its launch configuration:
     particle, event and site balance in every generation, and the three k
