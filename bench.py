@@ -84,6 +84,9 @@ def parse():
     ap.add_argument("--lds-tally-min", type=int, default=0,
                     help="live-count bound from which an advance launch stages its flux tally "
                          "in LDS (0 = library default, negative = never)")
+    ap.add_argument("--lt-flights", type=int, default=0,
+                    help="flights per particle of the LDS-staged advance launches "
+                         "(0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-gens", type=int, default=4,
                     help="generations of the headline lattice the CPU oracle runs (about 10 s)")
@@ -337,7 +340,7 @@ def main():
     # next one a little); the generations are statistically alike
     ctx = mcx.Context(prob, device=0, block_size=a.block, tail_threshold=a.tail,
                       time_kernels="advance", time_stride=TIME_STRIDE, flights=a.flights,
-                      rounds=a.rounds, lds_tally_min=a.lds_tally_min)
+                      rounds=a.rounds, lds_tally_min=a.lds_tally_min, lt_flights=a.lt_flights)
     for w in range(a.warmup):
         ctx.run()
         log(f"warmup {w + 1}/{a.warmup} done")
@@ -365,7 +368,7 @@ def main():
     # event kernel timed
     bctx = mcx.Context(prob, device=0, block_size=a.block, tail_threshold=a.tail,
                        time_kernels=True, flights=a.flights, rounds=a.rounds,
-                       lds_tally_min=a.lds_tally_min)
+                       lds_tally_min=a.lds_tally_min, lt_flights=a.lt_flights)
     bctx.run()
     brk = bctx.timing()
     bctx.close()
@@ -479,7 +482,8 @@ def main():
                    "histories_per_step": N * G, "block_size": a.block or 512,
                    "tail_threshold": a.tail or min(131072, max(4096, N // 8)),
                    "lds_tally_min": a.lds_tally_min or 524288,
-                   "flights_per_advance_launch": a.flights or 8},
+                   "flights_per_advance_launch": a.flights or 8,
+                   "flights_per_lds_staged_launch": a.lt_flights or min(a.flights or 8, 5)},
         "events_per_s": round(segs / elapsed, 1),
         "segments_per_history": round(segs / histories, 4),
         "k_eff": {"collision": round(float(km[0]), 6), "sigma": round(float(ks[0]), 6)},

@@ -163,6 +163,10 @@ typedef struct {
                                instead of one device atomic per flight) when the device's
                                LDS per block holds it.  Results are identical either way.
                                0 = default (2^19); negative = never */
+  int32_t lt_flights;       /* flights per particle of those LDS-staged advance launches
+                               (the large ones; `flights` applies to the others).  Results
+                               are identical for every value.  0 = default
+                               (min(flights, 5)); at most 65536 */
 } mcx_options;
 
 /* Lattice of pin universes (paper Sec. 1: CSG geometry).  Cell (i, j),

@@ -36,6 +36,10 @@ constexpr int DEFAULT_FLIGHTS = 8;
 constexpr int DEFAULT_ROUNDS = 1;
 // live-count bound from which an advance launch stages its flux tally in LDS
 constexpr int32_t DEFAULT_LDS_TALLY_MIN = 1 << 19;
+// flights per particle of the LDS-staged launches (the large ones): fewer
+// than the small launches' `flights`, so that lanes idle less behind the
+// wavefront's longest chain of crossings
+constexpr int DEFAULT_LT_FLIGHTS = 5;
 constexpr int LT_BLOCK = 768;  // threads per block of the LDS-staged advance kernel
 // polls (about a microsecond each) before a wait of the asynchronous engine
 // gives up and reports an error
@@ -275,6 +279,11 @@ int mcx_create(mcx_ctx** out, const mcx_options* opt) {
   if (c->opt.max_events <= 0) c->opt.max_events = DEFAULT_MAX_EVENTS;
   if (c->opt.flights == 0) c->opt.flights = DEFAULT_FLIGHTS;
   if (c->opt.lds_tally_min == 0) c->opt.lds_tally_min = DEFAULT_LDS_TALLY_MIN;
+  if (c->opt.lt_flights == 0) c->opt.lt_flights = std::min(c->opt.flights, DEFAULT_LT_FLIGHTS);
+  if (c->opt.lt_flights < 0 || c->opt.lt_flights > 65536) {
+    delete c;
+    return MCX_EINVAL;
+  }
   if (c->opt.rounds == 0) c->opt.rounds = DEFAULT_ROUNDS;
   if (c->opt.rounds < 1 || c->opt.rounds * (c->opt.block_size ? c->opt.block_size : DEFAULT_BLOCK) > 4096) {
     delete c;
@@ -1327,7 +1336,8 @@ static int run_generation(mcx_ctx* c, int gen) {
                                    c->d.cnt_col + it, A, c->d.R, c->d.cnt_live + it + 2,
                                    c->d.cnt_col + it + 1, bound, block, s));
     else if (lt_grid > 0 && (int64_t)bound >= (int64_t)c->opt.lds_tally_min)
-      HIP_TRY(c, launch_advance_lt(prec, rec, T, gen, fl, c->d.bank[cur], c->d.cnt_live + it,
+      HIP_TRY(c, launch_advance_lt(prec, rec, T, gen, (uint32_t)c->opt.lt_flights, c->d.bank[cur],
+                                   c->d.cnt_live + it,
                                    c->d.bank[1 - cur], c->d.cnt_live + it + 1, c->d.bank[2],
                                    c->d.cnt_col + it, A, c->d.R, c->d.cnt_live + it + 2,
                                    c->d.cnt_col + it + 1, bound, LT_BLOCK, lt_grid, s));

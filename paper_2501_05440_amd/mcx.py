@@ -52,7 +52,7 @@ class Options(C.Structure):
                 ("p_grid", C.c_int32), ("p_tau", C.c_double), ("p_sort", C.c_int32),
                 ("flights", C.c_int32), ("event_log", C.c_int32),
                 ("time_stride", C.c_int32), ("rounds", C.c_int32),
-                ("lds_tally_min", C.c_int32)]
+                ("lds_tally_min", C.c_int32), ("lt_flights", C.c_int32)]
 
 
 class Geometry(C.Structure):
@@ -247,7 +247,8 @@ class Context:
     def __init__(self, problem, device=0, record=False, block_size=0, tail_threshold=0,
                  lookahead=0, max_events=None, time_kernels=False, n_gen_max=None,
                  stream=None, precision="fp64", engine="event", persistent=None, flights=0,
-                 event_log=0, time_stride=0, rounds=0, lds_tally_min=0, workspace=True):
+                 event_log=0, time_stride=0, rounds=0, lds_tally_min=0, lt_flights=0,
+                 workspace=True):
         import torch
 
         self.problem = problem
@@ -270,6 +271,7 @@ class Context:
         o.time_stride = time_stride
         o.rounds = rounds
         o.lds_tally_min = lds_tally_min
+        o.lt_flights = lt_flights
         self.event_log = event_log
         # True / 1: every event kernel; "advance" / 2: the advance kernels only
         o.time_kernels = 2 if time_kernels in ("advance", 2) else int(bool(time_kernels))

@@ -224,14 +224,16 @@ def test_refilled_advance_full_size_matches_oracle(oracle):
                                            (3, "fp64", 70001)])
 def test_lds_tally_advance_gives_identical_results(flights, prec, n):
     """The advance kernel that stages the flux tally in LDS (every launch
-    forced onto it) against the one that adds every flight to device memory:
-    bit-identical generation results, tallies and records, for ragged last
-    chunks, one flight per launch, uncapped flights, FP32-mixed, and more
-    particles than the grid holds at once (grid-stride chunks)."""
+    forced onto it, with half the flights per launch) against the one that
+    adds every flight to device memory: bit-identical generation results,
+    tallies and records, for ragged last chunks, one flight per launch,
+    uncapped flights, FP32-mixed, and more particles than the grid holds at
+    once (grid-stride chunks)."""
     banner(f"LDS-staged tally advance flights={flights} {prec} n={n}")
     prob = P.lattice_17x17(n_per_gen=n, n_gen=3, n_inactive=1)
     ref = mcx.run(prob, record=True, precision=prec, lds_tally_min=-1, flights=flights)
-    got = mcx.run(prob, record=True, precision=prec, lds_tally_min=1, flights=flights)
+    got = mcx.run(prob, record=True, precision=prec, lds_tally_min=1, flights=flights,
+                  lt_flights=max(1, flights // 2))
     for k in ("gen_k", "gen_entropy", "gen_counts", "flux_mean", "prod_mean", "k_mean",
               "flux_sigma", "prod_sigma"):
         assert np.array_equal(ref[k], got[k]), k
