@@ -455,7 +455,7 @@ __device__ __forceinline__ void tally_add(unsigned long long* pairs, unsigned lo
 
 // One flight at the particle's energy (see the multigroup segment for the
 // geometry).  *q_tl receives the fixed-point track-length k term.
-template <class R, bool REC, bool HALVES>
+template <class R, bool REC, bool HALVES, bool TLDS = false>
 __device__ __forceinline__ int segment_ce(const Tables& T, const Geo& L, PartCE<R>& p, Stream& rs,
                                           const Accum& A, const Records& Rc, bool* refl_out,
                                           uint64_t* q_tl, CECache<R>& cache) {
@@ -531,6 +531,14 @@ __device__ __forceinline__ int segment_ce(const Tables& T, const Geo& L, PartCE<
       if (e1 >= t1) break;
     }
     p.t = t1;
+  } else if constexpr (TLDS) {
+    // the block's LDS flux words (halves), added to device memory once per block
+    const uint64_t q = quantize(d, T.q_flux);
+    if (q) {
+      unsigned long long* w = lds_tally(T);
+      atomicAdd(w + 2 * bin, (unsigned long long)(q & 0xFFFFFFFFull));
+      atomicAdd(w + 2 * bin + 1, (unsigned long long)(q >> 32));
+    }
   } else {
     tally_add<HALVES>(A.tally, A.tally_t, stripe_off, bin, quantize(d, T.q_flux));
   }
@@ -755,7 +763,11 @@ __global__ void k_ce_birth(Tables T, uint32_t gen, uint32_t n, const double* sx,
   store_ce<R>(out, id, p);
 }
 
-template <class R, bool REC>
+// TL: the block's flux tally is staged in LDS (16 B per bin, dynamic LDS at
+// T.lds_tally_off; no time grid) and each nonzero bin is added to the
+// block's stripe of device memory once, instead of one returning device
+// atomic per flight on the few hot bins of a small problem.
+template <class R, bool REC, bool TL>
 __global__ void __launch_bounds__(1024) k_ce_advance(Tables T, uint32_t gen, uint32_t flights,
                                                      Bank in, const uint32_t* __restrict__ n_in_p,
                                                      Bank live, uint32_t* n_live, Bank col,
@@ -766,6 +778,12 @@ __global__ void __launch_bounds__(1024) k_ce_advance(Tables T, uint32_t gen, uin
     *clr_col = 0;
   }
   const uint32_t n_in = *n_in_p;
+  if (TL) {
+    if (blockIdx.x * blockDim.x >= n_in) return;  // the whole block
+    unsigned long long* tw = lds_tally(T);
+    for (uint32_t w = threadIdx.x; w < 2u * (uint32_t)T.n_bins; w += blockDim.x) tw[w] = 0ull;
+    __syncthreads();
+  }
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   int ev = EV_NONE;
   uint32_t c_seg = 0, c_cross = 0, c_refl = 0;
@@ -784,7 +802,7 @@ __global__ void __launch_bounds__(1024) k_ce_advance(Tables T, uint32_t gen, uin
       }
       bool refl = false;
       uint64_t q = 0;
-      ev = segment_ce<R, REC, false>(T, T.geo, p, rs, A, Rc, &refl, &q, cache);
+      ev = segment_ce<R, REC, false, TL>(T, T.geo, p, rs, A, Rc, &refl, &q, cache);
       tl_lo += q & 0xFFFFFFFFull;
       tl_hi += q >> 32;
       p.nseg += 1;
@@ -823,6 +841,20 @@ __global__ void __launch_bounds__(1024) k_ce_advance(Tables T, uint32_t gen, uin
   wave_flag(A.cnt + CNT_ADV_ITEMS * STRIPES, k < n_in);
   wave_count(A.cnt + CNT_ADV_SEGS * STRIPES, c_seg);
   wave_acc_halves(A.k + K_TL * STRIPES * 2, tl_lo, tl_hi);
+  if (TL) {
+    // one exact 128-bit add per nonzero bin into this block's stripe
+    __syncthreads();
+    const unsigned long long* tw = lds_tally(T);
+    unsigned long long* tb =
+        A.tally + (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
+    for (uint32_t b = threadIdx.x; b < (uint32_t)T.n_bins; b += blockDim.x) {
+      const unsigned long long lo = tw[2 * b], hi = tw[2 * b + 1];
+      if ((lo | hi) == 0ull) continue;
+      const unsigned long long w0 = lo + (hi << 32);
+      const unsigned long long w1 = (hi >> 32) + (w0 < lo ? 1ull : 0ull);
+      acc_add128(tb + 2 * b, w0, w1);
+    }
+  }
 }
 
 template <class R, bool REC>
@@ -1089,13 +1121,24 @@ hipError_t launch_ce_birth(int prec, const Tables& T, uint32_t gen, uint32_t n, 
   return hipGetLastError();
 }
 
+// the LDS-staged flux words of the flight kernel: small tallies, no time grid
+constexpr size_t CE_LDS_TALLY_MAX = 32768;
+
 template <class R, bool REC>
-static void ce_advance_k(dim3 g, dim3 b, hipStream_t s, const Tables& T, uint32_t gen,
+static void ce_advance_k(dim3 g, dim3 b, hipStream_t s, const Tables& T0, uint32_t gen,
                          uint32_t flights, const Bank& in, const uint32_t* n_in, const Bank& live,
                          uint32_t* n_live, const Bank& col, uint32_t* n_col, const Accum& A,
                          const Records& Rc, uint32_t* clr_live, uint32_t* clr_col) {
-  hipLaunchKernelGGL((k_ce_advance<R, REC>), g, b, 0, s, T, gen, flights, in, n_in, live, n_live,
-                     col, n_col, A, Rc, clr_live, clr_col);
+  const size_t lb = 16 * (size_t)T0.n_bins;
+  if (!T0.time && !T0.probs && lb <= CE_LDS_TALLY_MAX) {
+    Tables T = T0;
+    T.lds_tally_off = 0;
+    hipLaunchKernelGGL((k_ce_advance<R, REC, true>), g, b, lb, s, T, gen, flights, in, n_in, live,
+                       n_live, col, n_col, A, Rc, clr_live, clr_col);
+  } else {
+    hipLaunchKernelGGL((k_ce_advance<R, REC, false>), g, b, 0, s, T0, gen, flights, in, n_in,
+                       live, n_live, col, n_col, A, Rc, clr_live, clr_col);
+  }
 }
 
 hipError_t launch_ce_advance(int prec, bool rec, const Tables& T, uint32_t gen, uint32_t flights,
