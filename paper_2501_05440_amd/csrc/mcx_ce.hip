@@ -780,9 +780,7 @@ __global__ void __launch_bounds__(1024) k_ce_advance(Tables T, uint32_t gen, uin
   const uint32_t n_in = *n_in_p;
   if (TL) {
     if (blockIdx.x * blockDim.x >= n_in) return;  // the whole block
-    unsigned long long* tw = lds_tally(T);
-    for (uint32_t w = threadIdx.x; w < 2u * (uint32_t)T.n_bins; w += blockDim.x) tw[w] = 0ull;
-    __syncthreads();
+    lds_tally_clear(T);
   }
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   int ev = EV_NONE;
@@ -841,20 +839,7 @@ __global__ void __launch_bounds__(1024) k_ce_advance(Tables T, uint32_t gen, uin
   wave_flag(A.cnt + CNT_ADV_ITEMS * STRIPES, k < n_in);
   wave_count(A.cnt + CNT_ADV_SEGS * STRIPES, c_seg);
   wave_acc_halves(A.k + K_TL * STRIPES * 2, tl_lo, tl_hi);
-  if (TL) {
-    // one exact 128-bit add per nonzero bin into this block's stripe
-    __syncthreads();
-    const unsigned long long* tw = lds_tally(T);
-    unsigned long long* tb =
-        A.tally + (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
-    for (uint32_t b = threadIdx.x; b < (uint32_t)T.n_bins; b += blockDim.x) {
-      const unsigned long long lo = tw[2 * b], hi = tw[2 * b + 1];
-      if ((lo | hi) == 0ull) continue;
-      const unsigned long long w0 = lo + (hi << 32);
-      const unsigned long long w1 = (hi >> 32) + (w0 < lo ? 1ull : 0ull);
-      acc_add128(tb + 2 * b, w0, w1);
-    }
-  }
+  if (TL) lds_tally_flush(T, A);
 }
 
 template <class R, bool REC>
@@ -905,11 +890,12 @@ __global__ void __launch_bounds__(1024) k_ce_collide(Tables T, uint32_t gen, Ban
   wave_acc(A.k + K_ABS * STRIPES * 2, q_kabs);
 }
 
-template <class R, bool REC>
+template <class R, bool REC, bool TL>
 __global__ void __launch_bounds__(256) k_ce_tail(Tables T, uint32_t gen, Bank in,
                                                  const uint32_t* __restrict__ n_in_p, Accum A,
                                                  Records Rc) {
   const uint32_t n_in = *n_in_p;
+  if (TL) lds_tally_clear(T);
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long c_seg = 0, c_col = 0, c_cross = 0, c_refl = 0, c_leak = 0, c_abs = 0,
                      c_kill = 0, c_sites = 0, c_scat = 0, c_cut = 0, c_cen = 0;
@@ -941,7 +927,7 @@ __global__ void __launch_bounds__(256) k_ce_tail(Tables T, uint32_t gen, Bank in
       } else {
         bool refl = false;
         uint64_t q = 0;
-        const int ev = segment_ce<R, REC, true>(T, T.geo, p, rs, A, Rc, &refl, &q, cache);
+        const int ev = segment_ce<R, REC, true, TL>(T, T.geo, p, rs, A, Rc, &refl, &q, cache);
         ktl[0] += q & 0xFFFFFFFFull;
         ktl[1] += q >> 32;
         ++nseg;
@@ -1012,16 +998,18 @@ __global__ void __launch_bounds__(256) k_ce_tail(Tables T, uint32_t gen, Bank in
   wave_acc_halves(A.k + K_COL * STRIPES * 2, kcol[0], kcol[1]);
   wave_acc_halves(A.k + K_ABS * STRIPES * 2, kabs[0], kabs[1]);
   wave_acc_halves(A.k + K_TL * STRIPES * 2, ktl[0], ktl[1]);
+  if (TL) lds_tally_flush(T, A);
 }
 
 // Monolithic event of the continuous-energy path (see k_mono): one segment
 // of every particle per launch, the collision or the crossing in the same
 // kernel, survivors to the processed bank.
-template <class R, bool REC>
+template <class R, bool REC, bool TL>
 __global__ void __launch_bounds__(1024) k_ce_mono(Tables T, uint32_t gen, Bank in,
                                                   const uint32_t* __restrict__ n_in_p, Bank out,
                                                   uint32_t* n_out, Accum A, Records Rc,
                                                   uint32_t* clr_out) {
+  if (TL) lds_tally_clear(T);
   if (blockIdx.x == 0 && threadIdx.x == 0) *clr_out = 0;
   const uint32_t n_in = *n_in_p;
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1042,7 +1030,7 @@ __global__ void __launch_bounds__(1024) k_ce_mono(Tables T, uint32_t gen, Bank i
     } else {
       CECache<R> cache;
       ce_cache_clear(cache);
-      ev = segment_ce<R, REC, false>(T, T.geo, p, rs, A, Rc, &refl, &q_tl, cache);
+      ev = segment_ce<R, REC, false, TL>(T, T.geo, p, rs, A, Rc, &refl, &q_tl, cache);
       p.nseg += 1;
       if (ev == EV_COLLIDE) {
         c = col_ce<R>(T, T.geo, p, cache);
@@ -1089,6 +1077,7 @@ __global__ void __launch_bounds__(1024) k_ce_mono(Tables T, uint32_t gen, Bank i
   wave_acc(A.k + K_COL * STRIPES * 2, q_kcol);
   wave_acc(A.k + K_ABS * STRIPES * 2, q_kabs);
   wave_acc(A.k + K_TL * STRIPES * 2, q_tl);
+  if (TL) lds_tally_flush(T, A);
 }
 
 // ---------------------------------------------------------------------------
@@ -1121,16 +1110,24 @@ hipError_t launch_ce_birth(int prec, const Tables& T, uint32_t gen, uint32_t n, 
   return hipGetLastError();
 }
 
-// the LDS-staged flux words of the flight kernel: small tallies, no time grid
+// the LDS-staged flux words of the flight, tail and monolithic kernels:
+// small tallies, no time grid
 constexpr size_t CE_LDS_TALLY_MAX = 32768;
+
+// Dynamic LDS of the staged flux words for these tables, or 0 when they are
+// not staged.
+static size_t ce_lt_bytes(const Tables& T) {
+  const size_t lb = 16 * (size_t)T.n_bins;
+  return (!T.time && !T.probs && lb <= CE_LDS_TALLY_MAX) ? lb : 0;
+}
 
 template <class R, bool REC>
 static void ce_advance_k(dim3 g, dim3 b, hipStream_t s, const Tables& T0, uint32_t gen,
                          uint32_t flights, const Bank& in, const uint32_t* n_in, const Bank& live,
                          uint32_t* n_live, const Bank& col, uint32_t* n_col, const Accum& A,
                          const Records& Rc, uint32_t* clr_live, uint32_t* clr_col) {
-  const size_t lb = 16 * (size_t)T0.n_bins;
-  if (!T0.time && !T0.probs && lb <= CE_LDS_TALLY_MAX) {
+  const size_t lb = ce_lt_bytes(T0);
+  if (lb) {
     Tables T = T0;
     T.lds_tally_off = 0;
     hipLaunchKernelGGL((k_ce_advance<R, REC, true>), g, b, lb, s, T, gen, flights, in, n_in, live,
@@ -1188,44 +1185,64 @@ hipError_t launch_ce_collide(int prec, bool rec, const Tables& T, uint32_t gen, 
   return hipGetLastError();
 }
 
-hipError_t launch_ce_mono(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in,
+hipError_t launch_ce_mono(int prec, bool rec, const Tables& T0, uint32_t gen, const Bank& in,
                           const uint32_t* n_in, const Bank& out, uint32_t* n_out, const Accum& A,
                           const Records& Rc, uint32_t* clr_out, uint32_t bound, int block,
                           hipStream_t s) {
   const dim3 g(std::max(1u, nblk_ce(bound, block))), b(block);
+  const size_t lb = ce_lt_bytes(T0);
+  Tables T = T0;
+  T.lds_tally_off = 0;
+#define MCX_CE_MONO(R_, REC_)                                                                   \
+  if (lb)                                                                                     \
+    hipLaunchKernelGGL((k_ce_mono<R_, REC_, true>), g, b, lb, s, T, gen, in, n_in, out, n_out, A, \
+                       Rc, clr_out);                                                          \
+  else                                                                                        \
+    hipLaunchKernelGGL((k_ce_mono<R_, REC_, false>), g, b, 0, s, T, gen, in, n_in, out, n_out, A, \
+                       Rc, clr_out);
   if (prec == 0) {
-    if (rec)
-      hipLaunchKernelGGL((k_ce_mono<double, true>), g, b, 0, s, T, gen, in, n_in, out, n_out, A,
-                         Rc, clr_out);
-    else
-      hipLaunchKernelGGL((k_ce_mono<double, false>), g, b, 0, s, T, gen, in, n_in, out, n_out, A,
-                         Rc, clr_out);
+    if (rec) {
+      MCX_CE_MONO(double, true)
+    } else {
+      MCX_CE_MONO(double, false)
+    }
   } else {
-    if (rec)
-      hipLaunchKernelGGL((k_ce_mono<float, true>), g, b, 0, s, T, gen, in, n_in, out, n_out, A,
-                         Rc, clr_out);
-    else
-      hipLaunchKernelGGL((k_ce_mono<float, false>), g, b, 0, s, T, gen, in, n_in, out, n_out, A,
-                         Rc, clr_out);
+    if (rec) {
+      MCX_CE_MONO(float, true)
+    } else {
+      MCX_CE_MONO(float, false)
+    }
   }
+#undef MCX_CE_MONO
   return hipGetLastError();
 }
 
-hipError_t launch_ce_tail(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in,
+hipError_t launch_ce_tail(int prec, bool rec, const Tables& T0, uint32_t gen, const Bank& in,
                           const uint32_t* n_in, const Accum& A, const Records& Rc, uint32_t bound,
                           hipStream_t s) {
   const dim3 g(std::max(1u, nblk_ce(bound, 64))), b(64);
+  const size_t lb = ce_lt_bytes(T0);
+  Tables T = T0;
+  T.lds_tally_off = 0;
+#define MCX_CE_TAIL(R_, REC_)                                                               \
+  if (lb)                                                                                 \
+    hipLaunchKernelGGL((k_ce_tail<R_, REC_, true>), g, b, lb, s, T, gen, in, n_in, A, Rc);  \
+  else                                                                                    \
+    hipLaunchKernelGGL((k_ce_tail<R_, REC_, false>), g, b, 0, s, T, gen, in, n_in, A, Rc);
   if (prec == 0) {
-    if (rec)
-      hipLaunchKernelGGL((k_ce_tail<double, true>), g, b, 0, s, T, gen, in, n_in, A, Rc);
-    else
-      hipLaunchKernelGGL((k_ce_tail<double, false>), g, b, 0, s, T, gen, in, n_in, A, Rc);
+    if (rec) {
+      MCX_CE_TAIL(double, true)
+    } else {
+      MCX_CE_TAIL(double, false)
+    }
   } else {
-    if (rec)
-      hipLaunchKernelGGL((k_ce_tail<float, true>), g, b, 0, s, T, gen, in, n_in, A, Rc);
-    else
-      hipLaunchKernelGGL((k_ce_tail<float, false>), g, b, 0, s, T, gen, in, n_in, A, Rc);
+    if (rec) {
+      MCX_CE_TAIL(float, true)
+    } else {
+      MCX_CE_TAIL(float, false)
+    }
   }
+#undef MCX_CE_TAIL
   return hipGetLastError();
 }
 

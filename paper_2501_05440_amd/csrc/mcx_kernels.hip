@@ -149,10 +149,7 @@ __global__ void __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(6, 8))
     *clr_col = 0;
   }
   if (!any) return;  // the whole block
-  unsigned long long* tw = lds_tally(T);
-  const uint32_t nw = 2u * (uint32_t)T.n_bins;
-  for (uint32_t w = threadIdx.x; w < nw; w += blockDim.x) tw[w] = 0ull;
-  __syncthreads();
+  lds_tally_clear(T);
 
   uint32_t c_seg = 0, c_cross = 0, c_refl = 0, c_leak = 0, c_kill = 0, c_cen = 0, c_items = 0;
   __shared__ uint32_t lds[2 * (MAX_WAVES + 1)];
@@ -206,18 +203,7 @@ __global__ void __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(6, 8))
   wave_count(A.cnt + CNT_CENSUS * STRIPES, c_cen);
   wave_count(A.cnt + CNT_ADV_ITEMS * STRIPES, c_items);
   wave_count(A.cnt + CNT_ADV_SEGS * STRIPES, c_seg);
-  __syncthreads();
-  // one exact 128-bit add per nonzero bin into this block's stripe
-  unsigned long long* tb =
-      A.tally + (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
-  for (uint32_t b = threadIdx.x; b < (uint32_t)T.n_bins; b += blockDim.x) {
-    const unsigned long long lo = tw[2 * b], hi = tw[2 * b + 1];
-    if ((lo | hi) == 0ull) continue;
-    // lo + hi 2^32 as (w1, w0)
-    const unsigned long long w0 = lo + (hi << 32);
-    const unsigned long long w1 = (hi >> 32) + (w0 < lo ? 1ull : 0ull);
-    acc_add128(tb + 2 * b, w0, w1);
-  }
+  lds_tally_flush(T, A);
 }
 
 // Advance with lanes refilled from the block's chunk of the input bank.
