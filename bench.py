@@ -146,6 +146,17 @@ def cpu_model():
     return "unknown"
 
 
+def kernel_breakdown(mcx, prob, **kw):
+    """Per-kernel times of one more run with every event kernel timed (the
+    events between launches slow a run a little, so the timed runs go
+    without them)."""
+    ctx = mcx.Context(prob, time_kernels=True, **kw)
+    ctx.run()
+    t = ctx.timing()
+    ctx.close()
+    return t
+
+
 def paired(g32, g64, ni):
     d = g32[ni:, 0] - g64[ni:, 0]
     return float(d.std(ddof=1) / math.sqrt(len(d)))
@@ -238,18 +249,19 @@ def batch_comparison(P, mcx, tune_cache, steps):
 
 def ce_measurement(P, mcx):
     """Continuous-energy pin cell, 1e6 histories x 50 generations (10
-    inactive), event engine, FP64 and FP32-mixed on the same streams."""
+    inactive), event engine, FP64 and FP32-mixed on the same streams; the
+    per-kernel times come from a separate fully timed run."""
     prob = P.ce_pin_cell()
     n = prob["run"]["n_per_gen"] * prob["run"]["n_gen"]
     ni = prob["run"]["n_inactive"]
     out, gk = {}, {}
     for prec in ("fp64", "fp32"):
-        ctx = mcx.Context(prob, time_kernels=True, precision=prec)
+        ctx = mcx.Context(prob, precision=prec)
         sec = timed_runs(ctx, 1)
-        t = ctx.timing()
         km, ks, pg = ctx.keff()
         _, c = ctx.generation_stats()
         ctx.close()
+        t = kernel_breakdown(mcx, prob, precision=prec)
         gk[prec] = (km, ks, pg)
         out[prec] = {"histories_per_s": round(n / sec, 1),
                      "events_per_s": round(float(c[:, 0].sum()) / sec, 1),
@@ -279,12 +291,12 @@ def time_dependent_measurement(P, mcx, cpu):
     for key, prob in (("pulsed_lattice", P.pulsed_lattice()),
                       ("ce_pulsed_pin_cell", P.ce_pulsed_pin_cell())):
         n = prob["run"]["n_per_gen"] * prob["run"]["n_gen"]
-        ctx = mcx.Context(prob, time_kernels=True)
+        ctx = mcx.Context(prob)
         sec = timed_runs(ctx, 1)
-        t = ctx.timing()
         _, c = ctx.generation_stats()
         tl = ctx.tallies()
         ctx.close()
+        t = kernel_breakdown(mcx, prob)
         r = {"histories_per_s": round(n / sec, 1),
              "events_per_s": round(float(c[:, 0].sum()) / sec, 1),
              "ms_per_step": round(sec * 1e3, 2),

@@ -340,8 +340,8 @@ __device__ __forceinline__ R watt_attempt(R a, R b, R x1, R x2, R x3, R x4) {
 }
 
 // Watt energy: attempts of four draws until one lies in (0, e_max].
-template <class R>
-__device__ __forceinline__ R watt_sample(const Tables& T, Stream& s) {
+template <class R, class S>
+__device__ __forceinline__ R watt_sample(const Tables& T, S& s) {
   const R a = (R)T.watt_a, b = (R)T.watt_b, e_max = (R)T.e_max;
   for (int t = 0; t < 10000; ++t) {
     const R x1 = Prec<R>::xi(s.next());
@@ -635,9 +635,9 @@ __device__ __forceinline__ ColCE<R> col_ce_stored(const Tables& T, const Geo& L,
   return c;
 }
 
-template <class R>
+template <class R, class S>
 __device__ __forceinline__ uint32_t fission_count_ce(const Tables& T, const ColCE<R>& c,
-                                                     Stream& rs, double k_used) {
+                                                     S& rs, double k_used) {
   if (T.fixed_source || !(c.nusf > R(0))) return 0u;
   const R xf = Prec<R>::xi(rs.next());
   const R f = floor(c.nusf / (c.x.st * (R)k_used) + xf);
@@ -647,8 +647,8 @@ __device__ __forceinline__ uint32_t fission_count_ce(const Tables& T, const ColC
 // Collision, second part: the nf sites reserved at slot (Watt energies),
 // the nuclide, then elastic scatter or absorption.  Returns FATE_ALIVE after
 // a scatter above the cutoff, FATE_CUTOFF or FATE_ABSORBED.
-template <class R>
-__device__ __forceinline__ int collide_rest_ce(const Tables& T, PartCE<R>& p, Stream& rs,
+template <class R, class S>
+__device__ __forceinline__ int collide_rest_ce(const Tables& T, PartCE<R>& p, S& rs,
                                                const ColCE<R>& c, uint32_t nf, uint32_t slot,
                                                const Accum& A, uint64_t* q_kabs) {
   for (uint32_t s = 0; s < nf; ++s) {
@@ -855,10 +855,14 @@ __global__ void __launch_bounds__(1024) k_ce_collide(Tables T, uint32_t gen, Ban
   ColCE<R> c;
   uint32_t nf = 0;
   uint64_t q_kcol = 0;
-  Stream rs(T.seed, TAG_TRANSPORT, 0, gen, T.prob, 0);
+  LockStream rs(T.seed, TAG_TRANSPORT, 0, gen, T.prob, 0);
   if (valid) {
     p = load_ce<R>(in, k);
-    rs = Stream(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
+    // both Philox blocks of the collision's first draws, evaluated by every
+    // lane at once
+    rs = LockStream(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
+    rs.top_up();
+    rs.fill_next();
     c = col_ce_stored<R>(T, T.geo, p, in, k);
     const double kc = (double)(c.nusf / c.x.st);
     q_kcol = quantize(kc, T.q_kcol);
