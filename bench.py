@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--lt-flights", type=int, default=0,
                     help="flights per particle of the LDS-staged advance launches "
                          "(0 = library default)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="headline: the event engine's launch configuration from the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-gens", type=int, default=4,
                     help="generations of the headline lattice the CPU oracle runs (about 10 s)")
@@ -353,6 +355,10 @@ def main():
     ctx = mcx.Context(prob, device=0, block_size=a.block, tail_threshold=a.tail,
                       time_kernels="advance", time_stride=TIME_STRIDE, flights=a.flights,
                       rounds=a.rounds, lds_tally_min=a.lds_tally_min, lt_flights=a.lt_flights)
+    tuned = None
+    if a.autotune:
+        tuned = ctx.autotune(a.tune_cache)
+        log(f"autotuned: {tuned}")
     for w in range(a.warmup):
         ctx.run()
         log(f"warmup {w + 1}/{a.warmup} done")

@@ -262,12 +262,15 @@ typedef struct {
   uint64_t problem_id;
 } mcx_problem;
 
-/* Persistent-engine launch configuration (mcx_autotune). */
+/* Launch configuration picked by mcx_autotune.  Persistent engine: block,
+   slots, grid, tau, sort.  Event engine: block (block_size), flights,
+   lt_flights and tail (tail_threshold); the other fields are 0. */
 typedef struct {
   int32_t block, slots, grid;
   double tau;
   double ms;                /* measured stream time of one batch (or generation) */
   int32_t sort;             /* collide lists ordered by material class */
+  int32_t flights, lt_flights, tail;
 } mcx_tune;
 
 /* Create a context on opt->device (NULL opt = defaults).  Project addition,
@@ -482,10 +485,13 @@ int mcx_get_batch_results(mcx_ctx* ctx, double* k, int64_t* counts);
    no passage. */
 int mcx_get_batch_tallies(mcx_ctx* ctx, int32_t p, double* flux, double* prod, int64_t n_bins);
 
-/* Pick the persistent-engine configuration (block, slots, grid, tau, then
-   the collide-list ordering) with the shortest measured run of the bound
+/* Pick the launch configuration with the shortest measured run of the bound
    problem or batch by timing a sweep of candidates on ctx's stream, and use
-   it from then on.  A non-NULL
+   it from then on: for the persistent engine and batches block, slots, grid,
+   tau, then the collide-list ordering; for the event engine (multigroup or
+   continuous energy) the block size, the flights per advance launch, the
+   flights of the LDS-staged launches and the tail threshold, two
+   generations per candidate.  A non-NULL
    cache_path names a text file of earlier results keyed by the workload's
    shape and the device: a hit skips the sweep, a miss appends the winner.
    Results do not depend on the configuration.  Overwrites the results of

@@ -2171,10 +2171,12 @@ static std::string tune_key(mcx_ctx* c) {
     dev = std::string(prop.gcnArchName) + "x" + std::to_string(prop.multiProcessorCount);
   // the shape of the workload: problems, histories, bins, materials, groups
   char buf[256];
-  std::snprintf(buf, sizeof buf, "dev=%s prec=%d batch=%d probs=%d hist=%llu bins=%d mat=%d grp=%d fixed=%d",
-                dev.c_str(), c->opt.precision, c->batch ? 1 : 0, c->batch ? c->n_probs : 1,
+  std::snprintf(buf, sizeof buf,
+                "dev=%s eng=%d prec=%d batch=%d probs=%d hist=%llu bins=%d mat=%d grp=%d fixed=%d ce=%d",
+                dev.c_str(), c->batch ? (int)MCX_ENGINE_PERSISTENT : c->opt.engine,
+                c->opt.precision, c->batch ? 1 : 0, c->batch ? c->n_probs : 1,
                 (unsigned long long)c->d.n_hist, c->d.n_bins, c->n_mat, c->G,
-                c->batch ? 1 : (c->src.fixed_source ? 1 : 0));
+                c->batch ? 1 : (c->src.fixed_source ? 1 : 0), c->ce ? 1 : 0);
   for (char* q = buf; *q; ++q)
     if (*q == '\n' || *q == '\t') *q = ' ';
   return buf;
@@ -2194,6 +2196,12 @@ static bool tune_lookup(const char* path, const std::string& key, mcx_tune* t) {
         persistent_config_valid(v.block, v.slots) && v.grid >= 1 && v.tau > 0.0 && v.tau <= 1.0 &&
         (v.sort == 0 || v.sort == 1)) {
       *t = v;  // the last matching line wins
+      hit = true;
+    } else if (std::sscanf(bar + 3, "event block=%d flights=%d lt_flights=%d tail=%d ms=%lf",
+                           &v.block, &v.flights, &v.lt_flights, &v.tail, &v.ms) == 5 &&
+               v.block >= 64 && v.block <= 1024 && v.block % 64 == 0 && v.flights >= 1 &&
+               v.flights <= 65536 && v.lt_flights >= 1 && v.lt_flights <= 65536 && v.tail > 0) {
+      *t = v;
       hit = true;
     }
   }
@@ -2217,13 +2225,79 @@ static int tune_trial(mcx_ctx* c, const PersistentCfg& cfg, double* ms) {
   return MCX_OK;
 }
 
+// Event engine: the block size, flights per advance launch, flights of the
+// LDS-staged launches and the tail threshold with the shortest run of two
+// generations.
+static int autotune_event(mcx_ctx* c, const char* cache_path, const std::string& key,
+                          mcx_tune* best) {
+  mcx_tune t{};
+  if (cache_path && tune_lookup(cache_path, key, &t) && t.flights > 0) {
+    c->opt.block_size = t.block;
+    c->opt.flights = t.flights;
+    c->opt.lt_flights = t.lt_flights;
+    c->opt.tail_threshold = t.tail;
+    if (best) *best = t;
+    return MCX_OK;
+  }
+  const int64_t N = c->d.N;
+  auto clamp_tail = [&](int64_t v) {
+    return (int)std::min<int64_t>(std::max<int64_t>(v, DEFAULT_TAIL), 1 << 20);
+  };
+  const int blocks[] = {256, 512};
+  const int flights[] = {6, 8};
+  const int lts[] = {3, 4, 5, 6};
+  const int tails[] = {clamp_tail(std::min<int64_t>(N / 16, DEFAULT_TAIL_MAX / 2)),
+                       clamp_tail(std::min<int64_t>(N / 8, DEFAULT_TAIL_MAX)),
+                       clamp_tail(std::min<int64_t>(N / 4, 2 * (int64_t)DEFAULT_TAIL_MAX))};
+  const mcx_options keep = c->opt;
+  double best_ms = 1e300;
+  mcx_tune win{};
+  for (int b : blocks)
+    for (int f : flights)
+      for (int lt : lts)
+        for (int tl : tails) {
+          c->opt.block_size = b;
+          c->opt.flights = f;
+          c->opt.lt_flights = lt;
+          c->opt.tail_threshold = tl;
+          // two generations per candidate (the first has its own source and
+          // k_used = 1), timed together
+          const int rc = mcx_run_generations(c, std::min(2, c->n_gen_max), 0);
+          if (rc != MCX_OK && rc != MCX_EGUARD) {
+            c->opt = keep;
+            return rc;
+          }
+          if (c->timing.run_ms < best_ms) {
+            best_ms = c->timing.run_ms;
+            win = mcx_tune{b, 0, 0, 0.0, best_ms, 0, f, lt, tl};
+          }
+        }
+  c->opt.block_size = win.block;
+  c->opt.flights = win.flights;
+  c->opt.lt_flights = win.lt_flights;
+  c->opt.tail_threshold = win.tail;
+  if (cache_path) {
+    FILE* f = std::fopen(cache_path, "a");
+    if (f) {
+      std::fprintf(f, "%s | event block=%d flights=%d lt_flights=%d tail=%d ms=%.4f\n",
+                   key.c_str(), win.block, win.flights, win.lt_flights, win.tail, win.ms);
+      std::fclose(f);
+    }
+  }
+  if (best) *best = win;
+  return MCX_OK;
+}
+
 int mcx_autotune(mcx_ctx* c, const char* cache_path, mcx_tune* best) {
   if (!c) return MCX_EINVAL;
   if (!c->bound) return fail(c, MCX_ESTATE, "bind a workspace first");
-  if (c->opt.engine == MCX_ENGINE_ASYNC || (!c->batch && c->opt.engine != MCX_ENGINE_PERSISTENT))
-    return fail(c, MCX_ESTATE, "the autotuner configures the persistent engine");
+  const bool event = !c->batch && c->opt.engine == MCX_ENGINE_EVENT;
+  if (!event && (c->opt.engine == MCX_ENGINE_ASYNC ||
+                 (!c->batch && c->opt.engine != MCX_ENGINE_PERSISTENT)))
+    return fail(c, MCX_ESTATE, "the autotuner configures the event and persistent engines");
   HIP_TRY(c, hipSetDevice(c->opt.device));
   const std::string key = tune_key(c);
+  if (event) return autotune_event(c, cache_path, key, best);
   mcx_tune t{};
   if (cache_path && tune_lookup(cache_path, key, &t)) {
     c->pcfg = PersistentCfg{t.block, t.slots, t.grid, t.tau, t.sort};
@@ -2276,7 +2350,7 @@ int mcx_autotune(mcx_ctx* c, const char* cache_path, mcx_tune* best) {
   }
   c->pcfg = win;
   drop_graph(c);
-  t = mcx_tune{win.block, win.slots, win.grid, win.tau, best_ms, win.sort};
+  t = mcx_tune{win.block, win.slots, win.grid, win.tau, best_ms, win.sort, 0, 0, 0};
   if (cache_path) {
     FILE* f = std::fopen(cache_path, "a");
     if (f) {

@@ -96,7 +96,8 @@ class Problem(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("block", C.c_int32), ("slots", C.c_int32), ("grid", C.c_int32),
-                ("tau", C.c_double), ("ms", C.c_double), ("sort", C.c_int32)]
+                ("tau", C.c_double), ("ms", C.c_double), ("sort", C.c_int32),
+                ("flights", C.c_int32), ("lt_flights", C.c_int32), ("tail", C.c_int32)]
 
 
 EVENT_DTYPE = np.dtype([
@@ -418,8 +419,10 @@ class Context:
         return {name: getattr(t, name) for name, _ in Timing._fields_}
 
     def autotune(self, cache_path=None):
-        """Persistent-engine configuration with the shortest measured run
-        (C++ sweep in the library, optionally cached in a text file)."""
+        """Launch configuration with the shortest measured run (persistent
+        engine: block, slots, grid, tau, sort; event engine: block, flights,
+        lt_flights, tail), swept in the library, optionally cached in a text
+        file."""
         t = Tune()
         path = None if cache_path is None else os.fsencode(cache_path)
         self._check(self.L.mcx_autotune(self.h, path, C.byref(t)))

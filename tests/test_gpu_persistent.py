@@ -234,6 +234,34 @@ def test_autotune_picks_a_valid_configuration_and_caches(tmp_path):
         b.close()
 
 
+def test_event_engine_autotune_picks_a_valid_configuration_and_caches(tmp_path):
+    """The event engine's autotuner: a configuration from its candidate sets
+    (block, flights, flights of the LDS-staged launches, tail threshold), a
+    cache hit on the second call, and a run afterwards equal bit for bit to
+    an untuned run (results do not depend on the launch configuration)."""
+    banner("event-engine autotune")
+    prob = P.lattice_17x17(n_per_gen=20000, n_gen=3, n_inactive=1)
+    cache = os.path.join(tmp_path, "tune.txt")
+    ref = mcx.run(prob, record=True)
+    ctx = mcx.Context(prob, record=True)
+    try:
+        t = ctx.autotune(cache)
+        assert t["block"] in (256, 512) and t["flights"] in (6, 8)
+        assert t["lt_flights"] in (3, 4, 5, 6) and t["tail"] >= 4096 and t["ms"] > 0
+        t2 = ctx.autotune(cache)  # cache hit
+        for k in ("block", "flights", "lt_flights", "tail"):
+            assert t2[k] == t[k], k
+        ctx.run()
+        m, s, pg = ctx.keff()
+        h, c = ctx.generation_stats()
+        assert np.array_equal(pg, ref["gen_k"])
+        assert np.array_equal(c, ref["gen_counts"])
+        for g in range(3):
+            assert np.array_equal(ctx.records(g), ref["records"][g])
+    finally:
+        ctx.close()
+
+
 def test_full_batch_512_problems():
     """The 512-problem batch (about 7.4e7 histories) in one launch: balance
     per problem, and sampled problems (smallest, largest, first) equal their
