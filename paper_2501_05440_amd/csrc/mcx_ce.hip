@@ -1134,6 +1134,8 @@ static void ce_advance_k(dim3 g, dim3 b, hipStream_t s, const Tables& T0, uint32
   if (lb) {
     Tables T = T0;
     T.lds_tally_off = 0;
+    T.lds_bin_lo = 0;
+    T.lds_bin_n = (uint32_t)T.n_bins;
     hipLaunchKernelGGL((k_ce_advance<R, REC, true>), g, b, lb, s, T, gen, flights, in, n_in, live,
                        n_live, col, n_col, A, Rc, clr_live, clr_col);
   } else {
@@ -1197,6 +1199,8 @@ hipError_t launch_ce_mono(int prec, bool rec, const Tables& T0, uint32_t gen, co
   const size_t lb = ce_lt_bytes(T0);
   Tables T = T0;
   T.lds_tally_off = 0;
+  T.lds_bin_lo = 0;
+  T.lds_bin_n = (uint32_t)T.n_bins;
 #define MCX_CE_MONO(R_, REC_)                                                                   \
   if (lb)                                                                                     \
     hipLaunchKernelGGL((k_ce_mono<R_, REC_, true>), g, b, lb, s, T, gen, in, n_in, out, n_out, A, \
@@ -1228,6 +1232,8 @@ hipError_t launch_ce_tail(int prec, bool rec, const Tables& T0, uint32_t gen, co
   const size_t lb = ce_lt_bytes(T0);
   Tables T = T0;
   T.lds_tally_off = 0;
+  T.lds_bin_lo = 0;
+  T.lds_bin_n = (uint32_t)T.n_bins;
 #define MCX_CE_TAIL(R_, REC_)                                                               \
   if (lb)                                                                                 \
     hipLaunchKernelGGL((k_ce_tail<R_, REC_, true>), g, b, lb, s, T, gen, in, n_in, A, Rc);  \

@@ -111,6 +111,9 @@ struct Tables {
   uint64_t n_hist_total;
   int tally_stripes;   // copies of the tally accumulators
   uint32_t lds_tally_off;  // byte offset of a block's staged flux words in dynamic LDS
+  // the staged words hold tally bins [lds_bin_lo, lds_bin_lo + lds_bin_n);
+  // other bins go to device memory directly
+  uint32_t lds_bin_lo, lds_bin_n;
   double q_flux, q_kcol, q_kabs;  // fixed-point scales 2^s
   int64_t max_events;
   // continuous energy (ce != 0; then G counts the flux tally's energy bins)

@@ -1161,6 +1161,8 @@ hipError_t launch_advance_lt(int prec, bool rec, const Tables& T0, uint32_t gen,
     return hipErrorInvalidValue;
   Tables T = T0;
   T.lds_tally_off = (uint32_t)((tb + 15) & ~(size_t)15);
+  T.lds_bin_lo = 0;
+  T.lds_bin_n = (uint32_t)T.n_bins;
   const size_t lb = advance_lt_lds_bytes(prec, T0);
   const unsigned nb = std::max(1u, nblk(bound, (unsigned)block));
   const dim3 g(std::min(nb, (unsigned)max_grid)), b(block);

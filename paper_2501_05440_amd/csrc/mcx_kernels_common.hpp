@@ -444,43 +444,57 @@ __device__ __forceinline__ unsigned long long* lds_tally(const Tables& T) {
   return reinterpret_cast<unsigned long long*>(lds_tab + T.lds_tally_off);
 }
 
-// Zero the block's LDS flux words (every thread of the block calls it).
+// Zero the block's LDS flux words, lds_bin_n bins (every thread of the block
+// calls it).
 __device__ __forceinline__ void lds_tally_clear(const Tables& T) {
   unsigned long long* tw = lds_tally(T);
-  for (uint32_t w = threadIdx.x; w < 2u * (uint32_t)T.n_bins; w += blockDim.x) tw[w] = 0ull;
+  for (uint32_t w = threadIdx.x; w < 2u * T.lds_bin_n; w += blockDim.x) tw[w] = 0ull;
   __syncthreads();
 }
 
 // Add each nonzero bin of the block's LDS flux words to the bin's 128-bit
 // pair in the block's stripe of device memory: lo + hi 2^32 exactly, one
-// add per bin (every thread of the block calls it).
-__device__ __forceinline__ void lds_tally_flush(const Tables& T, const Accum& A) {
+// add per bin (every thread of the block calls it).  zero: clear the words
+// too (for a window that moves on).
+__device__ __forceinline__ void lds_tally_flush(const Tables& T, const Accum& A,
+                                                bool zero = false) {
   __syncthreads();
-  const unsigned long long* tw = lds_tally(T);
+  unsigned long long* tw = lds_tally(T);
   unsigned long long* tb =
-      A.tally + (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins);
-  for (uint32_t b = threadIdx.x; b < (uint32_t)T.n_bins; b += blockDim.x) {
+      A.tally + (size_t)(blockIdx.x % (unsigned)T.tally_stripes) * (size_t)(2 * T.n_bins) +
+      2 * (size_t)T.lds_bin_lo;
+  for (uint32_t b = threadIdx.x; b < T.lds_bin_n; b += blockDim.x) {
     const unsigned long long lo = tw[2 * b], hi = tw[2 * b + 1];
     if ((lo | hi) == 0ull) continue;
     const unsigned long long w0 = lo + (hi << 32);
     const unsigned long long w1 = (hi >> 32) + (w0 < lo ? 1ull : 0ull);
     acc_add128(tb + 2 * b, w0, w1);
+    if (zero) {
+      tw[2 * b] = 0ull;
+      tw[2 * b + 1] = 0ull;
+    }
   }
+  if (zero) __syncthreads();
 }
 
 // One exact fixed-point flux term q (< 2^61) of bin `bin`.  TLDS: into the
 // block's LDS words as two 32-bit halves (LDS atomics, flushed once per
-// block); HALVES: the same halves as two non-returning atomics on the global
+// block) when the bin is in the block's window, else as below; HALVES: the same halves as two non-returning atomics on the global
 // half words; otherwise one returning 64-bit atomic on a 128-bit pair with a
 // carry word.
 template <bool HALVES, bool TLDS>
 __device__ __forceinline__ void flux_term(const Tables& T, unsigned long long* tb,
                                           unsigned long long* tt, int bin, uint64_t q) {
   if constexpr (TLDS) {
-    if (q) {
-      unsigned long long* w = lds_tally(T);
-      atomicAdd(w + 2 * bin, (unsigned long long)(q & 0xFFFFFFFFull));
-      atomicAdd(w + 2 * bin + 1, (unsigned long long)(q >> 32));
+    const uint32_t b = (uint32_t)bin - T.lds_bin_lo;
+    if (b < T.lds_bin_n) {
+      if (q) {
+        unsigned long long* w = lds_tally(T);
+        atomicAdd(w + 2 * b, (unsigned long long)(q & 0xFFFFFFFFull));
+        atomicAdd(w + 2 * b + 1, (unsigned long long)(q >> 32));
+      }
+    } else {
+      acc_add(tb + 2 * bin, q);  // outside the block's window
     }
   } else if constexpr (HALVES) {
     if (q) {

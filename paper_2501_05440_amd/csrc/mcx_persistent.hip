@@ -44,7 +44,17 @@ struct SlotMem {
   uint32_t n_list, n_free, got;
   uint32_t base;
   uint32_t exhausted;
+  uint32_t win_move, win_next;  // the tally window moves to bin win_next
 };
+
+// Flux words staged per block: a window of at most P_WIN_BINS tally bins
+// (16 B each) after the slots in LDS.  Histories enter a block in global
+// order, so a block works on a few consecutive problems of a batch at a
+// time; the window starts at the first bin of the problem of the chunk a
+// refill takes, and moves (after adding its words to device memory) when
+// that problem's bins leave it.  Flights of a bin outside it add to device
+// memory directly.
+constexpr uint32_t P_WIN_BINS = 256;
 
 template <class R, int S>
 __device__ __forceinline__ Part<R> slot_load(const SlotMem<R, S>& M, int s, const ProbDesc* P) {
@@ -129,7 +139,7 @@ __global__ void __launch_bounds__(PB) k_persistent(Tables T0, uint32_t gen, Accu
                                                    const double* sx, const double* sy,
                                                    const int32_t* sg,
                                                    const uint32_t* prev_status, int sort) {
-  const Tables T = kernel_tables<R, false>(T0);
+  Tables T = kernel_tables<R, false>(T0);
   extern __shared__ unsigned char lds_raw[];
   SlotMem<R, S>& M = *reinterpret_cast<SlotMem<R, S>*>(lds_raw);
   const ProbDesc* P = T.probs;
@@ -148,7 +158,7 @@ __global__ void __launch_bounds__(PB) k_persistent(Tables T0, uint32_t gen, Accu
 
   for (int s = threadIdx.x; s < S; s += PB) M.state[s] = SL_FREE;
   if (threadIdx.x == 0) M.exhausted = 0;
-  __syncthreads();
+  lds_tally_clear(T);  // (a barrier)
 
   for (;;) {
     // ---------------- refill ----------------
@@ -166,8 +176,23 @@ __global__ void __launch_bounds__(PB) k_persistent(Tables T0, uint32_t gen, Accu
           if ((uint64_t)b + want >= total) M.exhausted = 1;
         }
       }
+      // the tally window follows the problem of the new chunk
+      M.win_move = 0;
+      if (M.got && P) {
+        const int pi0 = problem_of(P, T.n_probs, (uint64_t)M.base);
+        const uint32_t lo0 = (uint32_t)P[pi0].geo.bin_base;
+        const uint32_t nb0 = (uint32_t)P[pi0].n_bins;
+        if (lo0 < T.lds_bin_lo || lo0 + min(nb0, T.lds_bin_n) > T.lds_bin_lo + T.lds_bin_n) {
+          M.win_move = 1;
+          M.win_next = lo0;
+        }
+      }
     }
     __syncthreads();
+    if (M.win_move) {
+      lds_tally_flush(T, A, true);
+      T.lds_bin_lo = M.win_next;
+    }
     const uint32_t got = M.got;
     if (got) {
       build_list<R, PB, S>(M, SL_FREE);  // got <= number of free slots
@@ -227,7 +252,7 @@ __global__ void __launch_bounds__(PB) k_persistent(Tables T0, uint32_t gen, Accu
       Stream rs(P ? P[pi].seed : T.seed, TAG_TRANSPORT, p.id, gen, P ? P[pi].prob : T.prob,
                 p.ctr);
       bool refl = false;
-      const int ev = segment<R, false, false>(T, L, p, rs, A, Rc, &refl);
+      const int ev = segment<R, false, false, Stream, true>(T, L, p, rs, A, Rc, &refl);
       p.ctr = rs.draw;
       M.nseg[s] += 1;
       if (ev == EV_CROSS || ev == EV_LEAK) M.ncross[s] += 1;
@@ -294,6 +319,7 @@ __global__ void __launch_bounds__(PB) k_persistent(Tables T0, uint32_t gen, Accu
     }
     __syncthreads();
   }
+  lds_tally_flush(T, A);
 }
 
 // Per-problem reduction of the per-history outputs: exact counter sums and
@@ -422,8 +448,12 @@ static hipError_t launch_p(unsigned grid, const Tables& T, uint32_t gen, const A
                            const HistOut& H, uint32_t* work, uint32_t tau, const double* sx,
                            const double* sy, const int32_t* sg, const uint32_t* prev_status,
                            int sort, hipStream_t s) {
-  const size_t lds = sizeof(SlotMem<R, S>);
-  hipLaunchKernelGGL((k_persistent<R, PB, S>), dim3(grid), dim3(PB), lds, s, T, gen, A, H, work,
+  Tables Tw = T;
+  Tw.lds_tally_off = (uint32_t)((sizeof(SlotMem<R, S>) + 15) & ~(size_t)15);
+  Tw.lds_bin_lo = 0;
+  Tw.lds_bin_n = std::min<uint32_t>((uint32_t)T.n_bins, P_WIN_BINS);
+  const size_t lds = Tw.lds_tally_off + 16 * (size_t)Tw.lds_bin_n;
+  hipLaunchKernelGGL((k_persistent<R, PB, S>), dim3(grid), dim3(PB), lds, s, Tw, gen, A, H, work,
                      tau, sx, sy, sg, prev_status, sort);
   return hipGetLastError();
 }
@@ -457,14 +487,15 @@ hipError_t launch_persistent(int prec, const PersistentCfg& cfg, const Tables& T
 
 size_t persistent_lds_bytes(int prec, int block, int slots) {
   (void)block;
+  size_t b = 0;
   if (prec == 0) {
-    if (slots == 256) return sizeof(SlotMem<double, 256>);
-    if (slots == 512) return sizeof(SlotMem<double, 512>);
+    if (slots == 256) b = sizeof(SlotMem<double, 256>);
+    if (slots == 512) b = sizeof(SlotMem<double, 512>);
   } else {
-    if (slots == 256) return sizeof(SlotMem<float, 256>);
-    if (slots == 512) return sizeof(SlotMem<float, 512>);
+    if (slots == 256) b = sizeof(SlotMem<float, 256>);
+    if (slots == 512) b = sizeof(SlotMem<float, 512>);
   }
-  return 0;
+  return b ? ((b + 15) & ~(size_t)15) + 16 * (size_t)P_WIN_BINS : 0;
 }
 
 bool persistent_config_valid(int block, int slots) {
