@@ -25,6 +25,12 @@
  * distance and cos/sin(2 pi xi) for the azimuth, are taken correctly rounded
  * (the binary64 value nearest the exact result), so that the result of every
  * operation of a history has a single definition independent of any libm.
+ *
+ * Parity unpinned: the k estimates and tallies of the heterogeneous problems
+ * (the pin cell, the 17x17 lattice, the continuous-energy pin cell) have no
+ * closed form; they are pinned only through the closed-form limits the tests
+ * reduce them to (infinite media, one-material cells, slabs, symmetric
+ * lattices), through invariants, and through agreement with the GPU path.
  */
 #define _GNU_SOURCE
 #include "oracle.h"
