@@ -133,6 +133,8 @@ struct Dev {
   double *k_used = nullptr, *xi0 = nullptr, *k_stat = nullptr;
   double *tal_stat = nullptr;  // [mean flux | mean prod | sigma flux | sigma prod]
   uint32_t* ent_hist = nullptr;
+  uint32_t* bk_fill = nullptr;  // per bucket of canonical positions: sites filed
+  Staging st{};                 // sites filed by bucket (k-eigenvalue runs)
   double* tl_part = nullptr;  // per-block production sums of the generation tallies
   uint32_t* gen_status = nullptr;  // [n_gen_max] status bits per generation
   // persistent engine: per-history outputs, work counter
@@ -202,6 +204,7 @@ struct mcx_ctx {
 
   // results of the last run
   int last_n_gen = 0, last_n_inactive = 0, req_n_inactive = 0;
+  int run_last_gen = -1;  // the last generation of the run in progress
   bool ran = false, can_continue = false;
   std::vector<double> h_gen_k, h_gen_h, h_kstat;
   std::vector<unsigned long long> h_gen_cnt;
@@ -820,6 +823,13 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   d.can_y = cv.take<double>(fis_cap);
   d.can_g = cv.take<int32_t>(fis_cap);
   d.can_e = ce ? cv.take<double>(fis_cap) : nullptr;
+  const bool keig = !batch && !c->src.fixed_source;
+  const size_t n_bk = keig ? bank_buckets(fis_cap) : 0;
+  if (keig) {
+    const size_t n_st = n_bk * 1024;
+    d.st.mg = ce ? nullptr : cv.take<StSite>(n_st);
+    d.st.ce = ce ? cv.take<StSiteCE>(n_st) : nullptr;
+  }
   A.nsite_id = cv.take<uint32_t>(std::max<size_t>(N, n_hist));
   if (persistent) {
     d.h_kcol = cv.take<unsigned long long>(2 * n_hist);
@@ -867,7 +877,7 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   const size_t w_tally_t = (size_t)stripes * 2 * nb;
   const size_t w_k = 3 * STRIPES * 2;
   const size_t w_cnt = (size_t)N_CNT_ALL * STRIPES;
-  const size_t w_misc = 2 + (n_ent + 1) / 2;
+  const size_t w_misc = 2 + (n_ent + 1) / 2 + (n_bk + 1) / 2;
   const size_t w_prob = batch ? (size_t)c->n_probs * (N_CNT + 4) : 0;
   // continuous-energy time-dependent mode: the density accumulators
   const size_t w_dens = (ce && !c->t_edges.empty()) ? w_tally + w_tally_t : 0;
@@ -887,6 +897,7 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
     A.n_fis = reinterpret_cast<uint32_t*>(pw);
     d.work = reinterpret_cast<uint32_t*>(pw + 1);
     d.ent_hist = reinterpret_cast<uint32_t*>(pw + 2);
+    d.bk_fill = n_bk ? reinterpret_cast<uint32_t*>(pw + 2 + (n_ent + 1) / 2) : nullptr;
     pw += w_misc;
     A.dens = w_dens ? pw : nullptr;
     A.dens_t = w_dens ? pw + w_tally : nullptr;
@@ -1409,13 +1420,14 @@ static int generation_end(mcx_ctx* c, int gen) {
   if (!T.fixed_source) {
     HIP_TRY(c, launch_scan(A.nsite_id, N, c->d.chunk_sum, c->d.offs, c->d.scan_total, s));
     HIP_TRY(c, launch_gen_check(T, A.n_fis, c->d.scan_total, A.status, s));
-    HIP_TRY(c, launch_canon(A.fis, A.n_fis, c->d.offs, A.nsite_id, c->d.fis_cap, c->d.can_x,
-                            c->d.can_y, c->d.can_g, c->d.can_e, A.status, c->d.fis_cap, s));
-    HIP_TRY(c, launch_entropy(T, gen, c->d.can_x, c->d.can_y, A.n_fis, c->d.fis_cap, c->d.ent_hist,
-                              c->d.gen_h, c->d.fis_cap, s));
-    HIP_TRY(c, launch_comb(N, A.n_fis, c->d.fis_cap, c->d.xi0, c->d.can_x, c->d.can_y,
-                           c->d.can_g, c->d.can_e, c->d.src_x, c->d.src_y, c->d.src_g,
-                           c->d.src_e, s));
+    // the canonical bank is kept for mcx_get_bank: written out in the run's
+    // last generation only
+    const bool keep = gen == c->run_last_gen;
+    HIP_TRY(c, launch_bank_end(T, gen, A.fis, A.n_fis, c->d.offs, c->d.fis_cap, c->d.bk_fill,
+                               c->d.st, N, c->d.xi0, keep ? c->d.can_x : nullptr,
+                               keep ? c->d.can_y : nullptr, keep ? c->d.can_g : nullptr,
+                               keep ? c->d.can_e : nullptr, c->d.src_x, c->d.src_y, c->d.src_g,
+                               c->d.src_e, c->d.ent_hist, c->d.gen_h, A.status, s));
   } else {
     HIP_TRY(c, launch_fill_u64(reinterpret_cast<unsigned long long*>(c->d.gen_h + gen), 1, 0ull, s));
   }
@@ -1515,6 +1527,7 @@ static int run_range(mcx_ctx* c, int g0, int g1, int n_inactive) {
   // once the run has finished (a failed generation makes the later ones run
   // empty)
   int rc = MCX_OK;
+  c->run_last_gen = g1 - 1;
   for (int g = g0; g < g1; ++g) {
     rc = run_generation(c, g);
     if (rc != MCX_OK) break;

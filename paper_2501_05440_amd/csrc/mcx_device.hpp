@@ -193,6 +193,23 @@ struct Sites {
   double* e;  // continuous energy: site energies
 };
 
+// Fission sites filed by bucket of canonical positions (generation end), one
+// record per site: key = position within the bucket (low 16 bits) | group << 16.
+struct StSite {
+  double x, y;
+  uint32_t key;
+  int32_t pad;
+};
+struct StSiteCE {
+  double x, y, e;
+  uint32_t key;
+  int32_t pad;
+};
+struct Staging {
+  StSite* mg;
+  StSiteCE* ce;  // continuous energy (then mg is null)
+};
+
 // One logged flight: position after it, its length and energy, the cell,
 // region and group (or energy bin) it flew in, and how it ended
 // (1 collision, 2 surface crossing, 3 leak, 4 census).

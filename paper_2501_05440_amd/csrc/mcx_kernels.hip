@@ -692,28 +692,179 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_chunk(const uint32_t* in,
   }
 }
 
-// Canonical bank: site s of history parent goes to offset[parent] + seq.
-__global__ void k_canon(Sites fis, const uint32_t* n_fis_p, const uint32_t* offs,
-                        const uint32_t* nsite_id, uint32_t cap, double* cx, double* cy,
-                        int32_t* cg, double* ce, uint32_t* status) {
+// Canonical bank, entropy and combing, in two passes over the banked sites.
+// Site seq of history parent has canonical position offset[parent] + seq.
+// Pass 1 (k_bucket) files every site, in banking order, under the bucket of
+// BK_SIZE consecutive canonical positions that holds its position (one
+// atomic per bucket and wavefront, one record per site).  Pass 2 (k_place)
+// loads a bucket into LDS, each site at its place, writes the canonical
+// entries in order, bins them on the entropy mesh, and writes the source
+// entries of the next generation that combing takes from those positions.
+// Writing each site straight to its canonical position instead scatters
+// single words over partial cache lines.  A site whose seq is not below its
+// history's count lands on a position of another history or past the bank:
+// pass 2 finds it as a position claimed twice or a bucket count that does not
+// match.
+constexpr uint32_t BK_SHIFT = 10;
+constexpr uint32_t BK_SIZE = 1u << BK_SHIFT;
+
+template <bool CE>
+__global__ void __launch_bounds__(256) k_bucket(Sites fis, const uint32_t* n_fis_p,
+                                                const uint32_t* offs, uint32_t cap,
+                                                uint32_t* bk_fill, Staging st,
+                                                uint32_t* status) {
   const uint32_t n = min(*n_fis_p, cap);
-  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
-    const uint32_t par = fis.parent[s];
-    const uint32_t q = fis.seq[s];
-    if (q >= nsite_id[par]) {
-      atomicOr(status, ST_SITE_SEQ);
-      continue;
+  const uint32_t lane = lane_id();
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  // the loop runs on the index of the wavefront's first lane, so every lane
+  // takes the same trips and the ballots below see the whole wavefront
+  for (uint32_t s0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); s0 < n; s0 += stride) {
+    const uint32_t s = s0 + lane;
+    bool ok = s < n;
+    uint32_t pos = 0;
+    if (ok) {
+      pos = offs[fis.parent[s]] + fis.seq[s];
+      if (pos >= cap) {  // after an overflow, which the host reports, or a bad seq
+        atomicOr(status, ST_OVERFLOW);
+        ok = false;
+      }
     }
-    const uint32_t pos = offs[par] + q;
-    if (pos >= cap) {  // only after an overflow, which the host reports
-      atomicOr(status, ST_OVERFLOW);
-      continue;
+    const uint32_t bk = pos >> BK_SHIFT;
+    uint32_t slot = 0;
+    unsigned long long todo = __ballot(ok);
+    while (todo != 0ull) {
+      const int leader = __ffsll((long long)todo) - 1;
+      const uint32_t lb = __shfl(bk, leader);
+      const unsigned long long same = __ballot(ok && bk == lb) & todo;
+      uint32_t base = 0;
+      if ((int)lane == leader) base = atomicAdd(&bk_fill[lb], (uint32_t)__popcll(same));
+      base = __shfl(base, leader);
+      if ((same >> lane) & 1ull) slot = base + (uint32_t)__popcll(same & below);
+      todo &= ~same;
     }
-    cx[pos] = fis.x[s];
-    cy[pos] = fis.y[s];
-    cg[pos] = fis.g[s];
-    if (ce) ce[pos] = fis.e[s];
+    if (ok) {
+      if (slot >= BK_SIZE) {  // more sites than positions: two claim one
+        atomicOr(status, ST_SCAN);
+      } else {
+        const size_t e = ((size_t)bk << BK_SHIFT) + slot;
+        const uint32_t key = (pos & (BK_SIZE - 1u)) | ((uint32_t)fis.g[s] << 16);
+        if (CE)
+          st.ce[e] = StSiteCE{fis.x[s], fis.y[s], fis.e[s], key, 0};
+        else
+          st.mg[e] = StSite{fis.x[s], fis.y[s], key, 0};
+      }
+    }
   }
+}
+
+// Combing: source site i of the next generation is canonical entry
+// floor((i + xi0) M / N), capped at M - 1 (non-decreasing in i).
+__device__ __forceinline__ uint32_t comb_pick(uint32_t i, double xi0, uint32_t m, uint32_t n) {
+  const double t = ((double)i + xi0) * (double)m / (double)n;
+  uint64_t k = (uint64_t)floor(t);
+  if (k > m - 1) k = m - 1;
+  return (uint32_t)k;
+}
+
+// The smallest i in [0, n] whose pick is at least target (n if none): an
+// estimate from the inverse, then exact steps with comb_pick itself, so the
+// source indices of neighbouring buckets meet without gap or overlap.
+__device__ uint32_t comb_first(uint32_t target, double xi0, uint32_t m, uint32_t n) {
+  if (target == 0u) return 0u;
+  const double est = ceil((double)target * (double)n / (double)m - xi0);
+  uint32_t i = est <= 0.0 ? 0u : (est >= (double)n ? n : (uint32_t)est);
+  while (i > 0u && comb_pick(i - 1u, xi0, m, n) >= target) --i;
+  while (i < n && comb_pick(i, xi0, m, n) < target) ++i;
+  return i;
+}
+
+constexpr int PLACE_HIST = 4096;  // entropy meshes up to this many bins are binned in LDS
+
+template <bool CE>
+__global__ void __launch_bounds__(256) k_place(Tables T, const uint32_t* n_fis_p, uint32_t cap,
+                                               uint32_t n, const double* xi0_p,
+                                               const uint32_t* bk_fill, Staging st, double* cx,
+                                               double* cy, int32_t* cg, double* ce, double* sx,
+                                               double* sy, int32_t* sg, double* se,
+                                               uint32_t* hist, uint32_t* status) {
+  __shared__ double lx[BK_SIZE], ly[BK_SIZE];
+  __shared__ double le[CE ? BK_SIZE : 1];
+  __shared__ int32_t lg[BK_SIZE];
+  __shared__ uint32_t h[PLACE_HIST];
+  __shared__ uint32_t seen[BK_SIZE / 32];
+  __shared__ uint32_t range[2];
+  const uint32_t m = min(*n_fis_p, cap);
+  const double xi0 = *xi0_p;
+  const int nb = T.ent_nx * T.ent_ny;
+  const bool in_lds = nb <= PLACE_HIST;
+  if (in_lds)
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) h[b] = 0u;
+  __syncthreads();
+  const uint32_t n_bk = (uint32_t)(((uint64_t)m + BK_SIZE - 1u) >> BK_SHIFT);
+  for (uint32_t b = blockIdx.x; b < n_bk; b += gridDim.x) {
+    const uint32_t k0 = b << BK_SHIFT;
+    const uint32_t cnt = min(BK_SIZE, m - k0);
+    if (bk_fill[b] != cnt) {  // positions missing or claimed twice
+      if (threadIdx.x == 0) atomicOr(status, ST_SCAN);
+      continue;
+    }
+    if (threadIdx.x < 2) range[threadIdx.x] = comb_first(k0 + threadIdx.x * cnt, xi0, m, n);
+    if (threadIdx.x < BK_SIZE / 32) seen[threadIdx.x] = 0u;
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < cnt; t += blockDim.x) {
+      const size_t e = (size_t)k0 + t;  // bucket b's staging entries start at b * BK_SIZE
+      double x, y, en = 0.0;
+      uint32_t key;
+      if (CE) {
+        const StSiteCE r = st.ce[e];
+        x = r.x;
+        y = r.y;
+        en = r.e;
+        key = r.key;
+      } else {
+        const StSite r = st.mg[e];
+        x = r.x;
+        y = r.y;
+        key = r.key;
+      }
+      const uint32_t p = key & (BK_SIZE - 1u);
+      if (atomicOr(&seen[p >> 5], 1u << (p & 31u)) & (1u << (p & 31u)))
+        atomicOr(status, ST_SCAN);  // position claimed twice
+      lx[p] = x;
+      ly[p] = y;
+      lg[p] = (int32_t)(key >> 16);
+      if (CE) le[p] = en;
+      int bx = (int)floor((x - T.geo.x0) / T.geo.width * (double)T.ent_nx);
+      int by = (int)floor((y - T.geo.y0) / T.geo.height * (double)T.ent_ny);
+      bx = bx < 0 ? 0 : (bx > T.ent_nx - 1 ? T.ent_nx - 1 : bx);
+      by = by < 0 ? 0 : (by > T.ent_ny - 1 ? T.ent_ny - 1 : by);
+      if (in_lds)
+        atomicAdd(&h[by * T.ent_nx + bx], 1u);
+      else
+        atomicAdd(&hist[by * T.ent_nx + bx], 1u);
+    }
+    __syncthreads();
+    if (cx)  // the canonical bank itself is kept only when asked for
+      for (uint32_t t = threadIdx.x; t < cnt; t += blockDim.x) {
+        cx[k0 + t] = lx[t];
+        cy[k0 + t] = ly[t];
+        cg[k0 + t] = lg[t];
+        if (CE) ce[k0 + t] = le[t];
+      }
+    const uint32_t i1 = range[1];
+    for (uint32_t i = range[0] + threadIdx.x; i < i1; i += blockDim.x) {
+      const uint32_t k = comb_pick(i, xi0, m, n) - k0;
+      sx[i] = lx[k];
+      sy[i] = ly[k];
+      sg[i] = lg[k];
+      if (CE) se[i] = le[k];
+    }
+    __syncthreads();  // the next bucket reuses the LDS arrays and the range
+  }
+  if (in_lds)
+    for (int b = threadIdx.x; b < nb; b += blockDim.x)
+      if (h[b]) atomicAdd(&hist[b], h[b]);
 }
 
 // Exact wave-wide sums (one wave of 64 lanes, one stripe per lane).
@@ -900,37 +1051,6 @@ __global__ void __launch_bounds__(64 * GT_WAVES) k_gen_tallies(Tables T, uint32_
 
 int gen_tally_blocks(int n_bins) { return (n_bins + GT_BINS - 1) / GT_BINS; }
 
-// Shannon entropy of the canonical bank over the entropy mesh: per-block
-// histograms in LDS (meshes up to LDS_HIST bins), merged with one global
-// atomic per nonzero bin and block.
-constexpr int LDS_HIST = 8192;
-
-__global__ void __launch_bounds__(256) k_entropy_hist(Tables T, const double* cx, const double* cy,
-                                                     const uint32_t* n_p, uint32_t cap,
-                                                     uint32_t* hist) {
-  __shared__ uint32_t h[LDS_HIST];
-  const int nb = T.ent_nx * T.ent_ny;
-  const bool in_lds = nb <= LDS_HIST;
-  if (in_lds)
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) h[b] = 0u;
-  __syncthreads();
-  const uint32_t n = min(*n_p, cap);
-  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
-    int bx = (int)floor((cx[s] - T.geo.x0) / T.geo.width * (double)T.ent_nx);
-    int by = (int)floor((cy[s] - T.geo.y0) / T.geo.height * (double)T.ent_ny);
-    bx = bx < 0 ? 0 : (bx > T.ent_nx - 1 ? T.ent_nx - 1 : bx);
-    by = by < 0 ? 0 : (by > T.ent_ny - 1 ? T.ent_ny - 1 : by);
-    if (in_lds)
-      atomicAdd(&h[by * T.ent_nx + bx], 1u);
-    else
-      atomicAdd(&hist[by * T.ent_nx + bx], 1u);
-  }
-  __syncthreads();
-  if (in_lds)
-    for (int b = threadIdx.x; b < nb; b += blockDim.x)
-      if (h[b]) atomicAdd(&hist[b], h[b]);
-}
-
 // H = -sum_b p_b log2 p_b: the terms in parallel, summed in a fixed-order
 // tree.
 __global__ void __launch_bounds__(256) k_entropy_final(Tables T, uint32_t gen,
@@ -965,24 +1085,6 @@ __global__ void k_gen_check(Tables T, const uint32_t* n_fis, const uint32_t* sca
   if (*scan_total != *n_fis) st |= ST_SCAN;
   if (*n_fis == 0) st |= ST_EXTINCT;
   if (st) atomicOr(status, st);
-}
-
-// Combing: source site i of the next generation is canonical entry
-// floor((i + xi0) M / N), capped at M - 1.
-__global__ void k_comb(uint32_t n, const uint32_t* m_p, uint32_t cap, const double* xi0_p,
-                       const double* cx, const double* cy, const int32_t* cg, const double* ce,
-                       double* sx, double* sy, int32_t* sg, double* se) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t m = min(*m_p, cap);  // m > cap only after an overflow
-  if (m == 0) return;
-  const double t = ((double)i + *xi0_p) * (double)m / (double)n;
-  uint64_t k = (uint64_t)floor(t);
-  if (k > m - 1) k = m - 1;
-  sx[i] = cx[k];
-  sy[i] = cy[k];
-  sg[i] = cg[k];
-  if (se) se[i] = ce[k];
 }
 
 // Active-generation mean and standard deviation of the mean, per bin, and
@@ -1334,16 +1436,6 @@ hipError_t launch_gen_check(const Tables& T, const uint32_t* n_fis, const uint32
   return hipGetLastError();
 }
 
-hipError_t launch_canon(const Sites& fis, const uint32_t* n_fis, const uint32_t* offs,
-                        const uint32_t* nsite_id, uint32_t cap, double* cx, double* cy,
-                        int32_t* cg, double* ce, uint32_t* status, uint32_t bound,
-                        hipStream_t s) {
-  const unsigned g = std::max(1u, std::min(nblk(bound, 256), 8192u));
-  hipLaunchKernelGGL(k_canon, dim3(g), dim3(256), 0, s, fis, n_fis, offs, nsite_id, cap, cx, cy,
-                     cg, ce, status);
-  return hipGetLastError();
-}
-
 hipError_t launch_gen_totals(const Tables& T, uint32_t gen, uint32_t n, const Accum& A,
                              const double* tl_part, double* gen_k, unsigned long long* gen_cnt,
                              uint32_t* gen_m, double* k_used, double* xi0, hipStream_t s) {
@@ -1359,20 +1451,34 @@ hipError_t launch_gen_tallies(const Tables& T, uint32_t gen, uint32_t n, const A
   return hipGetLastError();
 }
 
-hipError_t launch_entropy(const Tables& T, uint32_t gen, const double* cx, const double* cy,
-                          const uint32_t* n_p, uint32_t cap, uint32_t* hist, double* gen_h,
-                          uint32_t bound, hipStream_t s) {
-  const unsigned g = std::max(1u, std::min(nblk(bound, 256 * 16), 1024u));
-  hipLaunchKernelGGL(k_entropy_hist, dim3(g), dim3(256), 0, s, T, cx, cy, n_p, cap, hist);
-  hipLaunchKernelGGL(k_entropy_final, dim3(1), dim3(256), 0, s, T, gen, hist, n_p, gen_h);
-  return hipGetLastError();
-}
+uint32_t bank_buckets(uint32_t cap) { return nblk(cap, (int)BK_SIZE); }
 
-hipError_t launch_comb(uint32_t n, const uint32_t* m_p, uint32_t cap, const double* xi0,
-                       const double* cx, const double* cy, const int32_t* cg, const double* ce,
-                       double* sx, double* sy, int32_t* sg, double* se, hipStream_t s) {
-  hipLaunchKernelGGL(k_comb, dim3(nblk(n, 256)), dim3(256), 0, s, n, m_p, cap, xi0, cx, cy, cg,
-                     ce, sx, sy, sg, se);
+hipError_t launch_bank_end(const Tables& T, uint32_t gen, const Sites& fis, const uint32_t* n_fis,
+                           const uint32_t* offs, uint32_t cap,
+                           uint32_t* bk_fill, const Staging& st, uint32_t n, const double* xi0,
+                           double* cx, double* cy, int32_t* cg, double* ce, double* sx,
+                           double* sy, int32_t* sg, double* se, uint32_t* hist, double* gen_h,
+                           uint32_t* status, hipStream_t s) {
+  // the staging records carved decide the form (cx/cy/cg/ce may be null)
+  const bool is_ce = st.ce != nullptr;
+  if (is_ce ? (st.mg != nullptr || !fis.e || !se) : (st.mg == nullptr || se != nullptr))
+    return hipErrorInvalidValue;
+  if (!bk_fill || !hist || (cx && (!cy || !cg || (is_ce && !ce)))) return hipErrorInvalidValue;
+  const unsigned g1 = std::max(1u, std::min(nblk(cap, 256), 8192u));
+  if (is_ce)
+    hipLaunchKernelGGL((k_bucket<true>), dim3(g1), dim3(256), 0, s, fis, n_fis, offs, cap,
+                       bk_fill, st, status);
+  else
+    hipLaunchKernelGGL((k_bucket<false>), dim3(g1), dim3(256), 0, s, fis, n_fis, offs, cap,
+                       bk_fill, st, status);
+  const unsigned g2 = std::max(1u, std::min(bank_buckets(cap), 1024u));
+  if (is_ce)
+    hipLaunchKernelGGL((k_place<true>), dim3(g2), dim3(256), 0, s, T, n_fis, cap, n, xi0, bk_fill,
+                       st, cx, cy, cg, ce, sx, sy, sg, se, hist, status);
+  else
+    hipLaunchKernelGGL((k_place<false>), dim3(g2), dim3(256), 0, s, T, n_fis, cap, n, xi0,
+                       bk_fill, st, cx, cy, cg, ce, sx, sy, sg, se, hist, status);
+  hipLaunchKernelGGL(k_entropy_final, dim3(1), dim3(256), 0, s, T, gen, hist, n_fis, gen_h);
   return hipGetLastError();
 }
 
