@@ -575,21 +575,21 @@ static int sample_source(const ctx_t* C, int64_t id, int gen, double* sx, double
   return -1;
 }
 
-static void run_history(ctx_t* C, int64_t id, chunk_t* ch) {
+static void run_history(ctx_t* C, int64_t id, int64_t slot, chunk_t* ch) {
   const orc_problem* p = C->p;
   const int G = p->n_grp;
   stream_t rs;
   stream_init(&rs, p->seed, ORC_TAG_TRANSPORT, (uint64_t)id, (uint64_t)C->gen, p->problem_id);
 
-  double x = C->src_x[id], y = C->src_y[id];
-  int g = C->src_g[id];
+  double x = C->src_x[slot], y = C->src_y[slot];
+  int g = C->src_g[slot];
   int i, j, r;
   locate(p, x, y, &i, &j, &r);
   double dir[3];
   if (C->src_dir) {
-    dir[0] = C->src_dir[3 * id + 0];
-    dir[1] = C->src_dir[3 * id + 1];
-    dir[2] = C->src_dir[3 * id + 2];
+    dir[0] = C->src_dir[3 * slot + 0];
+    dir[1] = C->src_dir[3 * slot + 1];
+    dir[2] = C->src_dir[3 * slot + 2];
   } else {
     double xm = next_uniform(&rs);
     double xp = next_uniform(&rs);
@@ -780,7 +780,7 @@ static void run_history(ctx_t* C, int64_t id, chunk_t* ch) {
   if (fate == ORC_KILLED) ch->counts[ORC_C_KILLED] += 1;
   if (fate == ORC_CENSUS) ch->counts[ORC_C_CENSUS] += 1;
   if (C->records) {
-    orc_record* rec = &C->records[id];
+    orc_record* rec = &C->records[slot];
     rec->t_final = t;
     rec->n_seg = n_seg;
     rec->n_col = n_col;
@@ -805,21 +805,21 @@ static void run_history(ctx_t* C, int64_t id, chunk_t* ch) {
    absorbs.  Draw order per collision: fission (k-eigenvalue, fissile), four
    per Watt attempt per site, nuclide, scatter test, then for a scatter the
    centre-of-mass cosine and, above the cutoff, the azimuth. */
-static void run_history_ce(ctx_t* C, int64_t id, chunk_t* ch) {
+static void run_history_ce(ctx_t* C, int64_t id, int64_t slot, chunk_t* ch) {
   const orc_problem* p = C->p;
   const orc_ce* ce = p->ce;
   const int NB = ce->n_ebins;
   stream_t rs;
   stream_init(&rs, p->seed, ORC_TAG_TRANSPORT, (uint64_t)id, (uint64_t)C->gen, p->problem_id);
 
-  double x = C->src_x[id], y = C->src_y[id], e = C->src_e[id];
+  double x = C->src_x[slot], y = C->src_y[slot], e = C->src_e[slot];
   int i, j, r;
   locate(p, x, y, &i, &j, &r);
   double dir[3];
   if (C->src_dir) {
-    dir[0] = C->src_dir[3 * id + 0];
-    dir[1] = C->src_dir[3 * id + 1];
-    dir[2] = C->src_dir[3 * id + 2];
+    dir[0] = C->src_dir[3 * slot + 0];
+    dir[1] = C->src_dir[3 * slot + 1];
+    dir[2] = C->src_dir[3 * slot + 2];
   } else {
     double xm = next_uniform(&rs);
     double xp = next_uniform(&rs);
@@ -1025,7 +1025,7 @@ static void run_history_ce(ctx_t* C, int64_t id, chunk_t* ch) {
   if (fate == ORC_CUTOFF) ch->counts[ORC_C_CUTOFF] += 1;
   if (fate == ORC_CENSUS) ch->counts[ORC_C_CENSUS] += 1;
   if (C->records) {
-    orc_record* rec = &C->records[id];
+    orc_record* rec = &C->records[slot];
     rec->n_seg = n_seg;
     rec->n_col = n_col;
     rec->n_cross = n_cross;
@@ -1054,9 +1054,9 @@ static void* worker(void* arg) {
     int64_t hi = lo + C->chunk_size;
     if (hi > n) hi = n;
     if (C->p->ce)
-      for (int64_t id = lo; id < hi; ++id) run_history_ce(C, id, ch);
+      for (int64_t id = lo; id < hi; ++id) run_history_ce(C, id, id, ch);
     else
-      for (int64_t id = lo; id < hi; ++id) run_history(C, id, ch);
+      for (int64_t id = lo; id < hi; ++id) run_history(C, id, id, ch);
   }
   return NULL;
 }
@@ -1147,20 +1147,17 @@ static int validate(const orc_problem* p, orc_output* out) {
   return ORC_OK;
 }
 
-int orc_run(const orc_problem* p, orc_output* out) {
-  out->errmsg[0] = 0;
-  int rc = validate(p, out);
-  if (rc) return rc;
+/* The run context of problem p: the fissile flag of each material and, for
+   multigroup data, each group's total scattering cross section (at most
+   sigma_t). */
+static int ctx_begin(ctx_t* C, const orc_problem* p, orc_output* out) {
   const int G = p->n_grp;
-  const int64_t N = p->n_per_gen;
-
-  ctx_t C;
-  memset(&C, 0, sizeof(C));
-  C.p = p;
-  C.n_bins = orc_n_bins(p);
-  C.mr1 = p->max_rings + 1;
-  C.fissile = calloc((size_t)p->n_mat, sizeof(int32_t));
-  C.sig_s_tot = calloc((size_t)p->n_mat * (p->ce ? 1 : G), sizeof(double));
+  memset(C, 0, sizeof(*C));
+  C->p = p;
+  C->n_bins = orc_n_bins(p);
+  C->mr1 = p->max_rings + 1;
+  C->fissile = calloc((size_t)p->n_mat, sizeof(int32_t));
+  C->sig_s_tot = calloc((size_t)p->n_mat * (p->ce ? 1 : G), sizeof(double));
   if (p->ce) {
     /* fissile: a nuclide with a nonzero density and some fission cross section */
     const orc_ce* ce = p->ce;
@@ -1170,25 +1167,36 @@ int orc_run(const orc_problem* p, orc_output* out) {
         if (!(ce->mat_dens[m * ce->max_nuc + k] > 0.0) || !(ce->nu > 0.0)) continue;
         for (int q = 0; q < ce->n_pts; ++q)
           if (ce->sig_f[(int64_t)n * ce->n_pts + q] > 0.0) {
-            C.fissile[m] = 1;
+            C->fissile[m] = 1;
             break;
           }
       }
   }
   for (int m = 0; m < (p->ce ? 0 : p->n_mat); ++m) {
     for (int g = 0; g < G; ++g) {
-      if (p->nu_sig_f[m * G + g] > 0.0) C.fissile[m] = 1;
+      if (p->nu_sig_f[m * G + g] > 0.0) C->fissile[m] = 1;
       double s = 0.0;
       for (int h = 0; h < G; ++h) s += p->sig_s[((int64_t)m * G + g) * G + h];
-      C.sig_s_tot[m * G + g] = s;
+      C->sig_s_tot[m * G + g] = s;
       if (s > p->sig_t[m * G + g]) {
-        free(C.fissile);
-        free(C.sig_s_tot);
+        free(C->fissile);
+        free(C->sig_s_tot);
         return fail(out, ORC_EINVAL, "sig_s exceeds sig_t");
       }
     }
   }
+  return ORC_OK;
+}
 
+int orc_run(const orc_problem* p, orc_output* out) {
+  out->errmsg[0] = 0;
+  int rc = validate(p, out);
+  if (rc) return rc;
+  const int64_t N = p->n_per_gen;
+
+  ctx_t C;
+  rc = ctx_begin(&C, p, out);
+  if (rc) return rc;
   /* fixed chunking: at most 256 chunks of at least 512 histories */
   C.chunk_size = 512;
   if ((N + C.chunk_size - 1) / C.chunk_size > 256) C.chunk_size = (N + 255) / 256;
@@ -1411,5 +1419,84 @@ done:
   free(ent_counts);
   free(comb_idx);
   sites_free(&bank);
+  return rc;
+}
+
+/* Histories ids[0..n_ids) of the first generation only, each with the
+   source sample, transport and record orc_run gives it there (k_used = 1):
+   a first-generation history depends on nothing but the problem, the seed
+   and its id, so a sample of a run too large to compute whole can be checked
+   history by history.  out->records receives one record per listed id, in
+   list order; no other output is written. */
+int orc_histories(const orc_problem* p, const int64_t* ids, int64_t n_ids, orc_output* out) {
+  out->errmsg[0] = 0;
+  int rc = validate(p, out);
+  if (rc) return rc;
+  if (n_ids < 0 || (n_ids > 0 && (!ids || !out->records)))
+    return fail(out, ORC_EINVAL, "history list");
+  for (int64_t k = 0; k < n_ids; ++k)
+    if (ids[k] < 0 || ids[k] >= p->n_per_gen) return fail(out, ORC_EINVAL, "history id");
+  ctx_t C;
+  rc = ctx_begin(&C, p, out);
+  if (rc) return rc;
+  chunk_t ch;
+  memset(&ch, 0, sizeof(ch));
+  ch.flux = calloc((size_t)C.n_bins, sizeof(nsum_t));
+  ch.prod = calloc((size_t)C.n_bins, sizeof(nsum_t));
+  const size_t n = n_ids > 0 ? (size_t)n_ids : 1;
+  double* sx = malloc(n * sizeof(double));
+  double* sy = malloc(n * sizeof(double));
+  int32_t* sg = malloc(n * sizeof(int32_t));
+  double* se = malloc(n * sizeof(double));
+  double* sd = p->ext_state ? malloc(n * 3 * sizeof(double)) : NULL;
+  if (!ch.flux || !ch.prod || !sx || !sy || !sg || !se || (p->ext_state && !sd)) {
+    rc = fail(out, ORC_ENOMEM, "out of host memory");
+    goto done;
+  }
+  for (int64_t k = 0; k < n_ids; ++k) {
+    const int64_t id = ids[k];
+    if (p->ext_state) {
+      sx[k] = p->ext_state[6 * id + 0];
+      sy[k] = p->ext_state[6 * id + 1];
+      sd[3 * k + 0] = p->ext_state[6 * id + 2];
+      sd[3 * k + 1] = p->ext_state[6 * id + 3];
+      sd[3 * k + 2] = p->ext_state[6 * id + 4];
+      sg[k] = p->ce ? 0 : (int32_t)p->ext_state[6 * id + 5];
+      se[k] = p->ce ? p->ext_state[6 * id + 5] : 0.0;
+    } else if (sample_source(&C, id, 0, &sx[k], &sy[k], &sg[k], &se[k])) {
+      rc = fail(out, ORC_EINVAL, "source rejection sampling found no fissile point");
+      goto done;
+    }
+  }
+  C.gen = 0;
+  C.k_used = 1.0;
+  C.src_x = sx;
+  C.src_y = sy;
+  C.src_g = sg;
+  C.src_e = se;
+  C.src_dir = sd;
+  C.records = out->records;
+  C.events = NULL;
+  for (int64_t k = 0; k < n_ids; ++k) {
+    if (p->ce)
+      run_history_ce(&C, ids[k], k, &ch);
+    else
+      run_history(&C, ids[k], k, &ch);
+    if (ch.err) {
+      rc = fail(out, ch.err, "out of host memory in the fission bank");
+      goto done;
+    }
+  }
+done:
+  free(sx);
+  free(sy);
+  free(sg);
+  free(se);
+  free(sd);
+  free(ch.flux);
+  free(ch.prod);
+  sites_free(&ch.sites);
+  free(C.fissile);
+  free(C.sig_s_tot);
   return rc;
 }

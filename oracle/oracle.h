@@ -185,6 +185,12 @@ int64_t orc_n_bins(const orc_problem* p);
 
 int orc_run(const orc_problem* p, orc_output* out);
 
+/* Histories ids[0..n_ids) of the first generation only, with the records
+   orc_run would give them (out->records: n_ids records in list order; no
+   other output).  For checking a sample of a run too large to compute
+   whole. */
+int orc_histories(const orc_problem* p, const int64_t* ids, int64_t n_ids, orc_output* out);
+
 /* building blocks, exported for the pins */
 void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
 double orc_uniform(uint64_t word);

@@ -123,6 +123,9 @@ def lib():
         L = C.CDLL(LIB_PATH)
         L.orc_run.argtypes = [C.POINTER(_Problem), C.POINTER(_Output)]
         L.orc_run.restype = C.c_int
+        L.orc_histories.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_int64,
+                                    C.POINTER(_Output)]
+        L.orc_histories.restype = C.c_int
         L.orc_n_bins.argtypes = [C.POINTER(_Problem)]
         L.orc_n_bins.restype = C.c_int64
         L.orc_philox4x64_10.argtypes = [C.POINTER(C.c_uint64)] * 3
@@ -309,9 +312,8 @@ def _ptr(a):
     return None if a is None else a.ctypes.data
 
 
-def run(problem, n_threads=None, records=False, per_gen_tallies=False, bank_cap=0,
-        ext_state=None, events=0, source=False):
-    """Run the oracle on a problem dict; returns a dict of numpy arrays."""
+def _problem(problem, n_threads=None, ext_state=None):
+    """The orc_problem of a problem dict, and the arrays it points into."""
     geo, rp = problem["geometry"], problem["run"]
     ce = problem.get("ce")
     keep = []
@@ -337,6 +339,7 @@ def run(problem, n_threads=None, records=False, per_gen_tallies=False, bank_cap=
         sig_t = sig_s = nusf = chi = None
         n_mat, n_grp = len(ce["mat_n"]), 0
         ce_s = _ce_struct(ce, keep)
+        keep.append(ce_s)
     ext = None if ext_state is None else arr(ext_state, np.float64)
     if ext is not None:
         assert ext.shape == (rp["n_per_gen"], 6)
@@ -370,7 +373,14 @@ def run(problem, n_threads=None, records=False, per_gen_tallies=False, bank_cap=
         t_s.speed = None if tm.get("speed") is None else arr(tm["speed"], np.float64).ctypes.data
         keep.append(t_s)
         P.time = C.addressof(t_s)
+    return P, keep
 
+
+def run(problem, n_threads=None, records=False, per_gen_tallies=False, bank_cap=0,
+        ext_state=None, events=0, source=False):
+    """Run the oracle on a problem dict; returns a dict of numpy arrays."""
+    rp = problem["run"]
+    P, keep = _problem(problem, n_threads, ext_state)
     L = lib()
     nb = L.orc_n_bins(C.byref(P))
     G, N = rp["n_gen"], rp["n_per_gen"]
@@ -412,4 +422,21 @@ def run(problem, n_threads=None, records=False, per_gen_tallies=False, bank_cap=
         res["bank"] = res["bank"][: min(bank_cap, O.bank_len)]
     res["bank_len"] = int(O.bank_len)
     res["n_bins"] = int(nb)
+    del keep
     return res
+
+
+def histories(problem, ids, ext_state=None):
+    """Records of the first-generation histories ids (any ids below the
+    problem's n_per_gen), as run() gives them, without running the rest of
+    the generation (orc_histories)."""
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    P, keep = _problem(problem, 1, ext_state)
+    out = np.zeros(len(ids), RECORD_DTYPE)
+    O = _Output()
+    O.records = _ptr(out)
+    rc = lib().orc_histories(C.byref(P), _ptr(ids), len(ids), C.byref(O))
+    if rc != 0:
+        raise OracleError(rc, O.errmsg.decode())
+    del keep
+    return out
