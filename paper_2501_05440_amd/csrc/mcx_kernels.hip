@@ -672,23 +672,34 @@ __global__ void __launch_bounds__(1024) k_scan_chunks(uint32_t* chunk_sum, uint3
 __global__ void __launch_bounds__(SCAN_THREADS) k_scan_chunk(const uint32_t* in, uint32_t n,
                                                              const uint32_t* chunk_off,
                                                              uint32_t* out) {
+  // The chunk passes through LDS, so that the global loads and stores are
+  // coalesced; thread t scans entries [16 t, 16 t + 16) of it (rows padded to
+  // an odd stride, so that the row reads do not share banks).
+  constexpr int PAD = SCAN_PER_THREAD + 1;
+  __shared__ uint32_t buf[SCAN_THREADS * PAD];
   __shared__ uint32_t lds[SCAN_THREADS / 64 + 1];
   const size_t base = (size_t)blockIdx.x * SCAN_CHUNK;
-  // each thread owns SCAN_PER_THREAD consecutive entries
-  const size_t t0 = base + (size_t)threadIdx.x * SCAN_PER_THREAD;
-  uint32_t v[SCAN_PER_THREAD];
-  uint32_t s = 0;
   for (int e = 0; e < SCAN_PER_THREAD; ++e) {
-    const size_t k = t0 + e;
-    v[e] = k < n ? in[k] : 0u;
-    s += v[e];
+    const uint32_t j = (uint32_t)e * SCAN_THREADS + threadIdx.x;
+    const size_t k = base + j;
+    buf[(j / SCAN_PER_THREAD) * PAD + j % SCAN_PER_THREAD] = k < n ? in[k] : 0u;
   }
+  __syncthreads();
+  uint32_t* mine = buf + threadIdx.x * PAD;
+  uint32_t s = 0;
+  for (int e = 0; e < SCAN_PER_THREAD; ++e) s += mine[e];
   uint32_t total;
   uint32_t run = block_excl_scan(s, lds, &total) + chunk_off[blockIdx.x];
   for (int e = 0; e < SCAN_PER_THREAD; ++e) {
-    const size_t k = t0 + e;
-    if (k < n) out[k] = run;
-    run += v[e];
+    const uint32_t v = mine[e];
+    mine[e] = run;
+    run += v;
+  }
+  __syncthreads();
+  for (int e = 0; e < SCAN_PER_THREAD; ++e) {
+    const uint32_t j = (uint32_t)e * SCAN_THREADS + threadIdx.x;
+    const size_t k = base + j;
+    if (k < n) out[k] = buf[(j / SCAN_PER_THREAD) * PAD + j % SCAN_PER_THREAD];
   }
 }
 

@@ -15,6 +15,7 @@ import pytest
 
 from paper_2501_05440_amd import problems as P
 
+
 def _ids(n):
     return np.array([n - 1, 0, 7, n // 2, 1, 7, n - 2, 3 * n // 4, 123 % n], np.int64)
 
