@@ -824,9 +824,9 @@ static size_t carve(const mcx_ctx* c, Dev& d, char* base, int n_gen_max) {
   d.can_g = cv.take<int32_t>(fis_cap);
   d.can_e = ce ? cv.take<double>(fis_cap) : nullptr;
   const bool keig = !batch && !c->src.fixed_source;
-  const size_t n_bk = keig ? bank_buckets(fis_cap) : 0;
+  const size_t n_bk = keig ? bank_buckets(N) : 0;
   if (keig) {
-    const size_t n_st = n_bk * 1024;
+    const size_t n_st = fis_cap;
     d.st.mg = ce ? nullptr : cv.take<StSite>(n_st);
     d.st.ce = ce ? cv.take<StSiteCE>(n_st) : nullptr;
   }
@@ -1423,8 +1423,8 @@ static int generation_end(mcx_ctx* c, int gen) {
     // the canonical bank is kept for mcx_get_bank: written out in the run's
     // last generation only
     const bool keep = gen == c->run_last_gen;
-    HIP_TRY(c, launch_bank_end(T, gen, A.fis, A.n_fis, c->d.offs, c->d.fis_cap, c->d.bk_fill,
-                               c->d.st, N, c->d.xi0, keep ? c->d.can_x : nullptr,
+    HIP_TRY(c, launch_bank_end(T, gen, A.fis, A.n_fis, c->d.offs, c->d.scan_total, N,
+                               c->d.fis_cap, c->d.bk_fill, c->d.st, N, c->d.xi0, keep ? c->d.can_x : nullptr,
                                keep ? c->d.can_y : nullptr, keep ? c->d.can_g : nullptr,
                                keep ? c->d.can_e : nullptr, c->d.src_x, c->d.src_y, c->d.src_g,
                                c->d.src_e, c->d.ent_hist, c->d.gen_h, A.status, s));

@@ -193,12 +193,12 @@ struct Sites {
   double* e;  // continuous energy: site energies
 };
 
-// Fission sites filed by bucket of canonical positions (generation end), one
-// record per site: key = position within the bucket (low 16 bits) | group << 16.
+// Fission sites filed by bucket of parent histories (generation end), one
+// record per site: key = parent within its bucket (low 10 bits) | seq << 10.
 struct StSite {
   double x, y;
   uint32_t key;
-  int32_t pad;
+  int32_t g;
 };
 struct StSiteCE {
   double x, y, e;

@@ -704,27 +704,28 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_chunk(const uint32_t* in,
 }
 
 // Canonical bank, entropy and combing, in two passes over the banked sites.
-// Site seq of history parent has canonical position offset[parent] + seq.
-// Pass 1 (k_bucket) files every site, in banking order, under the bucket of
-// BK_SIZE consecutive canonical positions that holds its position (one
-// atomic per bucket and wavefront, one record per site).  Pass 2 (k_place)
-// loads a bucket into LDS, each site at its place, writes the canonical
-// entries in order, bins them on the entropy mesh, and writes the source
-// entries of the next generation that combing takes from those positions.
-// Writing each site straight to its canonical position instead scatters
-// single words over partial cache lines.  A site whose seq is not below its
-// history's count lands on a position of another history or past the bank:
-// pass 2 finds it as a position claimed twice or a bucket count that does not
-// match.
-constexpr uint32_t BK_SHIFT = 10;
-constexpr uint32_t BK_SIZE = 1u << BK_SHIFT;
+// Site seq of history parent has canonical position offset[parent] + seq, so
+// the sites of histories [h0, h0 + PB_SIZE) fill the positions [offset[h0],
+// offset[h0 + PB_SIZE]).  Pass 1 (k_bucket) files every site, in banking
+// order, into that range of the staging array for its parent's bucket (the
+// bucket bases are a table of 4 bytes per PB_SIZE histories, which stays in
+// cache, where a lookup of each parent's own offset would miss for nearly
+// every site: banking order is far from parent order).  Pass 2 (k_place) loads a bucket's offsets and sites
+// into LDS, each site at its place, writes the canonical entries in order,
+// bins them on the entropy mesh, and writes the source entries of the next
+// generation that combing takes from those positions.  A bucket with more
+// sites than the LDS holds writes each site and its combed entries directly.
+constexpr uint32_t PB_SHIFT = 10;
+constexpr uint32_t PB_SIZE = 1u << PB_SHIFT;  // histories per bucket
+constexpr uint32_t PLACE_CAP = 1536;          // sites of a bucket placed in LDS
 
 template <bool CE>
 __global__ void __launch_bounds__(256) k_bucket(Sites fis, const uint32_t* n_fis_p,
-                                                const uint32_t* offs, uint32_t cap,
-                                                uint32_t* bk_fill, Staging st,
-                                                uint32_t* status) {
+                                                const uint32_t* offs, const uint32_t* total_p,
+                                                uint32_t n_hist, uint32_t cap, uint32_t* bk_fill,
+                                                Staging st, uint32_t* status) {
   const uint32_t n = min(*n_fis_p, cap);
+  const uint32_t total = *total_p;  // the sum of the per-history site counts
   const uint32_t lane = lane_id();
   const unsigned long long below = (1ull << lane) - 1ull;
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -733,37 +734,55 @@ __global__ void __launch_bounds__(256) k_bucket(Sites fis, const uint32_t* n_fis
   for (uint32_t s0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); s0 < n; s0 += stride) {
     const uint32_t s = s0 + lane;
     bool ok = s < n;
-    uint32_t pos = 0;
+    uint32_t par = 0, q = 0;
     if (ok) {
-      pos = offs[fis.parent[s]] + fis.seq[s];
-      if (pos >= cap) {  // after an overflow, which the host reports, or a bad seq
-        atomicOr(status, ST_OVERFLOW);
+      par = fis.parent[s];
+      q = fis.seq[s];
+      if (par >= n_hist) {
+        atomicOr(status, ST_SCAN);
         ok = false;
       }
     }
-    const uint32_t bk = pos >> BK_SHIFT;
-    uint32_t slot = 0;
+    const uint32_t bk = par >> PB_SHIFT;
+    // group the lanes by bucket (the lowest lane of a group leads it) ...
+    uint32_t lead = lane, rank = 0, size = 0;
     unsigned long long todo = __ballot(ok);
     while (todo != 0ull) {
-      const int leader = __ffsll((long long)todo) - 1;
-      const uint32_t lb = __shfl(bk, leader);
+      const int first = __ffsll((long long)todo) - 1;
+      const uint32_t lb = __shfl(bk, first);
       const unsigned long long same = __ballot(ok && bk == lb) & todo;
-      uint32_t base = 0;
-      if ((int)lane == leader) base = atomicAdd(&bk_fill[lb], (uint32_t)__popcll(same));
-      base = __shfl(base, leader);
-      if ((same >> lane) & 1ull) slot = base + (uint32_t)__popcll(same & below);
+      if ((same >> lane) & 1ull) {
+        lead = (uint32_t)first;
+        rank = (uint32_t)__popcll(same & below);
+        size = (uint32_t)__popcll(same);
+      }
       todo &= ~same;
     }
+    // ... then every leader reserves its group's slots at once: one round
+    // trip per wavefront, however many buckets its sites fall into
+    uint32_t base = 0, room = 0;
+    if (ok && lead == lane) {
+      const uint32_t h1 = (bk + 1u) << PB_SHIFT;
+      const uint32_t b0 = offs[bk << PB_SHIFT];
+      const uint32_t b1 = h1 < n_hist ? offs[h1] : total;
+      const uint32_t got = atomicAdd(&bk_fill[bk], size);
+      base = b0 + got;
+      room = b1 >= b0 && b1 - b0 > got ? b1 - b0 - got : 0u;
+    }
+    base = __shfl(base, (int)lead);
+    room = __shfl(room, (int)lead);
     if (ok) {
-      if (slot >= BK_SIZE) {  // more sites than positions: two claim one
+      if (rank >= room) {  // more sites than the bucket's histories count
         atomicOr(status, ST_SCAN);
+      } else if (base + rank >= cap) {  // only after an overflow, which the host reports
+        atomicOr(status, ST_OVERFLOW);
       } else {
-        const size_t e = ((size_t)bk << BK_SHIFT) + slot;
-        const uint32_t key = (pos & (BK_SIZE - 1u)) | ((uint32_t)fis.g[s] << 16);
+        const uint32_t idx = base + rank;
+        const uint32_t key = (par & (PB_SIZE - 1u)) | (q << PB_SHIFT);
         if (CE)
-          st.ce[e] = StSiteCE{fis.x[s], fis.y[s], fis.e[s], key, 0};
+          st.ce[idx] = StSiteCE{fis.x[s], fis.y[s], fis.e[s], key, 0};
         else
-          st.mg[e] = StSite{fis.x[s], fis.y[s], key, 0};
+          st.mg[idx] = StSite{fis.x[s], fis.y[s], key, fis.g[s]};
       }
     }
   }
@@ -791,42 +810,62 @@ __device__ uint32_t comb_first(uint32_t target, double xi0, uint32_t m, uint32_t
 }
 
 constexpr int PLACE_HIST = 4096;  // entropy meshes up to this many bins are binned in LDS
+                                  // (dynamic LDS of 4 B per bin)
 
 template <bool CE>
-__global__ void __launch_bounds__(256) k_place(Tables T, const uint32_t* n_fis_p, uint32_t cap,
-                                               uint32_t n, const double* xi0_p,
-                                               const uint32_t* bk_fill, Staging st, double* cx,
-                                               double* cy, int32_t* cg, double* ce, double* sx,
-                                               double* sy, int32_t* sg, double* se,
-                                               uint32_t* hist, uint32_t* status) {
-  __shared__ double lx[BK_SIZE], ly[BK_SIZE];
-  __shared__ double le[CE ? BK_SIZE : 1];
-  __shared__ int32_t lg[BK_SIZE];
-  __shared__ uint32_t h[PLACE_HIST];
-  __shared__ uint32_t seen[BK_SIZE / 32];
+__global__ void __launch_bounds__(256) k_place(Tables T, const uint32_t* n_fis_p,
+                                               const uint32_t* total_p, uint32_t cap,
+                                               uint32_t n_hist, uint32_t n, const double* xi0_p,
+                                               const uint32_t* offs, const uint32_t* bk_fill,
+                                               Staging st, double* cx, double* cy, int32_t* cg,
+                                               double* ce, double* sx, double* sy, int32_t* sg,
+                                               double* se, uint32_t* hist, uint32_t* status) {
+  __shared__ double lx[PLACE_CAP], ly[PLACE_CAP];
+  __shared__ double le[CE ? PLACE_CAP : 1];
+  __shared__ int32_t lg[PLACE_CAP];
+  __shared__ uint32_t lo[PB_SIZE + 1];  // the bucket's history offsets, from its first
+  __shared__ uint32_t seen[PLACE_CAP / 32];
   __shared__ uint32_t range[2];
-  const uint32_t m = min(*n_fis_p, cap);
+  extern __shared__ uint32_t h[];  // nb words when nb <= PLACE_HIST
+  const uint32_t m = min(*n_fis_p, cap);  // sites combing draws from
+  const uint32_t total = *total_p;
   const double xi0 = *xi0_p;
   const int nb = T.ent_nx * T.ent_ny;
   const bool in_lds = nb <= PLACE_HIST;
   if (in_lds)
     for (int b = threadIdx.x; b < nb; b += blockDim.x) h[b] = 0u;
   __syncthreads();
-  const uint32_t n_bk = (uint32_t)(((uint64_t)m + BK_SIZE - 1u) >> BK_SHIFT);
-  for (uint32_t b = blockIdx.x; b < n_bk; b += gridDim.x) {
-    const uint32_t k0 = b << BK_SHIFT;
-    const uint32_t cnt = min(BK_SIZE, m - k0);
-    if (bk_fill[b] != cnt) {  // positions missing or claimed twice
+  const uint32_t n_pb = (uint32_t)(((uint64_t)n_hist + PB_SIZE - 1u) >> PB_SHIFT);
+  for (uint32_t b = blockIdx.x; b < n_pb; b += gridDim.x) {
+    const uint32_t h0 = b << PB_SHIFT;
+    const uint32_t nh = min(PB_SIZE, n_hist - h0);
+    // the bucket's offsets (and the end of its range) in one round trip
+    for (uint32_t t = threadIdx.x; t <= nh; t += blockDim.x)
+      lo[t] = h0 + t < n_hist ? offs[h0 + t] : total;
+    if (threadIdx.x == 0) range[0] = bk_fill[b];
+    __syncthreads();
+    const uint32_t base = lo[0], end = lo[nh], filled = range[0];
+    __syncthreads();  // every thread has read range[0] and lo[0]
+    if (end < base || filled != end - base) {  // sites missing or left over
       if (threadIdx.x == 0) atomicOr(status, ST_SCAN);
       continue;
     }
-    if (threadIdx.x < 2) range[threadIdx.x] = comb_first(k0 + threadIdx.x * cnt, xi0, m, n);
-    if (threadIdx.x < BK_SIZE / 32) seen[threadIdx.x] = 0u;
+    const uint32_t cnt = end - base;
+    if (cnt == 0u) continue;
+    if (end > m) {  // past the bank: only after an overflow, which the host reports
+      if (threadIdx.x == 0) atomicOr(status, ST_OVERFLOW);
+      continue;
+    }
+    const bool fits = cnt <= PLACE_CAP;
+    for (uint32_t t = threadIdx.x; t <= nh; t += blockDim.x) lo[t] -= base;
+    if (fits && threadIdx.x < 2) range[threadIdx.x] = comb_first(base + threadIdx.x * cnt, xi0, m, n);
+    if (threadIdx.x < PLACE_CAP / 32) seen[threadIdx.x] = 0u;
     __syncthreads();
     for (uint32_t t = threadIdx.x; t < cnt; t += blockDim.x) {
-      const size_t e = (size_t)k0 + t;  // bucket b's staging entries start at b * BK_SIZE
+      const size_t e = (size_t)base + t;
       double x, y, en = 0.0;
       uint32_t key;
+      int32_t g = 0;
       if (CE) {
         const StSiteCE r = st.ce[e];
         x = r.x;
@@ -838,14 +877,18 @@ __global__ void __launch_bounds__(256) k_place(Tables T, const uint32_t* n_fis_p
         x = r.x;
         y = r.y;
         key = r.key;
+        g = r.g;
       }
-      const uint32_t p = key & (BK_SIZE - 1u);
-      if (atomicOr(&seen[p >> 5], 1u << (p & 31u)) & (1u << (p & 31u)))
-        atomicOr(status, ST_SCAN);  // position claimed twice
-      lx[p] = x;
-      ly[p] = y;
-      lg[p] = (int32_t)(key >> 16);
-      if (CE) le[p] = en;
+      const uint32_t pl = key & (PB_SIZE - 1u), q = key >> PB_SHIFT;
+      if (pl >= nh || q >= lo[pl + 1] - lo[pl]) {  // seq not below its history's count
+        atomicOr(status, ST_SITE_SEQ);
+        continue;
+      }
+      const uint32_t p = lo[pl] + q;  // place within the bucket's positions
+      if (p >= cnt) {  // offsets not increasing: an inconsistent scan
+        atomicOr(status, ST_SCAN);
+        continue;
+      }
       int bx = (int)floor((x - T.geo.x0) / T.geo.width * (double)T.ent_nx);
       int by = (int)floor((y - T.geo.y0) / T.geo.height * (double)T.ent_ny);
       bx = bx < 0 ? 0 : (bx > T.ent_nx - 1 ? T.ent_nx - 1 : bx);
@@ -854,22 +897,49 @@ __global__ void __launch_bounds__(256) k_place(Tables T, const uint32_t* n_fis_p
         atomicAdd(&h[by * T.ent_nx + bx], 1u);
       else
         atomicAdd(&hist[by * T.ent_nx + bx], 1u);
+      if (fits) {
+        if (atomicOr(&seen[p >> 5], 1u << (p & 31u)) & (1u << (p & 31u)))
+          atomicOr(status, ST_SCAN);  // position claimed twice
+        lx[p] = x;
+        ly[p] = y;
+        lg[p] = g;
+        if (CE) le[p] = en;
+      } else {
+        // a bucket larger than the LDS: this site's canonical entry and the
+        // source entries combed from it, written directly
+        const uint32_t k = base + p;
+        if (cx) {
+          cx[k] = x;
+          cy[k] = y;
+          cg[k] = g;
+          if (CE) ce[k] = en;
+        }
+        const uint32_t i1 = comb_first(k + 1u, xi0, m, n);
+        for (uint32_t i = comb_first(k, xi0, m, n); i < i1; ++i) {
+          sx[i] = x;
+          sy[i] = y;
+          sg[i] = g;
+          if (CE) se[i] = en;
+        }
+      }
     }
     __syncthreads();
-    if (cx)  // the canonical bank itself is kept only when asked for
-      for (uint32_t t = threadIdx.x; t < cnt; t += blockDim.x) {
-        cx[k0 + t] = lx[t];
-        cy[k0 + t] = ly[t];
-        cg[k0 + t] = lg[t];
-        if (CE) ce[k0 + t] = le[t];
+    if (fits) {
+      if (cx)  // the canonical bank itself is kept only when asked for
+        for (uint32_t t = threadIdx.x; t < cnt; t += blockDim.x) {
+          cx[base + t] = lx[t];
+          cy[base + t] = ly[t];
+          cg[base + t] = lg[t];
+          if (CE) ce[base + t] = le[t];
+        }
+      const uint32_t i1 = range[1];
+      for (uint32_t i = range[0] + threadIdx.x; i < i1; i += blockDim.x) {
+        const uint32_t k = comb_pick(i, xi0, m, n) - base;
+        sx[i] = lx[k];
+        sy[i] = ly[k];
+        sg[i] = lg[k];
+        if (CE) se[i] = le[k];
       }
-    const uint32_t i1 = range[1];
-    for (uint32_t i = range[0] + threadIdx.x; i < i1; i += blockDim.x) {
-      const uint32_t k = comb_pick(i, xi0, m, n) - k0;
-      sx[i] = lx[k];
-      sy[i] = ly[k];
-      sg[i] = lg[k];
-      if (CE) se[i] = le[k];
     }
     __syncthreads();  // the next bucket reuses the LDS arrays and the range
   }
@@ -1462,33 +1532,37 @@ hipError_t launch_gen_tallies(const Tables& T, uint32_t gen, uint32_t n, const A
   return hipGetLastError();
 }
 
-uint32_t bank_buckets(uint32_t cap) { return nblk(cap, (int)BK_SIZE); }
+uint32_t bank_buckets(uint32_t n_hist) { return nblk(n_hist, (int)PB_SIZE); }
 
 hipError_t launch_bank_end(const Tables& T, uint32_t gen, const Sites& fis, const uint32_t* n_fis,
-                           const uint32_t* offs, uint32_t cap,
-                           uint32_t* bk_fill, const Staging& st, uint32_t n, const double* xi0,
-                           double* cx, double* cy, int32_t* cg, double* ce, double* sx,
-                           double* sy, int32_t* sg, double* se, uint32_t* hist, double* gen_h,
-                           uint32_t* status, hipStream_t s) {
+                           const uint32_t* offs, const uint32_t* total, uint32_t n_hist,
+                           uint32_t cap, uint32_t* bk_fill, const Staging& st, uint32_t n,
+                           const double* xi0, double* cx, double* cy, int32_t* cg, double* ce,
+                           double* sx, double* sy, int32_t* sg, double* se, uint32_t* hist,
+                           double* gen_h, uint32_t* status, hipStream_t s) {
   // the staging records carved decide the form (cx/cy/cg/ce may be null)
   const bool is_ce = st.ce != nullptr;
   if (is_ce ? (st.mg != nullptr || !fis.e || !se) : (st.mg == nullptr || se != nullptr))
     return hipErrorInvalidValue;
-  if (!bk_fill || !hist || (cx && (!cy || !cg || (is_ce && !ce)))) return hipErrorInvalidValue;
+  if (!bk_fill || !hist || !total || (cx && (!cy || !cg || (is_ce && !ce))))
+    return hipErrorInvalidValue;
   const unsigned g1 = std::max(1u, std::min(nblk(cap, 256), 8192u));
   if (is_ce)
-    hipLaunchKernelGGL((k_bucket<true>), dim3(g1), dim3(256), 0, s, fis, n_fis, offs, cap,
-                       bk_fill, st, status);
+    hipLaunchKernelGGL((k_bucket<true>), dim3(g1), dim3(256), 0, s, fis, n_fis, offs, total,
+                       n_hist, cap, bk_fill, st, status);
   else
-    hipLaunchKernelGGL((k_bucket<false>), dim3(g1), dim3(256), 0, s, fis, n_fis, offs, cap,
-                       bk_fill, st, status);
-  const unsigned g2 = std::max(1u, std::min(bank_buckets(cap), 1024u));
+    hipLaunchKernelGGL((k_bucket<false>), dim3(g1), dim3(256), 0, s, fis, n_fis, offs, total,
+                       n_hist, cap, bk_fill, st, status);
+  const unsigned g2 = std::max(1u, std::min(bank_buckets(n_hist), 1024u));
+  const int nb = T.ent_nx * T.ent_ny;
+  const size_t lh = nb <= PLACE_HIST ? sizeof(uint32_t) * (size_t)std::max(nb, 1) : 0;
   if (is_ce)
-    hipLaunchKernelGGL((k_place<true>), dim3(g2), dim3(256), 0, s, T, n_fis, cap, n, xi0, bk_fill,
-                       st, cx, cy, cg, ce, sx, sy, sg, se, hist, status);
+    hipLaunchKernelGGL((k_place<true>), dim3(g2), dim3(256), lh, s, T, n_fis, total, cap, n_hist,
+                       n, xi0, offs, bk_fill, st, cx, cy, cg, ce, sx, sy, sg, se, hist, status);
   else
-    hipLaunchKernelGGL((k_place<false>), dim3(g2), dim3(256), 0, s, T, n_fis, cap, n, xi0,
-                       bk_fill, st, cx, cy, cg, ce, sx, sy, sg, se, hist, status);
+    hipLaunchKernelGGL((k_place<false>), dim3(g2), dim3(256), lh, s, T, n_fis, total, cap,
+                       n_hist, n, xi0, offs, bk_fill, st, cx, cy, cg, ce, sx, sy, sg, se, hist,
+                       status);
   hipLaunchKernelGGL(k_entropy_final, dim3(1), dim3(256), 0, s, T, gen, hist, n_fis, gen_h);
   return hipGetLastError();
 }

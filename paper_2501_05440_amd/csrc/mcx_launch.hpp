@@ -71,18 +71,18 @@ hipError_t launch_gen_totals(const Tables& T, uint32_t gen, uint32_t n, const Ac
                              const double* tl_part, double* gen_k, unsigned long long* gen_cnt,
                              uint32_t* gen_m, double* k_used, double* xi0, hipStream_t s);
 // Generation end of a k-eigenvalue run, after the scan of the per-history
-// site counts (offs) and k_gen_totals (xi0): the canonical bank in cx/cy/cg/ce
-// (not written when cx is null),
-// the entropy of generation gen, and the combed source of the next one in
-// sx/sy/sg/se.  bk_fill holds bank_buckets(cap) zeroed counters and the
-// staging array bank_buckets(cap) * 1024 records.
-uint32_t bank_buckets(uint32_t cap);
+// site counts (offs, their sum at total) and k_gen_totals (xi0): the
+// canonical bank in cx/cy/cg/ce (not written when cx is null), the entropy of
+// generation gen, and the combed source of the next one in sx/sy/sg/se.
+// bk_fill holds bank_buckets(n_hist) zeroed counters and the staging array
+// cap records.
+uint32_t bank_buckets(uint32_t n_hist);
 hipError_t launch_bank_end(const Tables& T, uint32_t gen, const Sites& fis, const uint32_t* n_fis,
-                           const uint32_t* offs, uint32_t cap,
-                           uint32_t* bk_fill, const Staging& st, uint32_t n, const double* xi0,
-                           double* cx, double* cy, int32_t* cg, double* ce, double* sx,
-                           double* sy, int32_t* sg, double* se, uint32_t* hist, double* gen_h,
-                           uint32_t* status, hipStream_t s);
+                           const uint32_t* offs, const uint32_t* total, uint32_t n_hist,
+                           uint32_t cap, uint32_t* bk_fill, const Staging& st, uint32_t n,
+                           const double* xi0, double* cx, double* cy, int32_t* cg, double* ce,
+                           double* sx, double* sy, int32_t* sg, double* se, uint32_t* hist,
+                           double* gen_h, uint32_t* status, hipStream_t s);
 hipError_t launch_stats(int n_bins2, int n_gen, int n_inactive, const double* gen_tal,
                         double* tal_mean, double* tal_sigma, const double* gen_k, double* k_stat,
                         hipStream_t s);

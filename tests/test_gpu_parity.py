@@ -375,6 +375,22 @@ def test_headline_size_two_generations_parity(oracle):
                  atol=af * float(np.max(prob["xs"]["nu_sig_f"])))
 
 
+def test_supercritical_generation_end_parity(oracle):
+    """A one-group infinite medium with k = 3: the first generation (k_used
+    = 1) banks about three sites per history, so the sites of the first
+    1,024 histories (about 3,100) exceed what the generation end stages in
+    LDS per bucket and are written one by one, while the next bucket and the
+    later generations go through LDS.  Records, k, entropy and the last
+    bank against the oracle."""
+    banner("supercritical infinite medium 1500 x 3 records parity")
+    prob = P.homogeneous(P.one_group(1.0, 0.2, 2.4), 1500, 3, 1, seed=62)
+    g = mcx.run(prob, record=True, bank=True)
+    o = oracle.run(prob, records=True, bank_cap=4 * prob["run"]["n_per_gen"])
+    assert o["records"][0]["n_sites"][:1024].sum() > 2048
+    compare_runs(g, o, tallies=False)
+    assert np.array_equal(g["bank"], o["bank"])
+
+
 def test_largest_generation_sampled_parity(oracle):
     """2^28 histories per generation, the largest power of two whose
     workspace (about 110 GB with records) fits one MI355X: particle indices
