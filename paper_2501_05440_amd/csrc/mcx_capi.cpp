@@ -1308,6 +1308,8 @@ static int run_generation(mcx_ctx* c, int gen) {
     if (lb > 0 && lb <= c->lds_block_max)
       lt_grid = c->dev_cus * advance_lt_blocks_per_cu(prec, rec, LT_BLOCK, lb);
   }
+  // the collision kernel walks its bank with as many blocks as are resident
+  const int col_grid = ce || mono ? 0 : c->dev_cus * collide_blocks_per_cu(prec, rec, T, block);
   for (;;) {
     if (bound == 0) break;
     // every live particle makes at least one flight per iteration, so after
@@ -1372,7 +1374,7 @@ static int run_generation(mcx_ctx* c, int gen) {
     else
       HIP_TRY(c, launch_collide(prec, rec, T, gen, c->d.bank[2], c->d.cnt_col + it,
                                 c->d.bank[1 - cur], c->d.cnt_live + it + 1, A, c->d.R, bound,
-                                block, s));
+                                block, col_grid, s));
     HIP_TRY(c, time_mark(c, 1, false));
     }
     cur = 1 - cur;

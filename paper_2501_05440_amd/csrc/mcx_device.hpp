@@ -533,7 +533,7 @@ __device__ __forceinline__ void wave_acc_halves(unsigned long long* k_base, unsi
                                                 unsigned long long hi) {
   lo = wave_sum(lo);
   hi = wave_sum(hi);
-  if (lane_id() == 0) {
+  if (lane_id() == 0 && (lo | hi) != 0ull) {
     // lo + hi * 2^32 as a 128-bit (w1, w0)
     const unsigned long long hl = hi << 32, hh = hi >> 32;
     const unsigned long long w0 = lo + hl;

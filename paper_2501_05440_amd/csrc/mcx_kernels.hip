@@ -347,49 +347,65 @@ __global__ void __launch_bounds__(1024) k_collide(Tables T0, uint32_t gen, Bank 
                                                   uint32_t* n_live, Accum A, Records Rc) {
   const uint32_t n_in = *n_in_p;
   const Tables T = kernel_tables<R, LDS>(T0, blockIdx.x * blockDim.x < n_in);
-  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = k < n_in;
   const double k_used = *A.k_used;
-  Part<R> p;
-  ColXS<R> x{0, R(1), R(0)};
-  uint32_t nf = 0;
-  uint64_t q_kcol = 0;
-  // a collision takes about five draws: both blocks that hold them are
-  // evaluated up front by every lane at once, not at whichever draw each
-  // lane crosses a block boundary
-  LockStream rs(T.seed, TAG_TRANSPORT, 0, gen, T.prob, 0);
-  if (valid) {
-    p = load_part<R>(in, k);
-    rs = LockStream(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
-    rs.top_up();
-    rs.fill_next();
-    x = col_xs(T, T.geo, p);
-    const double kc = (double)(x.nusf / x.st);
-    q_kcol = quantize(kc, T.q_kcol);
-    if (REC) {
-      Rc.n_col[p.id] += 1;
-      Rc.kcol_sum[p.id] += kc;
-    }
-    nf = fission_count(T, x, rs, k_used);
-  }
   __shared__ uint32_t lds[2 * (MAX_WAVES + 1)];
-  const uint32_t slot = block_reserve(nf, A.n_fis, lds);
-  bool alive = false;
-  uint64_t q_kabs = 0;
-  if (valid) {
-    alive = collide_rest<R, REC>(T, p, rs, x, nf, slot, A, &q_kabs);
-    p.ctr = rs.draw;
-    if (!alive) die<R, REC>(p, FATE_ABSORBED, A, Rc);
+  // The grid walks the bank (as many blocks as are resident on the large
+  // launches): each thread keeps its counts and its exact k sums and adds
+  // them once, so a wavefront's counter atomics and the round trip of its
+  // 128-bit sums are paid once per launch, not once per 64 collisions.
+  uint32_t c_col = 0, c_scat = 0, c_abs = 0, c_sites = 0;
+  unsigned long long kc_lo = 0, kc_hi = 0, ka_lo = 0, ka_hi = 0;
+  const uint32_t step = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n_in; base += step) {
+    const uint32_t k = base + threadIdx.x;
+    const bool valid = k < n_in;
+    Part<R> p;
+    ColXS<R> x{0, R(1), R(0)};
+    uint32_t nf = 0;
+    // a collision takes about five draws: both blocks that hold them are
+    // evaluated up front by every lane at once, not at whichever draw each
+    // lane crosses a block boundary
+    LockStream rs(T.seed, TAG_TRANSPORT, 0, gen, T.prob, 0);
+    if (valid) {
+      p = load_part<R>(in, k);
+      rs = LockStream(T.seed, TAG_TRANSPORT, p.id, gen, T.prob, p.ctr);
+      rs.top_up();
+      rs.fill_next();
+      x = col_xs(T, T.geo, p);
+      const double kc = (double)(x.nusf / x.st);
+      const uint64_t q = quantize(kc, T.q_kcol);
+      kc_lo += q & 0xFFFFFFFFull;
+      kc_hi += q >> 32;
+      if (REC) {
+        Rc.n_col[p.id] += 1;
+        Rc.kcol_sum[p.id] += kc;
+      }
+      nf = fission_count(T, x, rs, k_used);
+    }
+    const uint32_t slot = block_reserve(nf, A.n_fis, lds);
+    bool alive = false;
+    uint64_t q_kabs = 0;
+    if (valid) {
+      alive = collide_rest<R, REC>(T, p, rs, x, nf, slot, A, &q_kabs);
+      p.ctr = rs.draw;
+      if (!alive) die<R, REC>(p, FATE_ABSORBED, A, Rc);
+    }
+    ka_lo += q_kabs & 0xFFFFFFFFull;
+    ka_hi += q_kabs >> 32;
+    const uint32_t pl = block_reserve(alive ? 1u : 0u, n_live, lds);
+    if (alive) store_part(live, pl, p);
+    c_col += valid ? 1u : 0u;
+    c_scat += alive ? 1u : 0u;
+    c_abs += (valid && !alive) ? 1u : 0u;
+    c_sites += nf;
   }
-  const uint32_t pl = block_reserve(alive ? 1u : 0u, n_live, lds);
-  if (alive) store_part(live, pl, p);
-  wave_flag(A.cnt + CNT_COL * STRIPES, valid);
-  wave_flag(A.cnt + CNT_COL_ITEMS * STRIPES, valid);
-  wave_flag(A.cnt + CNT_SCAT * STRIPES, alive);
-  wave_flag(A.cnt + CNT_ABS * STRIPES, valid && !alive);
-  wave_count(A.cnt + CNT_SITES * STRIPES, nf);
-  wave_acc(A.k + K_COL * STRIPES * 2, q_kcol);
-  wave_acc(A.k + K_ABS * STRIPES * 2, q_kabs);
+  wave_count(A.cnt + CNT_COL * STRIPES, c_col);
+  wave_count(A.cnt + CNT_COL_ITEMS * STRIPES, c_col);
+  wave_count(A.cnt + CNT_SCAT * STRIPES, c_scat);
+  wave_count(A.cnt + CNT_ABS * STRIPES, c_abs);
+  wave_count(A.cnt + CNT_SITES * STRIPES, c_sites);
+  wave_acc_halves(A.k + K_COL * STRIPES * 2, kc_lo, kc_hi);
+  wave_acc_halves(A.k + K_ABS * STRIPES * 2, ka_lo, ka_hi);
 }
 
 // History-based finish of the last live particles: one lane runs its
@@ -1420,11 +1436,35 @@ static void collide_k(dim3 g, dim3 b, size_t lb, hipStream_t s, const Tables& T,
                        Rc);
 }
 
+int collide_blocks_per_cu(int prec, bool rec, const Tables& T, int block) {
+  const size_t lb = mg_lds_bytes(prec, T);
+  int n = 0;
+  hipError_t e;
+  if (prec == 0) {
+    if (rec)
+      e = lb ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_collide<double, true, true>, block, lb)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_collide<double, true, false>, block, 0);
+    else
+      e = lb ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_collide<double, false, true>, block, lb)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_collide<double, false, false>, block, 0);
+  } else {
+    if (rec)
+      e = lb ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_collide<float, true, true>, block, lb)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_collide<float, true, false>, block, 0);
+    else
+      e = lb ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_collide<float, false, true>, block, lb)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_collide<float, false, false>, block, 0);
+  }
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
 hipError_t launch_collide(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in,
                           const uint32_t* n_in, const Bank& live, uint32_t* n_live,
                           const Accum& A, const Records& Rc, uint32_t bound, int block,
-                          hipStream_t s) {
-  const dim3 g(std::max(1u, nblk(bound, block))), b(block);
+                          int max_grid, hipStream_t s) {
+  uint32_t nb = std::max(1u, nblk(bound, block));
+  if (max_grid > 0) nb = std::min<uint32_t>(nb, (uint32_t)max_grid);
+  const dim3 g(nb), b(block);
   const size_t lb = mg_lds_bytes(prec, T);
   if (prec == 0) {
     if (rec)

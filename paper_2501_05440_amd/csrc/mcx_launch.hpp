@@ -45,10 +45,12 @@ hipError_t launch_advance_refill(int prec, bool rec, const Tables& T, uint32_t g
                                  const Bank& col, uint32_t* n_col, const Accum& A,
                                  const Records& Rc, uint32_t* clr_live, uint32_t* clr_col,
                                  uint32_t bound, int block, hipStream_t s);
+// max_grid > 0: at most that many blocks, which walk the bank grid-stride
+int collide_blocks_per_cu(int prec, bool rec, const Tables& T, int block);
 hipError_t launch_collide(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in,
                           const uint32_t* n_in, const Bank& live, uint32_t* n_live,
                           const Accum& A, const Records& Rc, uint32_t bound, int block,
-                          hipStream_t s);
+                          int max_grid, hipStream_t s);
 hipError_t launch_tail(int prec, bool rec, const Tables& T, uint32_t gen, const Bank& in, const uint32_t* n_in, const Accum& A, const Records& Rc,
                        uint32_t bound, hipStream_t s);
 // monolithic event: one segment of every particle per launch, collision or
