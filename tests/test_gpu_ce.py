@@ -45,6 +45,23 @@ def compare(g, o, records=True):
                 assert_close(g["records"][gen][f], o["records"][gen][f], what=f"gen {gen} {f}")
 
 
+def test_ce_supercritical_generation_end_parity(oracle):
+    """A flat continuous-energy medium with k near 2.4: the first generation
+    banks about 2.4 sites per history, so the sites of the first 1,024
+    histories exceed what the generation end stages in LDS per bucket and are
+    written one by one (energies included), while the next bucket and the
+    later generations go through LDS.  Records, k, entropy and the last bank
+    against the oracle."""
+    banner("CE supercritical flat medium 1500 x 3 records parity")
+    ce = P.ce_flat(sig_s=0.5, sig_c=0.0, sig_f=1.5, awr=200.0)
+    prob = P.ce_homogeneous(ce, 1500, 3, 1, seed=71)
+    g = mcx.run(prob, record=True, bank=True)
+    o = oracle.run(prob, records=True, bank_cap=20000)
+    assert o["records"][0]["n_sites"][:1024].sum() > 2048
+    compare(g, o)
+    assert np.array_equal(g["bank"], o["bank"])
+
+
 def test_ce_pin_cell_records_parity(oracle):
     """The continuous-energy pin cell, 3000 histories x 4 generations: every
     history, the flux tallies per generation and the final bank."""
